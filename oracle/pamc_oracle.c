@@ -1,0 +1,675 @@
+/*
+ * pamc_oracle.c -- plain CPU population annealing Monte Carlo (PAMC) for the
+ * three-dimensional +-J Edwards-Anderson spin glass.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously correct oracle that
+ * the GPU library is checked against.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark load it.  It shares no code,
+ * header, table or constant generator with the GPU library.
+ *
+ * Paper: A. Barzegar, C. Pattison, W. Wang, H. G. Katzgraber, "Optimization
+ * of population annealing Monte Carlo for large-scale spin-glass simulations"
+ * (arXiv:1710.09025).  Passages followed:
+ *   Sec. II.A, Eq. (1)   H = -sum_<ij> J_ij S_i S_j, nearest neighbours on an
+ *                        L^D lattice, N = L^D spins.
+ *   Sec. II.B            PAMC outline: R replicas initialised at random at
+ *                        beta = 0; on each lowering beta -> beta' the mean
+ *                        number of copies of replica i is proportional to
+ *                        exp[-(beta'-beta) E_i], normalised so that the
+ *                        expected new population is R(beta'); then N_S
+ *                        Metropolis sweeps per replica, one sweep being N
+ *                        attempted spin updates.
+ *   Sec. II.B, Eq. (2)   family entropy S_f = -sum_i nu_i ln nu_i and the
+ *                        entropic family size rho_s = R / e^{S_f}; the free
+ *                        energy by free-energy perturbation.
+ *   Sec. III.A           checkerboard spin selection on bipartite lattices.
+ *   Sec. III.D           rho_s uses the local population size R at each beta.
+ *   Sec. V.A, Eq. (9)    observables are population averages; the spin
+ *                        overlap is measured only at selected temperatures.
+ *
+ * Readings where the paper is silent (the design notes list every one):
+ *   periodic boundaries; +-J couplings; for odd L a three-colouring
+ *   c = (g(x)+g(y)+g(z)) mod 3 with g(v) = v mod 2 for v < L-1 and
+ *   g(L-1) = 2; a Philox4x32-10 counter contract for every random number;
+ *   Metropolis acceptance as a uint32 threshold compare; nearest-integer
+ *   (floor/ceil) resampling normalised to the nominal R; weights taken
+ *   relative to E_min as a fixed product of powers of exp(-2 dbeta); a
+ *   pairwise summation tree for the normaliser and for the family term;
+ *   the order sweep -> measure -> resample at every beta_k, beta_0 included.
+ *
+ * Spins are stored as int8 +-1, replica-major, sites in lexicographic order
+ * s = x + L (y + L z).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_ERR_INVALID = -1,
+    ORC_ERR_NOMEM = -2,
+    ORC_ERR_CAPACITY = -3,
+    ORC_ERR_EXTINCT = -4,
+    ORC_ERR_STATE = -6
+};
+
+/* Philox stream tags, the top four bits of counter word 3. */
+#define TAG_INIT 0x10000000u
+#define TAG_SWEEP 0x20000000u
+#define TAG_RESAMPLE 0x30000000u
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications    */
+/* with the round key added by XOR, the key bumped by the Weyl constants     */
+/* between rounds.                                                           */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+static uint32_t draw(uint64_t seed, uint32_t x, uint32_t y, uint32_t z, uint32_t w, int word)
+{
+    uint32_t ctr[4] = {x, y, z, w};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[word];
+}
+
+/* ------------------------------------------------------------------------ */
+/* State                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int L, N, ncol;
+    int64_t R, Rcap;
+    int nT, NS;
+    uint64_t seed;
+    double *beta;
+    int8_t *J;      /* [3][N]: bond (s, d) joins s and s + e_d            */
+    int *nbr;       /* [N][6]: +x, -x, +y, -y, +z, -z                     */
+    int8_t *Jn;     /* [N][6]: coupling of the bond to that neighbour     */
+    int *colour;    /* [N]                                                */
+    int *crank;     /* [N]: rank of s among sites of its colour           */
+    int8_t *spin, *spin2;
+    int32_t *E, *E2;
+    uint32_t *fam, *fam2;
+    uint32_t *ncopy;
+    int64_t Rk;
+    int k;
+    double lnZ;
+    uint8_t *ovl;   /* [nT]: measure the overlap at this step             */
+    int nthreads;
+    /* per-step records */
+    int64_t *o_R, *o_sumE, *o_sumE2;
+    int32_t *o_Emin, *o_Emax;
+    double *o_S, *o_T, *o_lnQ, *o_lnZ;
+    int64_t *o_q; /* [nT][2N+1] */
+} orc_t;
+
+static int site(int L, int x, int y, int z) { return x + L * (y + L * z); }
+
+/* Colour of a site (Sec. III.A checkerboard; three colours for odd L). */
+static int colour_of(int L, int x, int y, int z)
+{
+    if (L % 2 == 0) return (x + y + z) % 2;
+    int gx = (x == L - 1) ? 2 : x % 2;
+    int gy = (y == L - 1) ? 2 : y % 2;
+    int gz = (z == L - 1) ? 2 : z % 2;
+    return (gx + gy + gz) % 3;
+}
+
+void orc_destroy(orc_t *o)
+{
+    if (!o) return;
+    free(o->beta);
+    free(o->J);
+    free(o->nbr);
+    free(o->Jn);
+    free(o->colour);
+    free(o->crank);
+    free(o->spin);
+    free(o->spin2);
+    free(o->E);
+    free(o->E2);
+    free(o->fam);
+    free(o->fam2);
+    free(o->ncopy);
+    free(o->ovl);
+    free(o->o_R);
+    free(o->o_sumE);
+    free(o->o_sumE2);
+    free(o->o_Emin);
+    free(o->o_Emax);
+    free(o->o_S);
+    free(o->o_T);
+    free(o->o_lnQ);
+    free(o->o_lnZ);
+    free(o->o_q);
+    free(o);
+}
+
+/* Energy of one replica, Eq. (1): each of the 3N bonds counted once. */
+static int32_t energy(const orc_t *o, const int8_t *S)
+{
+    int32_t e = 0;
+    for (int s = 0; s < o->N; ++s)
+        for (int d = 0; d < 3; ++d) e -= o->J[d * o->N + s] * S[s] * S[o->nbr[s * 6 + 2 * d]];
+    return e;
+}
+
+/* Random initial replicas at beta = 0 (Sec. II.B): S = +1 when bit 31 of the
+ * INIT draw is set. */
+static void init_population(orc_t *o)
+{
+    for (int64_t r = 0; r < o->R; ++r) {
+        int8_t *S = o->spin + r * o->N;
+        for (int s = 0; s < o->N; ++s) {
+            uint32_t u = draw(o->seed, (uint32_t)(s >> 2), (uint32_t)r, 0u, TAG_INIT, s & 3);
+            S[s] = (u >> 31) ? 1 : -1;
+        }
+        o->E[r] = energy(o, S);
+        o->fam[r] = (uint32_t)r;
+    }
+    o->Rk = o->R;
+    o->k = 0;
+    o->lnZ = (double)o->N * log(2.0);
+}
+
+orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double *beta, int nT, int NS,
+                  uint64_t seed, const uint8_t *overlap_steps)
+{
+    if (L < 2 || L > 32 || R < 1 || nT < 1 || NS < 1 || !J || !beta) return NULL;
+    if (Rcap < R) return NULL;
+    for (int i = 0; i < nT; ++i) {
+        if (!(beta[i] >= 0.0) || !isfinite(beta[i])) return NULL;
+        if (i > 0 && beta[i] < beta[i - 1]) return NULL;
+    }
+    orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
+    if (!o) return NULL;
+    o->L = L;
+    o->N = L * L * L;
+    o->ncol = (L % 2 == 0) ? 2 : 3;
+    o->R = R;
+    o->Rcap = Rcap;
+    o->nT = nT;
+    o->NS = NS;
+    o->seed = seed;
+    o->nthreads = 1;
+    int N = o->N;
+    o->beta = (double *)malloc(sizeof(double) * nT);
+    o->J = (int8_t *)malloc(3 * (size_t)N);
+    o->nbr = (int *)malloc(sizeof(int) * 6 * (size_t)N);
+    o->Jn = (int8_t *)malloc(6 * (size_t)N);
+    o->colour = (int *)malloc(sizeof(int) * N);
+    o->crank = (int *)malloc(sizeof(int) * N);
+    o->spin = (int8_t *)malloc((size_t)Rcap * N);
+    o->spin2 = (int8_t *)malloc((size_t)Rcap * N);
+    o->E = (int32_t *)malloc(sizeof(int32_t) * Rcap);
+    o->E2 = (int32_t *)malloc(sizeof(int32_t) * Rcap);
+    o->fam = (uint32_t *)malloc(sizeof(uint32_t) * Rcap);
+    o->fam2 = (uint32_t *)malloc(sizeof(uint32_t) * Rcap);
+    o->ncopy = (uint32_t *)malloc(sizeof(uint32_t) * Rcap);
+    o->ovl = (uint8_t *)calloc(nT, 1);
+    o->o_R = (int64_t *)calloc(nT, sizeof(int64_t));
+    o->o_sumE = (int64_t *)calloc(nT, sizeof(int64_t));
+    o->o_sumE2 = (int64_t *)calloc(nT, sizeof(int64_t));
+    o->o_Emin = (int32_t *)calloc(nT, sizeof(int32_t));
+    o->o_Emax = (int32_t *)calloc(nT, sizeof(int32_t));
+    o->o_S = (double *)calloc(nT, sizeof(double));
+    o->o_T = (double *)calloc(nT, sizeof(double));
+    o->o_lnQ = (double *)calloc(nT, sizeof(double));
+    o->o_lnZ = (double *)calloc(nT, sizeof(double));
+    o->o_q = (int64_t *)calloc((size_t)nT * (2 * N + 1), sizeof(int64_t));
+    if (!o->beta || !o->J || !o->nbr || !o->Jn || !o->colour || !o->crank || !o->spin || !o->spin2 ||
+        !o->E || !o->E2 || !o->fam || !o->fam2 || !o->ncopy || !o->ovl || !o->o_R || !o->o_sumE ||
+        !o->o_sumE2 || !o->o_Emin || !o->o_Emax || !o->o_S || !o->o_T || !o->o_lnQ || !o->o_lnZ ||
+        !o->o_q) {
+        orc_destroy(o);
+        return NULL;
+    }
+    memcpy(o->beta, beta, sizeof(double) * nT);
+    for (int i = 0; i < 3 * N; ++i) {
+        if (J[i] != 1 && J[i] != -1) {
+            orc_destroy(o);
+            return NULL;
+        }
+        o->J[i] = J[i];
+    }
+    if (overlap_steps)
+        memcpy(o->ovl, overlap_steps, nT);
+    else
+        o->ovl[nT - 1] = 1;
+
+    /* Lattice (Sec. II.A): periodic neighbours and the coupling of each of
+     * the six bonds of a site.  Bond (s, d) is stored at J[d][s] and joins s
+     * to s + e_d, so the bond to s - e_d is J[d][s - e_d].  For L = 2 the
+     * two x-neighbours coincide but the two bonds stay distinct. */
+    int count[3] = {0, 0, 0};
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                int s = site(L, x, y, z);
+                int xp = site(L, (x + 1) % L, y, z), xm = site(L, (x + L - 1) % L, y, z);
+                int yp = site(L, x, (y + 1) % L, z), ym = site(L, x, (y + L - 1) % L, z);
+                int zp = site(L, x, y, (z + 1) % L), zm = site(L, x, y, (z + L - 1) % L);
+                int *nb = o->nbr + 6 * s;
+                nb[0] = xp;
+                nb[1] = xm;
+                nb[2] = yp;
+                nb[3] = ym;
+                nb[4] = zp;
+                nb[5] = zm;
+                int8_t *jn = o->Jn + 6 * s;
+                jn[0] = o->J[0 * N + s];
+                jn[1] = o->J[0 * N + xm];
+                jn[2] = o->J[1 * N + s];
+                jn[3] = o->J[1 * N + ym];
+                jn[4] = o->J[2 * N + s];
+                jn[5] = o->J[2 * N + zm];
+                int c = colour_of(L, x, y, z);
+                o->colour[s] = c;
+                o->crank[s] = count[c]++;
+            }
+    init_population(o);
+    return o;
+}
+
+void orc_set_threads(orc_t *o, int n) { o->nthreads = n < 1 ? 1 : n; }
+
+/* Metropolis acceptance thresholds for dE = 4, 8, 12 at inverse temperature
+ * b: accept a move with dE > 0 when its uniform uint32 draw u is below
+ * floor(exp(-b dE) 2^32), capped at 2^32 - 1.  beta = 0 accepts every move
+ * (the flag), because 2^32 itself does not fit in 32 bits. */
+void orc_thresholds(double b, uint32_t T[3], int *accept_all)
+{
+    *accept_all = (b == 0.0);
+    for (int j = 0; j < 3; ++j) {
+        double dE = 4.0 * (j + 1);
+        double x = floor(exp(-b * dE) * 4294967296.0);
+        T[j] = (x >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)x;
+    }
+}
+
+/* N_S Metropolis sweeps of one replica at step k (Sec. II.B; checkerboard
+ * order of Sec. III.A): colours ascending; inside a colour sites share no
+ * bond, so visiting them lexicographically equals updating them at once. */
+static void sweep_replica(orc_t *o, int64_t r, const uint32_t T[3], int accept_all)
+{
+    int8_t *S = o->spin + r * o->N;
+    int32_t E = o->E[r];
+    for (int t = 0; t < o->NS; ++t)
+        for (int c = 0; c < o->ncol; ++c)
+            for (int s = 0; s < o->N; ++s) {
+                if (o->colour[s] != c) continue;
+                const int *nb = o->nbr + 6 * s;
+                const int8_t *jn = o->Jn + 6 * s;
+                int h = 0;
+                for (int d = 0; d < 6; ++d) h += jn[d] * S[nb[d]];
+                int dE = 2 * S[s] * h;
+                int i = o->crank[s];
+                uint32_t u = draw(o->seed, ((uint32_t)c << 24) | (uint32_t)(i >> 2), (uint32_t)r,
+                                  (uint32_t)o->k, TAG_SWEEP | (uint32_t)t, i & 3);
+                int accept = accept_all || dE <= 0 || u < T[dE / 4 - 1];
+                if (accept) {
+                    S[s] = (int8_t)-S[s];
+                    E += dE;
+                }
+            }
+    o->E[r] = E;
+}
+
+/* Pairwise summation tree over n leaves (n a power of two): level by level,
+ * node i of the next level is left child 2i plus right child 2i+1. */
+static double pairwise_tree(double *a, int64_t n)
+{
+    while (n > 1) {
+        for (int64_t i = 0; i < n / 2; ++i) a[i] = a[2 * i] + a[2 * i + 1];
+        n /= 2;
+    }
+    return a[0];
+}
+
+static int64_t pow2_at_least(int64_t n)
+{
+    int64_t p = 1;
+    while (p < n) p *= 2;
+    return p;
+}
+
+/* Measurements at step k (Sec. II.B, Eq. (2); Sec. V.A, Eq. (9)). */
+static int measure(orc_t *o)
+{
+    int k = o->k, N = o->N;
+    int64_t sumE = 0, sumE2 = 0;
+    int32_t Emin = o->E[0], Emax = o->E[0];
+    for (int64_t r = 0; r < o->Rk; ++r) {
+        int64_t e = o->E[r];
+        sumE += e;
+        sumE2 += e * e;
+        if (o->E[r] < Emin) Emin = o->E[r];
+        if (o->E[r] > Emax) Emax = o->E[r];
+    }
+    o->o_R[k] = o->Rk;
+    o->o_sumE[k] = sumE;
+    o->o_sumE2[k] = sumE2;
+    o->o_Emin[k] = Emin;
+    o->o_Emax[k] = Emax;
+    o->o_lnZ[k] = o->lnZ;
+
+    /* Family term sum_i n_i ln n_i over the initial replicas i (families),
+     * n_i = number of descendants of i; summed by the pairwise tree over
+     * family ids 0 .. P-1 (P = smallest power of two >= R). */
+    int64_t P = pow2_at_least(o->R);
+    uint32_t *cnt = (uint32_t *)calloc((size_t)o->R, sizeof(uint32_t));
+    double *leaf = (double *)calloc((size_t)P, sizeof(double));
+    if (!cnt || !leaf) {
+        free(cnt);
+        free(leaf);
+        return ORC_ERR_NOMEM;
+    }
+    for (int64_t r = 0; r < o->Rk; ++r) cnt[o->fam[r]]++;
+    for (int64_t f = 0; f < o->R; ++f)
+        leaf[f] = cnt[f] > 0 ? (double)cnt[f] * log((double)cnt[f]) : 0.0;
+    o->o_T[k] = pairwise_tree(leaf, P);
+    free(cnt);
+    free(leaf);
+
+    /* Spin overlap at selected steps (Sec. V.A): replica r is paired with
+     * r + floor(R_k / 2); Q = sum_s S_s S'_s, histogram over Q + N. */
+    if (o->ovl[k]) {
+        int64_t *q = o->o_q + (size_t)k * (2 * N + 1);
+        int64_t h = o->Rk / 2;
+        for (int64_t r = 0; r < h; ++r) {
+            const int8_t *a = o->spin + r * N, *b = o->spin + (r + h) * N;
+            int Q = 0;
+            for (int s = 0; s < N; ++s) Q += a[s] * b[s];
+            q[Q + N]++;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Resampling from beta_k to beta_{k+1} (Sec. II.B).  The mean number of
+ * copies of replica i is tau_i = R exp[-(beta'-beta) E_i] / sum_j exp[...],
+ * so that the expected new population is the nominal R; replica i gets
+ * floor(tau_i) copies plus one more with probability frac(tau_i).  Copies
+ * keep source order (families stay contiguous). */
+static int resample(orc_t *o)
+{
+    int k = o->k, N = o->N;
+    double dbeta = o->beta[k + 1] - o->beta[k];
+    int32_t Emin = o->o_Emin[k], Emax = o->o_Emax[k];
+    int64_t M = (Emax - Emin) / 2; /* energies differ by multiples of 2 */
+    int64_t P = pow2_at_least(M + 1);
+    int64_t *hist = (int64_t *)calloc((size_t)(M + 1), sizeof(int64_t));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(M + 1));
+    double *leaf = (double *)calloc((size_t)P, sizeof(double));
+    uint32_t *B = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(M + 1));
+    uint32_t *F = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(M + 1));
+    if (!hist || !w || !leaf || !B || !F) {
+        free(hist);
+        free(w);
+        free(leaf);
+        free(B);
+        free(F);
+        return ORC_ERR_NOMEM;
+    }
+    for (int64_t r = 0; r < o->Rk; ++r) hist[(o->E[r] - Emin) / 2]++;
+
+    /* Level weights w[m] = exp(-dbeta (E - E_min)) = rho^m, rho = exp(-2 dbeta),
+     * formed as the product of rho^(2^b) over the set bits b of m, ascending. */
+    double rho = exp(-2.0 * dbeta);
+    double pw[64];
+    pw[0] = rho;
+    for (int b = 1; b < 64; ++b) pw[b] = pw[b - 1] * pw[b - 1];
+    for (int64_t m = 0; m <= M; ++m) {
+        double x = 1.0;
+        for (int b = 0; b < 63; ++b)
+            if ((m >> b) & 1) x = x * pw[b];
+        w[m] = x;
+    }
+    for (int64_t m = 0; m <= M; ++m) leaf[m] = (double)hist[m] * w[m];
+    double S = pairwise_tree(leaf, P);
+
+    for (int64_t m = 0; m <= M; ++m) {
+        double tau = ((double)o->R * w[m]) / S;
+        double fl = floor(tau);
+        B[m] = (uint32_t)fl;
+        F[m] = (uint32_t)floor((tau - fl) * 4294967296.0);
+    }
+
+    int64_t Rn = 0;
+    for (int64_t r = 0; r < o->Rk; ++r) {
+        int64_t m = (o->E[r] - Emin) / 2;
+        uint32_t u = draw(o->seed, 0u, (uint32_t)r, (uint32_t)k, TAG_RESAMPLE, 0);
+        o->ncopy[r] = B[m] + (u < F[m] ? 1u : 0u);
+        Rn += o->ncopy[r];
+    }
+    free(hist);
+    free(w);
+    free(leaf);
+    free(B);
+    free(F);
+    if (Rn > o->Rcap) return ORC_ERR_CAPACITY;
+    if (Rn == 0) return ORC_ERR_EXTINCT;
+
+    int64_t d = 0;
+    for (int64_t r = 0; r < o->Rk; ++r)
+        for (uint32_t j = 0; j < o->ncopy[r]; ++j, ++d) {
+            memcpy(o->spin2 + d * N, o->spin + r * N, (size_t)N);
+            o->E2[d] = o->E[r];
+            o->fam2[d] = o->fam[r];
+        }
+    int8_t *ts = o->spin;
+    o->spin = o->spin2;
+    o->spin2 = ts;
+    int32_t *te = o->E;
+    o->E = o->E2;
+    o->E2 = te;
+    uint32_t *tf = o->fam;
+    o->fam = o->fam2;
+    o->fam2 = tf;
+
+    /* Free-energy perturbation: Q_k = (1/R_k) sum_i exp(-dbeta E_i)
+     * = exp(-dbeta E_min) S / R_k, and ln Z_{k+1} = ln Z_k + ln Q_k. */
+    double lnQ = (-dbeta * (double)Emin) + log(S) - log((double)o->Rk);
+    o->o_S[k] = S;
+    o->o_lnQ[k] = lnQ;
+    o->lnZ = o->lnZ + lnQ;
+    o->Rk = Rn;
+    return ORC_OK;
+}
+
+/* Run up to n_steps temperature steps (n_steps < 0: to the end).  A step k
+ * is: N_S sweeps at beta_k, measurement, and (k < nT-1) resampling. */
+int orc_run(orc_t *o, int n_steps)
+{
+    if (!o) return ORC_ERR_INVALID;
+    int done = 0;
+    while (o->k < o->nT && (n_steps < 0 || done < n_steps)) {
+        uint32_t T[3];
+        int all;
+        orc_thresholds(o->beta[o->k], T, &all);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(o->nthreads)
+#endif
+        for (int64_t r = 0; r < o->Rk; ++r) sweep_replica(o, r, T, all);
+        int st = measure(o);
+        if (st != ORC_OK) return st;
+        if (o->k < o->nT - 1) {
+            st = resample(o);
+            if (st != ORC_OK) return st;
+        }
+        o->k += 1;
+        done += 1;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors for the ctypes wrapper                                          */
+/* ------------------------------------------------------------------------ */
+int orc_step(const orc_t *o) { return o->k; }
+int64_t orc_population(const orc_t *o) { return o->Rk; }
+int orc_num_spins(const orc_t *o) { return o->N; }
+double orc_lnZ(const orc_t *o) { return o->lnZ; }
+
+/* Per-step records: ints[k][5] = R_k, sum E, sum E^2, E_min, E_max;
+ * dbl[k][4] = S_k (normaliser), family term T_k, ln Q_k, ln Z_k. */
+int orc_records(const orc_t *o, int64_t *ints, double *dbl, int64_t *qhist)
+{
+    for (int k = 0; k < o->nT; ++k) {
+        ints[5 * k + 0] = o->o_R[k];
+        ints[5 * k + 1] = o->o_sumE[k];
+        ints[5 * k + 2] = o->o_sumE2[k];
+        ints[5 * k + 3] = o->o_Emin[k];
+        ints[5 * k + 4] = o->o_Emax[k];
+        dbl[4 * k + 0] = o->o_S[k];
+        dbl[4 * k + 1] = o->o_T[k];
+        dbl[4 * k + 2] = o->o_lnQ[k];
+        dbl[4 * k + 3] = o->o_lnZ[k];
+    }
+    if (qhist) memcpy(qhist, o->o_q, sizeof(int64_t) * (size_t)o->nT * (2 * o->N + 1));
+    return ORC_OK;
+}
+
+/* Current population: spins [R_k][N] int8 +-1 lexicographic, E, family. */
+int orc_get_state(const orc_t *o, int8_t *spins, int32_t *E, uint32_t *fam)
+{
+    memcpy(spins, o->spin, (size_t)o->Rk * o->N);
+    memcpy(E, o->E, sizeof(int32_t) * (size_t)o->Rk);
+    memcpy(fam, o->fam, sizeof(uint32_t) * (size_t)o->Rk);
+    return ORC_OK;
+}
+
+/* Replace the population (checkpoint resume / step-wise parity).  Energies
+ * are recomputed from the spins with Eq. (1). */
+int orc_set_state(orc_t *o, int k, int64_t Rk, const int8_t *spins, const uint32_t *fam, double lnZ)
+{
+    if (k < 0 || k >= o->nT || Rk < 1 || Rk > o->Rcap) return ORC_ERR_INVALID;
+    for (int64_t i = 0; i < Rk * o->N; ++i)
+        if (spins[i] != 1 && spins[i] != -1) return ORC_ERR_INVALID;
+    for (int64_t r = 0; r < Rk; ++r)
+        if (fam[r] >= (uint64_t)o->R) return ORC_ERR_INVALID;
+    memcpy(o->spin, spins, (size_t)Rk * o->N);
+    memcpy(o->fam, fam, sizeof(uint32_t) * (size_t)Rk);
+    for (int64_t r = 0; r < Rk; ++r) o->E[r] = energy(o, o->spin + r * o->N);
+    o->Rk = Rk;
+    o->k = k;
+    o->lnZ = lnZ;
+    return ORC_OK;
+}
+
+/* Energy of arbitrary configurations of this instance (Eq. (1)). */
+int orc_energies(const orc_t *o, const int8_t *spins, int64_t n, int32_t *E)
+{
+    for (int64_t r = 0; r < n; ++r) E[r] = energy(o, spins + r * o->N);
+    return ORC_OK;
+}
+
+/* Colour and colour rank of every site, for tests of the colouring. */
+int orc_colouring(const orc_t *o, int32_t *colour, int32_t *crank)
+{
+    for (int s = 0; s < o->N; ++s) {
+        colour[s] = o->colour[s];
+        crank[s] = o->crank[s];
+    }
+    return o->ncol;
+}
+
+/* Neighbour table [N][6] (+x, -x, +y, -y, +z, -z). */
+int orc_neighbours(const orc_t *o, int32_t *nb)
+{
+    for (int i = 0; i < 6 * o->N; ++i) nb[i] = o->nbr[i];
+    return ORC_OK;
+}
+
+/* Derived observables per step k (Sec. II.B, Eq. (2); Sec. V.A, Eq. (9)),
+ * out[k][12] = beta, R_k, <E>, <E>/N, C_V, ln Q_k, ln Z_k, beta F_k, f_k,
+ * S_f, rho_s, and the overlap Binder cumulant g_SG (NaN when the overlap was
+ * not measured at k).  Definitions:
+ *   <E> = sum E / R_k;  C_V = beta^2 var(E) / N with the variance taken
+ *   exactly in integers, (R_k sum E^2 - (sum E)^2) / R_k^2;
+ *   beta F = -ln Z;  f = -ln Z / (beta N) (NaN at beta = 0);
+ *   S_f = ln R_k - (1/R_k) sum_i n_i ln n_i  (= -sum_i nu_i ln nu_i);
+ *   rho_s = R_k / e^{S_f} with the local R_k;
+ *   q = Q / N, <q^p> = sum_Q h[Q] q^p / sum_Q h[Q] in ascending Q,
+ *   g_SG = (3 - <q^4>/<q^2>^2) / 2.
+ * ovl_out[k][3] = <|q|>, <q^2>, <q^4> (NaN when not measured). */
+int orc_observables(const orc_t *o, double *out, double *ovl_out)
+{
+    int N = o->N;
+    for (int k = 0; k < o->nT; ++k) {
+        double *v = out + 12 * k;
+        double b = o->beta[k];
+        int64_t Rk = o->o_R[k];
+        for (int i = 0; i < 12; ++i) v[i] = NAN;
+        for (int i = 0; i < 3; ++i) ovl_out[3 * k + i] = NAN;
+        v[0] = b;
+        if (Rk <= 0) continue;
+        double R = (double)Rk;
+        double meanE = (double)o->o_sumE[k] / R;
+        __int128 num = (__int128)Rk * (__int128)o->o_sumE2[k] - (__int128)o->o_sumE[k] * (__int128)o->o_sumE[k];
+        double var = (double)num / (R * R);
+        v[1] = R;
+        v[2] = meanE;
+        v[3] = meanE / (double)N;
+        v[4] = (b * b) * var / (double)N;
+        v[5] = (k < o->nT - 1) ? o->o_lnQ[k] : NAN;
+        v[6] = o->o_lnZ[k];
+        v[7] = -o->o_lnZ[k];
+        v[8] = (b > 0.0) ? -o->o_lnZ[k] / (b * (double)N) : NAN;
+        double Sf = log(R) - o->o_T[k] / R;
+        v[9] = Sf;
+        v[10] = R / exp(Sf);
+        if (o->ovl[k]) {
+            const int64_t *h = o->o_q + (size_t)k * (2 * N + 1);
+            int64_t n = 0;
+            double m1 = 0.0, m2 = 0.0, m4 = 0.0;
+            for (int Q = -N; Q <= N; ++Q) {
+                int64_t c = h[Q + N];
+                if (c == 0) continue;
+                double q = (double)Q / (double)N;
+                n += c;
+                m1 += (double)c * fabs(q);
+                m2 += (double)c * (q * q);
+                m4 += (double)c * ((q * q) * (q * q));
+            }
+            if (n > 0) {
+                m1 /= (double)n;
+                m2 /= (double)n;
+                m4 /= (double)n;
+                ovl_out[3 * k + 0] = m1;
+                ovl_out[3 * k + 1] = m2;
+                ovl_out[3 * k + 2] = m4;
+                v[11] = 0.5 * (3.0 - m4 / (m2 * m2));
+            }
+        }
+    }
+    return ORC_OK;
+}

@@ -1,0 +1,104 @@
+"""Seeded synthetic inputs for population annealing runs.
+
+This module holds no part of the method's arithmetic: it only draws problem
+instances (couplings), builds temperature schedules and the workload
+descriptions, so that the GPU library, the oracle, the tests and the
+benchmark all see the same inputs.  The paper's own disorder instances are not
+published; +-J couplings with probability 1/2 each from a seeded generator
+stand in for them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def pm_j_couplings(L: int, disorder_seed: int) -> np.ndarray:
+    """+-J couplings, int8 [3][L^3]: J[d][s] couples site s to s + e_d."""
+    N = L ** 3
+    rng = np.random.Generator(np.random.PCG64(np.uint64(disorder_seed)))
+    bits = rng.integers(0, 2, size=(3, N), dtype=np.int8)
+    return (2 * bits - 1).astype(np.int8)
+
+
+def ferro_couplings(L: int) -> np.ndarray:
+    return np.ones((3, L ** 3), dtype=np.int8)
+
+
+def mattis_couplings(L: int, seed: int):
+    """Mattis instance J_ij = eps_i eps_j: ground state energy exactly -3N."""
+    N = L ** 3
+    rng = np.random.Generator(np.random.PCG64(np.uint64(seed)))
+    eps = (2 * rng.integers(0, 2, size=N) - 1).astype(np.int8)
+    J = np.empty((3, N), dtype=np.int8)
+    idx = np.arange(N)
+    x, y, z = idx % L, (idx // L) % L, idx // (L * L)
+    nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z),
+          x + L * (y + L * ((z + 1) % L))]
+    for d in range(3):
+        J[d] = eps * eps[nb[d]]
+    return J, eps
+
+
+def gauge_transform(L: int, couplings: np.ndarray, eps: np.ndarray) -> np.ndarray:
+    """J_ij -> eps_i J_ij eps_j for a +-1 vector eps over the sites."""
+    N = L ** 3
+    idx = np.arange(N)
+    x, y, z = idx % L, (idx // L) % L, idx // (L * L)
+    nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z),
+          x + L * (y + L * ((z + 1) % L))]
+    J = np.array(couplings, dtype=np.int8).reshape(3, N).copy()
+    for d in range(3):
+        J[d] = (eps * J[d] * eps[nb[d]]).astype(np.int8)
+    return J
+
+
+def linear_beta(beta_max: float, n_temps: int) -> np.ndarray:
+    """Linear-in-beta schedule beta_k = beta_max k / (n_temps - 1)."""
+    if n_temps == 1:
+        return np.zeros(1)
+    return np.array([beta_max * k / (n_temps - 1) for k in range(n_temps)], dtype=np.float64)
+
+
+def random_spins(R: int, N: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.uint64(seed)))
+    return (2 * rng.integers(0, 2, size=(R, N), dtype=np.int8) - 1).astype(np.int8)
+
+
+# Workloads (3D +-J Edwards-Anderson, periodic boundaries, N_S = 10 sweeps).
+WORKLOADS = {
+    "L4_R1000": dict(L=4, R=1000, n_temps=101, beta_max=5.0, sweeps=10, disorder_seed=1, seed=1),
+    "L8_R100000": dict(L=8, R=100_000, n_temps=201, beta_max=5.0, sweeps=10, disorder_seed=2,
+                       seed=2),
+    "L16_R500000": dict(L=16, R=500_000, n_temps=301, beta_max=5.0, sweeps=10, disorder_seed=3,
+                        seed=3),
+}
+
+
+def batch_instances(n: int, sizes=(4, 6, 8, 10, 12), R: int = 20_000, n_temps: int = 201,
+                    sweeps: int = 10, shuffle_seed: int = 4):
+    """Mixed-size instance list: n/len(sizes) instances of each L, shuffled."""
+    per = n // len(sizes)
+    Ls = np.repeat(np.array(sizes), per)
+    Ls = np.concatenate([Ls, np.array(sizes[: n - len(Ls)], dtype=Ls.dtype)])
+    rng = np.random.Generator(np.random.PCG64(np.uint64(shuffle_seed)))
+    rng.shuffle(Ls)
+    out = []
+    for i, L in enumerate(Ls):
+        out.append(dict(L=int(L), couplings=pm_j_couplings(int(L), 1_000_000 + i), R=R,
+                        beta=linear_beta(5.0, n_temps), sweeps=sweeps, seed=2_000_000 + i))
+    return out
+
+
+def serving_requests(n: int, rate: float = 50.0, seed: int = 5, Lmin: int = 4, Lmax: int = 14,
+                     Rmin: int = 5000, Rmax: int = 50000, n_temps: int = 101, sweeps: int = 10):
+    """Poisson arrivals (exponential gaps) of random instances."""
+    rng = np.random.Generator(np.random.PCG64(np.uint64(seed)))
+    gaps = rng.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        L = int(rng.integers(Lmin, Lmax + 1))
+        R = int(rng.integers(Rmin, Rmax + 1))
+        out.append(dict(arrival=float(t[i]), L=L, couplings=pm_j_couplings(L, 3_000_000 + i), R=R,
+                        beta=linear_beta(5.0, n_temps), sweeps=sweeps, seed=4_000_000 + i))
+    return out
