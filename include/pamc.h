@@ -1,0 +1,250 @@
+/*
+ * pamc.h -- population annealing Monte Carlo for 3D +-J Edwards-Anderson spin
+ * glasses on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one of Barzegar, Pattison, Wang and Katzgraber,
+ * "Optimization of population annealing Monte Carlo for large-scale
+ * spin-glass simulations" (arXiv:1710.09025):
+ *   - Sec. II.A, Eq. (1): H = -sum_<ij> J_ij S_i S_j on the periodic L^3
+ *     lattice, N = L^3 Ising spins, couplings J_ij = +-1;
+ *   - Sec. II.B: R replicas start at random at beta_0 = 0; at each of the
+ *     n_temps inverse temperatures beta_k the library runs `sweeps`
+ *     Metropolis sweeps on every replica (one sweep = N attempted flips,
+ *     checkerboard order of Sec. III.A), measures, and resamples to
+ *     beta_{k+1}: replica i gets floor(tau_i) or ceil(tau_i) copies with
+ *     tau_i = R exp(-(beta_{k+1}-beta_k) E_i) / sum_j exp(...), so the
+ *     expected population stays R;
+ *   - Sec. II.B, Eq. (2), Sec. V.A, Eq. (9): per-step observables (mean
+ *     energy, specific heat, free energy by free-energy perturbation, family
+ *     entropy S_f, entropic family size rho_s) and, at selected steps, the
+ *     spin-overlap histogram.
+ *
+ * Every random number is a Philox4x32-10 word keyed by the run's seed and
+ * counted by (site, replica row, step, sweep), so every output is a pure
+ * function of (L, couplings, R, beta, sweeps, seed): it does not depend on
+ * options, spin format, launch shapes, streams or batch composition.
+ *
+ * Conventions for every call:
+ *   - all pointers are host pointers unless stated otherwise;
+ *   - inputs are copied, the caller keeps ownership of its buffers;
+ *   - outputs go to caller-owned host buffers of the stated size;
+ *   - every call returns a status (PAMC_OK or a negative PAMC_ERR_*); none
+ *     aborts or throws; pamc_last_error() gives a message for the calling
+ *     thread;
+ *   - a failed call leaves the handle as it was, except PAMC_ERR_DEVICE,
+ *     after which the handle only accepts pamc_destroy().
+ * A handle is used by one thread at a time.
+ */
+#ifndef PAMC_H
+#define PAMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PAMC_OK = 0,
+    PAMC_ERR_INVALID = -1,  /* an argument is out of range                  */
+    PAMC_ERR_NOMEM = -2,    /* a device or host allocation failed           */
+    PAMC_ERR_CAPACITY = -3, /* resampling would exceed the capacity         */
+    PAMC_ERR_EXTINCT = -4,  /* resampling produced an empty population      */
+    PAMC_ERR_DEVICE = -5,   /* a HIP call failed; the handle is poisoned     */
+    PAMC_ERR_STATE = -6,    /* the call does not fit the handle's state     */
+    PAMC_ERR_BUSY = -7,     /* the request or handle is not finished        */
+    PAMC_ERR_REJECTED = -8  /* a serving request can never fit the budget   */
+};
+
+/* Spin storage on the device. */
+enum { PAMC_SPINS_INT8 = 0, PAMC_SPINS_PACKED = 1 };
+
+typedef struct pamc_options {
+    int spin_format;         /* PAMC_SPINS_INT8 (default) or PAMC_SPINS_PACKED  */
+    int64_t capacity;        /* rows reserved per buffer; 0 = R + ceil(8 sqrt R) + 64 */
+    void *stream;            /* hipStream_t to run on; NULL = a library stream  */
+    /* optional device allocator (e.g. a framework's caching allocator):
+     * alloc(bytes, user) returns device memory or NULL; free(ptr, user). */
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *alloc_user;
+    const int32_t *overlap_steps; /* steps at which to histogram the overlap; */
+    int n_overlap_steps;          /* NULL/0 = only the last step             */
+    int fuse_gather;         /* 1 (default): the next sweep reads surviving rows
+                                through the copy map; 0: a separate gather
+                                kernel copies them first (same results)      */
+    int device;              /* HIP device ordinal; -1 = current device       */
+    int timing;              /* 1: record HIP events around the sweep and the
+                                resampling kernels of every step (see
+                                pamc_phase_times); 0 (default): no events   */
+} pamc_options;
+
+/* Fills *opt with the defaults described above. */
+void pamc_default_options(pamc_options *opt);
+
+typedef struct pamc_ctx pamc_ctx;
+
+/* Creates a run and initialises R random replicas at step 0 (Sec. II.B).
+ *   L          linear size, 2 <= L <= 32 (N = L^3);
+ *   couplings  int8 [3][N], +-1; couplings[d*N + s] joins site s and its
+ *              periodic neighbour s + e_d (d = 0, 1, 2 for x, y, z; site
+ *              s = x + L (y + L z));
+ *   R          nominal population, 1 <= R; capacity must stay below 2^31;
+ *   beta       double [n_temps], finite, >= 0, non-decreasing (beta_0 = 0
+ *              anchors ln Z at N ln 2);
+ *   sweeps     Metropolis sweeps per temperature, >= 1;
+ *   seed       Philox key;
+ *   opt        NULL for defaults.
+ * Errors: PAMC_ERR_INVALID, PAMC_ERR_NOMEM, PAMC_ERR_DEVICE. */
+int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps,
+                int sweeps, uint64_t seed, const pamc_options *opt, pamc_ctx **out);
+
+/* Runs up to n_steps temperature steps (n_steps < 0: to the end); a step k
+ * is the sweeps at beta_k, the measurements, and for k < n_temps - 1 the
+ * resampling to beta_{k+1}.  Returns PAMC_OK when the requested steps (or
+ * the run) finished.  PAMC_ERR_CAPACITY / PAMC_ERR_EXTINCT: the step whose
+ * resampling failed is not applied; the handle keeps the population of that
+ * step after its sweeps, and the failure is sticky.  Synchronises the
+ * stream before returning. */
+int pamc_anneal(pamc_ctx *ctx, int n_steps);
+
+/* Enqueues up to n_steps steps without waiting; the result is read by
+ * pamc_sync.  For timing and overlap with other host work. */
+int pamc_anneal_async(pamc_ctx *ctx, int n_steps);
+int pamc_sync(pamc_ctx *ctx);
+
+/* Per-step observables, measured after the sweeps at beta_k. */
+typedef struct pamc_step_obs {
+    double beta;
+    int64_t R;          /* population R_k                                  */
+    int64_t sum_E;      /* sum of energies (exact)                         */
+    int64_t sum_E2;     /* sum of squared energies (exact)                 */
+    int32_t E_min, E_max;
+    double mean_E;      /* sum_E / R_k                                     */
+    double e;           /* mean_E / N                                      */
+    double C_V;         /* beta^2 var(E) / N, var from the exact sums      */
+    double lnQ;         /* ln[(1/R_k) sum_i exp(-(beta_{k+1}-beta_k) E_i)]; NaN at the last step */
+    double lnZ;         /* N ln 2 + sum_{j<k} lnQ_j                       */
+    double betaF;       /* -lnZ                                           */
+    double f;           /* -lnZ / (beta N); NaN at beta = 0               */
+    double S_f;         /* family entropy, Eq. (2)                        */
+    double rho_s;       /* R_k / exp(S_f)                                 */
+    double q_abs, q2, q4, g_SG; /* overlap moments and Binder cumulant at
+                                   overlap steps, NaN elsewhere            */
+    int32_t measured;   /* 1 once step k has run                           */
+} pamc_step_obs;
+
+/* Copies the observables of steps 0 .. n-1 (n <= n_temps) into out[n]. */
+int pamc_observables(const pamc_ctx *ctx, pamc_step_obs *out, int n);
+
+/* Overlap histogram of step k: hist[Q + N] for Q = sum_s S^a_s S^b_s over
+ * the pairs (r, r + floor(R_k/2)), r < floor(R_k/2); int64 [2N+1].
+ * PAMC_ERR_STATE if k is not an overlap step or has not run. */
+int pamc_overlap_hist(const pamc_ctx *ctx, int step, int64_t *hist);
+
+/* Per-step normalisers: S_k = sum over the population of
+ * exp(-(beta_{k+1}-beta_k)(E_i - E_min)) as summed by the library, and the
+ * family term T_k = sum_i n_i ln n_i.  double [n] each; NULL to skip. */
+int pamc_step_sums(const pamc_ctx *ctx, double *S, double *T, int n);
+
+/* Population state.  spins: int8 [R_k][N] of +-1 in lexicographic site
+ * order; E: int32 [R_k]; family: uint32 [R_k] (index of the initial
+ * replica each row descends from, non-decreasing). */
+typedef struct pamc_state {
+    int step;        /* next step to run, 0 .. n_temps                    */
+    int64_t R;       /* R_k                                               */
+    double lnZ;      /* ln Z_k                                            */
+    int8_t *spins;
+    int32_t *E;
+    uint32_t *family;
+} pamc_state;
+
+/* Reads the current step and population size (no copies). */
+int pamc_get_shape(const pamc_ctx *ctx, int *step, int64_t *R);
+
+/* Copies the current population into the caller's buffers (sized by
+ * pamc_get_shape); any NULL array is skipped. */
+int pamc_get_state(pamc_ctx *ctx, pamc_state *st);
+
+/* Replaces the population (checkpoint resume, step-wise checks): step in
+ * [0, n_temps), 1 <= R <= capacity, spins +-1, family < R (nominal).
+ * Energies are recomputed from the spins; st->E is ignored. */
+int pamc_set_state(pamc_ctx *ctx, const pamc_state *st);
+
+/* Metropolis thresholds of every step: out[k][0..2] for dE = 4, 8, 12,
+ * accept_all[k] = 1 when beta_k = 0 (every move accepted). */
+int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all);
+
+/* Device time of the steps run since the previous call (options.timing =
+ * 1): sweep_ms sums the sweep kernels of every step (sweeps of all
+ * replicas, energies, histogram), other_ms the measurement and resampling
+ * kernels; n_steps counts the steps.  Measured with HIP events on the run's
+ * stream.  PAMC_ERR_STATE if timing is off. */
+int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *other_ms, int64_t *n_steps);
+
+/* Device footprint in bytes of a run with these parameters. */
+int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt);
+
+void pamc_destroy(pamc_ctx *ctx);
+
+const char *pamc_status_string(int status);
+const char *pamc_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: many independent instances of mixed L annealed together.   */
+/* Results equal those of separate pamc_create/pamc_anneal runs.            */
+/* ------------------------------------------------------------------------ */
+typedef struct pamc_instance {
+    int L;
+    const int8_t *couplings; /* [3][L^3] */
+    int64_t R;
+    const double *beta;      /* [n_temps] */
+    int n_temps;
+    int sweeps;
+    uint64_t seed;
+} pamc_instance;
+
+typedef struct pamc_batch pamc_batch;
+
+int pamc_batch_create(int n, const pamc_instance *inst, const pamc_options *opt, pamc_batch **out);
+int pamc_batch_anneal(pamc_batch *b);
+int pamc_batch_observables(const pamc_batch *b, int i, pamc_step_obs *out, int n);
+int pamc_batch_get_state(pamc_batch *b, int i, pamc_state *st);
+int pamc_batch_shape(const pamc_batch *b, int i, int *step, int64_t *R);
+void pamc_batch_destroy(pamc_batch *b);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop that admits instances while others run.          */
+/* ------------------------------------------------------------------------ */
+typedef struct pamc_server pamc_server;
+
+typedef struct pamc_server_options {
+    int max_active;      /* most instances on the device at once (0 = 256) */
+    int device;          /* -1 = current                                    */
+} pamc_server_options;
+
+typedef struct pamc_result {
+    int status;                /* PAMC_OK or the error of this request     */
+    int n_temps;
+    pamc_step_obs *obs;        /* caller buffer [n_temps], filled on success */
+    double submit_time_s;      /* host clock, seconds                      */
+    double admit_time_s;
+    double finish_time_s;
+} pamc_result;
+
+/* hbm_budget_bytes bounds the device memory of admitted requests. */
+int pamc_server_create(size_t hbm_budget_bytes, const pamc_server_options *opt, pamc_server **out);
+/* Thread-safe.  PAMC_ERR_REJECTED if the request alone exceeds the budget. */
+int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_id);
+/* PAMC_ERR_BUSY while the request is queued or running. */
+int pamc_server_poll(pamc_server *s, uint64_t req_id, pamc_result *out);
+int pamc_server_cancel(pamc_server *s, uint64_t req_id);
+/* Counters: completed, queued, active. */
+int pamc_server_stats(pamc_server *s, int64_t *completed, int64_t *queued, int64_t *active);
+void pamc_server_destroy(pamc_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAMC_H */

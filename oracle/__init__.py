@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.orc_observables.argtypes = [P, P, P]
         L.orc_thresholds.argtypes = [dbl, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_sweep_rows.argtypes = [P, i32, i64, P, P, P]
+        L.orc_measure_resample.argtypes = [P]
         L.enum_dos.argtypes = [i32, P, P]
         L.enum_energies.argtypes = [i32, P, P]
         L.enum_overlap.argtypes = [i32, P, dbl, P]
@@ -203,6 +205,21 @@ class Oracle:
                                  ctypes.c_double(lnZ))
         if st != OK:
             raise ValueError(f"oracle set_state failed: {st}")
+
+    def sweep_rows(self, step, rows, spins):
+        """N_S sweeps of step `step` applied to the given replicas, keyed by
+        their row indices; returns (spins after, energies)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        sp = np.array(spins, dtype=np.int8, order="C", copy=True)
+        E = np.zeros(len(rows), dtype=np.int32)
+        st = lib().orc_sweep_rows(self._h, int(step), len(rows), _ptr(rows), _ptr(sp), _ptr(E))
+        if st != OK:
+            raise ValueError(f"oracle sweep_rows failed: {st}")
+        return sp, E
+
+    def measure_resample(self) -> int:
+        """Measure and resample the current population without sweeping it."""
+        return lib().orc_measure_resample(self._h)
 
     def energies(self, spins):
         spins = np.ascontiguousarray(spins, dtype=np.int8)

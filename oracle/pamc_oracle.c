@@ -186,6 +186,9 @@ static int32_t energy(const orc_t *o, const int8_t *S)
  * INIT draw is set. */
 static void init_population(orc_t *o)
 {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t r = 0; r < o->R; ++r) {
         int8_t *S = o->spin + r * o->N;
         for (int s = 0; s < o->N; ++s) {
@@ -317,11 +320,13 @@ void orc_thresholds(double b, uint32_t T[3], int *accept_all)
 
 /* N_S Metropolis sweeps of one replica at step k (Sec. II.B; checkerboard
  * order of Sec. III.A): colours ascending; inside a colour sites share no
- * bond, so visiting them lexicographically equals updating them at once. */
-static void sweep_replica(orc_t *o, int64_t r, const uint32_t T[3], int accept_all)
+ * bond, so visiting them lexicographically equals updating them at once.
+ * S is the replica's configuration, *E its energy, r its row index (which
+ * keys the draws together with k). */
+static void sweep_one(const orc_t *o, int8_t *S, int32_t *Ep, int64_t r, int k, const uint32_t T[3],
+                      int accept_all)
 {
-    int8_t *S = o->spin + r * o->N;
-    int32_t E = o->E[r];
+    int32_t E = *Ep;
     for (int t = 0; t < o->NS; ++t)
         for (int c = 0; c < o->ncol; ++c)
             for (int s = 0; s < o->N; ++s) {
@@ -333,14 +338,19 @@ static void sweep_replica(orc_t *o, int64_t r, const uint32_t T[3], int accept_a
                 int dE = 2 * S[s] * h;
                 int i = o->crank[s];
                 uint32_t u = draw(o->seed, ((uint32_t)c << 24) | (uint32_t)(i >> 2), (uint32_t)r,
-                                  (uint32_t)o->k, TAG_SWEEP | (uint32_t)t, i & 3);
+                                  (uint32_t)k, TAG_SWEEP | (uint32_t)t, i & 3);
                 int accept = accept_all || dE <= 0 || u < T[dE / 4 - 1];
                 if (accept) {
                     S[s] = (int8_t)-S[s];
                     E += dE;
                 }
             }
-    o->E[r] = E;
+    *Ep = E;
+}
+
+static void sweep_replica(orc_t *o, int64_t r, const uint32_t T[3], int accept_all)
+{
+    sweep_one(o, o->spin + r * o->N, &o->E[r], r, o->k, T, accept_all);
 }
 
 /* Pairwise summation tree over n leaves (n a power of two): level by level,
@@ -578,6 +588,9 @@ int orc_set_state(orc_t *o, int k, int64_t Rk, const int8_t *spins, const uint32
         if (fam[r] >= (uint64_t)o->R) return ORC_ERR_INVALID;
     memcpy(o->spin, spins, (size_t)Rk * o->N);
     memcpy(o->fam, fam, sizeof(uint32_t) * (size_t)Rk);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(o->nthreads)
+#endif
     for (int64_t r = 0; r < Rk; ++r) o->E[r] = energy(o, o->spin + r * o->N);
     o->Rk = Rk;
     o->k = k;
@@ -671,5 +684,43 @@ int orc_observables(const orc_t *o, double *out, double *ovl_out)
             }
         }
     }
+    return ORC_OK;
+}
+
+/* Sweeps of selected replicas at step k, for checks that sample a large
+ * population: rows[i] is the replica's row index (it keys the draws) and
+ * spins[i][N] (int8 +-1) is overwritten by its configuration after the N_S
+ * sweeps of step k; E[i] receives its energy.  The handle's population is
+ * untouched. */
+int orc_sweep_rows(orc_t *o, int k, int64_t n, const int64_t *rows, int8_t *spins, int32_t *E)
+{
+    if (k < 0 || k >= o->nT || n < 0) return ORC_ERR_INVALID;
+    uint32_t T[3];
+    int all;
+    orc_thresholds(o->beta[k], T, &all);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(o->nthreads)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int8_t *S = spins + i * o->N;
+        E[i] = energy(o, S);
+        sweep_one(o, S, &E[i], rows[i], k, T, all);
+    }
+    return ORC_OK;
+}
+
+/* Measurement and resampling of the current population at the current step
+ * without sweeping it first (the population is taken as the post-sweep
+ * state of that step), then advance to the next step. */
+int orc_measure_resample(orc_t *o)
+{
+    if (o->k >= o->nT) return ORC_ERR_STATE;
+    int st = measure(o);
+    if (st != ORC_OK) return st;
+    if (o->k < o->nT - 1) {
+        st = resample(o);
+        if (st != ORC_OK) return st;
+    }
+    o->k += 1;
     return ORC_OK;
 }

@@ -1,0 +1,355 @@
+"""Population annealing Monte Carlo for 3D +-J Edwards-Anderson spin glasses
+on AMD Instinct MI355X (gfx950).
+
+Python binding of the C ABI in ``include/pamc.h``: it marshals arguments and
+results; every step of the method runs in the HIP kernels of ``libpamc.so``.
+PyTorch, when present, supplies the HIP stream and (optionally) the caching
+allocator for device memory.  There is no CPU fallback: if the library is
+missing, construction raises.
+
+The method is that of Barzegar, Pattison, Wang and Katzgraber,
+arXiv:1710.09025: Sec. II.B (population annealing with N_S Metropolis sweeps
+per temperature and resampling proportional to exp[-(beta'-beta) E_i]),
+Sec. III.A (checkerboard spin selection), Eq. (2) (family entropy), Sec. V.A
+(observables, overlap histograms).
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+
+import numpy as np
+
+from . import _capi
+
+__all__ = ["Pamc", "PamcBatch", "PamcServer", "PamcError", "OBS_FIELDS", "default_capacity"]
+
+OBS_FIELDS = ("beta", "R", "sum_E", "sum_E2", "E_min", "E_max", "mean_E", "e", "C_V", "lnQ", "lnZ",
+              "betaF", "f", "S_f", "rho_s", "q_abs", "q2", "q4", "g_SG", "measured")
+
+
+class PamcError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        lib = _capi.load()
+        msg = lib.pamc_last_error().decode(errors="replace")
+        name = lib.pamc_status_string(status).decode()
+        super().__init__(f"{what}: {name} ({status}): {msg}")
+        self.status = status
+
+
+def _check(status: int, what: str):
+    if status != _capi.OK:
+        raise PamcError(status, what)
+
+
+def default_capacity(R: int) -> int:
+    return int(R + int(np.ceil(8.0 * np.sqrt(R))) + 64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _obs_to_dict(arr) -> dict:
+    out = {}
+    for name in OBS_FIELDS:
+        out[name] = np.array([getattr(o, name) for o in arr])
+    return out
+
+
+class _TorchGlue:
+    """Stream and caching-allocator callbacks from PyTorch (plumbing only)."""
+
+    def __init__(self, use_allocator: bool):
+        import torch  # noqa: F401
+
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        # a stream of our own at the default priority; its handle is non-null
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._alloc = None
+        self._free = None
+        if use_allocator:
+            def _a(nbytes, _user):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+                except Exception:
+                    return None
+
+            def _f(ptr, _user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._alloc = _capi.ALLOC_FN(_a)
+            self._free = _capi.FREE_FN(_f)
+
+    def fill(self, opt: _capi.Options):
+        opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        opt.device = self.device
+        if self._alloc is not None:
+            opt.alloc = self._alloc
+            opt.free = self._free
+
+
+def _torch_available() -> bool:
+    try:
+        import torch
+
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
+                  torch_stream=True, torch_allocator=False, keep=None, timing=False):
+    lib = _capi.load()
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    opt.spin_format = int(spin_format)
+    if capacity is not None:
+        opt.capacity = int(capacity)
+    opt.fuse_gather = 1 if fuse_gather else 0
+    opt.timing = 1 if timing else 0
+    if overlap_steps is not None:
+        ov = np.ascontiguousarray(overlap_steps, dtype=np.int32)
+        keep.append(ov)
+        opt.overlap_steps = ov.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        opt.n_overlap_steps = len(ov)
+    if torch_stream and _torch_available():
+        glue = _TorchGlue(torch_allocator)
+        glue.fill(opt)
+        keep.append(glue)
+    return opt
+
+
+class Pamc:
+    """One population-annealing run on the GPU (``pamc_create``)."""
+
+    def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
+                 fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False):
+        lib = _capi.load()
+        self.L = int(L)
+        self.N = self.L ** 3
+        self.R = int(R)
+        self.beta = np.ascontiguousarray(beta, dtype=np.float64)
+        self.nT = len(self.beta)
+        self._keep = []
+        J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
+        opt = _make_options(capacity, overlap_steps, fuse_gather, torch_stream=torch_stream,
+                            torch_allocator=torch_allocator, keep=self._keep, timing=timing)
+        self._opt = opt
+        h = ctypes.c_void_p()
+        _check(lib.pamc_create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),
+                               ctypes.c_uint64(int(seed) & (2**64 - 1)), ctypes.byref(opt),
+                               ctypes.byref(h)), "pamc_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _capi.load().pamc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def anneal(self, n_steps: int = -1) -> int:
+        """Runs up to n_steps steps; returns the status (raises on device errors)."""
+        st = _capi.load().pamc_anneal(self._h, int(n_steps))
+        if st not in (_capi.OK, _capi.ERR_CAPACITY, _capi.ERR_EXTINCT):
+            raise PamcError(st, "pamc_anneal")
+        return st
+
+    def anneal_async(self, n_steps: int = -1):
+        _check(_capi.load().pamc_anneal_async(self._h, int(n_steps)), "pamc_anneal_async")
+
+    def sync(self) -> int:
+        return _capi.load().pamc_sync(self._h)
+
+    def observables(self) -> dict:
+        arr = (_capi.StepObs * self.nT)()
+        _check(_capi.load().pamc_observables(self._h, arr, self.nT), "pamc_observables")
+        return _obs_to_dict(arr)
+
+    def overlap_hist(self, step: int) -> np.ndarray:
+        h = np.zeros(2 * self.N + 1, dtype=np.int64)
+        _check(_capi.load().pamc_overlap_hist(self._h, int(step), _ptr(h)), "pamc_overlap_hist")
+        return h
+
+    def step_sums(self):
+        S = np.zeros(self.nT)
+        T = np.zeros(self.nT)
+        _check(_capi.load().pamc_step_sums(self._h, _ptr(S), _ptr(T), self.nT), "pamc_step_sums")
+        return S, T
+
+    def shape(self):
+        k = ctypes.c_int()
+        R = ctypes.c_int64()
+        _check(_capi.load().pamc_get_shape(self._h, ctypes.byref(k), ctypes.byref(R)), "pamc_get_shape")
+        return k.value, R.value
+
+    def get_state(self) -> dict:
+        k, Rk = self.shape()
+        spins = np.zeros((Rk, self.N), dtype=np.int8)
+        E = np.zeros(Rk, dtype=np.int32)
+        fam = np.zeros(Rk, dtype=np.uint32)
+        st = _capi.State(0, 0, 0.0, _ptr(spins).value, _ptr(E).value, _ptr(fam).value)
+        _check(_capi.load().pamc_get_state(self._h, ctypes.byref(st)), "pamc_get_state")
+        return {"step": st.step, "R": st.R, "lnZ": st.lnZ, "spins": spins[: st.R], "E": E[: st.R],
+                "family": fam[: st.R]}
+
+    def set_state(self, step, spins, family, lnZ):
+        spins = np.ascontiguousarray(spins, dtype=np.int8)
+        family = np.ascontiguousarray(family, dtype=np.uint32)
+        st = _capi.State(int(step), spins.shape[0], float(lnZ), _ptr(spins).value, None, _ptr(family).value)
+        _check(_capi.load().pamc_set_state(self._h, ctypes.byref(st)), "pamc_set_state")
+
+    def phase_times(self):
+        """(sweep ms, resampling ms, steps) since the last call (timing=True)."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(_capi.load().pamc_phase_times(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+               "pamc_phase_times")
+        return a.value, b.value, n.value
+
+    @property
+    def stream_handle(self) -> int:
+        return int(self._opt.stream or 0)
+
+    def thresholds(self):
+        T = np.zeros((self.nT, 3), dtype=np.uint32)
+        acc = np.zeros(self.nT, dtype=np.uint8)
+        _check(_capi.load().pamc_thresholds(self._h, _ptr(T), _ptr(acc)), "pamc_thresholds")
+        return T, acc
+
+
+class PamcBatch:
+    """Many independent instances annealed together (``pamc_batch_*``)."""
+
+    def __init__(self, instances, fuse_gather=True, torch_stream=True):
+        lib = _capi.load()
+        self._keep = []
+        n = len(instances)
+        arr = (_capi.Instance * n)()
+        self.nT = []
+        self.N = []
+        for i, d in enumerate(instances):
+            L = int(d["L"])
+            J = np.ascontiguousarray(d["couplings"], dtype=np.int8).reshape(3, L ** 3)
+            b = np.ascontiguousarray(d["beta"], dtype=np.float64)
+            self._keep += [J, b]
+            arr[i] = _capi.Instance(L, _ptr(J).value, int(d["R"]), _ptr(b).value, len(b), int(d["sweeps"]),
+                                    int(d["seed"]) & (2**64 - 1))
+            self.nT.append(len(b))
+            self.N.append(L ** 3)
+        opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep)
+        h = ctypes.c_void_p()
+        _check(lib.pamc_batch_create(n, arr, ctypes.byref(opt), ctypes.byref(h)), "pamc_batch_create")
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _capi.load().pamc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def anneal(self) -> int:
+        st = _capi.load().pamc_batch_anneal(self._h)
+        if st not in (_capi.OK, _capi.ERR_CAPACITY, _capi.ERR_EXTINCT):
+            raise PamcError(st, "pamc_batch_anneal")
+        return st
+
+    def observables(self, i: int) -> dict:
+        arr = (_capi.StepObs * self.nT[i])()
+        _check(_capi.load().pamc_batch_observables(self._h, int(i), arr, self.nT[i]), "pamc_batch_observables")
+        return _obs_to_dict(arr)
+
+    def get_state(self, i: int) -> dict:
+        k = ctypes.c_int()
+        R = ctypes.c_int64()
+        _check(_capi.load().pamc_batch_shape(self._h, int(i), ctypes.byref(k), ctypes.byref(R)), "shape")
+        N = self.N[i]
+        spins = np.zeros((R.value, N), dtype=np.int8)
+        E = np.zeros(R.value, dtype=np.int32)
+        fam = np.zeros(R.value, dtype=np.uint32)
+        st = _capi.State(0, 0, 0.0, _ptr(spins).value, _ptr(E).value, _ptr(fam).value)
+        _check(_capi.load().pamc_batch_get_state(self._h, int(i), ctypes.byref(st)), "pamc_batch_get_state")
+        return {"step": st.step, "R": st.R, "lnZ": st.lnZ, "spins": spins, "E": E, "family": fam}
+
+
+class PamcServer:
+    """Request loop with continuous batching under an HBM budget."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 256):
+        lib = _capi.load()
+        opt = _capi.ServerOptions(int(max_active), -1)
+        h = ctypes.c_void_p()
+        _check(lib.pamc_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
+                                      ctypes.byref(h)), "pamc_server_create")
+        self._h = h
+        self._keep = {}
+        self._nT = {}
+
+    def submit(self, L, couplings, R, beta, sweeps, seed) -> int:
+        L = int(L)
+        J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, L ** 3)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        inst = _capi.Instance(L, _ptr(J).value, int(R), _ptr(b).value, len(b), int(sweeps),
+                              int(seed) & (2**64 - 1))
+        rid = ctypes.c_uint64()
+        _check(_capi.load().pamc_server_submit(self._h, ctypes.byref(inst), ctypes.byref(rid)), "submit")
+        self._nT[rid.value] = len(b)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while running; else (status, observables dict, times)."""
+        nT = self._nT[rid]
+        arr = (_capi.StepObs * nT)()
+        res = _capi.Result(0, nT, ctypes.cast(arr, ctypes.POINTER(_capi.StepObs)), 0.0, 0.0, 0.0)
+        st = _capi.load().pamc_server_poll(self._h, ctypes.c_uint64(rid), ctypes.byref(res))
+        if st == _capi.ERR_BUSY:
+            return None
+        _check(st, "poll")
+        times = {"submit": res.submit_time_s, "admit": res.admit_time_s, "finish": res.finish_time_s}
+        return res.status, _obs_to_dict(arr), times
+
+    def wait(self, rid: int, timeout: float = 600.0, interval: float = 0.002):
+        t0 = time.time()
+        while True:
+            r = self.poll(rid)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"request {rid} not finished")
+            time.sleep(interval)
+
+    def cancel(self, rid: int) -> int:
+        return _capi.load().pamc_server_cancel(self._h, ctypes.c_uint64(rid))
+
+    def stats(self):
+        c, q, a = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        st = _capi.load().pamc_server_stats(self._h, ctypes.byref(c), ctypes.byref(q), ctypes.byref(a))
+        return {"status": st, "completed": c.value, "queued": q.value, "active": a.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _capi.load().pamc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

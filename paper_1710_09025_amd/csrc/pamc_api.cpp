@@ -1,0 +1,345 @@
+// pamc_api.cpp -- the extern "C" boundary declared in include/pamc.h.
+// Argument validation, handle bookkeeping and status codes; the work is
+// done by pamc::Runner and the gfx950 kernels.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "runner.h"
+
+namespace pamc {
+const char *last_error_cstr();
+}
+
+using pamc::HostInst;
+using pamc::Runner;
+
+struct pamc_ctx {
+    Runner run;
+};
+
+struct pamc_batch {
+    Runner run;
+    int n = 0;
+};
+
+namespace pamc {
+int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
+              const pamc_options &opt, HostInst &h);
+}
+
+namespace {
+
+int invalid(const std::string &m)
+{
+    pamc::set_error(m);
+    return PAMC_ERR_INVALID;
+}
+
+}  // namespace
+
+// Validates one instance and fills the host description.
+int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
+              const pamc_options &opt, HostInst &h)
+{
+    if (L < 2 || L > 32) return invalid("L must be in [2, 32]");
+    if (!J) return invalid("couplings is NULL");
+    if (!beta) return invalid("beta is NULL");
+    if (R < 1) return invalid("R must be >= 1");
+    if (nT < 1) return invalid("n_temps must be >= 1");
+    if (NS < 1) return invalid("sweeps must be >= 1");
+    const int N = L * L * L;
+    for (int i = 0; i < 3 * N; ++i)
+        if (J[i] != 1 && J[i] != -1) return invalid("couplings must be +1 or -1");
+    for (int k = 0; k < nT; ++k) {
+        if (!std::isfinite(beta[k]) || beta[k] < 0.0) return invalid("beta must be finite and >= 0");
+        if (k > 0 && beta[k] < beta[k - 1]) return invalid("beta must be non-decreasing");
+    }
+    const int64_t cap = opt.capacity > 0 ? opt.capacity : pamc::default_capacity(R);
+    if (cap < R) return invalid("capacity must be >= R");
+    if (cap >= ((int64_t)1 << 31) - 1024) return invalid("capacity must stay below 2^31");
+    if (opt.spin_format != PAMC_SPINS_INT8 && opt.spin_format != PAMC_SPINS_PACKED)
+        return invalid("unknown spin format");
+    h.L = L;
+    h.N = N;
+    h.ncol = (L & 1) ? 3 : 2;
+    h.layout = pamc::choose_layout(L);
+    h.variant = h.layout == pamc::kLayoutLex ? pamc::kSweepLex : (L == 8 ? pamc::kSweepEO8 : pamc::kSweepEO16);
+    h.row_bytes = (N + 15) & ~15;
+    h.R = R;
+    h.Rcap = cap;
+    h.nT = nT;
+    h.NS = NS;
+    h.seed = seed;
+    h.beta.assign(beta, beta + nT);
+    h.J.assign(J, J + 3 * N);
+    h.ovl_slot.assign(nT, -1);
+    h.ovl_n = 0;
+    if (opt.overlap_steps && opt.n_overlap_steps > 0) {
+        for (int j = 0; j < opt.n_overlap_steps; ++j) {
+            const int k = opt.overlap_steps[j];
+            if (k < 0 || k >= nT) return invalid("overlap step out of range");
+            if (h.ovl_slot[k] < 0) h.ovl_slot[k] = h.ovl_n++;
+        }
+    } else {
+        h.ovl_slot[nT - 1] = h.ovl_n++;
+    }
+    if (h.variant == pamc::kSweepLex) {
+        int ncs[3] = {0, 0, 0};
+        for (int z = 0; z < L; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    int c;
+                    if ((L & 1) == 0)
+                        c = (x + y + z) & 1;
+                    else {
+                        auto g = [L](int v) { return v == L - 1 ? 2 : (v & 1); };
+                        c = (g(x) + g(y) + g(z)) % 3;
+                    }
+                    ncs[c]++;
+                }
+        int gmax = 1;
+        for (int c = 0; c < 3; ++c) gmax = std::max(gmax, (ncs[c] + 3) / 4);
+        int tr = (512 + gmax - 1) / gmax;
+        tr = std::min(tr, std::max(1, 16384 / h.row_bytes));
+        h.tile_rows = std::max(1, tr);
+    } else {
+        h.tile_rows = L == 8 ? 16 : 4;
+    }
+    return PAMC_OK;
+}
+
+namespace {
+
+pamc_options resolve(const pamc_options *opt)
+{
+    pamc_options o;
+    pamc_default_options(&o);
+    if (opt) o = *opt;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pamc_default_options(pamc_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->spin_format = PAMC_SPINS_INT8;
+    opt->fuse_gather = 1;
+    opt->device = -1;
+}
+
+const char *pamc_status_string(int s)
+{
+    switch (s) {
+    case PAMC_OK: return "ok";
+    case PAMC_ERR_INVALID: return "invalid argument";
+    case PAMC_ERR_NOMEM: return "out of memory";
+    case PAMC_ERR_CAPACITY: return "population capacity exceeded";
+    case PAMC_ERR_EXTINCT: return "population extinct";
+    case PAMC_ERR_DEVICE: return "device error";
+    case PAMC_ERR_STATE: return "invalid state for this call";
+    case PAMC_ERR_BUSY: return "busy";
+    case PAMC_ERR_REJECTED: return "rejected";
+    default: return "unknown status";
+    }
+}
+
+const char *pamc_last_error(void) { return pamc::last_error_cstr(); }
+
+int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt)
+{
+    if (L < 2 || L > 32 || R < 1 || n_temps < 1) return -1;
+    const pamc_options o = resolve(opt);
+    const int64_t cap = o.capacity > 0 ? o.capacity : pamc::default_capacity(R);
+    const int nov = (o.overlap_steps && o.n_overlap_steps > 0) ? o.n_overlap_steps : 1;
+    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov);
+}
+
+int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps, int sweeps,
+                uint64_t seed, const pamc_options *opt, pamc_ctx **out)
+{
+    if (!out) return invalid("out is NULL");
+    *out = nullptr;
+    const pamc_options o = resolve(opt);
+    std::vector<HostInst> v(1);
+    int st = pamc::make_inst(L, couplings, R, beta, n_temps, sweeps, seed, o, v[0]);
+    if (st != PAMC_OK) return st;
+    std::unique_ptr<pamc_ctx> c(new (std::nothrow) pamc_ctx());
+    if (!c) return PAMC_ERR_NOMEM;
+    st = c->run.setup(o, 1);
+    if (st != PAMC_OK) return st;
+    const int slot = c->run.add_instance(std::move(v[0]));
+    if (slot < 0) return slot;
+    st = c->run.init_instances({slot});
+    if (st != PAMC_OK) return st;
+    st = c->run.build_work({slot});
+    if (st != PAMC_OK) return st;
+    *out = c.release();
+    return PAMC_OK;
+}
+
+int pamc_anneal_async(pamc_ctx *ctx, int n_steps)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    if (ctx->run.poisoned()) return PAMC_ERR_DEVICE;
+    const int n = n_steps < 0 ? ctx->run.inst(0).nT : n_steps;
+    return ctx->run.enqueue_steps(n);
+}
+
+int pamc_sync(pamc_ctx *ctx)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    int st = ctx->run.sync();
+    if (st != PAMC_OK) return st;
+    return ctx->run.inst_status(0, nullptr, nullptr);
+}
+
+int pamc_anneal(pamc_ctx *ctx, int n_steps)
+{
+    int st = pamc_anneal_async(ctx, n_steps);
+    if (st != PAMC_OK) return st;
+    return pamc_sync(ctx);
+}
+
+int pamc_observables(const pamc_ctx *ctx, pamc_step_obs *out, int n)
+{
+    if (!ctx || !out) return invalid("NULL argument");
+    return const_cast<pamc_ctx *>(ctx)->run.observables(0, out, n);
+}
+
+int pamc_overlap_hist(const pamc_ctx *ctx, int step, int64_t *hist)
+{
+    if (!ctx || !hist) return invalid("NULL argument");
+    return const_cast<pamc_ctx *>(ctx)->run.overlap_hist(0, step, hist);
+}
+
+int pamc_step_sums(const pamc_ctx *ctx, double *S, double *T, int n)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    return const_cast<pamc_ctx *>(ctx)->run.step_sums(0, S, T, n);
+}
+
+int pamc_get_shape(const pamc_ctx *ctx, int *step, int64_t *R)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    Runner &r = const_cast<pamc_ctx *>(ctx)->run;
+    int st = r.sync();
+    if (st != PAMC_OK) return st;
+    st = r.inst_status(0, step, R);
+    // after a failed resampling the population is that of the failing step
+    if (st == PAMC_ERR_CAPACITY || st == PAMC_ERR_EXTINCT) return PAMC_OK;
+    return st;
+}
+
+int pamc_get_state(pamc_ctx *ctx, pamc_state *st)
+{
+    if (!ctx || !st) return invalid("NULL argument");
+    return ctx->run.get_state(0, st);
+}
+
+int pamc_set_state(pamc_ctx *ctx, const pamc_state *st)
+{
+    if (!ctx || !st) return invalid("NULL argument");
+    return ctx->run.set_state(0, st);
+}
+
+int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    return const_cast<pamc_ctx *>(ctx)->run.thresholds(0, out, accept_all);
+}
+
+int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *other_ms, int64_t *n_steps)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    return ctx->run.phase_times(sweep_ms, other_ms, n_steps);
+}
+
+void pamc_destroy(pamc_ctx *ctx) { delete ctx; }
+
+// ---------------------------------------------------------------------------
+int pamc_batch_create(int n, const pamc_instance *inst, const pamc_options *opt, pamc_batch **out)
+{
+    if (!out) return invalid("out is NULL");
+    *out = nullptr;
+    if (n < 1 || !inst) return invalid("need at least one instance");
+    const pamc_options o = resolve(opt);
+    std::vector<HostInst> v((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const pamc_instance &p = inst[i];
+        int st = pamc::make_inst(p.L, p.couplings, p.R, p.beta, p.n_temps, p.sweeps, p.seed, o, v[(size_t)i]);
+        if (st != PAMC_OK) {
+            pamc::set_error("instance " + std::to_string(i) + ": " + pamc_last_error());
+            return st;
+        }
+    }
+    std::unique_ptr<pamc_batch> b(new (std::nothrow) pamc_batch());
+    if (!b) return PAMC_ERR_NOMEM;
+    int st = b->run.setup(o, n);
+    if (st != PAMC_OK) return st;
+    std::vector<int> slots;
+    for (int i = 0; i < n; ++i) {
+        const int slot = b->run.add_instance(std::move(v[(size_t)i]));
+        if (slot < 0) return slot;
+        slots.push_back(slot);
+    }
+    st = b->run.init_instances(slots);
+    if (st != PAMC_OK) return st;
+    st = b->run.build_work(slots);
+    if (st != PAMC_OK) return st;
+    b->n = n;
+    *out = b.release();
+    return PAMC_OK;
+}
+
+int pamc_batch_anneal(pamc_batch *b)
+{
+    if (!b) return invalid("batch is NULL");
+    int maxT = 0;
+    for (int i = 0; i < b->n; ++i) maxT = std::max(maxT, b->run.inst(i).nT);
+    int st = b->run.enqueue_steps(maxT);
+    if (st != PAMC_OK) return st;
+    st = b->run.sync();
+    if (st != PAMC_OK) return st;
+    int worst = PAMC_OK;
+    for (int i = 0; i < b->n; ++i) {
+        const int s = b->run.inst_status(i, nullptr, nullptr);
+        if (s != PAMC_OK) worst = s;
+    }
+    return worst;
+}
+
+int pamc_batch_observables(const pamc_batch *b, int i, pamc_step_obs *out, int n)
+{
+    if (!b || !out) return invalid("NULL argument");
+    if (i < 0 || i >= b->n) return invalid("instance index out of range");
+    return const_cast<pamc_batch *>(b)->run.observables(i, out, n);
+}
+
+int pamc_batch_get_state(pamc_batch *b, int i, pamc_state *st)
+{
+    if (!b || !st) return invalid("NULL argument");
+    if (i < 0 || i >= b->n) return invalid("instance index out of range");
+    return b->run.get_state(i, st);
+}
+
+int pamc_batch_shape(const pamc_batch *b, int i, int *step, int64_t *R)
+{
+    if (!b) return invalid("batch is NULL");
+    if (i < 0 || i >= b->n) return invalid("instance index out of range");
+    Runner &r = const_cast<pamc_batch *>(b)->run;
+    int st = r.inst_status(i, step, R);
+    if (st == PAMC_ERR_CAPACITY || st == PAMC_ERR_EXTINCT) return PAMC_OK;
+    return st;
+}
+
+void pamc_batch_destroy(pamc_batch *b) { delete b; }
+
+}  // extern "C"

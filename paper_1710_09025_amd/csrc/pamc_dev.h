@@ -1,0 +1,127 @@
+// pamc_dev.h -- data layout shared by the host orchestrator and the gfx950
+// kernels of the population annealing library.
+//
+// Every kernel is segmented by instance: it reads the instance descriptor
+// `Inst` from device memory, so one run, a batch of mixed-size instances and
+// the serving loop all use the same kernels.  The current temperature step
+// k of each instance lives on the device, so a step can be captured once in
+// a hipGraph and replayed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pamc {
+
+// Philox stream tags, the top four bits of counter word 3.
+constexpr uint32_t kTagInit = 0x10000000u;
+constexpr uint32_t kTagSweep = 0x20000000u;
+constexpr uint32_t kTagResample = 0x30000000u;
+
+// Spin storage layouts inside one replica row.
+enum Layout : int32_t {
+    // byte per site (0: S = -1, 1: S = +1), lexicographic s = x + L(y + Lz)
+    kLayoutLex = 0,
+    // byte per site; each row (y, z) holds its even-x sites then its odd-x
+    // sites: pos = (zL + y)L + (x & 1)(L/2) + (x >> 1).  Used for L % 8 == 0
+    // so that four sites of one colour sharing a Philox block are one
+    // aligned 32-bit word, and so are their y, z and one x neighbour.
+    kLayoutEO = 1,
+};
+
+constexpr int kRowsPerBlock = 1024;  // rows handled per block by row kernels
+
+// Per-step integer record written on the device.
+struct StepRec {
+    int64_t R;      // R_k
+    int64_t sumE;   // sum of E
+    int64_t sumE2;  // sum of E^2
+    int32_t Emin, Emax;
+    double S;       // resampling normaliser (NaN at the last step)
+    double T;       // family term sum n ln n
+};
+
+struct Inst {
+    // problem
+    int32_t L, N, ncol, layout;
+    int32_t row_bytes;  // bytes per replica row in the spin buffers (>= N, multiple of 16)
+    int32_t nT, NS;
+    uint32_t key0, key1;
+    int32_t R;          // nominal population
+    int32_t Rcap;       // rows per buffer
+    int32_t nblk;       // ceil(Rcap / kRowsPerBlock)
+    int32_t nlev;       // 3N + 1 energy levels
+    int32_t fam_pow2;   // smallest power of two >= R (family tree leaves)
+    int32_t ovl_n;      // number of overlap steps
+    // double-buffered population
+    uint8_t *spins[2];
+    int32_t *E[2];
+    uint32_t *fam[2];
+    // resampling scratch
+    uint32_t *map;      // [Rcap] destination row -> source row
+    uint32_t *ncopy;    // [Rcap]
+    uint32_t *loff;     // [Rcap] offset inside the row block
+    uint32_t *bsum;     // [nblk]
+    uint32_t *boff;     // [nblk]
+    uint32_t *hist;     // [nlev] energy histogram, (E + 3N)/2
+    uint2 *BF;          // [nlev] (floor(tau), frac(tau) 2^32) per level above E_min
+    uint32_t *cnt;      // [R] descendants per family
+    double *fpart;      // [max(1, fam_pow2 / 2048)] family tree partial sums
+    // tables
+    const uint4 *thr;   // [nT] (T(dE=4), T(8), T(12), accept_all)
+    const double *beta; // [nT]
+    const double *rho;  // [nT] exp(-2 (beta_{k+1} - beta_k)), host libm
+    const double *nlnn; // [>= Rcap + 1] n ln n, host libm (shared)
+    const uint4 *site;  // lex layout: [N] {nb+x|nb-x<<16, nb+y|nb-y<<16, nb+z|nb-z<<16, jmask}
+    const uint16_t *grp;// lex layout: [ncol][gmax][4] sites of each Philox block (0xFFFF: none)
+    const uint32_t *jeo;// EO layout: [2][N/8][6] coupling words per block
+    int32_t ncs[3];     // sites per colour
+    int32_t gcs[3];     // Philox blocks per colour, ceil(ncs / 4)
+    int32_t gmax;
+    // progress and records
+    int32_t *k;         // current step (device scalar)
+    int32_t *cur;       // buffer holding the current population (0/1)
+    int32_t *mapped;    // 1: rows of the current step still live in buffer
+                        //    cur through `map` (gather pending)
+    uint32_t *Rk;       // [nT + 1]
+    StepRec *rec;       // [nT]
+    int32_t *ovl_slot;  // [nT] slot in qhist or -1
+    uint32_t *qhist;    // [ovl_n][2N + 1]
+    uint32_t *status;   // bit 0 capacity, bit 1 extinct; word 1: failing step
+};
+
+// Work item of the row-parallel kernels and of the sweep: instance index and
+// first row.
+struct Work {
+    uint32_t inst;
+    uint32_t row0;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
+// counter words 0 and 2 by the round multipliers, the high halves mixed with
+// words 1 and 3 and the round key; the key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        uint4 n;
+        n.x = (uint32_t)(b >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)b;
+        n.z = (uint32_t)(a >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)a;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t word_of(uint4 v, int i)
+{
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+}  // namespace pamc

@@ -1,0 +1,854 @@
+// runner.cpp -- host orchestration: validation results are assumed, this
+// file builds the host tables (thresholds, weights' rho, n ln n), lays out
+// each instance's device memory, builds the work lists of the segmented
+// kernels and enqueues the per-step launch sequence.
+#include "runner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace pamc {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+void *Allocator::get(size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (alloc) return alloc(bytes, user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void Allocator::put(void *p)
+{
+    if (!p) return;
+    if (free)
+        free(p, user);
+    else
+        (void)hipFree(p);
+}
+
+int64_t default_capacity(int64_t R) { return R + (int64_t)std::ceil(8.0 * std::sqrt((double)R)) + 64; }
+
+int choose_layout(int L) { return (L == 8 || L == 16) ? kLayoutEO : kLayoutLex; }
+
+// Colour of site (x, y, z): checkerboard for even L; for odd L the proper
+// three-colouring (g(x) + g(y) + g(z)) mod 3 with g(v) = v mod 2 below L-1
+// and g(L-1) = 2.
+static int colour_of(int L, int x, int y, int z)
+{
+    if ((L & 1) == 0) return (x + y + z) & 1;
+    auto g = [L](int v) { return v == L - 1 ? 2 : (v & 1); };
+    return (g(x) + g(y) + g(z)) % 3;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+namespace {
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    }
+};
+
+struct InstLayout {
+    size_t ctl, status, spins0, spins1, E0, E1, f0, f1, map, ncopy, loff, bsum, boff, hist, BF, cnt, fpart, thr,
+        beta, rho, site, grp, jeo, J, Rk, rec, ovl_slot, qhist, total;
+};
+
+InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
+{
+    const int N = L * L * L;
+    const int row_bytes = (N + 15) & ~15;
+    const int ncol = (L & 1) ? 3 : 2;
+    const int nblk = (int)((Rcap + kRowsPerBlock - 1) / kRowsPerBlock);
+    const int nlev = 3 * N + 1;
+    int64_t fp2 = 1;
+    while (fp2 < R) fp2 <<= 1;
+    int ncs[3] = {0, 0, 0};
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) ncs[colour_of(L, x, y, z)]++;
+    const int gmax = std::max((ncs[0] + 3) / 4, std::max((ncs[1] + 3) / 4, (ncs[2] + 3) / 4));
+    Carve c;
+    InstLayout l{};
+    l.ctl = c.take(16);
+    l.status = c.take(8);
+    l.spins0 = c.take((size_t)Rcap * row_bytes);
+    l.spins1 = c.take((size_t)Rcap * row_bytes);
+    l.E0 = c.take((size_t)Rcap * 4);
+    l.E1 = c.take((size_t)Rcap * 4);
+    l.f0 = c.take((size_t)Rcap * 4);
+    l.f1 = c.take((size_t)Rcap * 4);
+    l.map = c.take((size_t)Rcap * 4);
+    l.ncopy = c.take((size_t)Rcap * 4);
+    l.loff = c.take((size_t)Rcap * 4);
+    l.bsum = c.take((size_t)nblk * 4);
+    l.boff = c.take((size_t)nblk * 4);
+    l.hist = c.take((size_t)nlev * 4);
+    l.BF = c.take((size_t)nlev * 8);
+    l.cnt = c.take((size_t)R * 4);
+    l.fpart = c.take((size_t)std::max<int64_t>(1, fp2 / 2048) * 8);
+    l.thr = c.take((size_t)nT * 16);
+    l.beta = c.take((size_t)nT * 8);
+    l.rho = c.take((size_t)nT * 8);
+    l.site = c.take((size_t)N * 16);
+    l.grp = c.take((size_t)ncol * gmax * 4 * 2);
+    l.jeo = c.take((size_t)2 * (N / 8 + 1) * 6 * 4);
+    l.J = c.take((size_t)3 * N);
+    l.Rk = c.take((size_t)(nT + 1) * 4);
+    l.rec = c.take((size_t)nT * sizeof(StepRec));
+    l.ovl_slot = c.take((size_t)nT * 4);
+    l.qhist = c.take((size_t)std::max(1, n_ovl) * (2 * N + 1) * 4);
+    l.total = c.off;
+    return l;
+}
+}  // namespace
+
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl)
+{
+    // R <= Rcap; use Rcap for the family counters as an upper bound
+    return layout_of(L, Rcap, Rcap, nT, n_ovl).total;
+}
+
+Runner::~Runner()
+{
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (size_t i = 0; i < inst_.size(); ++i)
+        if (used_[i]) alloc_.put(inst_[i].block);
+    for (void *p : work_allocs_) alloc_.put(p);
+    for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
+    alloc_.put(d_insts_);
+    alloc_.put(d_nlnn_);
+    alloc_.put(d_Jptr_);
+    if (own_stream_ && stream_) (void)hipStreamDestroy(stream_);
+}
+
+int Runner::dev_fail(hipError_t e, const char *what)
+{
+    poisoned_ = true;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return PAMC_ERR_DEVICE;
+}
+
+#define HIPCHK(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return dev_fail(e_, what);     \
+    } while (0)
+
+int Runner::setup(const pamc_options &opt, int max_slots)
+{
+    alloc_.alloc = opt.alloc;
+    alloc_.free = opt.free;
+    alloc_.user = opt.alloc_user;
+    fuse_ = opt.fuse_gather != 0;
+    timing_ = opt.timing != 0;
+    max_slots_ = max_slots;
+    if (opt.device >= 0) HIPCHK(hipSetDevice(opt.device), "hipSetDevice");
+    HIPCHK(hipGetDevice(&device_), "hipGetDevice");
+    if (opt.stream) {
+        stream_ = (hipStream_t)opt.stream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");
+        own_stream_ = true;
+    }
+    inst_.resize((size_t)max_slots);
+    used_.assign((size_t)max_slots, 0);
+    d_insts_ = (Inst *)alloc_.get(sizeof(Inst) * (size_t)max_slots);
+    d_Jptr_ = (const int8_t **)alloc_.get(sizeof(void *) * (size_t)max_slots);
+    if (!d_insts_ || !d_Jptr_) {
+        set_error("device allocation failed (instance table)");
+        return PAMC_ERR_NOMEM;
+    }
+    return PAMC_OK;
+}
+
+// n ln n for n = 0 .. len-1 (host libm), shared by all instances; grows when
+// an instance with a larger capacity arrives.
+int Runner::ensure_nlnn(int64_t len)
+{
+    if (len <= nlnn_len_) return PAMC_OK;
+    HIPCHK(hipStreamSynchronize(stream_), "nlnn sync");
+    const int64_t n = std::max(len, 2 * nlnn_len_);
+    std::vector<double> nl((size_t)n);
+    nl[0] = 0.0;
+    for (int64_t q = 1; q < n; ++q) nl[(size_t)q] = (double)q * std::log((double)q);
+    double *d = (double *)alloc_.get(nl.size() * 8);
+    if (!d) {
+        set_error("device allocation failed (n ln n table)");
+        return PAMC_ERR_NOMEM;
+    }
+    HIPCHK(hipMemcpy(d, nl.data(), nl.size() * 8, hipMemcpyHostToDevice), "upload nlnn");
+    for (size_t i = 0; i < inst_.size(); ++i) {
+        if (!used_[i]) continue;
+        inst_[i].dev.nlnn = d;
+        HIPCHK(hipMemcpy(d_insts_ + i, &inst_[i].dev, sizeof(Inst), hipMemcpyHostToDevice), "update instance");
+    }
+    alloc_.put(d_nlnn_);
+    d_nlnn_ = d;
+    nlnn_len_ = n;
+    return PAMC_OK;
+}
+
+int Runner::add_instance(HostInst &&h)
+{
+    int slot = -1;
+    for (int i = 0; i < max_slots_; ++i)
+        if (!used_[i]) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) {
+        set_error("no free instance slot");
+        return PAMC_ERR_BUSY;
+    }
+    int st = ensure_nlnn(h.Rcap + 1);
+    if (st != PAMC_OK) return st;
+    inst_[slot] = std::move(h);
+    st = upload_inst(slot);
+    if (st != PAMC_OK) {
+        alloc_.put(inst_[slot].block);
+        inst_[slot].block = nullptr;
+        return st;
+    }
+    used_[slot] = 1;
+    const int8_t *jp = inst_[slot].Jdev;
+    HIPCHK(hipMemcpy(d_insts_ + slot, &inst_[slot].dev, sizeof(Inst), hipMemcpyHostToDevice), "upload instance");
+    HIPCHK(hipMemcpy(d_Jptr_ + slot, &jp, sizeof(void *), hipMemcpyHostToDevice), "upload J pointer");
+    return slot;
+}
+
+void Runner::remove_instance(int slot)
+{
+    if (slot < 0 || slot >= max_slots_ || !used_[slot]) return;
+    (void)hipStreamSynchronize(stream_);
+    alloc_.put(inst_[slot].block);
+    inst_[slot] = HostInst();
+    used_[slot] = 0;
+}
+
+int Runner::upload_inst(int i)
+{
+    HostInst &h = inst_[i];
+    const int L = h.L, N = h.N;
+    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n);
+    h.bytes = lay.total;
+    h.block = alloc_.get(lay.total);
+    if (!h.block) {
+        set_error("device allocation of " + std::to_string(lay.total) + " bytes failed");
+        return PAMC_ERR_NOMEM;
+    }
+    uint8_t *b = (uint8_t *)h.block;
+    HIPCHK(hipMemsetAsync(b, 0, lay.total, stream_), "clear instance memory");
+    Inst &d = h.dev;
+    std::memset(&d, 0, sizeof(d));
+    d.L = L;
+    d.N = N;
+    d.ncol = h.ncol;
+    d.layout = h.layout;
+    d.row_bytes = h.row_bytes;
+    d.nT = h.nT;
+    d.NS = h.NS;
+    d.key0 = (uint32_t)h.seed;
+    d.key1 = (uint32_t)(h.seed >> 32);
+    d.R = (int32_t)h.R;
+    d.Rcap = (int32_t)h.Rcap;
+    d.nblk = (int32_t)((h.Rcap + kRowsPerBlock - 1) / kRowsPerBlock);
+    d.nlev = 3 * N + 1;
+    int64_t fp2 = 1;
+    while (fp2 < h.R) fp2 <<= 1;
+    d.fam_pow2 = (int32_t)fp2;
+    d.ovl_n = h.ovl_n;
+    d.spins[0] = b + lay.spins0;
+    d.spins[1] = b + lay.spins1;
+    d.E[0] = (int32_t *)(b + lay.E0);
+    d.E[1] = (int32_t *)(b + lay.E1);
+    d.fam[0] = (uint32_t *)(b + lay.f0);
+    d.fam[1] = (uint32_t *)(b + lay.f1);
+    d.map = (uint32_t *)(b + lay.map);
+    d.ncopy = (uint32_t *)(b + lay.ncopy);
+    d.loff = (uint32_t *)(b + lay.loff);
+    d.bsum = (uint32_t *)(b + lay.bsum);
+    d.boff = (uint32_t *)(b + lay.boff);
+    d.hist = (uint32_t *)(b + lay.hist);
+    d.BF = (uint2 *)(b + lay.BF);
+    d.cnt = (uint32_t *)(b + lay.cnt);
+    d.fpart = (double *)(b + lay.fpart);
+    d.thr = (const uint4 *)(b + lay.thr);
+    d.beta = (const double *)(b + lay.beta);
+    d.rho = (const double *)(b + lay.rho);
+    d.nlnn = d_nlnn_;
+    d.site = (const uint4 *)(b + lay.site);
+    d.grp = (const uint16_t *)(b + lay.grp);
+    d.jeo = (const uint32_t *)(b + lay.jeo);
+    d.k = (int32_t *)(b + lay.ctl);
+    d.cur = d.k + 1;
+    d.mapped = d.k + 2;
+    d.Rk = (uint32_t *)(b + lay.Rk);
+    d.rec = (StepRec *)(b + lay.rec);
+    d.ovl_slot = (int32_t *)(b + lay.ovl_slot);
+    d.qhist = (uint32_t *)(b + lay.qhist);
+    d.status = (uint32_t *)(b + lay.status);
+    h.ctl = d.k;
+    h.Jdev = (int8_t *)(b + lay.J);
+
+    // --- thresholds: T_k(dE) = floor(exp(-beta_k dE) 2^32), capped; beta = 0
+    // accepts every move
+    std::vector<uint32_t> thr((size_t)h.nT * 4);
+    for (int k = 0; k < h.nT; ++k) {
+        const double bk = h.beta[k];
+        for (int j = 0; j < 3; ++j) {
+            const double p = std::exp(-bk * (4.0 * (j + 1)));
+            const double x = std::floor(p * 4294967296.0);
+            thr[4 * k + j] = x >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)x;
+        }
+        thr[4 * k + 3] = bk == 0.0 ? 1u : 0u;
+    }
+    // --- rho_k = exp(-2 (beta_{k+1} - beta_k)): weight ratio of adjacent levels
+    std::vector<double> rho((size_t)h.nT, 1.0);
+    for (int k = 0; k + 1 < h.nT; ++k) {
+        const double db = h.beta[k + 1] - h.beta[k];
+        rho[k] = std::exp(-2.0 * db);
+    }
+    // --- colours and colour ranks
+    std::vector<int> col(N), rank(N);
+    int ncs[3] = {0, 0, 0};
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int s = x + L * (y + L * z);
+                col[s] = colour_of(L, x, y, z);
+                rank[s] = ncs[col[s]]++;
+            }
+    for (int c = 0; c < 3; ++c) {
+        d.ncs[c] = ncs[c];
+        d.gcs[c] = (ncs[c] + 3) / 4;
+    }
+    d.gmax = std::max(d.gcs[0], std::max(d.gcs[1], d.gcs[2]));
+    auto J = [&](int dir, int s) { return (int)h.J[(size_t)dir * N + s]; };
+    auto site_of = [L](int x, int y, int z) { return ((x % L + L) % L) + L * (((y % L + L) % L) + L * ((z % L + L) % L)); };
+    // storage position of each site
+    h.lex_pos.resize(N);
+    for (int s = 0; s < N; ++s) {
+        const int x = s % L, yz = s / L;
+        h.lex_pos[s] = h.layout == kLayoutLex ? s : yz * L + (x & 1) * (L / 2) + (x >> 1);
+    }
+    std::vector<uint32_t> site((size_t)N * 4, 0u);
+    std::vector<uint16_t> grp((size_t)h.ncol * d.gmax * 4, (uint16_t)0xFFFF);
+    std::vector<uint32_t> jeo((size_t)2 * (N / 8 + 1) * 6, 0u);
+    if (h.layout == kLayoutLex) {
+        for (int z = 0; z < L; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    const int s = site_of(x, y, z);
+                    const int nb[6] = {site_of(x + 1, y, z), site_of(x - 1, y, z), site_of(x, y + 1, z),
+                                       site_of(x, y - 1, z), site_of(x, y, z + 1), site_of(x, y, z - 1)};
+                    // couplings of the six bonds; the bond to s - e_d is
+                    // stored at the lower site
+                    const int jv[6] = {J(0, s), J(0, nb[1]), J(1, s), J(1, nb[3]), J(2, s), J(2, nb[5])};
+                    uint32_t jm = 0;
+                    for (int q = 0; q < 6; ++q)
+                        if (jv[q] < 0) jm |= 1u << q;
+                    site[4 * s + 0] = (uint32_t)nb[0] | ((uint32_t)nb[1] << 16);
+                    site[4 * s + 1] = (uint32_t)nb[2] | ((uint32_t)nb[3] << 16);
+                    site[4 * s + 2] = (uint32_t)nb[4] | ((uint32_t)nb[5] << 16);
+                    site[4 * s + 3] = jm;
+                    const int c = col[s], r = rank[s];
+                    grp[((size_t)c * d.gmax + (r >> 2)) * 4 + (r & 3)] = (uint16_t)s;
+                }
+    } else {
+        const int H = L / 2, GPR = L / 8, G = N / 8;
+        for (int c = 0; c < 2; ++c)
+            for (int g = 0; g < G; ++g) {
+                const int row = g / GPR, jb = g % GPR;
+                const int y = row % L, z = row / L;
+                const int p = (c + y + z) & 1;
+                uint32_t w[6] = {0, 0, 0, 0, 0, 0};
+                for (int bb = 0; bb < 4; ++bb) {
+                    const int x = 2 * (4 * jb + bb) + p;
+                    const int s = site_of(x, y, z);
+                    const int xm = site_of(x - 1, y, z), ym = site_of(x, y - 1, z), zm = site_of(x, y, z - 1);
+                    // aligned x neighbour: x+1 for p = 0, x-1 for p = 1
+                    const int ja = p == 0 ? J(0, s) : J(0, xm);
+                    const int js = p == 0 ? J(0, xm) : J(0, s);
+                    const int jv[6] = {ja, js, J(1, s), J(1, ym), J(2, s), J(2, zm)};
+                    for (int q = 0; q < 6; ++q)
+                        if (jv[q] < 0) w[q] |= 1u << (8 * bb);
+                }
+                for (int q = 0; q < 6; ++q) jeo[((size_t)c * G + g) * 6 + q] = w[q];
+                (void)H;
+            }
+    }
+    std::vector<uint32_t> Rk0((size_t)h.nT + 1, 0u);
+    Rk0[0] = (uint32_t)h.R;
+    int32_t ctl[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(b + lay.ctl, ctl, 16, hipMemcpyHostToDevice, stream_), "upload ctl");
+    HIPCHK(hipMemcpyAsync(b + lay.thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, stream_), "upload thr");
+    HIPCHK(hipMemcpyAsync(b + lay.beta, h.beta.data(), h.beta.size() * 8, hipMemcpyHostToDevice, stream_),
+           "upload beta");
+    HIPCHK(hipMemcpyAsync(b + lay.rho, rho.data(), rho.size() * 8, hipMemcpyHostToDevice, stream_), "upload rho");
+    HIPCHK(hipMemcpyAsync(b + lay.site, site.data(), site.size() * 4, hipMemcpyHostToDevice, stream_),
+           "upload site");
+    HIPCHK(hipMemcpyAsync(b + lay.grp, grp.data(), grp.size() * 2, hipMemcpyHostToDevice, stream_), "upload grp");
+    HIPCHK(hipMemcpyAsync(b + lay.jeo, jeo.data(), jeo.size() * 4, hipMemcpyHostToDevice, stream_), "upload jeo");
+    HIPCHK(hipMemcpyAsync(b + lay.J, h.J.data(), h.J.size(), hipMemcpyHostToDevice, stream_), "upload J");
+    HIPCHK(hipMemcpyAsync(b + lay.Rk, Rk0.data(), Rk0.size() * 4, hipMemcpyHostToDevice, stream_), "upload Rk");
+    HIPCHK(hipMemcpyAsync(b + lay.ovl_slot, h.ovl_slot.data(), h.ovl_slot.size() * 4, hipMemcpyHostToDevice,
+                          stream_),
+           "upload ovl");
+    // host vectors must outlive the async copies
+    HIPCHK(hipStreamSynchronize(stream_), "upload sync");
+    h.k_enq = 0;
+    h.k_base = 0;
+    h.lnZ_base = (double)N * std::log(2.0);
+    return PAMC_OK;
+}
+
+int Runner::build_work(const std::vector<int> &active)
+{
+    HIPCHK(hipStreamSynchronize(stream_), "build_work sync");
+    for (void *p : work_allocs_) alloc_.put(p);
+    work_allocs_.clear();
+    sweep_groups_.clear();
+    active_ = active;
+    auto upload = [&](const void *src, size_t bytes) -> void * {
+        void *p = alloc_.get(bytes);
+        if (!p) return nullptr;
+        work_allocs_.push_back(p);
+        if (bytes && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        return p;
+    };
+    std::map<std::tuple<int, int, int>, std::vector<Work>> groups;
+    std::vector<Work> rows, chunks;
+    std::vector<uint32_t> list, big;
+    for (int i : active) {
+        const HostInst &h = inst_[i];
+        auto &g = groups[std::make_tuple(h.variant, h.tile_rows, h.row_bytes)];
+        for (int64_t r = 0; r < h.Rcap; r += h.tile_rows) g.push_back(Work{(uint32_t)i, (uint32_t)r});
+        for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r});
+        int64_t fp2 = 1;
+        while (fp2 < h.R) fp2 <<= 1;
+        for (int64_t f = 0; f < fp2; f += 2048) chunks.push_back(Work{(uint32_t)i, (uint32_t)f});
+        list.push_back((uint32_t)i);
+        if (fp2 > 2048) big.push_back((uint32_t)i);
+    }
+    for (auto &kv : groups) {
+        SweepGroup sg;
+        sg.variant = std::get<0>(kv.first);
+        sg.tile_rows = std::get<1>(kv.first);
+        sg.row_bytes = std::get<2>(kv.first);
+        sg.nwork = (int)kv.second.size();
+        sg.work = (Work *)upload(kv.second.data(), kv.second.size() * sizeof(Work));
+        if (!sg.work) return dev_fail(hipErrorOutOfMemory, "upload sweep work");
+        sweep_groups_.push_back(sg);
+    }
+    d_rows_ = (Work *)upload(rows.data(), rows.size() * sizeof(Work));
+    d_chunks_ = (Work *)upload(chunks.data(), chunks.size() * sizeof(Work));
+    d_list_ = (uint32_t *)upload(list.data(), list.size() * 4);
+    d_biglist_ = (uint32_t *)upload(big.data(), big.size() * 4);
+    if (!d_rows_ || !d_chunks_ || !d_list_ || !d_biglist_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
+    nrows_work_ = (int)rows.size();
+    nchunks_ = (int)chunks.size();
+    nlist_ = (int)list.size();
+    nbig_ = (int)big.size();
+    return PAMC_OK;
+}
+
+int Runner::init_instances(const std::vector<int> &slots)
+{
+    std::vector<Work> w;
+    for (int i : slots)
+        for (int64_t r = 0; r < inst_[i].R; r += kRowsPerBlock) w.push_back(Work{(uint32_t)i, (uint32_t)r});
+    if (w.empty()) return PAMC_OK;
+    Work *d = (Work *)alloc_.get(w.size() * sizeof(Work));
+    if (!d) return PAMC_ERR_NOMEM;
+    HIPCHK(hipMemcpy(d, w.data(), w.size() * sizeof(Work), hipMemcpyHostToDevice), "upload init work");
+    launch_init(d_insts_, d, (int)w.size(), stream_);
+    launch_energy(d_insts_, d, (int)w.size(), d_Jptr_, stream_);
+    HIPCHK(hipGetLastError(), "init launch");
+    HIPCHK(hipStreamSynchronize(stream_), "init sync");
+    alloc_.put(d);
+    return PAMC_OK;
+}
+
+int Runner::enqueue_step()
+{
+    if (poisoned_) return PAMC_ERR_DEVICE;
+    bool any_ovl = false;
+    for (int i : active_) {
+        HostInst &h = inst_[i];
+        if (h.k_enq < h.nT && h.ovl_slot[h.k_enq] >= 0) any_ovl = true;
+    }
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (timing_) {
+        while (ev_pool_.size() < ev_used_ + 3) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e), "hipEventCreate");
+            ev_pool_.push_back(e);
+        }
+        for (int j = 0; j < 3; ++j) ev[j] = ev_pool_[ev_used_ + j];
+        ev_used_ += 3;
+        HIPCHK(hipEventRecord(ev[0], stream_), "hipEventRecord");
+    }
+    for (auto &g : sweep_groups_) launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, stream_);
+    if (timing_) HIPCHK(hipEventRecord(ev[1], stream_), "hipEventRecord");
+    launch_measure(d_insts_, d_list_, nlist_, stream_);
+    launch_famcount(d_insts_, d_rows_, nrows_work_, stream_);
+    launch_famtree(d_insts_, d_chunks_, nchunks_, stream_);
+    launch_famfinal(d_insts_, d_biglist_, nbig_, stream_);
+    if (any_ovl) launch_overlap(d_insts_, d_rows_, nrows_work_, stream_);
+    launch_copycount(d_insts_, d_rows_, nrows_work_, stream_);
+    launch_scan(d_insts_, d_list_, nlist_, stream_);
+    launch_expand(d_insts_, d_rows_, nrows_work_, stream_);
+    if (!fuse_) {
+        launch_gather(d_insts_, d_rows_, nrows_work_, 1, stream_);
+        launch_flip(d_insts_, d_list_, nlist_, stream_);
+    }
+    launch_advance(d_insts_, d_list_, nlist_, stream_);
+    if (timing_) HIPCHK(hipEventRecord(ev[2], stream_), "hipEventRecord");
+    HIPCHK(hipGetLastError(), "step launch");
+    for (int i : active_) {
+        HostInst &h = inst_[i];
+        if (h.k_enq < h.nT) h.k_enq++;
+    }
+    return PAMC_OK;
+}
+
+int Runner::phase_times(double *sweep_ms, double *other_ms, int64_t *n_steps)
+{
+    if (!timing_) {
+        set_error("timing is off for this run");
+        return PAMC_ERR_STATE;
+    }
+    HIPCHK(hipStreamSynchronize(stream_), "timing sync");
+    double a = 0.0, b = 0.0;
+    for (size_t j = 0; j + 3 <= ev_used_; j += 3) {
+        float t1 = 0.f, t2 = 0.f;
+        HIPCHK(hipEventElapsedTime(&t1, ev_pool_[j], ev_pool_[j + 1]), "hipEventElapsedTime");
+        HIPCHK(hipEventElapsedTime(&t2, ev_pool_[j + 1], ev_pool_[j + 2]), "hipEventElapsedTime");
+        a += t1;
+        b += t2;
+    }
+    if (sweep_ms) *sweep_ms = a;
+    if (other_ms) *other_ms = b;
+    if (n_steps) *n_steps = (int64_t)(ev_used_ / 3);
+    ev_used_ = 0;
+    return PAMC_OK;
+}
+
+int Runner::enqueue_steps(int n)
+{
+    for (int s = 0; s < n; ++s) {
+        bool any = false;
+        for (int i : active_)
+            if (inst_[i].k_enq < inst_[i].nT) any = true;
+        if (!any) break;
+        int st = enqueue_step();
+        if (st != PAMC_OK) return st;
+    }
+    return PAMC_OK;
+}
+
+int Runner::sync()
+{
+    if (poisoned_) return PAMC_ERR_DEVICE;
+    HIPCHK(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+    return PAMC_OK;
+}
+
+int Runner::read_ctl(int i, int32_t ctl[3], uint32_t status[2])
+{
+    const HostInst &h = inst_[i];
+    HIPCHK(hipMemcpyAsync(ctl, h.ctl, 12, hipMemcpyDeviceToHost, stream_), "read ctl");
+    HIPCHK(hipMemcpyAsync(status, h.dev.status, 8, hipMemcpyDeviceToHost, stream_), "read status");
+    HIPCHK(hipStreamSynchronize(stream_), "read ctl sync");
+    return PAMC_OK;
+}
+
+int Runner::inst_status(int i, int *step, int64_t *Rk)
+{
+    int32_t ctl[3];
+    uint32_t status[2];
+    int st = read_ctl(i, ctl, status);
+    if (st != PAMC_OK) return st;
+    const HostInst &h = inst_[i];
+    uint32_t r = 0;
+    const int k = ctl[0];
+    // after the last step the population is that of step nT - 1
+    HIPCHK(hipMemcpy(&r, h.dev.Rk + std::min(k, h.nT - 1), 4, hipMemcpyDeviceToHost), "read Rk");
+    if (step) *step = k;
+    if (Rk) *Rk = r;
+    if (status[0] & 1u) {
+        set_error("resampling at step " + std::to_string(status[1]) + " exceeded the capacity");
+        return PAMC_ERR_CAPACITY;
+    }
+    if (status[0] & 2u) {
+        set_error("resampling at step " + std::to_string(status[1]) + " left no replica");
+        return PAMC_ERR_EXTINCT;
+    }
+    return PAMC_OK;
+}
+
+int Runner::observables(int i, pamc_step_obs *out, int n)
+{
+    const HostInst &h = inst_[i];
+    if (n < 0 || n > h.nT) {
+        set_error("observables: n out of range");
+        return PAMC_ERR_INVALID;
+    }
+    int32_t ctl[3];
+    uint32_t status[2];
+    int st = read_ctl(i, ctl, status);
+    if (st != PAMC_OK) return st;
+    std::vector<StepRec> rec((size_t)h.nT);
+    std::vector<uint32_t> q((size_t)std::max(1, h.ovl_n) * (2 * h.N + 1));
+    HIPCHK(hipMemcpy(rec.data(), h.dev.rec, rec.size() * sizeof(StepRec), hipMemcpyDeviceToHost), "read rec");
+    HIPCHK(hipMemcpy(q.data(), h.dev.qhist, q.size() * 4, hipMemcpyDeviceToHost), "read qhist");
+    // steps measured: those below the device step, plus the failing step
+    int kdone = ctl[0];
+    if (status[0]) kdone = (int)status[1] + 1;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const int N = h.N;
+    double lnZ = h.lnZ_base;
+    for (int k = 0; k < n; ++k) {
+        pamc_step_obs &o = out[k];
+        std::memset(&o, 0, sizeof(o));
+        o.beta = h.beta[k];
+        o.mean_E = o.e = o.C_V = o.lnQ = o.lnZ = o.betaF = o.f = o.S_f = o.rho_s = nan;
+        o.q_abs = o.q2 = o.q4 = o.g_SG = nan;
+        if (k < h.k_base || k >= kdone) continue;
+        const StepRec &r = rec[k];
+        o.measured = 1;
+        o.R = r.R;
+        o.sum_E = r.sumE;
+        o.sum_E2 = r.sumE2;
+        o.E_min = r.Emin;
+        o.E_max = r.Emax;
+        const double Rd = (double)r.R;
+        o.mean_E = (double)r.sumE / Rd;
+        o.e = o.mean_E / (double)N;
+        const __int128 num = (__int128)r.R * (__int128)r.sumE2 - (__int128)r.sumE * (__int128)r.sumE;
+        const double var = (double)num / (Rd * Rd);
+        o.C_V = (o.beta * o.beta) * var / (double)N;
+        o.lnZ = lnZ;
+        o.betaF = -lnZ;
+        o.f = o.beta > 0.0 ? -lnZ / (o.beta * (double)N) : nan;
+        o.S_f = std::log(Rd) - r.T / Rd;
+        o.rho_s = Rd / std::exp(o.S_f);
+        if (k < h.nT - 1 && k + 1 < kdone + (status[0] ? 0 : 1)) {
+            const double db = h.beta[k + 1] - h.beta[k];
+            o.lnQ = (-db * (double)r.Emin) + std::log(r.S) - std::log(Rd);
+            lnZ = lnZ + o.lnQ;
+        }
+        const int slot = h.ovl_slot[k];
+        if (slot >= 0) {
+            const uint32_t *hq = q.data() + (size_t)slot * (2 * N + 1);
+            int64_t cnt = 0;
+            double m1 = 0.0, m2 = 0.0, m4 = 0.0;
+            for (int Q = -N; Q <= N; ++Q) {
+                const int64_t c = hq[Q + N];
+                if (c == 0) continue;
+                const double qq = (double)Q / (double)N;
+                cnt += c;
+                m1 += (double)c * std::fabs(qq);
+                m2 += (double)c * (qq * qq);
+                m4 += (double)c * ((qq * qq) * (qq * qq));
+            }
+            if (cnt > 0) {
+                o.q_abs = m1 / (double)cnt;
+                o.q2 = m2 / (double)cnt;
+                o.q4 = m4 / (double)cnt;
+                o.g_SG = 0.5 * (3.0 - o.q4 / (o.q2 * o.q2));
+            }
+        }
+    }
+    return PAMC_OK;
+}
+
+int Runner::overlap_hist(int i, int step, int64_t *hist)
+{
+    const HostInst &h = inst_[i];
+    if (step < 0 || step >= h.nT || h.ovl_slot[step] < 0) {
+        set_error("not an overlap step");
+        return PAMC_ERR_STATE;
+    }
+    int32_t ctl[3];
+    uint32_t status[2];
+    int st = read_ctl(i, ctl, status);
+    if (st != PAMC_OK) return st;
+    if (step >= ctl[0]) {
+        set_error("overlap step has not run");
+        return PAMC_ERR_STATE;
+    }
+    std::vector<uint32_t> q((size_t)(2 * h.N + 1));
+    HIPCHK(hipMemcpy(q.data(), h.dev.qhist + (size_t)h.ovl_slot[step] * (2 * h.N + 1), q.size() * 4,
+                     hipMemcpyDeviceToHost),
+           "read qhist");
+    for (size_t j = 0; j < q.size(); ++j) hist[j] = q[j];
+    return PAMC_OK;
+}
+
+int Runner::step_sums(int i, double *S, double *T, int n)
+{
+    const HostInst &h = inst_[i];
+    if (n < 0 || n > h.nT) return PAMC_ERR_INVALID;
+    std::vector<StepRec> rec((size_t)h.nT);
+    HIPCHK(hipStreamSynchronize(stream_), "sync");
+    HIPCHK(hipMemcpy(rec.data(), h.dev.rec, rec.size() * sizeof(StepRec), hipMemcpyDeviceToHost), "read rec");
+    for (int k = 0; k < n; ++k) {
+        if (S) S[k] = rec[k].S;
+        if (T) T[k] = rec[k].T;
+    }
+    return PAMC_OK;
+}
+
+// Bring a pending copy map into the other buffer so that rows are stored
+// in order (used before export).
+int Runner::materialise(int i)
+{
+    HostInst &h = inst_[i];
+    int32_t ctl[3];
+    uint32_t status[2];
+    int st = read_ctl(i, ctl, status);
+    if (st != PAMC_OK) return st;
+    if (!ctl[2]) return PAMC_OK;
+    std::vector<Work> rows;
+    for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r});
+    Work *d = (Work *)alloc_.get(rows.size() * sizeof(Work));
+    uint32_t *l = (uint32_t *)alloc_.get(4);
+    if (!d || !l) {
+        alloc_.put(d);
+        alloc_.put(l);
+        return PAMC_ERR_NOMEM;
+    }
+    const uint32_t idx = (uint32_t)i;
+    HIPCHK(hipMemcpy(d, rows.data(), rows.size() * sizeof(Work), hipMemcpyHostToDevice), "upload rows");
+    HIPCHK(hipMemcpy(l, &idx, 4, hipMemcpyHostToDevice), "upload list");
+    launch_gather(d_insts_, d, (int)rows.size(), 0, stream_);
+    launch_flip(d_insts_, l, 1, stream_);
+    HIPCHK(hipGetLastError(), "gather launch");
+    HIPCHK(hipStreamSynchronize(stream_), "gather sync");
+    alloc_.put(d);
+    alloc_.put(l);
+    return PAMC_OK;
+}
+
+int Runner::get_state(int i, pamc_state *stt)
+{
+    HostInst &h = inst_[i];
+    int st = sync();
+    if (st != PAMC_OK) return st;
+    st = materialise(i);
+    if (st != PAMC_OK) return st;
+    int32_t ctl[3];
+    uint32_t status[2];
+    st = read_ctl(i, ctl, status);
+    if (st != PAMC_OK) return st;
+    uint32_t Rk = 0;
+    HIPCHK(hipMemcpy(&Rk, h.dev.Rk + std::min(ctl[0], h.nT - 1), 4, hipMemcpyDeviceToHost), "read Rk");
+    if (status[0]) {
+        // the failing step's population after its sweeps
+        HIPCHK(hipMemcpy(&Rk, h.dev.Rk + status[1], 4, hipMemcpyDeviceToHost), "read Rk");
+    }
+    stt->step = ctl[0];
+    stt->R = Rk;
+    // ln Z at the current step
+    {
+        std::vector<pamc_step_obs> obs((size_t)h.nT);
+        st = observables(i, obs.data(), h.nT);
+        if (st != PAMC_OK) return st;
+        double lnZ = h.lnZ_base;
+        for (int k = h.k_base; k < ctl[0] && k < h.nT; ++k)
+            if (!std::isnan(obs[k].lnQ)) lnZ = lnZ + obs[k].lnQ;
+        stt->lnZ = lnZ;
+    }
+    const int cur = ctl[1];
+    if (stt->spins) {
+        std::vector<uint8_t> buf((size_t)Rk * h.row_bytes);
+        HIPCHK(hipMemcpy(buf.data(), h.dev.spins[cur], buf.size(), hipMemcpyDeviceToHost), "read spins");
+        for (uint32_t r = 0; r < Rk; ++r) {
+            const uint8_t *row = buf.data() + (size_t)r * h.row_bytes;
+            int8_t *o = stt->spins + (size_t)r * h.N;
+            for (int s = 0; s < h.N; ++s) o[s] = row[h.lex_pos[s]] ? 1 : -1;
+        }
+    }
+    if (stt->E) HIPCHK(hipMemcpy(stt->E, h.dev.E[cur], (size_t)Rk * 4, hipMemcpyDeviceToHost), "read E");
+    if (stt->family)
+        HIPCHK(hipMemcpy(stt->family, h.dev.fam[cur], (size_t)Rk * 4, hipMemcpyDeviceToHost), "read family");
+    return PAMC_OK;
+}
+
+int Runner::set_state(int i, const pamc_state *st)
+{
+    HostInst &h = inst_[i];
+    if (!st || !st->spins || !st->family || st->step < 0 || st->step >= h.nT || st->R < 1 || st->R > h.Rcap) {
+        set_error("set_state: invalid state");
+        return PAMC_ERR_INVALID;
+    }
+    const int64_t R = st->R;
+    std::vector<uint8_t> buf((size_t)R * h.row_bytes, 0);
+    for (int64_t r = 0; r < R; ++r) {
+        const int8_t *in = st->spins + (size_t)r * h.N;
+        uint8_t *row = buf.data() + (size_t)r * h.row_bytes;
+        for (int s = 0; s < h.N; ++s) {
+            if (in[s] != 1 && in[s] != -1) {
+                set_error("set_state: spins must be +-1");
+                return PAMC_ERR_INVALID;
+            }
+            row[h.lex_pos[s]] = in[s] > 0 ? 1 : 0;
+        }
+        if ((int64_t)st->family[r] >= h.R) {
+            set_error("set_state: family id out of range");
+            return PAMC_ERR_INVALID;
+        }
+    }
+    int stt = sync();
+    if (stt != PAMC_OK) return stt;
+    const int32_t ctl[3] = {st->step, 0, 0};
+    const uint32_t status[2] = {0, 0};
+    const uint32_t Rk = (uint32_t)R;
+    HIPCHK(hipMemcpy(h.dev.spins[0], buf.data(), buf.size(), hipMemcpyHostToDevice), "write spins");
+    HIPCHK(hipMemcpy(h.dev.fam[0], st->family, (size_t)R * 4, hipMemcpyHostToDevice), "write family");
+    HIPCHK(hipMemcpy(h.ctl, ctl, 12, hipMemcpyHostToDevice), "write ctl");
+    HIPCHK(hipMemcpy(h.dev.status, status, 8, hipMemcpyHostToDevice), "write status");
+    HIPCHK(hipMemcpy(h.dev.Rk + st->step, &Rk, 4, hipMemcpyHostToDevice), "write Rk");
+    // energies from the spins (Eq. (1)) for the imported rows
+    std::vector<Work> rows;
+    for (int64_t r = 0; r < R; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r});
+    Work *d = (Work *)alloc_.get(rows.size() * sizeof(Work));
+    if (!d) return PAMC_ERR_NOMEM;
+    HIPCHK(hipMemcpy(d, rows.data(), rows.size() * sizeof(Work), hipMemcpyHostToDevice), "upload rows");
+    launch_energy(d_insts_, d, (int)rows.size(), d_Jptr_, stream_);
+    HIPCHK(hipGetLastError(), "energy launch");
+    HIPCHK(hipStreamSynchronize(stream_), "energy sync");
+    alloc_.put(d);
+    h.k_enq = st->step;
+    h.k_base = st->step;
+    h.lnZ_base = st->lnZ;
+    return PAMC_OK;
+}
+
+int Runner::thresholds(int i, uint32_t *out, uint8_t *acc)
+{
+    const HostInst &h = inst_[i];
+    std::vector<uint32_t> thr((size_t)h.nT * 4);
+    HIPCHK(hipMemcpy(thr.data(), h.dev.thr, thr.size() * 4, hipMemcpyDeviceToHost), "read thr");
+    for (int k = 0; k < h.nT; ++k) {
+        if (out)
+            for (int j = 0; j < 3; ++j) out[3 * k + j] = thr[4 * k + j];
+        if (acc) acc[k] = (uint8_t)thr[4 * k + 3];
+    }
+    return PAMC_OK;
+}
+
+}  // namespace pamc

@@ -1,0 +1,144 @@
+// runner.h -- host orchestration of the population annealing kernels.
+//
+// A Runner owns a set of instances (one for pamc_create, many for a batch or
+// the serving loop), their device memory, the work lists the segmented
+// kernels run over, and the stream.  Steps are enqueued without host
+// synchronisation: the temperature index, the population size and the
+// buffer roles of every instance live on the device.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pamc.h"
+#include "launch.h"
+#include "pamc_dev.h"
+
+namespace pamc {
+
+struct HostInst {
+    int L = 0, N = 0, ncol = 0, layout = 0, variant = 0;
+    int row_bytes = 0, tile_rows = 0;
+    int64_t R = 0, Rcap = 0;
+    int nT = 0, NS = 0;
+    uint64_t seed = 0;
+    std::vector<double> beta;
+    std::vector<int8_t> J;             // [3][N]
+    std::vector<int32_t> ovl_slot;     // [nT]
+    int ovl_n = 0;
+    int k_enq = 0;                     // steps enqueued so far
+    double lnZ_base = 0.0;             // ln Z at step k_base
+    int k_base = 0;
+    std::vector<int> lex_pos;          // lexicographic site -> storage position
+    // device memory
+    void *block = nullptr;             // everything of this instance
+    size_t bytes = 0;
+    int8_t *Jdev = nullptr;
+    int32_t *ctl = nullptr;            // k, cur, mapped
+    Inst dev{};                        // descriptor as uploaded
+    bool poisoned = false;
+};
+
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free)(void *, void *) = nullptr;
+    void *user = nullptr;
+    void *get(size_t bytes);
+    void put(void *p);
+};
+
+// Footprint and table construction helpers.
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl);
+int64_t default_capacity(int64_t R);
+int choose_layout(int L);
+
+class Runner {
+public:
+    Runner() = default;
+    ~Runner();
+    // Stream, allocator and slot capacity of the device instance table.
+    int setup(const pamc_options &opt, int max_slots);
+    // Allocates an instance's device memory and tables; returns its slot
+    // (>= 0) or a negative status.  The population is not initialised.
+    int add_instance(HostInst &&h);
+    void remove_instance(int slot);
+    // Random initial population (step 0) and energies of these instances.
+    int init_instances(const std::vector<int> &slots);
+    // Device work lists of the segmented kernels for this active set.
+    int build_work(const std::vector<int> &active);
+    // Enqueue one step of every active instance not yet finished.
+    int enqueue_step();
+    // Enqueue up to n steps, in lock step.
+    int enqueue_steps(int n);
+    int sync();
+    // Status of slot i after a sync: PAMC_OK / CAPACITY / EXTINCT, and its
+    // device step and population.
+    int inst_status(int i, int *step, int64_t *Rk);
+    int observables(int i, pamc_step_obs *out, int n);
+    int overlap_hist(int i, int step, int64_t *hist);
+    int step_sums(int i, double *S, double *T, int n);
+    int get_state(int i, pamc_state *st);
+    int set_state(int i, const pamc_state *st);
+    int thresholds(int i, uint32_t *out, uint8_t *acc);
+    const HostInst &inst(int i) const { return inst_[i]; }
+    HostInst &inst(int i) { return inst_[i]; }
+    const std::vector<int> &active() const { return active_; }
+    hipStream_t stream() const { return stream_; }
+    bool fused() const { return fuse_; }
+    bool poisoned() const { return poisoned_; }
+    // Sums of the recorded per-step event intervals since the last call.
+    int phase_times(double *sweep_ms, double *other_ms, int64_t *n_steps);
+    bool timing() const { return timing_; }
+
+private:
+    int upload_inst(int i);
+    int ensure_nlnn(int64_t len);
+    int read_ctl(int i, int32_t ctl[3], uint32_t status[2]);
+    int materialise(int i);
+    int dev_fail(hipError_t e, const char *what);
+
+    std::vector<HostInst> inst_;   // by slot
+    std::vector<char> used_;       // slot in use
+    Allocator alloc_;
+    hipStream_t stream_ = nullptr;
+    bool own_stream_ = false;
+    bool fuse_ = true;
+    bool poisoned_ = false;
+    int device_ = 0;
+    int max_slots_ = 0;
+
+    // shared device data
+    Inst *d_insts_ = nullptr;      // [max_slots]
+    const int8_t **d_Jptr_ = nullptr;
+    double *d_nlnn_ = nullptr;
+    int64_t nlnn_len_ = 0;
+
+    // work lists for the current active set
+    struct SweepGroup {
+        int variant, tile_rows, row_bytes;
+        Work *work;
+        int nwork;
+    };
+    std::vector<SweepGroup> sweep_groups_;
+    Work *d_rows_ = nullptr;
+    int nrows_work_ = 0;
+    Work *d_chunks_ = nullptr;
+    int nchunks_ = 0;
+    uint32_t *d_list_ = nullptr;
+    uint32_t *d_biglist_ = nullptr;  // instances with more than 2048 families
+    int nlist_ = 0, nbig_ = 0;
+    std::vector<void *> work_allocs_;
+    std::vector<int> active_;
+    // timing: three events per enqueued step (before the sweeps, after the
+    // sweeps, after the step), reused from a pool
+    bool timing_ = false;
+    std::vector<hipEvent_t> ev_pool_;
+    size_t ev_used_ = 0;
+};
+
+void set_error(const std::string &msg);
+
+}  // namespace pamc

@@ -1,0 +1,445 @@
+// sweep.hip -- initial population, energies and the checkerboard Metropolis
+// sweeps (paper Sec. II.B and Sec. III.A) for gfx950.
+//
+// A block loads a tile of replica rows into LDS, runs all N_S sweeps of the
+// current temperature on chip, recomputes each replica's energy (Eq. (1))
+// from the final spins, and writes the rows back once.  When the previous
+// resampling left a copy map, the tile is read through it, so the gather of
+// surviving replicas costs no separate pass over HBM.
+//
+// Random numbers: the draw for a site of colour c whose rank among the
+// sites of that colour is i, in replica row r, step k and sweep t, is word
+// (i & 3) of Philox4x32-10 at counter ((c << 24) | (i >> 2), r, k,
+// TAG_SWEEP | t) under the run's key.  Acceptance for dE > 0 is u < T_k(dE)
+// with uint32 thresholds prepared on the host.
+#include "pamc_dev.h"
+#include "launch.h"
+
+namespace pamc {
+
+__device__ __forceinline__ const Inst &inst_ref(const Inst *insts, uint32_t i) { return insts[i]; }
+
+// Storage position of lexicographic site s in a replica row.
+__device__ __forceinline__ int storage_pos(int layout, int L, int s)
+{
+    if (layout == kLayoutLex) return s;
+    const int x = s % L, yz = s / L;
+    return yz * L + (x & 1) * (L >> 1) + (x >> 1);
+}
+
+// ---------------------------------------------------------------------------
+// Initial replicas (Sec. II.B: random configurations at beta = 0).  Site s
+// of row r takes S = +1 when bit 31 of word (s & 3) of Philox at counter
+// (s >> 2, r, 0, TAG_INIT) is set.  One thread per Philox block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init(const Inst *insts, const Work *work)
+{
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int nq = (I.N + 3) >> 2;
+    const int rows = min(kRowsPerBlock, I.R - (int)w.row0);
+    uint8_t *sp = I.spins[0];
+    for (int it = threadIdx.x; it < rows * nq; it += blockDim.x) {
+        const int q = it / nq, b = it - q * nq;
+        const uint32_t r = w.row0 + q;
+        const uint4 v = philox10(make_uint4((uint32_t)b, r, 0u, kTagInit), I.key0, I.key1);
+        for (int j = 0; j < 4; ++j) {
+            const int s = 4 * b + j;
+            if (s >= I.N) break;
+            sp[(size_t)r * I.row_bytes + storage_pos(I.layout, I.L, s)] = (uint8_t)(word_of(v, j) >> 31);
+        }
+    }
+    for (int q = threadIdx.x; q < rows; q += blockDim.x) I.fam[0][w.row0 + q] = w.row0 + q;
+}
+
+// ---------------------------------------------------------------------------
+// Energies of the rows of the current buffer, Eq. (1): E = -sum over the 3N
+// bonds (s, s + e_d) of J S_s S_{s+e_d}.  One wave per row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *work, const int8_t *const *Jraw)
+{
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k >= I.nT) return;
+    const int Rk = (int)I.Rk[k];
+    const int cur = *I.cur;
+    const int8_t *J = Jraw[w.inst];
+    const int L = I.L, N = I.N;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = wave; q < kRowsPerBlock; q += 4) {
+        const int r = (int)w.row0 + q;
+        if (r >= Rk) break;
+        const uint8_t *S = I.spins[cur] + (size_t)r * I.row_bytes;
+        int e = 0;
+        for (int s = lane; s < N; s += 64) {
+            const int x = s % L, y = (s / L) % L, z = s / (L * L);
+            const int ss = 2 * S[storage_pos(I.layout, L, s)] - 1;
+            const int nb[3] = {(x + 1) % L + L * (y + L * z), x + L * ((y + 1) % L + L * z),
+                               x + L * (y + L * ((z + 1) % L))};
+            for (int d = 0; d < 3; ++d)
+                e -= J[d * N + s] * ss * (2 * S[storage_pos(I.layout, L, nb[d])] - 1);
+        }
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+        if (lane == 0) I.E[cur][r] = e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shared tile load / store.  Rows of the tile come from buffer `cur`, either
+// directly (in place) or through the copy map (then they go to the other
+// buffer, with their family ids).
+// ---------------------------------------------------------------------------
+struct TileIO {
+    const uint8_t *src;
+    uint8_t *dst;
+    const uint32_t *map;  // nullptr: identity
+    const uint32_t *fsrc;
+    uint32_t *fdst;
+    int32_t *Edst;
+};
+
+__device__ __forceinline__ TileIO tile_io(const Inst &I)
+{
+    TileIO io;
+    const int cur = *I.cur;
+    const int mapped = *I.mapped;
+    io.src = I.spins[cur];
+    io.map = mapped ? I.map : nullptr;
+    io.dst = mapped ? I.spins[cur ^ 1] : I.spins[cur];
+    io.fsrc = I.fam[cur];
+    io.fdst = mapped ? I.fam[cur ^ 1] : nullptr;
+    io.Edst = mapped ? I.E[cur ^ 1] : I.E[cur];
+    return io;
+}
+
+__device__ __forceinline__ void tile_load(const TileIO &io, uint8_t *tile, int r0, int nrows, int row_bytes)
+{
+    const int per_row = row_bytes >> 4;
+    for (int it = threadIdx.x; it < nrows * per_row; it += blockDim.x) {
+        const int q = it / per_row, c = it - q * per_row;
+        const uint32_t r = (uint32_t)(r0 + q);
+        const uint32_t sr = io.map ? io.map[r] : r;
+        const uint4 v = *reinterpret_cast<const uint4 *>(io.src + (size_t)sr * row_bytes + 16 * c);
+        *reinterpret_cast<uint4 *>(tile + q * row_bytes + 16 * c) = v;
+    }
+}
+
+__device__ __forceinline__ void tile_store(const TileIO &io, const uint8_t *tile, int r0, int nrows, int row_bytes)
+{
+    const int per_row = row_bytes >> 4;
+    for (int it = threadIdx.x; it < nrows * per_row; it += blockDim.x) {
+        const int q = it / per_row, c = it - q * per_row;
+        const uint4 v = *reinterpret_cast<const uint4 *>(tile + q * row_bytes + 16 * c);
+        *reinterpret_cast<uint4 *>(io.dst + (size_t)(r0 + q) * row_bytes + 16 * c) = v;
+    }
+    if (io.map)
+        for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
+}
+
+// Energy -> histogram bin and stored energy, for the rows of the tile.
+__device__ __forceinline__ void tile_energy_out(const Inst &I, const TileIO &io, const int *unsat, int r0, int nrows)
+{
+    for (int q = threadIdx.x; q < nrows; q += blockDim.x) {
+        const int E = 2 * unsat[q] - 3 * I.N;
+        io.Edst[r0 + q] = E;
+        atomicAdd(&I.hist[(E + 3 * I.N) >> 1], 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General sweep: any L >= 2, two colours for even L, three for odd L.
+// Storage is lexicographic.  Each work item is one Philox block (four
+// consecutive sites of one colour) of one replica of the tile; per site the
+// six neighbours and the couplings come from a per-site record.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work *work, int tile_rows)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k >= I.nT || I.status[0]) return;
+    const int Rk = (int)I.Rk[k];
+    const int r0 = (int)w.row0;
+    const int nrows = min(tile_rows, Rk - r0);
+    if (nrows <= 0) return;
+    const int row_bytes = I.row_bytes;
+    int *unsat = reinterpret_cast<int *>(lds + tile_rows * row_bytes);
+    const TileIO io = tile_io(I);
+    tile_load(io, lds, r0, nrows, row_bytes);
+    for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] = 0;
+    const uint4 th = I.thr[k];
+    const bool all = th.w != 0;
+    const uint32_t key0 = I.key0, key1 = I.key1;
+    __syncthreads();
+
+    for (int t = 0; t < I.NS; ++t) {
+        for (int c = 0; c < I.ncol; ++c) {
+            const int G = I.gcs[c];
+            const int items = nrows * G;
+            const uint16_t *grp = I.grp + (size_t)c * I.gmax * 4;
+            for (int it = threadIdx.x; it < items; it += blockDim.x) {
+                const int q = it / G, g = it - q * G;
+                const uint32_t r = (uint32_t)(r0 + q);
+                const uint4 u = philox10(make_uint4(((uint32_t)c << 24) | (uint32_t)g, r, (uint32_t)k,
+                                                    kTagSweep | (uint32_t)t),
+                                         key0, key1);
+                uint8_t *S = lds + q * row_bytes;
+                const uint16_t *gs = grp + 4 * g;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int pos = gs[j];
+                    if (pos == 0xFFFF) break;
+                    const uint4 rec = I.site[pos];
+                    const uint32_t s0 = S[pos];
+                    const uint32_t jm = rec.w;
+                    // unsatisfied bonds: S_s S_nb J = -1  <=>  s ^ nb ^ [J = -1] = 1
+                    const uint32_t n = (s0 ^ S[rec.x & 0xFFFF] ^ (jm & 1)) + (s0 ^ S[rec.x >> 16] ^ ((jm >> 1) & 1)) +
+                                       (s0 ^ S[rec.y & 0xFFFF] ^ ((jm >> 2) & 1)) + (s0 ^ S[rec.y >> 16] ^ ((jm >> 3) & 1)) +
+                                       (s0 ^ S[rec.z & 0xFFFF] ^ ((jm >> 4) & 1)) + (s0 ^ S[rec.z >> 16] ^ ((jm >> 5) & 1));
+                    // dE = 12 - 4 n: n = 0, 1, 2 need the draw; n >= 3 is downhill
+                    const uint32_t T = n == 0 ? th.z : (n == 1 ? th.y : th.x);
+                    const bool acc = all || n >= 3 || word_of(u, j) < T;
+                    if (acc) S[pos] = (uint8_t)(s0 ^ 1u);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // energies: E = 2U - 3N with U the unsatisfied bonds (s, s + e_d)
+    for (int it = threadIdx.x; it < nrows * I.N; it += blockDim.x) {
+        const int q = it / I.N, s = it - q * I.N;
+        const uint8_t *S = lds + q * row_bytes;
+        const uint4 rec = I.site[s];
+        const uint32_t s0 = S[s];
+        const uint32_t jm = rec.w;
+        const int n = (int)((s0 ^ S[rec.x & 0xFFFF] ^ (jm & 1)) + (s0 ^ S[rec.y & 0xFFFF] ^ ((jm >> 2) & 1)) +
+                            (s0 ^ S[rec.z & 0xFFFF] ^ ((jm >> 4) & 1)));
+        atomicAdd(&unsat[q], n);
+    }
+    __syncthreads();
+    tile_store(io, lds, r0, nrows, row_bytes);
+    tile_energy_out(I, io, unsat, r0, nrows);
+}
+
+// ---------------------------------------------------------------------------
+// SWAR sweep for L in {8, 16}.  Storage layout kLayoutEO: row (y, z) holds
+// its L/2 even-x sites then its L/2 odd-x sites.  The sites of colour c in
+// row (y, z) are the half p = (c + y + z) & 1, so Philox block g = (row,
+// jb) of colour c is the aligned 32-bit word at row*L + p*L/2 + 4 jb, one
+// byte per site.  Its neighbours: the same word position in rows y +- 1 and
+// z +- 1, the word at the same position of the other half (one x
+// neighbour), and that word shifted by one byte (the other x neighbour),
+// built with a byte-align of two words.  Per byte the six terms
+// s ^ nb ^ [J = -1] are summed without carries (<= 6 per byte).
+// ---------------------------------------------------------------------------
+template <int L>
+struct EOShape {
+    static constexpr int N = L * L * L;
+    static constexpr int H = L / 2;        // sites per half row
+    static constexpr int GPR = L / 8;      // Philox blocks per half row
+    static constexpr int G = N / 8;        // Philox blocks per colour
+    static constexpr int TPR = G < 256 ? G : 256;  // threads per replica
+    static constexpr int RP = 256 / TPR;   // replicas swept at once
+    static constexpr int GPT = G / TPR;    // blocks per thread per colour
+};
+
+struct EOGroup {
+    uint32_t own, hi, lo, yp, ym, zp, zm;  // LDS byte offsets within a row
+    uint32_t sh;                            // byte shift for the x neighbour
+    uint32_t ctr;                           // Philox counter word 0
+    uint32_t j[6];                          // coupling bytes (1: J = -1)
+};
+
+template <int L>
+__device__ __forceinline__ void eo_group_setup(EOGroup &gr, const uint32_t *jeo, int c, int g)
+{
+    using S = EOShape<L>;
+    const int row = g / S::GPR, jb = g - row * S::GPR;
+    const int y = row % L, z = row / L;
+    const int p = (c + y + z) & 1;
+    const int rb = row * L;
+    gr.own = rb + p * S::H + 4 * jb;
+    const uint32_t oth = rb + (1 - p) * S::H + 4 * jb;
+    // p = 1: the other x neighbour is one site to the right (next word),
+    // p = 0: one site to the left (previous word), with periodic wrap.
+    const uint32_t adj = rb + (1 - p) * S::H + 4 * ((jb + (p ? 1 : S::GPR - 1)) % S::GPR);
+    gr.hi = p ? adj : oth;
+    gr.lo = p ? oth : adj;
+    gr.sh = p ? 1u : 3u;
+    gr.yp = ((z * L + (y + 1) % L) * L) + p * S::H + 4 * jb;
+    gr.ym = ((z * L + (y + L - 1) % L) * L) + p * S::H + 4 * jb;
+    gr.zp = ((((z + 1) % L) * L + y) * L) + p * S::H + 4 * jb;
+    gr.zm = ((((z + L - 1) % L) * L + y) * L) + p * S::H + 4 * jb;
+    gr.ctr = ((uint32_t)c << 24) | (uint32_t)g;
+    const uint32_t *jw = jeo + ((size_t)c * S::G + g) * 6;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) gr.j[d] = jw[d];
+}
+
+__device__ __forceinline__ uint32_t lds32(const uint8_t *base, uint32_t off)
+{
+    return *reinterpret_cast<const uint32_t *>(base + off);
+}
+
+// Per byte: number of unsatisfied bonds of the four sites of the block.
+__device__ __forceinline__ uint32_t eo_unsat(const uint8_t *row, const EOGroup &gr, uint32_t own)
+{
+    const uint32_t hi = lds32(row, gr.hi), lo = lds32(row, gr.lo);
+    const uint32_t xa = gr.sh == 1u ? lo : hi;  // the aligned x neighbour word
+    const uint32_t xs = __builtin_amdgcn_alignbyte(hi, lo, gr.sh);
+    return (own ^ xa ^ gr.j[0]) + (own ^ xs ^ gr.j[1]) + (own ^ lds32(row, gr.yp) ^ gr.j[2]) +
+           (own ^ lds32(row, gr.ym) ^ gr.j[3]) + (own ^ lds32(row, gr.zp) ^ gr.j[4]) +
+           (own ^ lds32(row, gr.zm) ^ gr.j[5]);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work *work, int tile_rows)
+{
+    using SH = EOShape<L>;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k >= I.nT || I.status[0]) return;
+    const int Rk = (int)I.Rk[k];
+    const int r0 = (int)w.row0;
+    const int nrows = min(tile_rows, Rk - r0);
+    if (nrows <= 0) return;
+    const int row_bytes = I.row_bytes;
+    uint32_t *thr = reinterpret_cast<uint32_t *>(lds + tile_rows * row_bytes);  // [8]
+    int *unsat = reinterpret_cast<int *>(thr + 8);
+    const TileIO io = tile_io(I);
+    tile_load(io, lds, r0, nrows, row_bytes);
+    const uint4 th = I.thr[k];
+    const bool all = th.w != 0;
+    if (threadIdx.x < 8) thr[threadIdx.x] = threadIdx.x == 0 ? th.z : threadIdx.x == 1 ? th.y : threadIdx.x == 2 ? th.x : 0u;
+    for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] = 0;
+
+    const int lane_r = threadIdx.x % SH::TPR;  // position inside the replica
+    const int qsub = threadIdx.x / SH::TPR;    // which of the RP replicas
+    EOGroup gr[2][SH::GPT];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int gi = 0; gi < SH::GPT; ++gi) eo_group_setup<L>(gr[c][gi], I.jeo, c, lane_r + gi * SH::TPR);
+    const uint32_t key0 = I.key0, key1 = I.key1;
+    __syncthreads();
+
+    for (int qb = 0; qb < nrows; qb += SH::RP) {
+        const int q = qb + qsub;
+        const bool active = q < nrows;
+        uint8_t *row = lds + q * row_bytes;
+        const uint32_t r = (uint32_t)(r0 + q);
+        for (int t = 0; t < I.NS; ++t) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (active) {
+#pragma unroll
+                    for (int gi = 0; gi < SH::GPT; ++gi) {
+                        const EOGroup &g = gr[c][gi];
+                        const uint32_t own = lds32(row, g.own);
+                        const uint32_t n = eo_unsat(row, g, own);
+                        uint32_t flip;
+                        if (all) {
+                            flip = 0x01010101u;
+                        } else {
+                            const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                            // n >= 3 (dE <= 0) is always accepted
+                            flip = ((n + 0x05050505u) >> 3) & 0x01010101u;
+                            flip |= (u.x < thr[n & 7u] ? 1u : 0u);
+                            flip |= (u.y < thr[(n >> 8) & 7u] ? 1u : 0u) << 8;
+                            flip |= (u.z < thr[(n >> 16) & 7u] ? 1u : 0u) << 16;
+                            flip |= (u.w < thr[(n >> 24) & 7u] ? 1u : 0u) << 24;
+                        }
+                        *reinterpret_cast<uint32_t *>(row + g.own) = own ^ flip;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // energy: every bond joins a colour-0 and a colour-1 site, so the
+        // unsatisfied bonds are the sum of n over colour-0 sites.
+        if (active) {
+            uint32_t part = 0;
+#pragma unroll
+            for (int gi = 0; gi < SH::GPT; ++gi) {
+                const uint32_t own = lds32(row, gr[0][gi].own);
+                const uint32_t n = eo_unsat(row, gr[0][gi], own);
+                part += (n & 0xFFu) + ((n >> 8) & 0xFFu) + ((n >> 16) & 0xFFu) + (n >> 24);
+            }
+            atomicAdd(&unsat[q], (int)part);
+        }
+        __syncthreads();
+    }
+    tile_store(io, lds, r0, nrows, row_bytes);
+    tile_energy_out(I, io, unsat, r0, nrows);
+}
+
+// ---------------------------------------------------------------------------
+// Stand-alone gather of surviving replicas: destination row d of the other
+// buffer receives source row map[d] (spins, energy, family).  Used when the
+// gather is not fused into the next sweep and to materialise a population
+// for export.  koff selects R_{k + koff} as the destination count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *work, int koff)
+{
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k + koff > I.nT || I.status[0] || !*I.mapped) return;
+    const int Rn = (int)I.Rk[k + koff];
+    const int cur = *I.cur;
+    const int rows = min(kRowsPerBlock, Rn - (int)w.row0);
+    if (rows <= 0) return;
+    const int per_row = I.row_bytes >> 4;
+    const uint8_t *src = I.spins[cur];
+    uint8_t *dst = I.spins[cur ^ 1];
+    for (int it = threadIdx.x; it < rows * per_row; it += blockDim.x) {
+        const int q = it / per_row, c = it - q * per_row;
+        const uint32_t d = w.row0 + q;
+        const uint32_t s = I.map[d];
+        *reinterpret_cast<uint4 *>(dst + (size_t)d * I.row_bytes + 16 * c) =
+            *reinterpret_cast<const uint4 *>(src + (size_t)s * I.row_bytes + 16 * c);
+    }
+    for (int q = threadIdx.x; q < rows; q += blockDim.x) {
+        const uint32_t d = w.row0 + q, s = I.map[d];
+        I.E[cur ^ 1][d] = I.E[cur][s];
+        I.fam[cur ^ 1][d] = I.fam[cur][s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void launch_init(const Inst *insts, const Work *work, int nwork, hipStream_t st)
+{
+    if (nwork) k_init<<<nwork, 256, 0, st>>>(insts, work);
+}
+
+void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st)
+{
+    if (nwork) k_energy<<<nwork, 256, 0, st>>>(insts, work, Jraw);
+}
+
+void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes,
+                  hipStream_t st)
+{
+    if (!nwork) return;
+    const size_t lds = (size_t)tile_rows * row_bytes + 32 + 4 * (size_t)tile_rows;
+    switch (variant) {
+    case kSweepLex: k_sweep_lex<<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;
+    case kSweepEO8: k_sweep_eo<8><<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;
+    case kSweepEO16: k_sweep_eo<16><<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;
+    default: break;
+    }
+}
+
+void launch_gather(const Inst *insts, const Work *work, int nwork, int koff, hipStream_t st)
+{
+    if (nwork) k_gather<<<nwork, 256, 0, st>>>(insts, work, koff);
+}
+
+}  // namespace pamc

@@ -1,0 +1,108 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/pamc.h; host-side argument validation returns the documented status
+codes before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pamc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(pamc_[a-z_0-9]+)\s*\(", text))
+    # typedef'd struct names are not functions
+    return sorted(n for n in names if not n.endswith("_t"))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1710_09025_amd import _capi
+
+    return _capi.load()
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for n in ("pamc_create", "pamc_anneal", "pamc_observables", "pamc_get_state", "pamc_set_state",
+              "pamc_batch_create", "pamc_server_submit"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_the_header():
+    from paper_1710_09025_amd import _capi
+
+    assert set(declared_functions()) == set(_capi.SIGNATURES)
+
+
+def test_status_strings(lib):
+    for st in range(0, -9, -1):
+        assert lib.pamc_status_string(st)
+
+
+def test_default_options(lib):
+    from paper_1710_09025_amd import _capi
+
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    assert opt.fuse_gather == 1 and opt.device == -1 and opt.capacity == 0
+
+
+def test_footprint_scales_with_population(lib):
+    a = lib.pamc_footprint(8, 10000, 201, None)
+    b = lib.pamc_footprint(8, 20000, 201, None)
+    assert 0 < a < b
+    # two spin buffers of R_cap rows of N bytes dominate
+    cap = 20000 + int(np.ceil(8 * np.sqrt(20000))) + 64
+    assert b >= 2 * cap * 512
+    assert lib.pamc_footprint(1, 10, 10, None) == -1
+
+
+@pytest.mark.parametrize("case", ["L", "coupling", "beta_order", "beta_nan", "R", "sweeps", "capacity"])
+def test_invalid_arguments_are_rejected_on_the_host(lib, case):
+    from paper_1710_09025_amd import _capi
+
+    L, R, NS = 4, 100, 2
+    J = np.ones((3, 64), dtype=np.int8)
+    beta = np.linspace(0, 1, 5)
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    if case == "L":
+        L = 1
+    elif case == "coupling":
+        J[1, 5] = 0
+    elif case == "beta_order":
+        beta = beta[::-1].copy()
+    elif case == "beta_nan":
+        beta[2] = np.nan
+    elif case == "R":
+        R = 0
+    elif case == "sweeps":
+        NS = 0
+    elif case == "capacity":
+        opt.capacity = 50
+    h = ctypes.c_void_p()
+    st = lib.pamc_create(L, J.ctypes.data_as(ctypes.c_void_p), R, beta.ctypes.data_as(ctypes.c_void_p),
+                         len(beta), NS, 1, ctypes.byref(opt), ctypes.byref(h))
+    assert st == _capi.ERR_INVALID
+    assert not h.value
+    assert lib.pamc_last_error()
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_1710_09025_amd import _capi
+
+    monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_capi, "_lib", None)
+    with pytest.raises(_capi.LibraryMissing):
+        _capi.load()
