@@ -75,6 +75,9 @@ typedef struct pamc_options {
                                 through the copy map; 0: a separate gather
                                 kernel copies them first (same results)      */
     int device;              /* HIP device ordinal; -1 = current device       */
+    int tile_rows;           /* replica rows per sweep workgroup; 0 = the
+                                library's choice for the lattice size (any
+                                value gives identical results)               */
     int timing;              /* 1: record HIP events around the sweep and the
                                 resampling kernels of every step (see
                                 pamc_phase_times); 0 (default): no events   */

@@ -100,7 +100,7 @@ def _torch_available() -> bool:
 
 
 def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
-                  torch_stream=True, torch_allocator=False, keep=None, timing=False):
+                  torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0):
     lib = _capi.load()
     opt = _capi.Options()
     lib.pamc_default_options(ctypes.byref(opt))
@@ -109,6 +109,7 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
         opt.capacity = int(capacity)
     opt.fuse_gather = 1 if fuse_gather else 0
     opt.timing = 1 if timing else 0
+    opt.tile_rows = int(tile_rows)
     if overlap_steps is not None:
         ov = np.ascontiguousarray(overlap_steps, dtype=np.int32)
         keep.append(ov)
@@ -125,7 +126,7 @@ class Pamc:
     """One population-annealing run on the GPU (``pamc_create``)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
-                 fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False):
+                 fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0):
         lib = _capi.load()
         self.L = int(L)
         self.N = self.L ** 3
@@ -135,7 +136,8 @@ class Pamc:
         self._keep = []
         J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
         opt = _make_options(capacity, overlap_steps, fuse_gather, torch_stream=torch_stream,
-                            torch_allocator=torch_allocator, keep=self._keep, timing=timing)
+                            torch_allocator=torch_allocator, keep=self._keep, timing=timing,
+                            tile_rows=tile_rows)
         self._opt = opt
         h = ctypes.c_void_p()
         _check(lib.pamc_create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),

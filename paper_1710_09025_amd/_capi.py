@@ -36,6 +36,7 @@ class Options(ctypes.Structure):
         ("n_overlap_steps", ctypes.c_int),
         ("fuse_gather", ctypes.c_int),
         ("device", ctypes.c_int),
+        ("tile_rows", ctypes.c_int),
         ("timing", ctypes.c_int),
     ]
 

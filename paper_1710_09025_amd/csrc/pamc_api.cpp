@@ -107,7 +107,14 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
         tr = std::min(tr, std::max(1, 16384 / h.row_bytes));
         h.tile_rows = std::max(1, tr);
     } else {
-        h.tile_rows = L == 8 ? 16 : 4;
+        h.tile_rows = L == 8 ? 32 : 8;
+    }
+    if (opt.tile_rows < 0 || opt.tile_rows > 4096) return invalid("tile_rows out of range");
+    if (opt.tile_rows > 0) {
+        // the tile must fit the 64 KB of LDS a workgroup may use
+        if ((int64_t)opt.tile_rows * h.row_bytes + 32 + 4 * opt.tile_rows > 65536)
+            return invalid("tile_rows too large for this lattice");
+        h.tile_rows = opt.tile_rows;
     }
     return PAMC_OK;
 }

@@ -62,6 +62,10 @@ struct Inst {
     uint32_t *loff;     // [Rcap] offset inside the row block
     uint32_t *bsum;     // [nblk]
     uint32_t *boff;     // [nblk]
+    uint32_t *sync;     // [2] workgroups finished in the current sweep / post launch
+    int32_t sweep_tiles;  // workgroups of this instance in a sweep launch
+    int32_t post_blocks;  // workgroups of this instance in a post launch
+    int32_t tile_rows;    // replica rows per sweep workgroup
     uint32_t *hist;     // [nlev] energy histogram, (E + 3N)/2
     uint2 *BF;          // [nlev] (floor(tau), frac(tau) 2^32) per level above E_min
     uint32_t *cnt;      // [R] descendants per family
@@ -89,11 +93,14 @@ struct Inst {
     uint32_t *status;   // bit 0 capacity, bit 1 extinct; word 1: failing step
 };
 
-// Work item of the row-parallel kernels and of the sweep: instance index and
-// first row.
+// Work item of the row-parallel kernels and of the sweep: instance index,
+// first row (or first family id), and the role of a post-kernel workgroup.
+enum PostRole : uint32_t { kRoleCopies = 0, kRoleFamilies = 1, kRoleOverlap = 2 };
 struct Work {
     uint32_t inst;
     uint32_t row0;
+    uint32_t role;
+    uint32_t pad;
 };
 
 // ---------------------------------------------------------------------------

@@ -61,7 +61,7 @@ struct Carve {
 };
 
 struct InstLayout {
-    size_t ctl, status, spins0, spins1, E0, E1, f0, f1, map, ncopy, loff, bsum, boff, hist, BF, cnt, fpart, thr,
+    size_t ctl, status, sync, spins0, spins1, E0, E1, f0, f1, map, ncopy, loff, bsum, boff, hist, BF, cnt, fpart, thr,
         beta, rho, site, grp, jeo, J, Rk, rec, ovl_slot, qhist, total;
 };
 
@@ -83,6 +83,7 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
     InstLayout l{};
     l.ctl = c.take(16);
     l.status = c.take(8);
+    l.sync = c.take(8);
     l.spins0 = c.take((size_t)Rcap * row_bytes);
     l.spins1 = c.take((size_t)Rcap * row_bytes);
     l.E0 = c.take((size_t)Rcap * 4);
@@ -299,6 +300,14 @@ int Runner::upload_inst(int i)
     d.ovl_slot = (int32_t *)(b + lay.ovl_slot);
     d.qhist = (uint32_t *)(b + lay.qhist);
     d.status = (uint32_t *)(b + lay.status);
+    d.sync = (uint32_t *)(b + lay.sync);
+    d.tile_rows = h.tile_rows;
+    d.sweep_tiles = (int32_t)((h.Rcap + h.tile_rows - 1) / h.tile_rows);
+    {
+        const int64_t nchunks = std::max<int64_t>(1, fp2 / 2048);
+        const int64_t novl = (h.Rcap / 2 + kRowsPerBlock - 1) / kRowsPerBlock;
+        d.post_blocks = (int32_t)(d.nblk + nchunks + novl);
+    }
     h.ctl = d.k;
     h.Jdev = (int8_t *)(b + lay.J);
 
@@ -429,18 +438,22 @@ int Runner::build_work(const std::vector<int> &active)
         return p;
     };
     std::map<std::tuple<int, int, int>, std::vector<Work>> groups;
-    std::vector<Work> rows, chunks;
-    std::vector<uint32_t> list, big;
+    std::vector<Work> rows, post;
+    std::vector<uint32_t> list;
     for (int i : active) {
         const HostInst &h = inst_[i];
+        const uint32_t ii = (uint32_t)i;
         auto &g = groups[std::make_tuple(h.variant, h.tile_rows, h.row_bytes)];
-        for (int64_t r = 0; r < h.Rcap; r += h.tile_rows) g.push_back(Work{(uint32_t)i, (uint32_t)r});
-        for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r});
+        for (int64_t r = 0; r < h.Rcap; r += h.tile_rows) g.push_back(Work{ii, (uint32_t)r, 0u, 0u});
+        for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) {
+            rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
+            post.push_back(Work{ii, (uint32_t)r, kRoleCopies, 0u});
+        }
         int64_t fp2 = 1;
         while (fp2 < h.R) fp2 <<= 1;
-        for (int64_t f = 0; f < fp2; f += 2048) chunks.push_back(Work{(uint32_t)i, (uint32_t)f});
-        list.push_back((uint32_t)i);
-        if (fp2 > 2048) big.push_back((uint32_t)i);
+        for (int64_t f = 0; f < fp2; f += 2048) post.push_back(Work{ii, (uint32_t)f, kRoleFamilies, 0u});
+        for (int64_t r = 0; r < h.Rcap / 2; r += kRowsPerBlock) post.push_back(Work{ii, (uint32_t)r, kRoleOverlap, 0u});
+        list.push_back(ii);
     }
     for (auto &kv : groups) {
         SweepGroup sg;
@@ -453,14 +466,12 @@ int Runner::build_work(const std::vector<int> &active)
         sweep_groups_.push_back(sg);
     }
     d_rows_ = (Work *)upload(rows.data(), rows.size() * sizeof(Work));
-    d_chunks_ = (Work *)upload(chunks.data(), chunks.size() * sizeof(Work));
+    d_post_ = (Work *)upload(post.data(), post.size() * sizeof(Work));
     d_list_ = (uint32_t *)upload(list.data(), list.size() * 4);
-    d_biglist_ = (uint32_t *)upload(big.data(), big.size() * 4);
-    if (!d_rows_ || !d_chunks_ || !d_list_ || !d_biglist_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
+    if (!d_rows_ || !d_post_ || !d_list_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
     nrows_work_ = (int)rows.size();
-    nchunks_ = (int)chunks.size();
+    npost_ = (int)post.size();
     nlist_ = (int)list.size();
-    nbig_ = (int)big.size();
     return PAMC_OK;
 }
 
@@ -468,7 +479,7 @@ int Runner::init_instances(const std::vector<int> &slots)
 {
     std::vector<Work> w;
     for (int i : slots)
-        for (int64_t r = 0; r < inst_[i].R; r += kRowsPerBlock) w.push_back(Work{(uint32_t)i, (uint32_t)r});
+        for (int64_t r = 0; r < inst_[i].R; r += kRowsPerBlock) w.push_back(Work{(uint32_t)i, (uint32_t)r, 0u, 0u});
     if (w.empty()) return PAMC_OK;
     Work *d = (Work *)alloc_.get(w.size() * sizeof(Work));
     if (!d) return PAMC_ERR_NOMEM;
@@ -484,11 +495,6 @@ int Runner::init_instances(const std::vector<int> &slots)
 int Runner::enqueue_step()
 {
     if (poisoned_) return PAMC_ERR_DEVICE;
-    bool any_ovl = false;
-    for (int i : active_) {
-        HostInst &h = inst_[i];
-        if (h.k_enq < h.nT && h.ovl_slot[h.k_enq] >= 0) any_ovl = true;
-    }
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (timing_) {
         while (ev_pool_.size() < ev_used_ + 3) {
@@ -502,19 +508,12 @@ int Runner::enqueue_step()
     }
     for (auto &g : sweep_groups_) launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, stream_);
     if (timing_) HIPCHK(hipEventRecord(ev[1], stream_), "hipEventRecord");
-    launch_measure(d_insts_, d_list_, nlist_, stream_);
-    launch_famcount(d_insts_, d_rows_, nrows_work_, stream_);
-    launch_famtree(d_insts_, d_chunks_, nchunks_, stream_);
-    launch_famfinal(d_insts_, d_biglist_, nbig_, stream_);
-    if (any_ovl) launch_overlap(d_insts_, d_rows_, nrows_work_, stream_);
-    launch_copycount(d_insts_, d_rows_, nrows_work_, stream_);
-    launch_scan(d_insts_, d_list_, nlist_, stream_);
+    launch_post(d_insts_, d_post_, npost_, stream_);
     launch_expand(d_insts_, d_rows_, nrows_work_, stream_);
     if (!fuse_) {
-        launch_gather(d_insts_, d_rows_, nrows_work_, 1, stream_);
+        launch_gather(d_insts_, d_rows_, nrows_work_, stream_);
         launch_flip(d_insts_, d_list_, nlist_, stream_);
     }
-    launch_advance(d_insts_, d_list_, nlist_, stream_);
     if (timing_) HIPCHK(hipEventRecord(ev[2], stream_), "hipEventRecord");
     HIPCHK(hipGetLastError(), "step launch");
     for (int i : active_) {
@@ -723,7 +722,7 @@ int Runner::materialise(int i)
     if (st != PAMC_OK) return st;
     if (!ctl[2]) return PAMC_OK;
     std::vector<Work> rows;
-    for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r});
+    for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r, 0u, 0u});
     Work *d = (Work *)alloc_.get(rows.size() * sizeof(Work));
     uint32_t *l = (uint32_t *)alloc_.get(4);
     if (!d || !l) {
@@ -734,7 +733,7 @@ int Runner::materialise(int i)
     const uint32_t idx = (uint32_t)i;
     HIPCHK(hipMemcpy(d, rows.data(), rows.size() * sizeof(Work), hipMemcpyHostToDevice), "upload rows");
     HIPCHK(hipMemcpy(l, &idx, 4, hipMemcpyHostToDevice), "upload list");
-    launch_gather(d_insts_, d, (int)rows.size(), 0, stream_);
+    launch_gather(d_insts_, d, (int)rows.size(), stream_);
     launch_flip(d_insts_, l, 1, stream_);
     HIPCHK(hipGetLastError(), "gather launch");
     HIPCHK(hipStreamSynchronize(stream_), "gather sync");
@@ -824,7 +823,7 @@ int Runner::set_state(int i, const pamc_state *st)
     HIPCHK(hipMemcpy(h.dev.Rk + st->step, &Rk, 4, hipMemcpyHostToDevice), "write Rk");
     // energies from the spins (Eq. (1)) for the imported rows
     std::vector<Work> rows;
-    for (int64_t r = 0; r < R; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r});
+    for (int64_t r = 0; r < R; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r, 0u, 0u});
     Work *d = (Work *)alloc_.get(rows.size() * sizeof(Work));
     if (!d) return PAMC_ERR_NOMEM;
     HIPCHK(hipMemcpy(d, rows.data(), rows.size() * sizeof(Work), hipMemcpyHostToDevice), "upload rows");

@@ -123,13 +123,12 @@ private:
         int nwork;
     };
     std::vector<SweepGroup> sweep_groups_;
-    Work *d_rows_ = nullptr;
+    Work *d_rows_ = nullptr;   // 1024-row blocks (expand, gather)
     int nrows_work_ = 0;
-    Work *d_chunks_ = nullptr;
-    int nchunks_ = 0;
+    Work *d_post_ = nullptr;   // post-launch workgroups with their roles
+    int npost_ = 0;
     uint32_t *d_list_ = nullptr;
-    uint32_t *d_biglist_ = nullptr;  // instances with more than 2048 families
-    int nlist_ = 0, nbig_ = 0;
+    int nlist_ = 0;
     std::vector<void *> work_allocs_;
     std::vector<int> active_;
     // timing: three events per enqueued step (before the sweeps, after the

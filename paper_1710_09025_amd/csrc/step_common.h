@@ -1,0 +1,198 @@
+// step_common.h -- device routines shared by the sweep and resampling
+// kernels: block reductions, the fixed pairwise summation tree, counting
+// with one atomic per distinct address of a wave, the end-of-launch
+// detection of the last workgroup of an instance, and the measurement of a
+// temperature step (paper Sec. II.B: reweighting factors exp[-(beta'-beta)
+// E_i] normalised to the nominal population).
+#pragma once
+#include "pamc_dev.h"
+
+#pragma clang fp contract(off)
+
+namespace pamc {
+
+__device__ __forceinline__ bool inst_live(const Inst &I, int k) { return k < I.nT && I.status[0] == 0; }
+
+// Reduction over the block (any multiple of 64 threads up to 1024); sh holds
+// one value per wave.
+template <typename T, typename Op>
+__device__ __forceinline__ T block_reduce(T v, T *sh, Op op)
+{
+    for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    T r = sh[0];
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 1; i < nw; ++i) r = op(r, sh[i]);
+    __syncthreads();
+    return r;
+}
+
+// Pairwise tree sum of the n = 2^p values a[0..n) held in LDS (destroys a):
+// level by level, node i of the next level is a[2i] + a[2i+1].  n <= blockDim.
+__device__ __forceinline__ double lds_pairwise(double *a, int n)
+{
+    for (; n > 1; n >>= 1) {
+        const int h = n >> 1;
+        double v = 0.0;
+        if ((int)threadIdx.x < h) v = a[2 * threadIdx.x] + a[2 * threadIdx.x + 1];
+        __syncthreads();
+        if ((int)threadIdx.x < h) a[threadIdx.x] = v;
+        __syncthreads();
+    }
+    return a[0];
+}
+
+// Pairwise tree sum of n = 2^p leaves leaf(0..n) with NT threads (n <=
+// 2 NT^2): aligned chunks of 2 NT leaves are subtrees of the global tree;
+// each is folded in LDS, then the chunk roots are folded.  a and roots hold
+// NT doubles each.
+template <int NT, typename Leaf>
+__device__ __forceinline__ double tree_sum(int n, Leaf leaf, double *a, double *roots)
+{
+    const int t = threadIdx.x;
+    if (n == 1) {
+        if (t == 0) a[0] = leaf(0);
+        __syncthreads();
+        const double r = a[0];
+        __syncthreads();
+        return r;
+    }
+    const int chunk = 2 * NT;
+    if (n <= chunk) {
+        a[t] = 2 * t < n ? leaf(2 * t) + leaf(2 * t + 1) : 0.0;
+        __syncthreads();
+        return lds_pairwise(a, n / 2);
+    }
+    const int nchunks = n / chunk;
+    for (int c = 0; c < nchunks; ++c) {
+        a[t] = leaf(c * chunk + 2 * t) + leaf(c * chunk + 2 * t + 1);
+        __syncthreads();
+        const double r = lds_pairwise(a, NT);
+        if (t == 0) roots[c] = r;
+    }
+    __syncthreads();
+    return lds_pairwise(roots, nchunks);
+}
+
+// w[m] = product over the set bits b of m, ascending, of pw[b] = rho^(2^b).
+__device__ __forceinline__ double level_weight(const double *pw, uint32_t m)
+{
+    double x = 1.0;
+    for (int b = 0; m != 0; ++b, m >>= 1)
+        if (m & 1u) x = x * pw[b];
+    return x;
+}
+
+// Adds one count per valid lane to arr[idx], one atomic per distinct index
+// of the wave: at low temperature most replicas share a few energies (and
+// sorted families share ids), and per-lane atomics on one address would
+// serialise.  Every lane of the wave must call it.
+__device__ __forceinline__ void count_wave(uint32_t *arr, uint32_t idx, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t li = __shfl(idx, leader);
+        const uint64_t same = __ballot(valid && idx == li) & pending;
+        if (lane == leader) atomicAdd(&arr[li], (uint32_t)__builtin_popcountll(same));
+        pending &= ~same;
+    }
+}
+
+// Called by every workgroup of an instance at the end of its work in a
+// launch: returns true in exactly one workgroup, the last to finish, after
+// which the writes of all the others are visible to it.
+__device__ __forceinline__ bool last_workgroup(uint32_t *counter, int expected)
+{
+    __shared__ int is_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        is_last = atomicAdd(counter, 1u) == (uint32_t)(expected - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// Measurement of step k after its sweeps, by one workgroup (blockDim a power
+// of two, <= 1024): E_min, E_max, sum E, sum E^2 from the energy histogram
+// (exact integers), and for k < nT-1 the level weights w[m] = exp(-2 dbeta m)
+// as a fixed product of rho^(2^b), their normaliser S by the pairwise tree
+// over 2^ceil(log2(M+1)) levels, and the table (floor(tau), floor(frac(tau)
+// 2^32)) with tau = R w / S.  Clears the histogram and moves the buffer roles
+// on when the sweep wrote the other buffer.  NT is the workgroup size.
+template <int NT>
+__device__ void measure_step(const Inst &I, int k)
+{
+    __shared__ int64_t sh64[16];
+    __shared__ int32_t sh32[16];
+    __shared__ double tree[NT];
+    __shared__ double roots[NT];
+    __shared__ double pw[40];
+    const int N3 = 3 * I.N;
+    int64_t s1 = 0, s2 = 0;
+    int32_t lmin = 0x7FFFFFFF, lmax = -1;
+    for (int m = threadIdx.x; m < I.nlev; m += blockDim.x) {
+        const uint32_t c = I.hist[m];
+        if (c) {
+            const int64_t e = 2 * m - N3;
+            s1 += (int64_t)c * e;
+            s2 += (int64_t)c * e * e;
+            lmin = min(lmin, m);
+            lmax = max(lmax, m);
+        }
+    }
+    s1 = block_reduce<int64_t>(s1, sh64, [](int64_t a, int64_t b) { return a + b; });
+    s2 = block_reduce<int64_t>(s2, sh64, [](int64_t a, int64_t b) { return a + b; });
+    lmin = block_reduce<int32_t>(lmin, sh32, [](int32_t a, int32_t b) { return min(a, b); });
+    lmax = block_reduce<int32_t>(lmax, sh32, [](int32_t a, int32_t b) { return max(a, b); });
+    StepRec *rec = I.rec + k;
+    if (threadIdx.x == 0) {
+        rec->R = I.Rk[k];
+        rec->sumE = s1;
+        rec->sumE2 = s2;
+        rec->Emin = 2 * lmin - N3;
+        rec->Emax = 2 * lmax - N3;
+        rec->S = __builtin_nan("");
+    }
+    if (k < I.nT - 1) {
+        if (threadIdx.x == 0) {
+            pw[0] = I.rho[k];
+            for (int b = 1; b < 40; ++b) pw[b] = pw[b - 1] * pw[b - 1];
+        }
+        __syncthreads();
+        const int nl = lmax - lmin + 1;
+        int P = 1;
+        while (P < nl) P <<= 1;
+        const double S = tree_sum<NT>(
+            P,
+            [&](int m) { return m < nl ? (double)I.hist[lmin + m] * level_weight(pw, (uint32_t)m) : 0.0; },
+            tree, roots);
+        const double Rd = (double)I.R;
+        for (int m = threadIdx.x; m < nl; m += blockDim.x) {
+            const double tau = (Rd * level_weight(pw, (uint32_t)m)) / S;
+            const double fl = __builtin_floor(tau);
+            uint2 bf;
+            bf.x = (uint32_t)fl;
+            bf.y = (uint32_t)__builtin_floor((tau - fl) * 4294967296.0);
+            I.BF[m] = bf;
+        }
+        if (threadIdx.x == 0) rec->S = S;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < I.nlev; m += blockDim.x) I.hist[m] = 0u;
+    // the sweep of this step moved the population to the other buffer
+    if (threadIdx.x == 0 && *I.mapped) {
+        *I.cur ^= 1;
+        *I.mapped = 0;
+    }
+}
+
+}  // namespace pamc

@@ -5,15 +5,19 @@
 // current temperature on chip, recomputes each replica's energy (Eq. (1))
 // from the final spins, and writes the rows back once.  When the previous
 // resampling left a copy map, the tile is read through it, so the gather of
-// surviving replicas costs no separate pass over HBM.
+// surviving replicas costs no separate pass over HBM.  The epilogue adds the
+// tile to the energy histogram and the family counts; the last workgroup of
+// an instance to finish then measures the step and prepares the resampling
+// table (measure_step).
 //
 // Random numbers: the draw for a site of colour c whose rank among the
 // sites of that colour is i, in replica row r, step k and sweep t, is word
 // (i & 3) of Philox4x32-10 at counter ((c << 24) | (i >> 2), r, k,
 // TAG_SWEEP | t) under the run's key.  Acceptance for dE > 0 is u < T_k(dE)
 // with uint32 thresholds prepared on the host.
-#include "pamc_dev.h"
 #include "launch.h"
+#include "pamc_dev.h"
+#include "step_common.h"
 
 namespace pamc {
 
@@ -140,11 +144,34 @@ __device__ __forceinline__ void tile_store(const TileIO &io, const uint8_t *tile
 // Energy -> histogram bin and stored energy, for the rows of the tile.
 __device__ __forceinline__ void tile_energy_out(const Inst &I, const TileIO &io, const int *unsat, int r0, int nrows)
 {
-    for (int q = threadIdx.x; q < nrows; q += blockDim.x) {
-        const int E = 2 * unsat[q] - 3 * I.N;
-        io.Edst[r0 + q] = E;
-        atomicAdd(&I.hist[(E + 3 * I.N) >> 1], 1u);
+    for (int base = 0; base < nrows; base += blockDim.x) {
+        const int q = base + (int)threadIdx.x;
+        const bool valid = q < nrows;
+        int E = 0;
+        if (valid) {
+            E = 2 * unsat[q] - 3 * I.N;
+            io.Edst[r0 + q] = E;
+        }
+        count_wave(I.hist, (uint32_t)((E + 3 * I.N) >> 1), valid);
     }
+}
+
+// Descendants per family: the tile's rows counted under their family ids.
+__device__ __forceinline__ void tile_family_count(const Inst &I, const TileIO &io, int r0, int nrows)
+{
+    for (int base = 0; base < nrows; base += blockDim.x) {
+        const int q = base + (int)threadIdx.x;
+        const bool valid = q < nrows;
+        uint32_t f = 0;
+        if (valid) f = io.map ? io.fsrc[io.map[r0 + q]] : io.fsrc[r0 + q];
+        count_wave(I.cnt, f, valid);
+    }
+}
+
+// End of a sweep workgroup: the last one of the instance measures the step.
+__device__ __forceinline__ void sweep_done(const Inst &I, int k)
+{
+    if (last_workgroup(&I.sync[0], I.sweep_tiles)) measure_step<256>(I, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -153,6 +180,8 @@ __device__ __forceinline__ void tile_energy_out(const Inst &I, const TileIO &io,
 // consecutive sites of one colour) of one replica of the tile; per site the
 // six neighbours and the couplings come from a per-site record.
 // ---------------------------------------------------------------------------
+__device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows);
+
 __global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work *work, int tile_rows)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -163,7 +192,12 @@ __global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows <= 0) return;
+    if (nrows > 0) sweep_tile_lex(I, k, lds, r0, nrows, tile_rows);
+    sweep_done(I, k);
+}
+
+__device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+{
     const int row_bytes = I.row_bytes;
     int *unsat = reinterpret_cast<int *>(lds + tile_rows * row_bytes);
     const TileIO io = tile_io(I);
@@ -222,6 +256,7 @@ __global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work
     __syncthreads();
     tile_store(io, lds, r0, nrows, row_bytes);
     tile_energy_out(I, io, unsat, r0, nrows);
+    tile_family_count(I, io, r0, nrows);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,10 +276,28 @@ struct EOShape {
     static constexpr int H = L / 2;        // sites per half row
     static constexpr int GPR = L / 8;      // Philox blocks per half row
     static constexpr int G = N / 8;        // Philox blocks per colour
-    static constexpr int TPR = G < 256 ? G : 256;  // threads per replica
+    // two Philox blocks per thread and colour (independent work to overlap
+    // LDS latency); a replica fits in one wave when TPR <= 64
+    static constexpr int TPR = G / 2 < 256 ? G / 2 : 256;  // threads per replica
     static constexpr int RP = 256 / TPR;   // replicas swept at once
     static constexpr int GPT = G / TPR;    // blocks per thread per colour
+    static constexpr bool kWaveLocal = TPR <= 64;
 };
+
+// Orders the LDS accesses of the threads sweeping one replica between two
+// colours.  When a replica lives inside one wave, the wave's LDS operations
+// complete in issue order, so a compiler fence and wave barrier suffice.
+template <bool kWaveLocal>
+__device__ __forceinline__ void colour_barrier()
+{
+    if constexpr (kWaveLocal) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
 
 struct EOGroup {
     uint32_t own, hi, lo, yp, ym, zp, zm;  // LDS byte offsets within a row
@@ -296,9 +349,11 @@ __device__ __forceinline__ uint32_t eo_unsat(const uint8_t *row, const EOGroup &
 }
 
 template <int L>
+__device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows);
+
+template <int L>
 __global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work *work, int tile_rows)
 {
-    using SH = EOShape<L>;
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
     const Inst &I = inst_ref(insts, w.inst);
@@ -307,7 +362,14 @@ __global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work 
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows <= 0) return;
+    if (nrows > 0) sweep_tile_eo<L>(I, k, lds, r0, nrows, tile_rows);
+    sweep_done(I, k);
+}
+
+template <int L>
+__device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+{
+    using SH = EOShape<L>;
     const int row_bytes = I.row_bytes;
     uint32_t *thr = reinterpret_cast<uint32_t *>(lds + tile_rows * row_bytes);  // [8]
     int *unsat = reinterpret_cast<int *>(thr + 8);
@@ -357,7 +419,7 @@ __global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work 
                         *reinterpret_cast<uint32_t *>(row + g.own) = own ^ flip;
                     }
                 }
-                __syncthreads();
+                colour_barrier<SH::kWaveLocal>();
             }
         }
         // energy: every bond joins a colour-0 and a colour-1 site, so the
@@ -376,21 +438,22 @@ __global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work 
     }
     tile_store(io, lds, r0, nrows, row_bytes);
     tile_energy_out(I, io, unsat, r0, nrows);
+    tile_family_count(I, io, r0, nrows);
 }
 
 // ---------------------------------------------------------------------------
 // Stand-alone gather of surviving replicas: destination row d of the other
 // buffer receives source row map[d] (spins, energy, family).  Used when the
 // gather is not fused into the next sweep and to materialise a population
-// for export.  koff selects R_{k + koff} as the destination count.
+// for export.  Runs after the step index has moved to the new population.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *work, int koff)
+__global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *work)
 {
     const Work w = work[blockIdx.x];
     const Inst &I = inst_ref(insts, w.inst);
     const int k = *I.k;
-    if (k + koff > I.nT || I.status[0] || !*I.mapped) return;
-    const int Rn = (int)I.Rk[k + koff];
+    if (k >= I.nT || I.status[0] || !*I.mapped) return;
+    const int Rn = (int)I.Rk[k];
     const int cur = *I.cur;
     const int rows = min(kRowsPerBlock, Rn - (int)w.row0);
     if (rows <= 0) return;
@@ -437,9 +500,9 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     }
 }
 
-void launch_gather(const Inst *insts, const Work *work, int nwork, int koff, hipStream_t st)
+void launch_gather(const Inst *insts, const Work *work, int nwork, hipStream_t st)
 {
-    if (nwork) k_gather<<<nwork, 256, 0, st>>>(insts, work, koff);
+    if (nwork) k_gather<<<nwork, 256, 0, st>>>(insts, work);
 }
 
 }  // namespace pamc
