@@ -47,11 +47,17 @@ HBM_PEAK_GBS = 8000.0
 ALU_OPS_PER_ATTEMPT = 16.75
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_counters.json")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_1710_09025_amd", "csrc", "sweep.hip")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_1710_09025_amd", "csrc", f)
+                 for f in ("sweep.hip", "step_common.h", "pamc_dev.h")]
 
 
 def source_hash() -> str:
-    return hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()[:16]
+    """Hash of the sources that define the sweep kernel; the committed HBM
+    counters apply only while it is unchanged."""
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def workload_inputs(name):
@@ -65,18 +71,18 @@ def attempts_of(obs, N, sweeps):
     return float(np.sum(obs["R"][obs["measured"] == 1])) * N * sweeps
 
 
-def time_anneals(name, steps, warmup, timing=True):
-    """Creates warmup + steps run handles up front, anneals them one after
-    another; returns wall time of the timed anneals and per-phase device
-    times."""
+def time_anneals(name, steps, warmup):
+    """Creates warmup + steps run handles up front (default options: each
+    temperature step is a replayed hipGraph) and anneals them one after
+    another for the wall time; one more anneal with HIP events around every
+    step's sweep launch gives the per-kernel device time."""
     import torch
 
     from paper_1710_09025_amd import Pamc
 
     cfg, J, beta = workload_inputs(name)
     N = cfg["L"] ** 3
-    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=timing)
-            for _ in range(warmup + steps)]
+    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"]) for _ in range(warmup + steps)]
     for r in runs[:warmup]:
         assert r.anneal() == 0
     torch.cuda.synchronize()
@@ -86,29 +92,27 @@ def time_anneals(name, steps, warmup, timing=True):
         assert st == 0, st
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    sweep_ms = other_ms = 0.0
-    nsteps = 0
-    if timing:
-        for r in runs[warmup:]:
-            a, b, n = r.phase_times()
-            sweep_ms += a
-            other_ms += b
-            nsteps += n
     obs = runs[-1].observables()
-    att = attempts_of(obs, N, cfg["sweeps"])
-    Rbar = float(np.mean(obs["R"]))
     for r in runs:
         r.close()
     del runs
+    timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True)
+    assert timed.anneal() == 0
+    sweep_ms, other_ms, nsteps = timed.phase_times()
+    obs_t = timed.observables()
+    for key in ("R", "sum_E", "sum_E2"):
+        assert np.array_equal(obs[key], obs_t[key]), "timed and graph runs differ"
+    timed.close()
     torch.cuda.empty_cache()
+    att = attempts_of(obs, N, cfg["sweeps"])
+    Rbar = float(np.mean(obs["R"]))
     return dict(cfg=cfg, wall_s=t1 - t0, sweep_ms=sweep_ms, other_ms=other_ms, nsteps=nsteps,
                 attempts_per_anneal=att, mean_R=Rbar, N=N)
 
 
 def roofline(res):
-    K = res["nsteps"] / res["cfg"]["n_temps"]
     sweep_s = res["sweep_ms"] / 1e3
-    ops = ALU_OPS_PER_ATTEMPT * res["attempts_per_anneal"] * K
+    ops = ALU_OPS_PER_ATTEMPT * res["attempts_per_anneal"]
     achieved = ops / sweep_s / 1e12
     traffic = None
     if os.path.exists(COUNTERS_FILE):
@@ -123,7 +127,8 @@ def roofline(res):
     alg_bytes = 2.0 * res["mean_R"] * rb + 16.0 * res["mean_R"]  # tile in + out, map/E/family
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
             "unit": "Tops/s (int32 VALU)", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
-            "kernel": "k_sweep_eo (N_S sweeps of every replica at one temperature)",
+            "kernel": f"k_sweep_eo<{res['cfg']['L']}> (N_S sweeps of every replica at one temperature)"
+                      if res["cfg"]["L"] in (8, 16) else "k_sweep_lex",
             "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
             "avg_launch_ms": round(res["sweep_ms"] / max(1, res["nsteps"]), 4),
             "hbm_gbs_algorithmic": round(alg_bytes / (res["sweep_ms"] / max(1, res["nsteps"]) / 1e3) / 1e9, 1),
@@ -149,6 +154,97 @@ def cpu_baseline(name, n_steps):
                       f"(full population R={cfg['R']}, L={cfg['L']}), {t1 - t0:.1f} s"}
 
 
+def batch_bench(n_inst, plain_per_L):
+    """Mixed-size batch: all instances annealed together (graph-replayed
+    steps) against separate per-instance runs on a stratified sample."""
+    import torch
+
+    from paper_1710_09025_amd import Pamc, PamcBatch
+
+    insts = pi.batch_instances(n_inst)
+    att = sum(float(d["R"]) * d["L"] ** 3 * d["sweeps"] * len(d["beta"]) for d in insts)
+    t0 = time.perf_counter()
+    b = PamcBatch(insts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = b.anneal()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert st == 0, st
+    # attempts actually run: sum_k R_k N N_S over every instance
+    att_run = 0.0
+    for i in range(0, n_inst):
+        o = b.observables(i)
+        att_run += float(np.sum(o["R"])) * insts[i]["L"] ** 3 * insts[i]["sweeps"]
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    # per-instance runs: plain_per_L instances of each size, one after another
+    per_L = {}
+    for L in sorted({d["L"] for d in insts}):
+        sample = [d for d in insts if d["L"] == L][:plain_per_L]
+        ts, tc = [], []
+        for d in sample:
+            c0 = time.perf_counter()
+            p = Pamc(d["L"], d["couplings"], d["R"], d["beta"], d["sweeps"], d["seed"])
+            torch.cuda.synchronize()
+            c1 = time.perf_counter()
+            assert p.anneal() == 0
+            torch.cuda.synchronize()
+            c2 = time.perf_counter()
+            p.close()
+            ts.append(c2 - c1)
+            tc.append(c2 - c0)
+        per_L[L] = (float(np.mean(ts)), float(np.mean(tc)), len(sample))
+    count = {L: sum(1 for d in insts if d["L"] == L) for L in per_L}
+    plain_anneal = sum(count[L] * per_L[L][0] for L in per_L)
+    plain_total = sum(count[L] * per_L[L][1] for L in per_L)
+    return {
+        "instances": n_inst,
+        "batched_instances_per_s": round(n_inst / (t2 - t1), 3),
+        "batched_instances_per_s_incl_create": round(n_inst / (t2 - t0), 3),
+        "batched_attempts_per_ns": round(att_run / ((t2 - t1) * 1e9), 3),
+        "batched_anneal_s": round(t2 - t1, 3),
+        "plain_instances_per_s": round(n_inst / plain_anneal, 3),
+        "plain_instances_per_s_incl_create": round(n_inst / plain_total, 3),
+        "plain_sample": f"{plain_per_L} per L, extrapolated by instance count",
+        "speedup": round(plain_anneal / (t2 - t1), 3),
+    }
+
+
+def serve_bench(n_req, rate, budget_gb):
+    """Poisson request stream replayed in real time against the serving loop."""
+    from paper_1710_09025_amd import PamcServer
+
+    reqs = pi.serving_requests(n_req, rate=rate)
+    srv = PamcServer(int(budget_gb * (1 << 30)), max_active=256)
+    ids = []
+    t0 = time.perf_counter()
+    for d in reqs:
+        now = time.perf_counter() - t0
+        if d["arrival"] > now:
+            time.sleep(d["arrival"] - now)
+        ids.append(srv.submit(d["L"], d["couplings"], d["R"], d["beta"], d["sweeps"], d["seed"]))
+    lat = []
+    last = 0.0
+    first = None
+    for rid in ids:
+        st, _, tm = srv.wait(rid, timeout=1200)
+        assert st == 0, st
+        lat.append(tm["finish"] - tm["submit"])
+        last = max(last, tm["finish"])
+        first = tm["submit"] if first is None else min(first, tm["submit"])
+    srv.close()
+    lat = np.array(lat)
+    att = sum(float(d["R"]) * d["L"] ** 3 * d["sweeps"] * len(d["beta"]) for d in reqs)
+    span = last - first
+    return {"requests": n_req, "offered_rate_per_s": rate, "hbm_budget_gb": budget_gb,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "instances_per_s": round(n_req / span, 3),
+            "attempts_per_ns": round(att / (span * 1e9), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,7 +254,26 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16, help="temperature steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--batch", type=int, default=2000, help="instances of the mixed-size batch (0: skip)")
+    ap.add_argument("--batch-plain", type=int, default=5, help="per-instance runs per L for the comparison")
+    ap.add_argument("--serve", type=int, default=300, help="requests of the serving stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -192,7 +307,7 @@ def main():
                                f"beta linear 0->{cfg['beta_max']}, N_S={cfg['sweeps']}, one instance",
                    "L": cfg["L"], "R": cfg["R"], "n_temps": cfg["n_temps"], "sweeps": cfg["sweeps"],
                    "step": "one complete anneal", "spins": "int8"},
-        "sweep_attempts_per_ns": round(res["attempts_per_anneal"] * args.steps / (res["sweep_ms"] * 1e6), 3),
+        "sweep_attempts_per_ns": round(res["attempts_per_anneal"] / (res["sweep_ms"] * 1e6), 3),
         "sweep_share": round(res["sweep_ms"] / (res["sweep_ms"] + res["other_ms"]), 4),
         "roofline": roofline(res),
     }
@@ -206,10 +321,14 @@ def main():
             r = time_anneals(name, k, w)
             extra[name] = {
                 "attempts_per_ns": round(r["attempts_per_anneal"] * k / (r["wall_s"] * 1e9), 3),
-                "sweep_attempts_per_ns": round(r["attempts_per_anneal"] * k / (r["sweep_ms"] * 1e6), 3),
+                "sweep_attempts_per_ns": round(r["attempts_per_anneal"] / (r["sweep_ms"] * 1e6), 3),
                 "ms_per_anneal": round(r["wall_s"] / k * 1e3, 3),
                 "sweep_share": round(r["sweep_ms"] / (r["sweep_ms"] + r["other_ms"]), 4),
             }
+        if args.batch:
+            extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
+        if args.serve:
+            extra["serving"] = serve_bench(args.serve, args.serve_rate, args.serve_budget_gb)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

@@ -78,6 +78,9 @@ typedef struct pamc_options {
     int tile_rows;           /* replica rows per sweep workgroup; 0 = the
                                 library's choice for the lattice size (any
                                 value gives identical results)               */
+    int graphs;              /* 1 (default): capture one temperature step in
+                                a hipGraph and replay it for every step (not
+                                with timing = 1); 0: launch kernels directly */
     int timing;              /* 1: record HIP events around the sweep and the
                                 resampling kernels of every step (see
                                 pamc_phase_times); 0 (default): no events   */

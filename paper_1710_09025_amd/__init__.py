@@ -100,7 +100,8 @@ def _torch_available() -> bool:
 
 
 def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
-                  torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0):
+                  torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0,
+                  graphs=True):
     lib = _capi.load()
     opt = _capi.Options()
     lib.pamc_default_options(ctypes.byref(opt))
@@ -110,6 +111,7 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     opt.fuse_gather = 1 if fuse_gather else 0
     opt.timing = 1 if timing else 0
     opt.tile_rows = int(tile_rows)
+    opt.graphs = 1 if graphs else 0
     if overlap_steps is not None:
         ov = np.ascontiguousarray(overlap_steps, dtype=np.int32)
         keep.append(ov)
@@ -126,7 +128,8 @@ class Pamc:
     """One population-annealing run on the GPU (``pamc_create``)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
-                 fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0):
+                 fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
+                 graphs=True):
         lib = _capi.load()
         self.L = int(L)
         self.N = self.L ** 3
@@ -137,7 +140,7 @@ class Pamc:
         J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
         opt = _make_options(capacity, overlap_steps, fuse_gather, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
-                            tile_rows=tile_rows)
+                            tile_rows=tile_rows, graphs=graphs)
         self._opt = opt
         h = ctypes.c_void_p()
         _check(lib.pamc_create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),
@@ -234,7 +237,7 @@ class Pamc:
 class PamcBatch:
     """Many independent instances annealed together (``pamc_batch_*``)."""
 
-    def __init__(self, instances, fuse_gather=True, torch_stream=True):
+    def __init__(self, instances, fuse_gather=True, torch_stream=True, graphs=True):
         lib = _capi.load()
         self._keep = []
         n = len(instances)
@@ -250,7 +253,7 @@ class PamcBatch:
                                     int(d["seed"]) & (2**64 - 1))
             self.nT.append(len(b))
             self.N.append(L ** 3)
-        opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep)
+        opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs)
         h = ctypes.c_void_p()
         _check(lib.pamc_batch_create(n, arr, ctypes.byref(opt), ctypes.byref(h)), "pamc_batch_create")
         self._h = h

@@ -37,6 +37,7 @@ class Options(ctypes.Structure):
         ("fuse_gather", ctypes.c_int),
         ("device", ctypes.c_int),
         ("tile_rows", ctypes.c_int),
+        ("graphs", ctypes.c_int),
         ("timing", ctypes.c_int),
     ]
 

@@ -139,6 +139,7 @@ void pamc_default_options(pamc_options *opt)
     std::memset(opt, 0, sizeof(*opt));
     opt->spin_format = PAMC_SPINS_INT8;
     opt->fuse_gather = 1;
+    opt->graphs = 1;
     opt->device = -1;
 }
 

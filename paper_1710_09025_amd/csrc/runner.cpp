@@ -128,6 +128,7 @@ Runner::~Runner()
         if (used_[i]) alloc_.put(inst_[i].block);
     for (void *p : work_allocs_) alloc_.put(p);
     for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
+    drop_graph();
     alloc_.put(d_insts_);
     alloc_.put(d_nlnn_);
     alloc_.put(d_Jptr_);
@@ -154,6 +155,7 @@ int Runner::setup(const pamc_options &opt, int max_slots)
     alloc_.user = opt.alloc_user;
     fuse_ = opt.fuse_gather != 0;
     timing_ = opt.timing != 0;
+    graphs_ = opt.graphs != 0 && !timing_;
     max_slots_ = max_slots;
     if (opt.device >= 0) HIPCHK(hipSetDevice(opt.device), "hipSetDevice");
     HIPCHK(hipGetDevice(&device_), "hipGetDevice");
@@ -426,6 +428,7 @@ int Runner::upload_inst(int i)
 int Runner::build_work(const std::vector<int> &active)
 {
     HIPCHK(hipStreamSynchronize(stream_), "build_work sync");
+    drop_graph();
     for (void *p : work_allocs_) alloc_.put(p);
     work_allocs_.clear();
     sweep_groups_.clear();
@@ -492,29 +495,57 @@ int Runner::init_instances(const std::vector<int> &slots)
     return PAMC_OK;
 }
 
-int Runner::enqueue_step()
+void Runner::drop_graph()
 {
-    if (poisoned_) return PAMC_ERR_DEVICE;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    if (timing_) {
-        while (ev_pool_.size() < ev_used_ + 3) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e), "hipEventCreate");
-            ev_pool_.push_back(e);
-        }
-        for (int j = 0; j < 3; ++j) ev[j] = ev_pool_[ev_used_ + j];
-        ev_used_ += 3;
-        HIPCHK(hipEventRecord(ev[0], stream_), "hipEventRecord");
-    }
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    graph_exec_ = nullptr;
+    graph_ = nullptr;
+}
+
+// The kernels of one temperature step, for every active instance.  Their
+// arguments do not change from step to step (the step index and the
+// population size live on the device), so the sequence can be captured once.
+int Runner::launch_step_kernels()
+{
     for (auto &g : sweep_groups_) launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, stream_);
-    if (timing_) HIPCHK(hipEventRecord(ev[1], stream_), "hipEventRecord");
+    if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 2], stream_), "hipEventRecord");
     launch_post(d_insts_, d_post_, npost_, stream_);
     launch_expand(d_insts_, d_rows_, nrows_work_, stream_);
     if (!fuse_) {
         launch_gather(d_insts_, d_rows_, nrows_work_, stream_);
         launch_flip(d_insts_, d_list_, nlist_, stream_);
     }
-    if (timing_) HIPCHK(hipEventRecord(ev[2], stream_), "hipEventRecord");
+    return PAMC_OK;
+}
+
+int Runner::enqueue_step()
+{
+    if (poisoned_) return PAMC_ERR_DEVICE;
+    if (timing_) {
+        while (ev_pool_.size() < ev_used_ + 3) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e), "hipEventCreate");
+            ev_pool_.push_back(e);
+        }
+        ev_used_ += 3;
+        HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 3], stream_), "hipEventRecord");
+    }
+    if (graphs_) {
+        if (!graph_exec_) {
+            HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            launch_step_kernels();
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamEndCapture(stream_, &g), "hipStreamEndCapture");
+            graph_ = g;
+            HIPCHK(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+        HIPCHK(hipGraphLaunch(graph_exec_, stream_), "hipGraphLaunch");
+    } else {
+        int st = launch_step_kernels();
+        if (st != PAMC_OK) return st;
+    }
+    if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 1], stream_), "hipEventRecord");
     HIPCHK(hipGetLastError(), "step launch");
     for (int i : active_) {
         HostInst &h = inst_[i];

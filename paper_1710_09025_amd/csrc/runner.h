@@ -131,6 +131,12 @@ private:
     int nlist_ = 0;
     std::vector<void *> work_allocs_;
     std::vector<int> active_;
+    // one captured temperature step, replayed for every step
+    bool graphs_ = true;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
+    void drop_graph();
+    int launch_step_kernels();
     // timing: three events per enqueued step (before the sweeps, after the
     // sweeps, after the step), reused from a pool
     bool timing_ = false;

@@ -83,6 +83,27 @@ def test_separate_gather_equals_fused(L):
         np.testing.assert_array_equal(oa[key], ob[key])
 
 
+def test_graph_replay_equals_direct_launches_every_step():
+    """The captured step is replayed once per temperature; after every replay
+    (with eager exports and synchronisation in between) the state equals the
+    state of a run that launches the kernels directly."""
+    inst = instance(6, 700, 12, 3, 4.0, disorder_seed=6, seed=12)
+    from paper_1710_09025_amd import Pamc
+
+    a = Pamc(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"], graphs=True)
+    b = Pamc(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"], graphs=False)
+    c = Pamc(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"], timing=True)
+    for k in range(len(inst["beta"])):
+        for p in (a, b, c):
+            assert p.anneal(1) == 0
+        sa = a.get_state()
+        compare_state(sa, b.get_state(), f"graph vs direct, step {k}")
+        compare_state(sa, c.get_state(), f"graph vs timed, step {k}")
+    oa, ob = a.observables(), b.observables()
+    for key in ("R", "sum_E", "lnZ", "S_f", "g_SG"):
+        np.testing.assert_array_equal(oa[key], ob[key])
+
+
 def test_torch_allocator_and_stream_give_same_result():
     inst = instance(8, 500, 11, 4, 4.0, disorder_seed=4, seed=6)
     a, _ = gpu_run(inst, torch_stream=False)
