@@ -6,13 +6,16 @@
 
 namespace pamc {
 
-enum SweepVariant { kSweepLex = 0, kSweepEO8 = 1, kSweepEO16 = 2 };
+enum SweepVariant { kSweepLex = 0, kSweepEO8 = 1, kSweepEO16 = 2, kSweepCM2 = 3, kSweepCM3 = 4 };
+
+// replicas swept at once by a colour-major workgroup with tpr threads each
+int cm_replicas_per_block(int tpr);
 
 void launch_init(const Inst *insts, const Work *work, int nwork, hipStream_t st);
 void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st);
 // sweeps of one temperature step; the last workgroup of each instance also
 // measures the step and prepares its resampling table
-void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes,
+void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
                   hipStream_t st);
 // copy counts, family entropy, overlap; the last workgroup of each instance
 // finishes the prefix sum and advances the step

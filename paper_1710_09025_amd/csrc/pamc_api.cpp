@@ -63,12 +63,14 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     if (cap >= ((int64_t)1 << 31) - 1024) return invalid("capacity must stay below 2^31");
     if (opt.spin_format != PAMC_SPINS_INT8 && opt.spin_format != PAMC_SPINS_PACKED)
         return invalid("unknown spin format");
+    const pamc::LayoutInfo li = pamc::layout_for(L);
     h.L = L;
     h.N = N;
-    h.ncol = (L & 1) ? 3 : 2;
-    h.layout = pamc::choose_layout(L);
-    h.variant = h.layout == pamc::kLayoutLex ? pamc::kSweepLex : (L == 8 ? pamc::kSweepEO8 : pamc::kSweepEO16);
-    h.row_bytes = (N + 15) & ~15;
+    h.ncol = li.ncol;
+    h.layout = li.layout;
+    h.variant = li.variant;
+    h.row_bytes = li.row_bytes;
+    h.tpr = li.tpr;
     h.R = R;
     h.Rcap = cap;
     h.nT = nT;
@@ -88,32 +90,22 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
         h.ovl_slot[nT - 1] = h.ovl_n++;
     }
     if (h.variant == pamc::kSweepLex) {
-        int ncs[3] = {0, 0, 0};
-        for (int z = 0; z < L; ++z)
-            for (int y = 0; y < L; ++y)
-                for (int x = 0; x < L; ++x) {
-                    int c;
-                    if ((L & 1) == 0)
-                        c = (x + y + z) & 1;
-                    else {
-                        auto g = [L](int v) { return v == L - 1 ? 2 : (v & 1); };
-                        c = (g(x) + g(y) + g(z)) % 3;
-                    }
-                    ncs[c]++;
-                }
-        int gmax = 1;
-        for (int c = 0; c < 3; ++c) gmax = std::max(gmax, (ncs[c] + 3) / 4);
-        int tr = (512 + gmax - 1) / gmax;
+        int tr = (512 + li.gmax - 1) / li.gmax;
         tr = std::min(tr, std::max(1, 16384 / h.row_bytes));
         h.tile_rows = std::max(1, tr);
-    } else {
+    } else if (h.variant == pamc::kSweepEO8 || h.variant == pamc::kSweepEO16) {
         h.tile_rows = L == 8 ? 32 : 8;
+    } else {
+        // colour-major: four passes of the replicas a workgroup sweeps at once
+        h.tile_rows = 4 * pamc::cm_replicas_per_block(h.tpr);
     }
     if (opt.tile_rows < 0 || opt.tile_rows > 4096) return invalid("tile_rows out of range");
     if (opt.tile_rows > 0) {
-        // the tile must fit the 64 KB of LDS a workgroup may use
-        if ((int64_t)opt.tile_rows * h.row_bytes + 32 + 4 * opt.tile_rows > 65536)
-            return invalid("tile_rows too large for this lattice");
+        // the workgroup's LDS (at most 64 KB) must hold its tile
+        const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3;
+        const int64_t lds = cm ? 2 * (int64_t)h.row_bytes * pamc::cm_replicas_per_block(h.tpr) + 32 + 4 * opt.tile_rows
+                               : (int64_t)opt.tile_rows * h.row_bytes + 32 + 4 * opt.tile_rows;
+        if (lds > 65536) return invalid("tile_rows too large for this lattice");
         h.tile_rows = opt.tile_rows;
     }
     return PAMC_OK;

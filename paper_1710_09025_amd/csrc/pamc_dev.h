@@ -26,9 +26,16 @@ enum Layout : int32_t {
     // so that four sites of one colour sharing a Philox block are one
     // aligned 32-bit word, and so are their y, z and one x neighbour.
     kLayoutEO = 1,
+    // byte per site, colour-major: the sites of colour 0 in lexicographic
+    // order, then colour 1 (and 2 for odd L), each colour padded to a
+    // multiple of four, so the four sites of one Philox block are one
+    // aligned 32-bit word for every L.
+    kLayoutCM = 2,
 };
 
 constexpr int kRowsPerBlock = 1024;  // rows handled per block by row kernels
+constexpr int kOvlPairs = 256;       // replica pairs per overlap workgroup
+constexpr int kOvlLdsBins = 8194;    // overlap histograms up to this many bins (L <= 16) are built in LDS
 
 // Per-step integer record written on the device.
 struct StepRec {
@@ -58,8 +65,7 @@ struct Inst {
     uint32_t *fam[2];
     // resampling scratch
     uint32_t *map;      // [Rcap] destination row -> source row
-    uint32_t *ncopy;    // [Rcap]
-    uint32_t *loff;     // [Rcap] offset inside the row block
+    uint32_t *loff;     // [Rcap] first destination of each row inside its row block
     uint32_t *bsum;     // [nblk]
     uint32_t *boff;     // [nblk]
     uint32_t *sync;     // [2] workgroups finished in the current sweep / post launch
@@ -78,6 +84,14 @@ struct Inst {
     const uint4 *site;  // lex layout: [N] {nb+x|nb-x<<16, nb+y|nb-y<<16, nb+z|nb-z<<16, jmask}
     const uint16_t *grp;// lex layout: [ncol][gmax][4] sites of each Philox block (0xFFFF: none)
     const uint32_t *jeo;// EO layout: [2][N/8][6] coupling words per block
+    const uint16_t *pos;// [N] storage position of each lexicographic site
+    // CM layout: per colour and Philox block, the 24 LDS byte offsets (within
+    // a replica slot) of the 6 neighbours of its 4 sites, in the spin copy or,
+    // for a -1 coupling, in the complemented copy at +row_bytes; word 24 is
+    // the mask of real (non-padding) sites, one 0x01 per byte.
+    const uint16_t *cmdesc;  // [ncol][gmax][32]
+    int32_t cbase[3];   // CM layout: first byte of each colour
+    int32_t tpr;        // CM layout: threads per replica
     int32_t ncs[3];     // sites per colour
     int32_t gcs[3];     // Philox blocks per colour, ceil(ncs / 4)
     int32_t gmax;

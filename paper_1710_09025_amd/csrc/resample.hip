@@ -7,7 +7,7 @@
 //   copies    n_r = floor(tau) + [u_r < frac(tau) 2^32] for 1024 rows, with
 //             their exclusive scan inside the workgroup;
 //   families  n ln n of 2048 family ids, summed by the pairwise tree;
-//   overlap   spin overlaps of 1024 replica pairs (at overlap steps).
+//   overlap   spin overlaps of 256 replica pairs (at overlap steps).
 // The last workgroup of an instance to finish scans the per-workgroup
 // totals into offsets, sets R_{k+1} and the capacity / extinction status,
 // folds the family partial sums, and advances the step.  An expand launch
@@ -61,10 +61,7 @@ __device__ void copies_role(const Inst &I, int k, uint32_t row0, uint32_t *sh)
     }
     uint32_t total;
     const uint32_t off = block_exscan(n, sh, &total);
-    if (r < I.Rcap) {
-        I.ncopy[r] = n;
-        I.loff[r] = off;
-    }
+    if (r < I.Rcap) I.loff[r] = off;
     if (threadIdx.x == 0) I.bsum[row0 / kRowsPerBlock] = total;
 }
 
@@ -100,26 +97,61 @@ __device__ void families_role(const Inst &I, int k, uint32_t base, double *a)
     }
 }
 
-// Overlap histogram: row r pairs with r + floor(R_k / 2).  Spins are 0/1
-// bytes, so the number of differing sites is the popcount of the XOR.
-__device__ void overlap_role(const Inst &I, int k, uint32_t row0)
+// Overlap histogram: row r pairs with r + floor(R_k / 2); this workgroup
+// takes the kOvlPairs pairs from row p0.  Spins are 0/1 bytes, so the number
+// of differing sites is the popcount of the XOR.  A pair is read by a group
+// of lanes sized to its row (16-byte loads), several pairs per wave for
+// short rows.  Low temperatures put most pairs into a few bins, so the
+// counts go to an LDS histogram first and only its non-empty bins reach
+// global memory.
+__device__ void overlap_role(const Inst &I, int k, uint32_t p0, uint32_t *qh)
 {
     const int slot = I.ovl_slot[k];
     if (slot < 0) return;
     const int h = (int)I.Rk[k] / 2;
+    if ((int)p0 >= h) return;
+    const int npairs = min(kOvlPairs, h - (int)p0);
+    const int nb = 2 * I.N + 1;
+    uint32_t *gh = I.qhist + (size_t)slot * nb;
+    const bool local = nb <= kOvlLdsBins;
+    if (local) {
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) qh[i] = 0u;
+        __syncthreads();
+    }
     const uint8_t *sp = I.spins[*I.cur];
-    const int words = I.row_bytes >> 2;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nw = blockDim.x >> 6;
-    for (int q = wave; q < kRowsPerBlock; q += nw) {
-        const int r = (int)row0 + q;
-        if (r >= h) break;
-        const uint32_t *a = reinterpret_cast<const uint32_t *>(sp + (size_t)r * I.row_bytes);
-        const uint32_t *b = reinterpret_cast<const uint32_t *>(sp + (size_t)(r + h) * I.row_bytes);
+    const int words = I.row_bytes >> 4;
+    int lpp = 1;  // lanes per pair, a power of two <= 64
+    while (lpp < words && lpp < 64) lpp <<= 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane / lpp, j = lane & (lpp - 1), ppw = 64 / lpp;
+    for (int q0 = wave * ppw; q0 < npairs; q0 += nw * ppw) {
+        const int q = q0 + sub;
         int diff = 0;
-        for (int i = lane; i < words; i += 64) diff += __builtin_popcount(a[i] ^ b[i]);
-        for (int off = 32; off > 0; off >>= 1) diff += __shfl_xor(diff, off);
-        if (lane == 0) atomicAdd(&I.qhist[(size_t)slot * (2 * I.N + 1) + (I.N - 2 * diff) + I.N], 1u);
+        if (q < npairs) {
+            const int r = (int)p0 + q;
+            const uint4 *a = reinterpret_cast<const uint4 *>(sp + (size_t)r * I.row_bytes);
+            const uint4 *b = reinterpret_cast<const uint4 *>(sp + (size_t)(r + h) * I.row_bytes);
+            for (int i = j; i < words; i += lpp) {
+                const uint4 x = a[i], y = b[i];
+                diff += __builtin_popcount(x.x ^ y.x) + __builtin_popcount(x.y ^ y.y) +
+                        __builtin_popcount(x.z ^ y.z) + __builtin_popcount(x.w ^ y.w);
+            }
+        }
+        for (int off = lpp >> 1; off > 0; off >>= 1) diff += __shfl_xor(diff, off);
+        if (q < npairs && j == 0) {
+            const int bin = (I.N - 2 * diff) + I.N;
+            if (local)
+                atomicAdd(&qh[bin], 1u);
+            else
+                atomicAdd(&gh[bin], 1u);
+        }
+    }
+    if (local) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+            const uint32_t c = qh[i];
+            if (c) atomicAdd(&gh[i], c);
+        }
     }
 }
 
@@ -160,7 +192,8 @@ __device__ void post_finish(const Inst &I, int k, uint32_t *sh, double *a)
 __global__ __launch_bounds__(1024) void k_post(const Inst *insts, const Work *work)
 {
     __shared__ uint32_t sh[17];
-    __shared__ double a[2048];
+    // pairwise-tree scratch, or the LDS overlap histogram
+    __shared__ double a[kOvlLdsBins / 2 + 1];
     const Work w = work[blockIdx.x];
     const Inst &I = insts[w.inst];
     const int k = *I.k;
@@ -170,26 +203,39 @@ __global__ __launch_bounds__(1024) void k_post(const Inst *insts, const Work *wo
     } else if (w.role == kRoleFamilies) {
         families_role(I, k, w.row0, a);
     } else {
-        overlap_role(I, k, w.row0);
+        overlap_role(I, k, w.row0, reinterpret_cast<uint32_t *>(a));
     }
     if (last_workgroup(&I.sync[1], I.post_blocks)) post_finish(I, k, sh, a);
 }
 
 // Copy map of the resampling of step k - 1 (the step index has advanced):
-// source row r owns destination rows [off_r, off_r + n_r).
+// source row r owns destination rows [off_r, off_r + n_r).  A few rows can
+// own thousands of copies when the temperature step is large, so the
+// workgroup of a row block walks the block's destinations instead of its
+// rows: destination j belongs to the last row whose local offset is <= j.
 __global__ __launch_bounds__(1024) void k_expand(const Inst *insts, const Work *work)
 {
+    __shared__ uint32_t off[kRowsPerBlock];
     const Work w = work[blockIdx.x];
     const Inst &I = insts[w.inst];
     const int k = *I.k;
     if (!inst_live(I, k) || k == 0 || !*I.mapped) return;
     const int Rold = (int)I.Rk[k - 1];
-    const int r = (int)w.row0 + (int)threadIdx.x;
-    if (r < Rold) {
-        const uint32_t o = I.boff[w.row0 / kRowsPerBlock] + I.loff[r];
-        const uint32_t n = I.ncopy[r];
-        for (uint32_t j = 0; j < n; ++j)
-            if (o + j < (uint32_t)I.Rcap) I.map[o + j] = (uint32_t)r;
+    const int row0 = (int)w.row0;
+    if (row0 >= Rold) return;
+    const int nrow = min(kRowsPerBlock, Rold - row0);
+    const uint32_t total = I.bsum[row0 / kRowsPerBlock];
+    const uint32_t base = I.boff[row0 / kRowsPerBlock];
+    if (total == 0u) return;
+    for (int t = threadIdx.x; t < nrow; t += blockDim.x) off[t] = I.loff[row0 + t];
+    __syncthreads();
+    const uint32_t lim = (uint32_t)I.Rcap - min(base, (uint32_t)I.Rcap);
+    const uint32_t end = min(total, lim);
+    for (uint32_t j = threadIdx.x; j < end; j += blockDim.x) {
+        int p = 0;  // off[0] = 0 <= j
+        for (int step = kRowsPerBlock / 2; step > 0; step >>= 1)
+            if (p + step < nrow && off[p + step] <= j) p += step;
+        I.map[base + j] = (uint32_t)(row0 + p);
     }
 }
 

@@ -35,7 +35,6 @@ void Allocator::put(void *p)
 
 int64_t default_capacity(int64_t R) { return R + (int64_t)std::ceil(8.0 * std::sqrt((double)R)) + 64; }
 
-int choose_layout(int L) { return (L == 8 || L == 16) ? kLayoutEO : kLayoutLex; }
 
 // Colour of site (x, y, z): checkerboard for even L; for odd L the proper
 // three-colouring (g(x) + g(y) + g(z)) mod 3 with g(v) = v mod 2 below L-1
@@ -49,6 +48,49 @@ static int colour_of(int L, int x, int y, int z)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// L = 8, 16: even/odd-x rows (SWAR words aligned to rows).  Otherwise the
+// colour-major layout when its largest colour fits a workgroup of 1024
+// threads and the slot offsets fit 16 bits; else lexicographic.
+LayoutInfo layout_for(int L)
+{
+    LayoutInfo li{};
+    const int N = L * L * L;
+    li.ncol = (L & 1) ? 3 : 2;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) li.ncs[colour_of(L, x, y, z)]++;
+    li.gmax = 1;
+    for (int c = 0; c < 3; ++c) li.gmax = std::max(li.gmax, (li.ncs[c] + 3) / 4);
+    li.row_bytes = (N + 15) & ~15;
+    if (L == 8 || L == 16) {
+        li.layout = kLayoutEO;
+        li.variant = L == 8 ? kSweepEO8 : kSweepEO16;
+        return li;
+    }
+    int cb = 0;
+    for (int c = 0; c < li.ncol; ++c) {
+        li.cbase[c] = cb;
+        cb += (li.ncs[c] + 3) & ~3;
+    }
+    const int rb = (cb + 15) & ~15;
+    int tpr = 1;
+    if (li.gmax <= 64) {
+        while (tpr < li.gmax) tpr <<= 1;
+    } else {
+        tpr = (li.gmax + 63) / 64 * 64;
+    }
+    if (tpr <= 1024 && 2 * rb <= 65535 && 2 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= 65536) {
+        li.layout = kLayoutCM;
+        li.variant = li.ncol == 2 ? kSweepCM2 : kSweepCM3;
+        li.row_bytes = rb;
+        li.tpr = tpr;
+        return li;
+    }
+    li.layout = kLayoutLex;
+    li.variant = kSweepLex;
+    return li;
+}
+
 namespace {
 struct Carve {
     size_t off = 0;
@@ -61,24 +103,21 @@ struct Carve {
 };
 
 struct InstLayout {
-    size_t ctl, status, sync, spins0, spins1, E0, E1, f0, f1, map, ncopy, loff, bsum, boff, hist, BF, cnt, fpart, thr,
-        beta, rho, site, grp, jeo, J, Rk, rec, ovl_slot, qhist, total;
+    size_t ctl, status, sync, spins0, spins1, E0, E1, f0, f1, map, loff, bsum, boff, hist, BF, cnt, fpart, thr,
+        beta, rho, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, total;
 };
 
 InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
 {
     const int N = L * L * L;
-    const int row_bytes = (N + 15) & ~15;
-    const int ncol = (L & 1) ? 3 : 2;
+    const LayoutInfo li = layout_for(L);
+    const int row_bytes = li.row_bytes;
+    const int ncol = li.ncol;
     const int nblk = (int)((Rcap + kRowsPerBlock - 1) / kRowsPerBlock);
     const int nlev = 3 * N + 1;
     int64_t fp2 = 1;
     while (fp2 < R) fp2 <<= 1;
-    int ncs[3] = {0, 0, 0};
-    for (int z = 0; z < L; ++z)
-        for (int y = 0; y < L; ++y)
-            for (int x = 0; x < L; ++x) ncs[colour_of(L, x, y, z)]++;
-    const int gmax = std::max((ncs[0] + 3) / 4, std::max((ncs[1] + 3) / 4, (ncs[2] + 3) / 4));
+    const int gmax = li.gmax;
     Carve c;
     InstLayout l{};
     l.ctl = c.take(16);
@@ -91,7 +130,6 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
     l.f0 = c.take((size_t)Rcap * 4);
     l.f1 = c.take((size_t)Rcap * 4);
     l.map = c.take((size_t)Rcap * 4);
-    l.ncopy = c.take((size_t)Rcap * 4);
     l.loff = c.take((size_t)Rcap * 4);
     l.bsum = c.take((size_t)nblk * 4);
     l.boff = c.take((size_t)nblk * 4);
@@ -106,6 +144,8 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
     l.grp = c.take((size_t)ncol * gmax * 4 * 2);
     l.jeo = c.take((size_t)2 * (N / 8 + 1) * 6 * 4);
     l.J = c.take((size_t)3 * N);
+    l.pos = c.take((size_t)N * 2);
+    l.cmdesc = li.layout == kLayoutCM ? c.take((size_t)ncol * gmax * 32 * 2) : c.take(16);
     l.Rk = c.take((size_t)(nT + 1) * 4);
     l.rec = c.take((size_t)nT * sizeof(StepRec));
     l.ovl_slot = c.take((size_t)nT * 4);
@@ -279,7 +319,6 @@ int Runner::upload_inst(int i)
     d.fam[0] = (uint32_t *)(b + lay.f0);
     d.fam[1] = (uint32_t *)(b + lay.f1);
     d.map = (uint32_t *)(b + lay.map);
-    d.ncopy = (uint32_t *)(b + lay.ncopy);
     d.loff = (uint32_t *)(b + lay.loff);
     d.bsum = (uint32_t *)(b + lay.bsum);
     d.boff = (uint32_t *)(b + lay.boff);
@@ -294,6 +333,8 @@ int Runner::upload_inst(int i)
     d.site = (const uint4 *)(b + lay.site);
     d.grp = (const uint16_t *)(b + lay.grp);
     d.jeo = (const uint32_t *)(b + lay.jeo);
+    d.pos = (const uint16_t *)(b + lay.pos);
+    d.cmdesc = (const uint16_t *)(b + lay.cmdesc);
     d.k = (int32_t *)(b + lay.ctl);
     d.cur = d.k + 1;
     d.mapped = d.k + 2;
@@ -307,7 +348,7 @@ int Runner::upload_inst(int i)
     d.sweep_tiles = (int32_t)((h.Rcap + h.tile_rows - 1) / h.tile_rows);
     {
         const int64_t nchunks = std::max<int64_t>(1, fp2 / 2048);
-        const int64_t novl = (h.Rcap / 2 + kRowsPerBlock - 1) / kRowsPerBlock;
+        const int64_t novl = (h.Rcap / 2 + kOvlPairs - 1) / kOvlPairs;
         d.post_blocks = (int32_t)(d.nblk + nchunks + novl);
     }
     h.ctl = d.k;
@@ -348,12 +389,23 @@ int Runner::upload_inst(int i)
     d.gmax = std::max(d.gcs[0], std::max(d.gcs[1], d.gcs[2]));
     auto J = [&](int dir, int s) { return (int)h.J[(size_t)dir * N + s]; };
     auto site_of = [L](int x, int y, int z) { return ((x % L + L) % L) + L * (((y % L + L) % L) + L * ((z % L + L) % L)); };
+    const LayoutInfo li = layout_for(L);
+    for (int c = 0; c < 3; ++c) d.cbase[c] = li.cbase[c];
+    d.tpr = li.tpr;
     // storage position of each site
     h.lex_pos.resize(N);
+    std::vector<uint16_t> pos16((size_t)N);
     for (int s = 0; s < N; ++s) {
         const int x = s % L, yz = s / L;
-        h.lex_pos[s] = h.layout == kLayoutLex ? s : yz * L + (x & 1) * (L / 2) + (x >> 1);
+        if (h.layout == kLayoutLex)
+            h.lex_pos[s] = s;
+        else if (h.layout == kLayoutEO)
+            h.lex_pos[s] = yz * L + (x & 1) * (L / 2) + (x >> 1);
+        else
+            h.lex_pos[s] = li.cbase[col[s]] + rank[s];
+        pos16[s] = (uint16_t)h.lex_pos[s];
     }
+    std::vector<uint16_t> cmdesc;
     std::vector<uint32_t> site((size_t)N * 4, 0u);
     std::vector<uint16_t> grp((size_t)h.ncol * d.gmax * 4, (uint16_t)0xFFFF);
     std::vector<uint32_t> jeo((size_t)2 * (N / 8 + 1) * 6, 0u);
@@ -377,6 +429,35 @@ int Runner::upload_inst(int i)
                     const int c = col[s], r = rank[s];
                     grp[((size_t)c * d.gmax + (r >> 2)) * 4 + (r & 3)] = (uint16_t)s;
                 }
+    } else if (h.layout == kLayoutCM) {
+        // per colour, Philox block and site: the LDS offsets of its six
+        // neighbours, in the complemented copy (+row_bytes) for a -1 bond
+        std::vector<int> site_at((size_t)3 * N, -1);
+        for (int s = 0; s < N; ++s) site_at[(size_t)col[s] * N + rank[s]] = s;
+        cmdesc.assign((size_t)h.ncol * d.gmax * 32, 0);
+        for (int c = 0; c < h.ncol; ++c)
+            for (int g = 0; g < d.gcs[c]; ++g) {
+                uint16_t *e = cmdesc.data() + ((size_t)c * d.gmax + g) * 32;
+                uint32_t vmask = 0;
+                for (int bb = 0; bb < 4; ++bb) {
+                    const int i = 4 * g + bb;
+                    if (i >= ncs[c]) {
+                        // padding byte: no site; point at itself (value 0)
+                        for (int dd = 0; dd < 6; ++dd) e[4 * dd + bb] = (uint16_t)(li.cbase[c] + i);
+                        continue;
+                    }
+                    vmask |= 1u << (8 * bb);
+                    const int s = site_at[(size_t)c * N + i];
+                    const int x = s % L, y = (s / L) % L, z = s / (L * L);
+                    const int nb[6] = {site_of(x + 1, y, z), site_of(x - 1, y, z), site_of(x, y + 1, z),
+                                       site_of(x, y - 1, z), site_of(x, y, z + 1), site_of(x, y, z - 1)};
+                    const int jv[6] = {J(0, s), J(0, nb[1]), J(1, s), J(1, nb[3]), J(2, s), J(2, nb[5])};
+                    for (int dd = 0; dd < 6; ++dd)
+                        e[4 * dd + bb] = (uint16_t)(h.lex_pos[nb[dd]] + (jv[dd] < 0 ? h.row_bytes : 0));
+                }
+                e[24] = (uint16_t)(vmask & 0xFFFFu);
+                e[25] = (uint16_t)(vmask >> 16);
+            }
     } else {
         const int H = L / 2, GPR = L / 8, G = N / 8;
         for (int c = 0; c < 2; ++c)
@@ -413,6 +494,10 @@ int Runner::upload_inst(int i)
     HIPCHK(hipMemcpyAsync(b + lay.grp, grp.data(), grp.size() * 2, hipMemcpyHostToDevice, stream_), "upload grp");
     HIPCHK(hipMemcpyAsync(b + lay.jeo, jeo.data(), jeo.size() * 4, hipMemcpyHostToDevice, stream_), "upload jeo");
     HIPCHK(hipMemcpyAsync(b + lay.J, h.J.data(), h.J.size(), hipMemcpyHostToDevice, stream_), "upload J");
+    HIPCHK(hipMemcpyAsync(b + lay.pos, pos16.data(), pos16.size() * 2, hipMemcpyHostToDevice, stream_), "upload pos");
+    if (!cmdesc.empty())
+        HIPCHK(hipMemcpyAsync(b + lay.cmdesc, cmdesc.data(), cmdesc.size() * 2, hipMemcpyHostToDevice, stream_),
+               "upload cm descriptors");
     HIPCHK(hipMemcpyAsync(b + lay.Rk, Rk0.data(), Rk0.size() * 4, hipMemcpyHostToDevice, stream_), "upload Rk");
     HIPCHK(hipMemcpyAsync(b + lay.ovl_slot, h.ovl_slot.data(), h.ovl_slot.size() * 4, hipMemcpyHostToDevice,
                           stream_),
@@ -440,13 +525,13 @@ int Runner::build_work(const std::vector<int> &active)
         if (bytes && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
         return p;
     };
-    std::map<std::tuple<int, int, int>, std::vector<Work>> groups;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<Work>> groups;
     std::vector<Work> rows, post;
     std::vector<uint32_t> list;
     for (int i : active) {
         const HostInst &h = inst_[i];
         const uint32_t ii = (uint32_t)i;
-        auto &g = groups[std::make_tuple(h.variant, h.tile_rows, h.row_bytes)];
+        auto &g = groups[std::make_tuple(h.variant, h.L, h.tile_rows, h.row_bytes, h.tpr)];
         for (int64_t r = 0; r < h.Rcap; r += h.tile_rows) g.push_back(Work{ii, (uint32_t)r, 0u, 0u});
         for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) {
             rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
@@ -455,14 +540,15 @@ int Runner::build_work(const std::vector<int> &active)
         int64_t fp2 = 1;
         while (fp2 < h.R) fp2 <<= 1;
         for (int64_t f = 0; f < fp2; f += 2048) post.push_back(Work{ii, (uint32_t)f, kRoleFamilies, 0u});
-        for (int64_t r = 0; r < h.Rcap / 2; r += kRowsPerBlock) post.push_back(Work{ii, (uint32_t)r, kRoleOverlap, 0u});
+        for (int64_t r = 0; r < h.Rcap / 2; r += kOvlPairs) post.push_back(Work{ii, (uint32_t)r, kRoleOverlap, 0u});
         list.push_back(ii);
     }
     for (auto &kv : groups) {
         SweepGroup sg;
         sg.variant = std::get<0>(kv.first);
-        sg.tile_rows = std::get<1>(kv.first);
-        sg.row_bytes = std::get<2>(kv.first);
+        sg.tile_rows = std::get<2>(kv.first);
+        sg.row_bytes = std::get<3>(kv.first);
+        sg.tpr = std::get<4>(kv.first);
         sg.nwork = (int)kv.second.size();
         sg.work = (Work *)upload(kv.second.data(), kv.second.size() * sizeof(Work));
         if (!sg.work) return dev_fail(hipErrorOutOfMemory, "upload sweep work");
@@ -508,7 +594,8 @@ void Runner::drop_graph()
 // population size live on the device), so the sequence can be captured once.
 int Runner::launch_step_kernels()
 {
-    for (auto &g : sweep_groups_) launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, stream_);
+    for (auto &g : sweep_groups_)
+        launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, stream_);
     if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 2], stream_), "hipEventRecord");
     launch_post(d_insts_, d_post_, npost_, stream_);
     launch_expand(d_insts_, d_rows_, nrows_work_, stream_);

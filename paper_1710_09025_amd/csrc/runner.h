@@ -22,6 +22,7 @@ namespace pamc {
 struct HostInst {
     int L = 0, N = 0, ncol = 0, layout = 0, variant = 0;
     int row_bytes = 0, tile_rows = 0;
+    int tpr = 0;                       // colour-major sweep: threads per replica
     int64_t R = 0, Rcap = 0;
     int nT = 0, NS = 0;
     uint64_t seed = 0;
@@ -53,7 +54,16 @@ struct Allocator {
 // Footprint and table construction helpers.
 size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl);
 int64_t default_capacity(int64_t R);
-int choose_layout(int L);
+// Storage layout for lattice size L, and the shape it implies.
+struct LayoutInfo {
+    int layout, variant, ncol;
+    int ncs[3];       // sites per colour
+    int cbase[3];     // colour-major: first byte of each colour
+    int row_bytes;    // bytes per replica row (multiple of 16)
+    int gmax;         // Philox blocks of the largest colour
+    int tpr;          // colour-major: threads per replica
+};
+LayoutInfo layout_for(int L);
 
 class Runner {
 public:
@@ -118,7 +128,7 @@ private:
 
     // work lists for the current active set
     struct SweepGroup {
-        int variant, tile_rows, row_bytes;
+        int variant, tile_rows, row_bytes, tpr;
         Work *work;
         int nwork;
     };

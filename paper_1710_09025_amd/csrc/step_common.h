@@ -31,7 +31,8 @@ __device__ __forceinline__ T block_reduce(T v, T *sh, Op op)
 }
 
 // Pairwise tree sum of the n = 2^p values a[0..n) held in LDS (destroys a):
-// level by level, node i of the next level is a[2i] + a[2i+1].  n <= blockDim.
+// level by level, node i of the next level is a[2i] + a[2i+1].
+// n <= 2 blockDim.
 __device__ __forceinline__ double lds_pairwise(double *a, int n)
 {
     for (; n > 1; n >>= 1) {
@@ -45,14 +46,16 @@ __device__ __forceinline__ double lds_pairwise(double *a, int n)
     return a[0];
 }
 
-// Pairwise tree sum of n = 2^p leaves leaf(0..n) with NT threads (n <=
-// 2 NT^2): aligned chunks of 2 NT leaves are subtrees of the global tree;
-// each is folded in LDS, then the chunk roots are folded.  a and roots hold
-// NT doubles each.
+// Pairwise tree sum of n = 2^p leaves leaf(0..n).  T = the largest power of
+// two <= min(blockDim, NT) threads take part: aligned chunks of 2T leaves
+// are subtrees of the global tree; each is folded in LDS, then the chunk
+// roots are folded.  a and roots hold NT doubles each; n <= 2 T NT.
 template <int NT, typename Leaf>
 __device__ __forceinline__ double tree_sum(int n, Leaf leaf, double *a, double *roots)
 {
     const int t = threadIdx.x;
+    int T = 1;
+    while (2 * T <= (int)blockDim.x && 2 * T <= NT) T <<= 1;
     if (n == 1) {
         if (t == 0) a[0] = leaf(0);
         __syncthreads();
@@ -60,17 +63,17 @@ __device__ __forceinline__ double tree_sum(int n, Leaf leaf, double *a, double *
         __syncthreads();
         return r;
     }
-    const int chunk = 2 * NT;
+    const int chunk = 2 * T;
     if (n <= chunk) {
-        a[t] = 2 * t < n ? leaf(2 * t) + leaf(2 * t + 1) : 0.0;
+        if (t < T) a[t] = 2 * t < n ? leaf(2 * t) + leaf(2 * t + 1) : 0.0;
         __syncthreads();
         return lds_pairwise(a, n / 2);
     }
     const int nchunks = n / chunk;
     for (int c = 0; c < nchunks; ++c) {
-        a[t] = leaf(c * chunk + 2 * t) + leaf(c * chunk + 2 * t + 1);
+        if (t < T) a[t] = leaf(c * chunk + 2 * t) + leaf(c * chunk + 2 * t + 1);
         __syncthreads();
-        const double r = lds_pairwise(a, NT);
+        const double r = lds_pairwise(a, T);
         if (t == 0) roots[c] = r;
     }
     __syncthreads();
@@ -127,7 +130,8 @@ __device__ __forceinline__ bool last_workgroup(uint32_t *counter, int expected)
 // as a fixed product of rho^(2^b), their normaliser S by the pairwise tree
 // over 2^ceil(log2(M+1)) levels, and the table (floor(tau), floor(frac(tau)
 // 2^32)) with tau = R w / S.  Clears the histogram and moves the buffer roles
-// on when the sweep wrote the other buffer.  NT is the workgroup size.
+// on when the sweep wrote the other buffer.  NT bounds the workgroup size
+// (scratch capacity); any workgroup of a multiple of 64 threads works.
 template <int NT>
 __device__ void measure_step(const Inst &I, int k)
 {

@@ -24,12 +24,7 @@ namespace pamc {
 __device__ __forceinline__ const Inst &inst_ref(const Inst *insts, uint32_t i) { return insts[i]; }
 
 // Storage position of lexicographic site s in a replica row.
-__device__ __forceinline__ int storage_pos(int layout, int L, int s)
-{
-    if (layout == kLayoutLex) return s;
-    const int x = s % L, yz = s / L;
-    return yz * L + (x & 1) * (L >> 1) + (x >> 1);
-}
+__device__ __forceinline__ int storage_pos(const Inst &I, int s) { return I.pos[s]; }
 
 // ---------------------------------------------------------------------------
 // Initial replicas (Sec. II.B: random configurations at beta = 0).  Site s
@@ -50,7 +45,7 @@ __global__ __launch_bounds__(256) void k_init(const Inst *insts, const Work *wor
         for (int j = 0; j < 4; ++j) {
             const int s = 4 * b + j;
             if (s >= I.N) break;
-            sp[(size_t)r * I.row_bytes + storage_pos(I.layout, I.L, s)] = (uint8_t)(word_of(v, j) >> 31);
+            sp[(size_t)r * I.row_bytes + storage_pos(I, s)] = (uint8_t)(word_of(v, j) >> 31);
         }
     }
     for (int q = threadIdx.x; q < rows; q += blockDim.x) I.fam[0][w.row0 + q] = w.row0 + q;
@@ -78,11 +73,11 @@ __global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *w
         int e = 0;
         for (int s = lane; s < N; s += 64) {
             const int x = s % L, y = (s / L) % L, z = s / (L * L);
-            const int ss = 2 * S[storage_pos(I.layout, L, s)] - 1;
+            const int ss = 2 * S[storage_pos(I, s)] - 1;
             const int nb[3] = {(x + 1) % L + L * (y + L * z), x + L * ((y + 1) % L + L * z),
                                x + L * (y + L * ((z + 1) % L))};
             for (int d = 0; d < 3; ++d)
-                e -= J[d * N + s] * ss * (2 * S[storage_pos(I.layout, L, nb[d])] - 1);
+                e -= J[d * N + s] * ss * (2 * S[storage_pos(I, nb[d])] - 1);
         }
         for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
         if (lane == 0) I.E[cur][r] = e;
@@ -442,6 +437,170 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
 }
 
 // ---------------------------------------------------------------------------
+// Colour-major SWAR sweep for any L whose largest colour has at most 4096
+// sites (two colours for even L, three for odd L).  Storage kLayoutCM: the
+// four sites of a Philox block are one aligned word of the row.  In LDS every
+// replica slot holds the row and its complement (0/1 swapped); a bond with
+// coupling -1 reads the neighbour from the complement, so byte-wise
+// s ^ nb_slot counts unsatisfied bonds directly.  A thread owns Philox block
+// g of every colour and keeps the 24 neighbour byte addresses of its four
+// sites in registers for all replicas and sweeps; each neighbour word is
+// assembled from four byte reads.  Energy: every bond joins two sites of
+// different colours, so U = (1/2) sum over all sites of their unsatisfied
+// bonds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void replica_barrier(int tpr)
+{
+    if (tpr <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int NCOL>
+struct CMBlock {
+    const uint8_t *nb[24];  // neighbour bytes (spin or complement copy)
+    uint8_t *own;           // the four sites, spin copy
+    uint32_t vmask;         // 0x01 in bytes of real sites
+    uint32_t ctr;           // Philox counter word 0
+    bool has;
+};
+
+template <int NCOL>
+__device__ __forceinline__ uint32_t cm_count(const CMBlock<NCOL> &b, uint32_t own)
+{
+    uint32_t n = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        uint32_t w = (uint32_t)b.nb[4 * d][0];
+        w |= (uint32_t)b.nb[4 * d + 1][0] << 8;
+        w |= (uint32_t)b.nb[4 * d + 2][0] << 16;
+        w |= (uint32_t)b.nb[4 * d + 3][0] << 24;
+        n += own ^ w;
+    }
+    return n;
+}
+
+template <int NCOL>
+__device__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+{
+    const int tpr = I.tpr;
+    const int RP = (int)blockDim.x / tpr;
+    const int row_bytes = I.row_bytes;
+    const int slot_bytes = 2 * row_bytes;
+    uint32_t *thr = reinterpret_cast<uint32_t *>(lds + RP * slot_bytes);  // [8]
+    int *unsat = reinterpret_cast<int *>(thr + 8);
+    const TileIO io = tile_io(I);
+    const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
+    uint8_t *slot = lds + qsub * slot_bytes;
+    CMBlock<NCOL> blk[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+        const int g = lane_r;
+        blk[c].has = g < I.gcs[c];
+        blk[c].ctr = ((uint32_t)c << 24) | (uint32_t)g;
+        const int gg = blk[c].has ? g : 0;
+        const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
+#pragma unroll
+        for (int i = 0; i < 24; ++i) blk[c].nb[i] = slot + d[i];
+        blk[c].vmask = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
+        blk[c].own = slot + I.cbase[c] + 4 * gg;
+    }
+    const uint4 th = I.thr[k];
+    const bool all = th.w != 0;
+    if (threadIdx.x < 8) thr[threadIdx.x] = threadIdx.x == 0 ? th.z : threadIdx.x == 1 ? th.y : threadIdx.x == 2 ? th.x : 0u;
+    for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) unsat[q] = 0;
+    const uint32_t key0 = I.key0, key1 = I.key1;
+    const int nvec = row_bytes >> 4;
+    __syncthreads();
+
+    for (int qb = 0; qb < nrows; qb += RP) {
+        const int q = qb + qsub;
+        const bool active = q < nrows;
+        const uint32_t r = (uint32_t)(r0 + q);
+        if (active) {
+            const uint32_t sr = io.map ? io.map[r] : r;
+            const uint4 *src = reinterpret_cast<const uint4 *>(io.src + (size_t)sr * row_bytes);
+            uint4 *sp = reinterpret_cast<uint4 *>(slot);
+            for (int i = lane_r; i < nvec; i += tpr) {
+                const uint4 v = src[i];
+                sp[i] = v;
+                sp[nvec + i] = make_uint4(v.x ^ 0x01010101u, v.y ^ 0x01010101u, v.z ^ 0x01010101u, v.w ^ 0x01010101u);
+            }
+        }
+        replica_barrier(tpr);
+        for (int t = 0; t < I.NS; ++t) {
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                const CMBlock<NCOL> &b = blk[c];
+                if (active && b.has) {
+                    const uint32_t own = *reinterpret_cast<const uint32_t *>(b.own);
+                    const uint32_t n = cm_count<NCOL>(b, own);
+                    uint32_t flip;
+                    if (all) {
+                        flip = 0x01010101u;
+                    } else {
+                        const uint4 u = philox10(make_uint4(b.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                        flip = ((n + 0x05050505u) >> 3) & 0x01010101u;
+                        flip |= (u.x < thr[n & 7u] ? 1u : 0u);
+                        flip |= (u.y < thr[(n >> 8) & 7u] ? 1u : 0u) << 8;
+                        flip |= (u.z < thr[(n >> 16) & 7u] ? 1u : 0u) << 16;
+                        flip |= (u.w < thr[(n >> 24) & 7u] ? 1u : 0u) << 24;
+                    }
+                    flip &= b.vmask;
+                    const uint32_t nw = own ^ flip;
+                    *reinterpret_cast<uint32_t *>(b.own) = nw;
+                    *reinterpret_cast<uint32_t *>(b.own + row_bytes) = nw ^ 0x01010101u;
+                }
+                replica_barrier(tpr);
+            }
+        }
+        if (active) {
+            uint32_t part = 0;
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                if (!blk[c].has) continue;
+                const uint32_t own = *reinterpret_cast<const uint32_t *>(blk[c].own);
+                // padding bytes have no neighbours of their own: mask them
+                const uint32_t n = cm_count<NCOL>(blk[c], own) & (blk[c].vmask * 0xFFu);
+                part += (n & 0xFFu) + ((n >> 8) & 0xFFu) + ((n >> 16) & 0xFFu) + (n >> 24);
+            }
+            atomicAdd(&unsat[q], (int)part);
+            const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
+            uint4 *dst = reinterpret_cast<uint4 *>(io.dst + (size_t)r * row_bytes);
+            for (int i = lane_r; i < nvec; i += tpr) dst[i] = sp[i];
+        }
+        replica_barrier(tpr);
+    }
+    __syncthreads();
+    // every bond was counted from both of its ends
+    for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] >>= 1;
+    if (io.map)
+        for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
+    __syncthreads();
+    tile_energy_out(I, io, unsat, r0, nrows);
+    tile_family_count(I, io, r0, nrows);
+}
+
+template <int NCOL>
+__global__ __launch_bounds__(1024) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k >= I.nT || I.status[0]) return;
+    const int Rk = (int)I.Rk[k];
+    const int r0 = (int)w.row0;
+    const int nrows = min(tile_rows, Rk - r0);
+    if (nrows > 0) sweep_tile_cm<NCOL>(I, k, lds, r0, nrows, tile_rows);
+    if (last_workgroup(&I.sync[0], I.sweep_tiles)) measure_step<512>(I, k);
+}
+
+// ---------------------------------------------------------------------------
 // Stand-alone gather of surviving replicas: destination row d of the other
 // buffer receives source row map[d] (spins, energy, family).  Used when the
 // gather is not fused into the next sweep and to materialise a population
@@ -487,10 +646,23 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
     if (nwork) k_energy<<<nwork, 256, 0, st>>>(insts, work, Jraw);
 }
 
-void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes,
+// Workgroup shape of the colour-major sweep: tpr threads per replica and
+// max(1, 256 / tpr) replicas swept at once.
+int cm_replicas_per_block(int tpr) { return tpr >= 256 ? 1 : 256 / tpr; }
+
+void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
                   hipStream_t st)
 {
     if (!nwork) return;
+    if (variant == kSweepCM2 || variant == kSweepCM3) {
+        const int rp = cm_replicas_per_block(tpr);
+        const size_t lds = 2 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
+        if (variant == kSweepCM2)
+            k_sweep_cm<2><<<nwork, tpr * rp, lds, st>>>(insts, work, tile_rows);
+        else
+            k_sweep_cm<3><<<nwork, tpr * rp, lds, st>>>(insts, work, tile_rows);
+        return;
+    }
     const size_t lds = (size_t)tile_rows * row_bytes + 32 + 4 * (size_t)tile_rows;
     switch (variant) {
     case kSweepLex: k_sweep_lex<<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;

@@ -44,8 +44,10 @@ def test_initial_population_matches_oracle():
     compare_state(p.get_state(), o.get_state(), "init")
 
 
-# (L, R, n_temps, sweeps, beta_max): general kernel (odd and even L, L = 2
-# with doubled bonds), SWAR kernels (L = 8, 16), tiles with ragged tails
+# (L, R, n_temps, sweeps, beta_max): colour-major kernel with two colours
+# (even L) and three (odd L), 1 to 384 threads per replica; L = 2 with
+# doubled bonds; even/odd-x kernels (L = 8, 16); the lexicographic kernel
+# (L = 24); tiles with ragged tails
 CASES = [
     (2, 500, 21, 10, 5.0),
     (3, 800, 31, 10, 5.0),
@@ -54,9 +56,14 @@ CASES = [
     (6, 333, 21, 4, 5.0),
     (7, 150, 11, 4, 3.0),
     (8, 2001, 31, 10, 5.0),
+    (9, 61, 7, 3, 4.0),
     (10, 120, 11, 4, 4.0),
+    (11, 37, 6, 3, 4.0),
     (12, 90, 9, 3, 4.0),
+    (13, 19, 5, 2, 4.0),
+    (14, 23, 5, 2, 4.0),
     (16, 150, 11, 10, 5.0),
+    (24, 9, 4, 1, 4.0),
 ]
 
 
@@ -70,6 +77,25 @@ def test_full_run_bit_exact(L, R, nT, NS, bmax):
     compare_run(p.observables(), p.step_sums(), o, what=f"L={L}")
     # overlap histogram of the last step
     np.testing.assert_array_equal(p.overlap_hist(nT - 1), o.records()["qhist"][nT - 1])
+
+
+def test_large_temperature_steps_and_overlaps_at_every_step():
+    """Six temperatures up to beta = 5 (d beta = 1): a few low-energy
+    replicas receive most of the copies, so single row blocks own thousands
+    of destinations.  R = 30000 spreads the overlap pairs over many
+    workgroups; overlaps are recorded at every step."""
+    inst = instance(6, 30000, 6, 3, 5.0, disorder_seed=21, seed=22)
+    steps = list(range(6))
+    p, st = gpu_run(inst, overlap_steps=steps)
+    o, sto = run_oracle(inst, overlap_steps=steps)
+    assert st == sto == 0
+    compare_state(p.get_state(), o.get_state(), "large d beta")
+    compare_run(p.observables(), p.step_sums(), o, what="large d beta")
+    q = o.records()["qhist"]
+    for k in steps:
+        np.testing.assert_array_equal(p.overlap_hist(k), q[k], err_msg=f"overlap histogram, step {k}")
+    # the copies really were concentrated
+    assert p.observables()["R"][1] == o.records()["R"][1]
 
 
 @pytest.mark.parametrize("L", [3, 8, 16])
