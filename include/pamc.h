@@ -76,8 +76,10 @@ typedef struct pamc_options {
                                 kernel copies them first (same results)      */
     int device;              /* HIP device ordinal; -1 = current device       */
     int tile_rows;           /* replica rows per sweep workgroup; 0 = the
-                                library's choice for the lattice size (any
-                                value gives identical results)               */
+                                library's choice for the lattice size; for
+                                L = 8 and 16 rounded up to a multiple of the
+                                replicas one pass sweeps (any value gives
+                                identical results)                           */
     int graphs;              /* 1 (default): capture one temperature step in
                                 a hipGraph and replay it for every step (not
                                 with timing = 1); 0: launch kernels directly */

@@ -10,6 +10,9 @@ enum SweepVariant { kSweepLex = 0, kSweepEO8 = 1, kSweepEO16 = 2, kSweepCM2 = 3,
 
 // replicas swept at once by a colour-major workgroup with tpr threads each
 int cm_replicas_per_block(int tpr);
+// replicas swept at once by an even/odd-x workgroup (L = 8 or 16); its tile
+// holds a multiple of this many rows
+int eo_replicas_per_pass(int L);
 
 void launch_init(const Inst *insts, const Work *work, int nwork, hipStream_t st);
 void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st);

@@ -101,12 +101,18 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     }
     if (opt.tile_rows < 0 || opt.tile_rows > 4096) return invalid("tile_rows out of range");
     if (opt.tile_rows > 0) {
+        int tr = opt.tile_rows;
+        // the even/odd-x kernel sweeps a fixed number of replicas per pass
+        if (h.variant == pamc::kSweepEO8 || h.variant == pamc::kSweepEO16) {
+            const int rp = pamc::eo_replicas_per_pass(L);
+            tr = (tr + rp - 1) / rp * rp;
+        }
         // the workgroup's LDS (at most 64 KB) must hold its tile
         const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3;
-        const int64_t lds = cm ? 2 * (int64_t)h.row_bytes * pamc::cm_replicas_per_block(h.tpr) + 32 + 4 * opt.tile_rows
-                               : (int64_t)opt.tile_rows * h.row_bytes + 32 + 4 * opt.tile_rows;
+        const int64_t lds = cm ? 2 * (int64_t)h.row_bytes * pamc::cm_replicas_per_block(h.tpr) + 32 + 4 * (int64_t)tr
+                               : (int64_t)tr * h.row_bytes + 32 + 4 * (int64_t)tr;
         if (lds > 65536) return invalid("tile_rows too large for this lattice");
-        h.tile_rows = opt.tile_rows;
+        h.tile_rows = tr;
     }
     return PAMC_OK;
 }

@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// (Device arithmetic shared by the kernels -- Philox, the three-way xor --
+// lives in step_common.h, which only the kernel sources include.)
+
 namespace pamc {
 
 // Philox stream tags, the top four bits of counter word 3.
@@ -116,33 +119,5 @@ struct Work {
     uint32_t role;
     uint32_t pad;
 };
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
-// counter words 0 and 2 by the round multipliers, the high halves mixed with
-// words 1 and 3 and the round key; the key advances by the Weyl constants.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c.x;
-        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-        uint4 n;
-        n.x = (uint32_t)(b >> 32) ^ c.y ^ k0;
-        n.y = (uint32_t)b;
-        n.z = (uint32_t)(a >> 32) ^ c.w ^ k1;
-        n.w = (uint32_t)a;
-        c = n;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
-__device__ __forceinline__ uint32_t word_of(uint4 v, int i)
-{
-    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
 
 }  // namespace pamc

@@ -1,15 +1,50 @@
 // step_common.h -- device routines shared by the sweep and resampling
-// kernels: block reductions, the fixed pairwise summation tree, counting
-// with one atomic per distinct address of a wave, the end-of-launch
-// detection of the last workgroup of an instance, and the measurement of a
-// temperature step (paper Sec. II.B: reweighting factors exp[-(beta'-beta)
-// E_i] normalised to the nominal population).
+// kernels: the Philox4x32-10 generator, block reductions, the fixed pairwise
+// summation tree, counting with one atomic per distinct address of a wave,
+// the end-of-launch detection of the last workgroup of an instance, and the
+// measurement of a temperature step (paper Sec. II.B: reweighting factors
+// exp[-(beta'-beta) E_i] normalised to the nominal population).
 #pragma once
 #include "pamc_dev.h"
 
 #pragma clang fp contract(off)
 
 namespace pamc {
+
+// a ^ b ^ c in one instruction: gfx950's three-input bitwise operation with
+// the truth table of a three-way exclusive or.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
+// counter words 0 and 2 by the round multipliers, the high halves mixed with
+// words 1 and 3 and the round key; the key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        uint4 n;
+        n.x = xor3((uint32_t)(b >> 32), c.y, k0);
+        n.y = (uint32_t)b;
+        n.z = xor3((uint32_t)(a >> 32), c.w, k1);
+        n.w = (uint32_t)a;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t word_of(uint4 v, int i)
+{
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
 
 __device__ __forceinline__ bool inst_live(const Inst &I, int k) { return k < I.nT && I.status[0] == 0; }
 

@@ -264,20 +264,27 @@ __device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int n
 // neighbour), and that word shifted by one byte (the other x neighbour),
 // built with a byte-align of two words.  Per byte the six terms
 // s ^ nb ^ [J = -1] are summed without carries (<= 6 per byte).
+//
+// A thread owns GPT Philox blocks of each colour in RPT replicas at once;
+// the replicas of one thread lie a fixed distance apart in LDS, so their
+// word addresses differ by an immediate offset.
 // ---------------------------------------------------------------------------
 template <int L>
 struct EOShape {
-    static constexpr int N = L * L * L;
+    static constexpr int N = L * L * L;    // also the row stride in bytes
     static constexpr int H = L / 2;        // sites per half row
     static constexpr int GPR = L / 8;      // Philox blocks per half row
     static constexpr int G = N / 8;        // Philox blocks per colour
-    // two Philox blocks per thread and colour (independent work to overlap
-    // LDS latency); a replica fits in one wave when TPR <= 64
-    static constexpr int TPR = G / 2 < 256 ? G / 2 : 256;  // threads per replica
-    static constexpr int RP = 256 / TPR;   // replicas swept at once
-    static constexpr int GPT = G / TPR;    // blocks per thread per colour
+    static constexpr int TPR = G < 256 ? G : 256;  // threads per replica
+    static constexpr int GPT = G / TPR;    // blocks per thread and colour
+    static constexpr int RPT = 2;          // replicas per thread
+    static constexpr int RPG = 256 / TPR;  // replica groups per workgroup
+    static constexpr int RP = RPG * RPT;   // replicas swept at once
+    static constexpr int RSTRIDE = RPG * N;  // LDS distance between a thread's replicas
     static constexpr bool kWaveLocal = TPR <= 64;
 };
+
+int eo_replicas_per_pass(int L) { return L == 8 ? EOShape<8>::RP : EOShape<16>::RP; }
 
 // Orders the LDS accesses of the threads sweeping one replica between two
 // colours.  When a replica lives inside one wave, the wave's LDS operations
@@ -338,9 +345,79 @@ __device__ __forceinline__ uint32_t eo_unsat(const uint8_t *row, const EOGroup &
     const uint32_t hi = lds32(row, gr.hi), lo = lds32(row, gr.lo);
     const uint32_t xa = gr.sh == 1u ? lo : hi;  // the aligned x neighbour word
     const uint32_t xs = __builtin_amdgcn_alignbyte(hi, lo, gr.sh);
-    return (own ^ xa ^ gr.j[0]) + (own ^ xs ^ gr.j[1]) + (own ^ lds32(row, gr.yp) ^ gr.j[2]) +
-           (own ^ lds32(row, gr.ym) ^ gr.j[3]) + (own ^ lds32(row, gr.zp) ^ gr.j[4]) +
-           (own ^ lds32(row, gr.zm) ^ gr.j[5]);
+    return (xor3(own, xa, gr.j[0]) + xor3(own, xs, gr.j[1]) + xor3(own, lds32(row, gr.yp), gr.j[2])) +
+           (xor3(own, lds32(row, gr.ym), gr.j[3]) + xor3(own, lds32(row, gr.zp), gr.j[4]) +
+            xor3(own, lds32(row, gr.zm), gr.j[5]));
+}
+
+// Metropolis decision of the four sites of a block: n >= 3 unsatisfied bonds
+// (dE <= 0) always flips; otherwise site i flips when word i of the draw is
+// below the threshold of its dE.  tab holds the thresholds by 4 n (bytes);
+// every byte of n is <= 6, so 4 n stays inside its byte.
+__device__ __forceinline__ uint32_t eo_flip(uint32_t n, uint4 u, const uint8_t *tab)
+{
+    const uint32_t n4 = n << 2;
+    uint32_t flip = ((n + 0x05050505u) >> 3) & 0x01010101u;
+    flip |= u.x < *reinterpret_cast<const uint32_t *>(tab + (n4 & 0x1Cu)) ? 0x00000001u : 0u;
+    flip |= u.y < *reinterpret_cast<const uint32_t *>(tab + __builtin_amdgcn_ubfe(n4, 8, 5)) ? 0x00000100u : 0u;
+    flip |= u.z < *reinterpret_cast<const uint32_t *>(tab + __builtin_amdgcn_ubfe(n4, 16, 5)) ? 0x00010000u : 0u;
+    flip |= u.w < *reinterpret_cast<const uint32_t *>(tab + __builtin_amdgcn_ubfe(n4, 24, 5)) ? 0x01000000u : 0u;
+    return flip;
+}
+
+// All N_S sweeps of the replicas of the tile.  ALL: beta = 0, every move is
+// accepted.  The replica groups of the last pass may run past the tile's
+// rows into unused LDS rows (the tile holds a multiple of RP rows); their
+// results are never stored.
+template <int L, bool ALL>
+__device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, const EOGroup (&gr)[2][EOShape<L>::GPT],
+                                          const uint8_t *tab, int *unsat, int r0, int nrows)
+{
+    using SH = EOShape<L>;
+    const int qsub = threadIdx.x / SH::TPR;
+    const uint32_t key0 = I.key0, key1 = I.key1;
+    for (int qb = 0; qb < nrows; qb += SH::RP) {
+        const int q0 = qb + qsub;
+        uint8_t *row = lds + q0 * SH::N;
+        for (int t = 0; t < I.NS; ++t) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int gi = 0; gi < SH::GPT; ++gi) {
+                    const EOGroup &g = gr[c][gi];
+#pragma unroll
+                    for (int j = 0; j < SH::RPT; ++j) {
+                        uint8_t *rj = row + j * SH::RSTRIDE;
+                        const uint32_t own = lds32(rj, g.own);
+                        const uint32_t n = eo_unsat(rj, g, own);
+                        uint32_t flip = 0x01010101u;
+                        if constexpr (!ALL) {
+                            const uint32_t r = (uint32_t)(r0 + q0 + j * SH::RPG);
+                            const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                            flip = eo_flip(n, u, tab);
+                        }
+                        *reinterpret_cast<uint32_t *>(rj + g.own) = own ^ flip;
+                    }
+                }
+                colour_barrier<SH::kWaveLocal>();
+            }
+        }
+        // energy: every bond joins a colour-0 and a colour-1 site, so the
+        // unsatisfied bonds are the sum of n over colour-0 sites.
+#pragma unroll
+        for (int j = 0; j < SH::RPT; ++j) {
+            const uint8_t *rj = row + j * SH::RSTRIDE;
+            uint32_t part = 0;
+#pragma unroll
+            for (int gi = 0; gi < SH::GPT; ++gi) {
+                const uint32_t n = eo_unsat(rj, gr[0][gi], lds32(rj, gr[0][gi].own));
+                part = __builtin_amdgcn_sad_u8(n, 0u, part);
+            }
+            atomicAdd(&unsat[q0 + j * SH::RPG], (int)part);
+        }
+        // the rows of the next pass belong to other replicas: no barrier
+    }
+    __syncthreads();
 }
 
 template <int L>
@@ -361,77 +438,36 @@ __global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work 
     sweep_done(I, k);
 }
 
+// The tile holds tile_rows rows (a multiple of EOShape<L>::RP) of N bytes,
+// then tile_rows unsatisfied-bond counters.
 template <int L>
 __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
 {
     using SH = EOShape<L>;
-    const int row_bytes = I.row_bytes;
-    uint32_t *thr = reinterpret_cast<uint32_t *>(lds + tile_rows * row_bytes);  // [8]
-    int *unsat = reinterpret_cast<int *>(thr + 8);
+    // thresholds by 4 n at a fixed LDS address: T(dE = 12, 8, 4) for
+    // n = 0, 1, 2; unused above
+    __shared__ uint32_t tab[8];
+    int *unsat = reinterpret_cast<int *>(lds + tile_rows * SH::N);
     const TileIO io = tile_io(I);
-    tile_load(io, lds, r0, nrows, row_bytes);
+    tile_load(io, lds, r0, nrows, SH::N);
     const uint4 th = I.thr[k];
     const bool all = th.w != 0;
-    if (threadIdx.x < 8) thr[threadIdx.x] = threadIdx.x == 0 ? th.z : threadIdx.x == 1 ? th.y : threadIdx.x == 2 ? th.x : 0u;
-    for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] = 0;
+    if (threadIdx.x < 8) tab[threadIdx.x] = threadIdx.x == 0 ? th.z : threadIdx.x == 1 ? th.y : threadIdx.x == 2 ? th.x : 0u;
+    for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) unsat[q] = 0;
 
     const int lane_r = threadIdx.x % SH::TPR;  // position inside the replica
-    const int qsub = threadIdx.x / SH::TPR;    // which of the RP replicas
     EOGroup gr[2][SH::GPT];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int gi = 0; gi < SH::GPT; ++gi) eo_group_setup<L>(gr[c][gi], I.jeo, c, lane_r + gi * SH::TPR);
-    const uint32_t key0 = I.key0, key1 = I.key1;
     __syncthreads();
-
-    for (int qb = 0; qb < nrows; qb += SH::RP) {
-        const int q = qb + qsub;
-        const bool active = q < nrows;
-        uint8_t *row = lds + q * row_bytes;
-        const uint32_t r = (uint32_t)(r0 + q);
-        for (int t = 0; t < I.NS; ++t) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                if (active) {
-#pragma unroll
-                    for (int gi = 0; gi < SH::GPT; ++gi) {
-                        const EOGroup &g = gr[c][gi];
-                        const uint32_t own = lds32(row, g.own);
-                        const uint32_t n = eo_unsat(row, g, own);
-                        uint32_t flip;
-                        if (all) {
-                            flip = 0x01010101u;
-                        } else {
-                            const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
-                            // n >= 3 (dE <= 0) is always accepted
-                            flip = ((n + 0x05050505u) >> 3) & 0x01010101u;
-                            flip |= (u.x < thr[n & 7u] ? 1u : 0u);
-                            flip |= (u.y < thr[(n >> 8) & 7u] ? 1u : 0u) << 8;
-                            flip |= (u.z < thr[(n >> 16) & 7u] ? 1u : 0u) << 16;
-                            flip |= (u.w < thr[(n >> 24) & 7u] ? 1u : 0u) << 24;
-                        }
-                        *reinterpret_cast<uint32_t *>(row + g.own) = own ^ flip;
-                    }
-                }
-                colour_barrier<SH::kWaveLocal>();
-            }
-        }
-        // energy: every bond joins a colour-0 and a colour-1 site, so the
-        // unsatisfied bonds are the sum of n over colour-0 sites.
-        if (active) {
-            uint32_t part = 0;
-#pragma unroll
-            for (int gi = 0; gi < SH::GPT; ++gi) {
-                const uint32_t own = lds32(row, gr[0][gi].own);
-                const uint32_t n = eo_unsat(row, gr[0][gi], own);
-                part += (n & 0xFFu) + ((n >> 8) & 0xFFu) + ((n >> 16) & 0xFFu) + (n >> 24);
-            }
-            atomicAdd(&unsat[q], (int)part);
-        }
-        __syncthreads();
-    }
-    tile_store(io, lds, r0, nrows, row_bytes);
+    const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
+    if (all)
+        eo_sweeps<L, true>(I, k, lds, gr, tb, unsat, r0, nrows);
+    else
+        eo_sweeps<L, false>(I, k, lds, gr, tb, unsat, r0, nrows);
+    tile_store(io, lds, r0, nrows, SH::N);
     tile_energy_out(I, io, unsat, r0, nrows);
     tile_family_count(I, io, r0, nrows);
 }
