@@ -86,10 +86,34 @@ typedef struct pamc_options {
     int timing;              /* 1: record HIP events around the sweep and the
                                 resampling kernels of every step (see
                                 pamc_phase_times); 0 (default): no events   */
+    int group_replicas;      /* L other than 8 and 16 (colour-major sweep):
+                                replicas one sweep workgroup holds at once;
+                                0 = the library's choice.  Its threads
+                                (threads per replica x group_replicas) must
+                                be whole 64-lane waves, at most 1024        */
+    int autotune;            /* 1: when tile_rows and group_replicas are 0,
+                                pick them by timing the candidate shapes on
+                                a throw-away run first (see pamc_autotune);
+                                0 (default): a fixed rule                   */
 } pamc_options;
 
 /* Fills *opt with the defaults described above. */
 void pamc_default_options(pamc_options *opt);
+
+/* Sweep workgroup shape for lattice size L, population R and `sweeps`
+ * sweeps per step, chosen by measurement: each candidate shape runs three
+ * temperature steps (one warm-up) of a throw-away run with seeded +-J
+ * couplings at beta = 0.5, timed by HIP events on opt's stream and device,
+ * and the fastest sweep wins.  Results of a run never depend on the shape.
+ * Choices are cached per process by (kernel, L, sweeps, capacity rounded up
+ * to a power of two); a cached shape is returned without measuring.  The
+ * throw-away run needs the device memory of one run of this size.
+ * Outputs (each may be NULL): *tile_rows, *group_replicas (0 where the
+ * kernel has a fixed value), *ns_per_attempt (sweep time per spin-flip
+ * attempt of the winner).
+ * Errors: PAMC_ERR_INVALID, PAMC_ERR_NOMEM, PAMC_ERR_DEVICE. */
+int pamc_autotune(int L, int64_t R, int sweeps, const pamc_options *opt, int *tile_rows, int *group_replicas,
+                  double *ns_per_attempt);
 
 typedef struct pamc_ctx pamc_ctx;
 
@@ -170,6 +194,8 @@ typedef struct pamc_state {
 
 /* Reads the current step and population size (no copies). */
 int pamc_get_shape(const pamc_ctx *ctx, int *step, int64_t *R);
+/* Sweep workgroup shape the run uses (see tile_rows, group_replicas). */
+int pamc_sweep_shape(const pamc_ctx *ctx, int *tile_rows, int *group_replicas);
 
 /* Copies the current population into the caller's buffers (sized by
  * pamc_get_shape); any NULL array is skipped. */
@@ -230,6 +256,9 @@ typedef struct pamc_server pamc_server;
 typedef struct pamc_server_options {
     int max_active;      /* most instances on the device at once (0 = 256) */
     int device;          /* -1 = current                                    */
+    int autotune;        /* 1: each request's sweep shape is chosen by
+                            measurement at submission (pamc_autotune, cached
+                            per process); 0: the fixed rule                 */
 } pamc_server_options;
 
 typedef struct pamc_result {

@@ -101,7 +101,7 @@ def _torch_available() -> bool:
 
 def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
                   torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0,
-                  graphs=True):
+                  graphs=True, group_replicas=0, autotune=False):
     lib = _capi.load()
     opt = _capi.Options()
     lib.pamc_default_options(ctypes.byref(opt))
@@ -111,6 +111,8 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     opt.fuse_gather = 1 if fuse_gather else 0
     opt.timing = 1 if timing else 0
     opt.tile_rows = int(tile_rows)
+    opt.group_replicas = int(group_replicas)
+    opt.autotune = 1 if autotune else 0
     opt.graphs = 1 if graphs else 0
     if overlap_steps is not None:
         ov = np.ascontiguousarray(overlap_steps, dtype=np.int32)
@@ -124,12 +126,23 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     return opt
 
 
+def autotune(L, R, sweeps, torch_stream=True):
+    """Sweep workgroup shape chosen by measurement (``pamc_autotune``):
+    (tile_rows, group_replicas, sweep ns per attempt).  Cached per process."""
+    keep = []
+    opt = _make_options(torch_stream=torch_stream, keep=keep)
+    t, g, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(_capi.load().pamc_autotune(int(L), int(R), int(sweeps), ctypes.byref(opt), ctypes.byref(t),
+                                      ctypes.byref(g), ctypes.byref(ns)), "pamc_autotune")
+    return t.value, g.value, ns.value
+
+
 class Pamc:
     """One population-annealing run on the GPU (``pamc_create``)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
-                 graphs=True):
+                 graphs=True, group_replicas=0, autotune=False):
         lib = _capi.load()
         self.L = int(L)
         self.N = self.L ** 3
@@ -140,7 +153,8 @@ class Pamc:
         J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
         opt = _make_options(capacity, overlap_steps, fuse_gather, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
-                            tile_rows=tile_rows, graphs=graphs)
+                            tile_rows=tile_rows, graphs=graphs, group_replicas=group_replicas,
+                            autotune=autotune)
         self._opt = opt
         h = ctypes.c_void_p()
         _check(lib.pamc_create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),
@@ -200,6 +214,13 @@ class Pamc:
         _check(_capi.load().pamc_get_shape(self._h, ctypes.byref(k), ctypes.byref(R)), "pamc_get_shape")
         return k.value, R.value
 
+    def sweep_shape(self):
+        """(tile_rows, group_replicas) of the sweep workgroups."""
+        t = ctypes.c_int()
+        g = ctypes.c_int()
+        _check(_capi.load().pamc_sweep_shape(self._h, ctypes.byref(t), ctypes.byref(g)), "pamc_sweep_shape")
+        return t.value, g.value
+
     def get_state(self) -> dict:
         k, Rk = self.shape()
         spins = np.zeros((Rk, self.N), dtype=np.int8)
@@ -237,7 +258,7 @@ class Pamc:
 class PamcBatch:
     """Many independent instances annealed together (``pamc_batch_*``)."""
 
-    def __init__(self, instances, fuse_gather=True, torch_stream=True, graphs=True):
+    def __init__(self, instances, fuse_gather=True, torch_stream=True, graphs=True, autotune=False):
         lib = _capi.load()
         self._keep = []
         n = len(instances)
@@ -253,7 +274,8 @@ class PamcBatch:
                                     int(d["seed"]) & (2**64 - 1))
             self.nT.append(len(b))
             self.N.append(L ** 3)
-        opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs)
+        opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs,
+                            autotune=autotune)
         h = ctypes.c_void_p()
         _check(lib.pamc_batch_create(n, arr, ctypes.byref(opt), ctypes.byref(h)), "pamc_batch_create")
         self._h = h
@@ -297,9 +319,9 @@ class PamcBatch:
 class PamcServer:
     """Request loop with continuous batching under an HBM budget."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 256):
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 256, autotune: bool = False):
         lib = _capi.load()
-        opt = _capi.ServerOptions(int(max_active), -1)
+        opt = _capi.ServerOptions(int(max_active), -1, 1 if autotune else 0)
         h = ctypes.c_void_p()
         _check(lib.pamc_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
                                       ctypes.byref(h)), "pamc_server_create")

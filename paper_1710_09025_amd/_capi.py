@@ -39,6 +39,8 @@ class Options(ctypes.Structure):
         ("tile_rows", ctypes.c_int),
         ("graphs", ctypes.c_int),
         ("timing", ctypes.c_int),
+        ("group_replicas", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -91,7 +93,7 @@ class Instance(ctypes.Structure):
 
 
 class ServerOptions(ctypes.Structure):
-    _fields_ = [("max_active", ctypes.c_int), ("device", ctypes.c_int)]
+    _fields_ = [("max_active", ctypes.c_int), ("device", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -109,6 +111,9 @@ class Result(ctypes.Structure):
 P = ctypes.c_void_p
 SIGNATURES = {
     "pamc_default_options": (None, [ctypes.POINTER(Options)]),
+    "pamc_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Options),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double)]),
     "pamc_create": (ctypes.c_int, [ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_uint64, ctypes.POINTER(Options), ctypes.POINTER(P)]),
     "pamc_anneal": (ctypes.c_int, [P, ctypes.c_int]),
@@ -118,6 +123,7 @@ SIGNATURES = {
     "pamc_overlap_hist": (ctypes.c_int, [P, ctypes.c_int, P]),
     "pamc_step_sums": (ctypes.c_int, [P, P, P, ctypes.c_int]),
     "pamc_get_shape": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]),
+    "pamc_sweep_shape": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "pamc_get_state": (ctypes.c_int, [P, ctypes.POINTER(State)]),
     "pamc_set_state": (ctypes.c_int, [P, ctypes.POINTER(State)]),
     "pamc_thresholds": (ctypes.c_int, [P, P, P]),

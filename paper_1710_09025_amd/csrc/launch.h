@@ -18,8 +18,10 @@ void launch_init(const Inst *insts, const Work *work, int nwork, hipStream_t st)
 void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st);
 // sweeps of one temperature step; the last workgroup of each instance also
 // measures the step and prepares its resampling table
+// (tpr, rp: threads per replica and replicas per workgroup of the
+// colour-major kernel; unused by the others)
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
-                  hipStream_t st);
+                  int rp, hipStream_t st);
 // copy counts, family entropy, overlap; the last workgroup of each instance
 // finishes the prefix sum and advances the step
 void launch_post(const Inst *insts, const Work *work, int nwork, hipStream_t st);

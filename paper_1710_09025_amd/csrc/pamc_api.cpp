@@ -29,6 +29,9 @@ struct pamc_batch {
 namespace pamc {
 int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
               const pamc_options &opt, HostInst &h);
+bool shape_valid(const HostInst &h, int tile_rows, int rp, const char **why);
+void default_shape(HostInst &h, int gmax);
+int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt);
 }
 
 namespace {
@@ -89,30 +92,27 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     } else {
         h.ovl_slot[nT - 1] = h.ovl_n++;
     }
-    if (h.variant == pamc::kSweepLex) {
-        int tr = (512 + li.gmax - 1) / li.gmax;
-        tr = std::min(tr, std::max(1, 16384 / h.row_bytes));
-        h.tile_rows = std::max(1, tr);
-    } else if (h.variant == pamc::kSweepEO8 || h.variant == pamc::kSweepEO16) {
-        h.tile_rows = L == 8 ? 32 : 8;
-    } else {
-        // colour-major: four passes of the replicas a workgroup sweeps at once
-        h.tile_rows = 4 * pamc::cm_replicas_per_block(h.tpr);
-    }
+    // sweep workgroup shape: explicit, tuned by measurement, or the default
+    pamc::default_shape(h, li.gmax);
     if (opt.tile_rows < 0 || opt.tile_rows > 4096) return invalid("tile_rows out of range");
-    if (opt.tile_rows > 0) {
-        int tr = opt.tile_rows;
+    if (opt.group_replicas < 0 || opt.group_replicas > 1024) return invalid("group_replicas out of range");
+    const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3;
+    if (opt.tile_rows > 0 || (cm && opt.group_replicas > 0)) {
+        const int rp = cm && opt.group_replicas > 0 ? opt.group_replicas : h.rp;
+        // without an explicit tile: the default number of passes per workgroup
+        int tr = opt.tile_rows > 0 ? opt.tile_rows : (cm ? h.tile_rows / h.rp * rp : h.tile_rows);
         // the even/odd-x kernel sweeps a fixed number of replicas per pass
         if (h.variant == pamc::kSweepEO8 || h.variant == pamc::kSweepEO16) {
-            const int rp = pamc::eo_replicas_per_pass(L);
-            tr = (tr + rp - 1) / rp * rp;
+            const int p = pamc::eo_replicas_per_pass(L);
+            tr = (tr + p - 1) / p * p;
         }
-        // the workgroup's LDS (at most 64 KB) must hold its tile
-        const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3;
-        const int64_t lds = cm ? 2 * (int64_t)h.row_bytes * pamc::cm_replicas_per_block(h.tpr) + 32 + 4 * (int64_t)tr
-                               : (int64_t)tr * h.row_bytes + 32 + 4 * (int64_t)tr;
-        if (lds > 65536) return invalid("tile_rows too large for this lattice");
+        const char *why = nullptr;
+        if (!pamc::shape_valid(h, tr, rp, &why)) return invalid(why);
         h.tile_rows = tr;
+        h.rp = rp;
+    } else if (opt.autotune) {
+        const int st = pamc::tune_shape(h, opt, nullptr);
+        if (st != PAMC_OK) return st;
     }
     return PAMC_OK;
 }
@@ -230,6 +230,47 @@ int pamc_step_sums(const pamc_ctx *ctx, double *S, double *T, int n)
 {
     if (!ctx) return invalid("ctx is NULL");
     return const_cast<pamc_ctx *>(ctx)->run.step_sums(0, S, T, n);
+}
+
+int pamc_sweep_shape(const pamc_ctx *ctx, int *tile_rows, int *group_replicas)
+{
+    if (!ctx) return invalid("ctx is NULL");
+    const HostInst &h = ctx->run.inst(0);
+    if (tile_rows) *tile_rows = h.tile_rows;
+    if (group_replicas) *group_replicas = h.rp;
+    return PAMC_OK;
+}
+
+int pamc_autotune(int L, int64_t R, int sweeps, const pamc_options *opt, int *tile_rows, int *group_replicas,
+                  double *ns_per_attempt)
+{
+    if (L < 2 || L > 32) return invalid("L must be in [2, 32]");
+    pamc_options o = resolve(opt);
+    o.tile_rows = 0;
+    o.group_replicas = 0;
+    o.autotune = 0;
+    // seeded +-J couplings (splitmix64): the sweep's speed does not depend
+    // on their values
+    const int N = L * L * L;
+    std::vector<int8_t> J((size_t)3 * N);
+    uint64_t x = 0x2545F4914F6CDD1Dull;
+    for (auto &j : J) {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        j = (z >> 63) ? 1 : -1;
+    }
+    const double beta[2] = {0.0, 0.5};
+    HostInst h;
+    int st = pamc::make_inst(L, J.data(), R, beta, 2, sweeps, 1, o, h);
+    if (st != PAMC_OK) return st;
+    st = pamc::tune_shape(h, o, ns_per_attempt);
+    if (st != PAMC_OK) return st;
+    if (tile_rows) *tile_rows = h.tile_rows;
+    if (group_replicas) *group_replicas = h.rp;
+    return PAMC_OK;
 }
 
 int pamc_get_shape(const pamc_ctx *ctx, int *step, int64_t *R)

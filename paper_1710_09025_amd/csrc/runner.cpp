@@ -510,6 +510,19 @@ int Runner::upload_inst(int i)
     return PAMC_OK;
 }
 
+int Runner::set_shape(int i, int tile_rows, int rp)
+{
+    if (i < 0 || i >= max_slots_ || !used_[i]) return PAMC_ERR_STATE;
+    HostInst &h = inst_[i];
+    h.tile_rows = tile_rows;
+    h.rp = rp;
+    h.dev.tile_rows = tile_rows;
+    h.dev.sweep_tiles = (int32_t)((h.Rcap + tile_rows - 1) / tile_rows);
+    HIPCHK(hipStreamSynchronize(stream_), "set_shape sync");
+    HIPCHK(hipMemcpy(d_insts_ + i, &h.dev, sizeof(Inst), hipMemcpyHostToDevice), "update instance shape");
+    return build_work(active_);
+}
+
 int Runner::build_work(const std::vector<int> &active)
 {
     HIPCHK(hipStreamSynchronize(stream_), "build_work sync");
@@ -525,13 +538,13 @@ int Runner::build_work(const std::vector<int> &active)
         if (bytes && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
         return p;
     };
-    std::map<std::tuple<int, int, int, int, int>, std::vector<Work>> groups;
+    std::map<std::tuple<int, int, int, int, int, int>, std::vector<Work>> groups;
     std::vector<Work> rows, post;
     std::vector<uint32_t> list;
     for (int i : active) {
         const HostInst &h = inst_[i];
         const uint32_t ii = (uint32_t)i;
-        auto &g = groups[std::make_tuple(h.variant, h.L, h.tile_rows, h.row_bytes, h.tpr)];
+        auto &g = groups[std::make_tuple(h.variant, h.L, h.tile_rows, h.row_bytes, h.tpr, h.rp)];
         for (int64_t r = 0; r < h.Rcap; r += h.tile_rows) g.push_back(Work{ii, (uint32_t)r, 0u, 0u});
         for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) {
             rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
@@ -549,6 +562,7 @@ int Runner::build_work(const std::vector<int> &active)
         sg.tile_rows = std::get<2>(kv.first);
         sg.row_bytes = std::get<3>(kv.first);
         sg.tpr = std::get<4>(kv.first);
+        sg.rp = std::get<5>(kv.first);
         sg.nwork = (int)kv.second.size();
         sg.work = (Work *)upload(kv.second.data(), kv.second.size() * sizeof(Work));
         if (!sg.work) return dev_fail(hipErrorOutOfMemory, "upload sweep work");
@@ -595,7 +609,7 @@ void Runner::drop_graph()
 int Runner::launch_step_kernels()
 {
     for (auto &g : sweep_groups_)
-        launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, stream_);
+        launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, stream_);
     if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 2], stream_), "hipEventRecord");
     launch_post(d_insts_, d_post_, npost_, stream_);
     launch_expand(d_insts_, d_rows_, nrows_work_, stream_);

@@ -23,6 +23,7 @@ struct HostInst {
     int L = 0, N = 0, ncol = 0, layout = 0, variant = 0;
     int row_bytes = 0, tile_rows = 0;
     int tpr = 0;                       // colour-major sweep: threads per replica
+    int rp = 0;                        // colour-major sweep: replicas per workgroup
     int64_t R = 0, Rcap = 0;
     int nT = 0, NS = 0;
     uint64_t seed = 0;
@@ -93,6 +94,9 @@ public:
     int get_state(int i, pamc_state *st);
     int set_state(int i, const pamc_state *st);
     int thresholds(int i, uint32_t *out, uint8_t *acc);
+    // Changes the sweep workgroup shape of slot i (between steps; results
+    // do not depend on it) and rebuilds the work lists of the active set.
+    int set_shape(int i, int tile_rows, int rp);
     const HostInst &inst(int i) const { return inst_[i]; }
     HostInst &inst(int i) { return inst_[i]; }
     const std::vector<int> &active() const { return active_; }
@@ -128,7 +132,7 @@ private:
 
     // work lists for the current active set
     struct SweepGroup {
-        int variant, tile_rows, row_bytes, tpr;
+        int variant, tile_rows, row_bytes, tpr, rp;
         Work *work;
         int nwork;
     };

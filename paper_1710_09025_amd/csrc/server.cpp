@@ -58,6 +58,8 @@ struct pamc_server {
     size_t budget = 0;
     size_t used = 0;
     int max_active = 256;
+    int device = -1;
+    bool autotune = false;  // sweep shapes chosen by measurement at submission
     std::mutex mu;
     std::condition_variable cv;
     std::deque<uint64_t> queue;
@@ -223,9 +225,11 @@ int pamc_server_create(size_t hbm_budget_bytes, const pamc_server_options *opt, 
     if (!s) return PAMC_ERR_NOMEM;
     s->budget = hbm_budget_bytes;
     s->max_active = (opt && opt->max_active > 0) ? opt->max_active : 256;
+    s->device = opt ? opt->device : -1;
+    s->autotune = opt && opt->autotune;
     pamc_options o;
     pamc_default_options(&o);
-    if (opt) o.device = opt->device;
+    o.device = s->device;
     int st = s->run.setup(o, s->max_active);
     if (st != PAMC_OK) {
         delete s;
@@ -244,6 +248,8 @@ int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_
     }
     pamc_options o;
     pamc_default_options(&o);
+    o.device = s->device;
+    o.autotune = s->autotune ? 1 : 0;
     Request r;
     int st = pamc::make_inst(inst->L, inst->couplings, inst->R, inst->beta, inst->n_temps, inst->sweeps, inst->seed,
                              o, r.h);

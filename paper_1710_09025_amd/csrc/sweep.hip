@@ -687,11 +687,10 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
 int cm_replicas_per_block(int tpr) { return tpr >= 256 ? 1 : 256 / tpr; }
 
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
-                  hipStream_t st)
+                  int rp, hipStream_t st)
 {
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
-        const int rp = cm_replicas_per_block(tpr);
         const size_t lds = 2 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
         if (variant == kSweepCM2)
             k_sweep_cm<2><<<nwork, tpr * rp, lds, st>>>(insts, work, tile_rows);

@@ -1,0 +1,189 @@
+// tune.cpp -- sweep workgroup shapes chosen by measurement.
+//
+// How fast the sweep runs depends on how many replica rows one workgroup
+// holds (tile_rows) and, for the colour-major kernel, on how many replicas
+// it sweeps at once (replicas per workgroup): a small population needs small
+// tiles to spread over the 256 compute units, a large one amortises the tile
+// load, the energy epilogue and the measurement tail over more rows.  The
+// tuner runs each candidate shape on a throw-away run of the instance (its
+// couplings, L, R, capacity and sweeps per step) at a constant beta = 0.5,
+// where every replica gets exactly one copy and the population stays at R,
+// and keeps the shape with the shortest sweep time measured by HIP events.
+// Every shape gives bit-identical results, so the choice only affects
+// speed.  Choices are cached for the life of the process, keyed by kernel,
+// L, sweeps per step and the capacity rounded up to a power of two.
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "runner.h"
+
+namespace pamc {
+
+int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
+              const pamc_options &opt, HostInst &h);
+
+namespace {
+
+constexpr int64_t kMaxLds = 65536;  // dynamic LDS of one sweep workgroup
+
+bool is_cm(const HostInst &h) { return h.variant == kSweepCM2 || h.variant == kSweepCM3; }
+bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kSweepEO16; }
+
+int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
+{
+    if (is_cm(h)) return 2 * (int64_t)h.row_bytes * rp + 32 + 4 * (int64_t)tile_rows;
+    return (int64_t)tile_rows * h.row_bytes + 32 + 4 * (int64_t)tile_rows;
+}
+
+struct Choice {
+    int tile_rows, rp;
+    double ns_per_attempt;
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int>, Choice> g_cache;
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+// Whether (tile_rows, rp) is a shape the instance's sweep kernel can run;
+// on failure *why says what is wrong.
+bool shape_valid(const HostInst &h, int tile_rows, int rp, const char **why)
+{
+    const char *w = nullptr;
+    if (tile_rows < 1 || tile_rows > 4096) {
+        w = "tile_rows must be in [1, 4096]";
+    } else if (is_eo(h) && tile_rows % eo_replicas_per_pass(h.L) != 0) {
+        w = "tile_rows must be a multiple of the replicas one pass sweeps";
+    } else if (is_cm(h) && (rp < 1 || (h.tpr * rp) % 64 != 0 || h.tpr * rp > 1024)) {
+        w = "replicas per workgroup must make whole waves of at most 1024 threads";
+    } else if (sweep_lds(h, tile_rows, is_cm(h) ? rp : 0) > kMaxLds) {
+        w = "the workgroup's tile does not fit in LDS";
+    }
+    if (why) *why = w;
+    return w == nullptr;
+}
+
+// The shape used without tuning: enough workgroups to fill the chip when
+// the population is small, up to four passes per workgroup when it is
+// large.  gmax: Philox blocks of the largest colour.
+void default_shape(HostInst &h, int gmax)
+{
+    const int64_t target = 512;  // workgroups: two per compute unit
+    if (is_eo(h)) {
+        const int rp = eo_replicas_per_pass(h.L);
+        const int64_t m = std::max<int64_t>(1, std::min<int64_t>(4, h.Rcap / (target * rp)));
+        h.tile_rows = (int)(m * rp);
+        h.rp = 0;
+    } else if (is_cm(h)) {
+        h.rp = cm_replicas_per_block(h.tpr);
+        const int64_t m = std::max<int64_t>(1, std::min<int64_t>(4, h.Rcap / (target * h.rp)));
+        h.tile_rows = (int)(m * h.rp);
+    } else {
+        // per-site kernel: about 512 Philox blocks of work per workgroup
+        int tr = (512 + gmax - 1) / gmax;
+        tr = std::min(tr, std::max(1, 16384 / h.row_bytes));
+        h.tile_rows = std::max(1, tr);
+        h.rp = 0;
+    }
+}
+
+std::vector<std::pair<int, int>> shape_candidates(const HostInst &h)
+{
+    std::vector<std::pair<int, int>> c;
+    if (is_eo(h)) {
+        const int rp = eo_replicas_per_pass(h.L);
+        for (int m = 1; m <= 64; m *= 2)
+            if (shape_valid(h, m * rp, 0, nullptr) && m * rp <= 2 * h.Rcap) c.emplace_back(m * rp, 0);
+    } else if (is_cm(h)) {
+        for (int rp = 1; h.tpr * rp <= 1024; rp *= 2) {
+            if ((h.tpr * rp) % 64 != 0) continue;
+            for (int m = 1; m <= 8; m *= 2)
+                if (shape_valid(h, m * rp, rp, nullptr) && m * rp <= 2 * h.Rcap) c.emplace_back(m * rp, rp);
+        }
+    } else {
+        for (int t = 1; t <= 4096; t *= 2)
+            if (shape_valid(h, t, 0, nullptr) && t <= 2 * h.Rcap) c.emplace_back(t, 0);
+    }
+    return c;
+}
+
+int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
+{
+    const auto key = std::make_tuple(h.variant, h.L, h.NS, ceil_log2(h.Rcap));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            h.tile_rows = it->second.tile_rows;
+            h.rp = it->second.rp;
+            if (ns_per_attempt) *ns_per_attempt = it->second.ns_per_attempt;
+            return PAMC_OK;
+        }
+    }
+    const auto cand = shape_candidates(h);
+    if (cand.empty()) {
+        set_error("no valid sweep shape for this lattice");
+        return PAMC_ERR_INVALID;
+    }
+    // throw-away run: constant beta, three steps per candidate (one warm-up)
+    pamc_options o = opt;
+    o.timing = 1;
+    o.graphs = 0;
+    o.overlap_steps = nullptr;
+    o.n_overlap_steps = 0;
+    o.capacity = h.Rcap;
+    o.tile_rows = 0;
+    o.group_replicas = 0;
+    o.autotune = 0;
+    o.fuse_gather = 1;
+    const int nT = 1 + 3 * (int)cand.size();
+    const std::vector<double> beta((size_t)nT, 0.5);
+    HostInst t;
+    int st = make_inst(h.L, h.J.data(), h.R, beta.data(), nT, h.NS, h.seed, o, t);
+    if (st != PAMC_OK) return st;
+    Runner run;
+    st = run.setup(o, 1);
+    if (st != PAMC_OK) return st;
+    const int slot = run.add_instance(std::move(t));
+    if (slot < 0) return slot;
+    st = run.init_instances({slot});
+    if (st == PAMC_OK) st = run.build_work({slot});
+    if (st != PAMC_OK) return st;
+    const double attempts = (double)h.R * h.N * h.NS;
+    Choice best{h.tile_rows, h.rp, INFINITY};
+    for (const auto &c : cand) {
+        st = run.set_shape(slot, c.first, c.second);
+        if (st == PAMC_OK) st = run.enqueue_steps(1);
+        if (st == PAMC_OK) st = run.sync();
+        double sw = 0.0, other = 0.0;
+        int64_t n = 0;
+        if (st == PAMC_OK) st = run.phase_times(&sw, &other, &n);
+        if (st == PAMC_OK) st = run.enqueue_steps(2);
+        if (st == PAMC_OK) st = run.sync();
+        if (st == PAMC_OK) st = run.phase_times(&sw, &other, &n);
+        if (st == PAMC_OK) st = run.inst_status(slot, nullptr, nullptr);
+        if (st != PAMC_OK) return st;
+        const double ns = sw * 1e6 / std::max<int64_t>(1, n) / attempts;
+        if (ns < best.ns_per_attempt) best = Choice{c.first, c.second, ns};
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = best;
+    }
+    h.tile_rows = best.tile_rows;
+    h.rp = best.rp;
+    if (ns_per_attempt) *ns_per_attempt = best.ns_per_attempt;
+    return PAMC_OK;
+}
+
+}  // namespace pamc

@@ -4,6 +4,7 @@ codes before any device work (no GPU needed)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -66,6 +67,64 @@ def test_footprint_scales_with_population(lib):
     cap = 20000 + int(np.ceil(8 * np.sqrt(20000))) + 64
     assert b >= 2 * cap * 512
     assert lib.pamc_footprint(1, 10, 10, None) == -1
+
+
+STRUCTS = {
+    "pamc_options": "Options",
+    "pamc_step_obs": "StepObs",
+    "pamc_state": "State",
+    "pamc_instance": "Instance",
+    "pamc_server_options": "ServerOptions",
+    "pamc_result": "Result",
+}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every field of the binding's ctypes structures sits at the offset the
+    C compiler gives it in include/pamc.h, and the sizes agree."""
+    from paper_1710_09025_amd import _capi
+
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(_capi, pyname)
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{pyname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        pyname, field, value = line.split()
+        cls = getattr(_capi, pyname)
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), (pyname, field, got, value)
+
+
+@pytest.mark.parametrize("case", ["tile_rows", "lds", "group_waves", "group_large"])
+def test_invalid_sweep_shapes_are_rejected_on_the_host(lib, case):
+    from paper_1710_09025_amd import _capi
+
+    L = {"tile_rows": 8, "lds": 16, "group_waves": 4, "group_large": 10}[case]
+    J = np.ones((3, L ** 3), dtype=np.int8)
+    beta = np.linspace(0, 1, 3)
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    if case == "tile_rows":
+        opt.tile_rows = 5000
+    elif case == "lds":
+        opt.tile_rows = 64          # 64 rows of 4096 bytes exceed the workgroup's LDS
+    elif case == "group_waves":
+        opt.group_replicas = 3      # 8 threads per replica: 24 threads, not whole waves
+    else:
+        opt.group_replicas = 16     # 128 threads per replica: 2048 threads
+    h = ctypes.c_void_p()
+    st = lib.pamc_create(L, J.ctypes.data_as(ctypes.c_void_p), 100, beta.ctypes.data_as(ctypes.c_void_p),
+                         len(beta), 1, 1, ctypes.byref(opt), ctypes.byref(h))
+    assert st == _capi.ERR_INVALID, lib.pamc_last_error()
+    assert not h.value
 
 
 @pytest.mark.parametrize("case", ["L", "coupling", "beta_order", "beta_nan", "R", "sweeps", "capacity"])
