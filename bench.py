@@ -71,18 +71,21 @@ def attempts_of(obs, N, sweeps):
     return float(np.sum(obs["R"][obs["measured"] == 1])) * N * sweeps
 
 
-def time_anneals(name, steps, warmup):
-    """Creates warmup + steps run handles up front (default options: each
-    temperature step is a replayed hipGraph) and anneals them one after
-    another for the wall time; one more anneal with HIP events around every
-    step's sweep launch gives the per-kernel device time."""
+def time_anneals(name, steps, warmup, autotune=True):
+    """Creates warmup + steps run handles up front (each temperature step a
+    replayed hipGraph; sweep shapes chosen by the autotuner at creation,
+    outside the timed region) and anneals them one after another for the
+    wall time; one more anneal with HIP events around every step's kernels
+    gives the per-kernel device time."""
     import torch
 
     from paper_1710_09025_amd import Pamc
 
     cfg, J, beta = workload_inputs(name)
     N = cfg["L"] ** 3
-    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"]) for _ in range(warmup + steps)]
+    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune)
+            for _ in range(warmup + steps)]
+    shape = runs[0].sweep_shape()
     for r in runs[:warmup]:
         assert r.anneal() == 0
     torch.cuda.synchronize()
@@ -96,9 +99,10 @@ def time_anneals(name, steps, warmup):
     for r in runs:
         r.close()
     del runs
-    timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True)
+    timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, autotune=autotune)
+    assert timed.sweep_shape() == shape
     assert timed.anneal() == 0
-    sweep_ms, other_ms, nsteps = timed.phase_times()
+    sweep_ms, other_ms, _, nsteps = timed.phase_times()
     obs_t = timed.observables()
     for key in ("R", "sum_E", "sum_E2"):
         assert np.array_equal(obs[key], obs_t[key]), "timed and graph runs differ"
@@ -107,7 +111,38 @@ def time_anneals(name, steps, warmup):
     att = attempts_of(obs, N, cfg["sweeps"])
     Rbar = float(np.mean(obs["R"]))
     return dict(cfg=cfg, wall_s=t1 - t0, sweep_ms=sweep_ms, other_ms=other_ms, nsteps=nsteps,
-                attempts_per_anneal=att, mean_R=Rbar, N=N)
+                attempts_per_anneal=att, mean_R=Rbar, N=N, shape=shape)
+
+
+def gather_bench(name, n_steps):
+    """The stand-alone gather of surviving replicas (fuse_gather off) over the
+    first n_steps temperature steps of a workload, timed with HIP events:
+    algorithmic bytes per output replica = row read + row write + energy and
+    family read and write + the copy-map read."""
+    import torch
+
+    from paper_1710_09025_amd import Pamc
+
+    cfg, J, beta = workload_inputs(name)
+    p = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, fuse_gather=False,
+             autotune=True)
+    assert p.anneal(n_steps) == 0
+    sweep_ms, resample_ms, gather_ms, nsteps = p.phase_times()
+    obs = p.observables()
+    k_now, R_now = p.shape()
+    assert k_now == n_steps
+    p.close()
+    torch.cuda.empty_cache()
+    rb = ((cfg["L"] ** 3 + 15) // 16) * 16
+    # the gather after step k writes the R_{k+1} replicas of step k + 1
+    rows = float(np.sum(obs["R"][1:n_steps])) + R_now
+    per_row = 2 * rb + 2 * 8 + 4
+    gbs = rows * per_row / (gather_ms / 1e3) / 1e9
+    return {"kernel": "k_gather", "steps": int(nsteps), "bytes_per_replica": per_row,
+            "avg_launch_ms": round(gather_ms / nsteps, 4), "achieved_gbs": round(gbs, 1),
+            "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "resample_ms_per_step": round(resample_ms / nsteps, 4),
+            "sweep_ms_per_step": round(sweep_ms / nsteps, 4)}
 
 
 def roofline(res):
@@ -130,6 +165,7 @@ def roofline(res):
             "kernel": f"k_sweep_eo<{res['cfg']['L']}> (N_S sweeps of every replica at one temperature)"
                       if res["cfg"]["L"] in (8, 16) else "k_sweep_lex",
             "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
+            "sweep_shape": {"tile_rows": res["shape"][0], "group_replicas": res["shape"][1]},
             "avg_launch_ms": round(res["sweep_ms"] / max(1, res["nsteps"]), 4),
             "hbm_gbs_algorithmic": round(alg_bytes / (res["sweep_ms"] / max(1, res["nsteps"]) / 1e3) / 1e9, 1),
             "hbm_frac_algorithmic": round(alg_bytes / (res["sweep_ms"] / max(1, res["nsteps"]) / 1e3) / 1e9
@@ -159,12 +195,11 @@ def batch_bench(n_inst, plain_per_L):
     steps) against separate per-instance runs on a stratified sample."""
     import torch
 
-    from paper_1710_09025_amd import Pamc, PamcBatch
+    from paper_1710_09025_amd import Pamc, PamcBatch, autotune
 
     insts = pi.batch_instances(n_inst)
-    att = sum(float(d["R"]) * d["L"] ** 3 * d["sweeps"] * len(d["beta"]) for d in insts)
     t0 = time.perf_counter()
-    b = PamcBatch(insts)
+    b = PamcBatch(insts, autotune=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = b.anneal()
@@ -186,7 +221,7 @@ def batch_bench(n_inst, plain_per_L):
         ts, tc = [], []
         for d in sample:
             c0 = time.perf_counter()
-            p = Pamc(d["L"], d["couplings"], d["R"], d["beta"], d["sweeps"], d["seed"])
+            p = Pamc(d["L"], d["couplings"], d["R"], d["beta"], d["sweeps"], d["seed"], autotune=True)
             torch.cuda.synchronize()
             c1 = time.perf_counter()
             assert p.anneal() == 0
@@ -197,6 +232,11 @@ def batch_bench(n_inst, plain_per_L):
             tc.append(c2 - c0)
         per_L[L] = (float(np.mean(ts)), float(np.mean(tc)), len(sample))
     count = {L: sum(1 for d in insts if d["L"] == L) for L in per_L}
+    shapes = {}
+    for L in per_L:
+        d = next(d for d in insts if d["L"] == L)
+        t, g, ns = autotune(L, d["R"], d["sweeps"])  # cached: the shapes both sides used
+        shapes[str(L)] = {"tile_rows": t, "group_replicas": g, "sweep_ns_per_attempt": round(ns, 6)}
     plain_anneal = sum(count[L] * per_L[L][0] for L in per_L)
     plain_total = sum(count[L] * per_L[L][1] for L in per_L)
     return {
@@ -209,7 +249,21 @@ def batch_bench(n_inst, plain_per_L):
         "plain_instances_per_s_incl_create": round(n_inst / plain_total, 3),
         "plain_sample": f"{plain_per_L} per L, extrapolated by instance count",
         "speedup": round(plain_anneal / (t2 - t1), 3),
+        "sweep_shapes_autotuned": shapes,
     }
+
+
+def warm_serving_shapes(sweeps=10):
+    """Tunes the sweep shapes of the serving size classes before the stream
+    (as a deployment would ship a tuning cache): every L of the request mix
+    and a grid of populations covering its capacity classes."""
+    from paper_1710_09025_amd import autotune
+
+    t0 = time.perf_counter()
+    for L in range(4, 15):
+        for R in (5000, 8000, 12000, 16000, 24000, 32000, 40000, 50000):
+            autotune(L, R, sweeps)
+    return time.perf_counter() - t0
 
 
 def serve_bench(n_req, rate, budget_gb):
@@ -217,7 +271,7 @@ def serve_bench(n_req, rate, budget_gb):
     from paper_1710_09025_amd import PamcServer
 
     reqs = pi.serving_requests(n_req, rate=rate)
-    srv = PamcServer(int(budget_gb * (1 << 30)), max_active=256)
+    srv = PamcServer(int(budget_gb * (1 << 30)), max_active=256, autotune=True)
     ids = []
     t0 = time.perf_counter()
     for d in reqs:
@@ -238,7 +292,7 @@ def serve_bench(n_req, rate, budget_gb):
     lat = np.array(lat)
     att = sum(float(d["R"]) * d["L"] ** 3 * d["sweeps"] * len(d["beta"]) for d in reqs)
     span = last - first
-    return {"requests": n_req, "offered_rate_per_s": rate, "hbm_budget_gb": budget_gb,
+    return {"requests": n_req, "offered_rate_per_s": round(rate, 3), "hbm_budget_gb": budget_gb,
             "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
             "instances_per_s": round(n_req / span, 3),
@@ -259,6 +313,10 @@ def main():
     ap.add_argument("--serve", type=int, default=300, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--serve-light", type=int, default=150,
+                    help="requests of the second stream at 0.8x the measured saturation rate (0: skip)")
+    ap.add_argument("--gather-steps", type=int, default=20,
+                    help="temperature steps of the stand-alone gather measurement (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -311,6 +369,8 @@ def main():
         "sweep_share": round(res["sweep_ms"] / (res["sweep_ms"] + res["other_ms"]), 4),
         "roofline": roofline(res),
     }
+    if args.gather_steps:
+        line["gather"] = {name: gather_bench(name, args.gather_steps) for name in (args.workload, "L16_R500000")}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
     if not args.no_extra:
@@ -328,7 +388,13 @@ def main():
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
         if args.serve:
-            extra["serving"] = serve_bench(args.serve, args.serve_rate, args.serve_budget_gb)
+            warm = warm_serving_shapes()
+            sat = serve_bench(args.serve, args.serve_rate, args.serve_budget_gb)
+            sat["shape_tuning_before_stream_s"] = round(warm, 2)
+            extra["serving"] = sat
+            if args.serve_light:
+                extra["serving_at_0.8x_saturation"] = serve_bench(
+                    args.serve_light, 0.8 * sat["instances_per_s"], args.serve_budget_gb)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

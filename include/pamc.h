@@ -211,11 +211,17 @@ int pamc_set_state(pamc_ctx *ctx, const pamc_state *st);
 int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all);
 
 /* Device time of the steps run since the previous call (options.timing =
- * 1): sweep_ms sums the sweep kernels of every step (sweeps of all
- * replicas, energies, histogram), other_ms the measurement and resampling
- * kernels; n_steps counts the steps.  Measured with HIP events on the run's
- * stream.  PAMC_ERR_STATE if timing is off. */
-int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *other_ms, int64_t *n_steps);
+ * 1), measured with HIP events on the run's stream:
+ *   sweep_ms     the sweep kernels (sweeps of all replicas, energies,
+ *                energy histogram, measurement and the resampling table);
+ *   resample_ms  copy counts, family and overlap statistics, prefix sum and
+ *                copy map;
+ *   gather_ms    the stand-alone gather of surviving replicas (zero when the
+ *                gather is fused into the next sweep, fuse_gather = 1);
+ *   n_steps      the number of steps.
+ * Any output may be NULL.  PAMC_ERR_STATE if timing is off. */
+int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *resample_ms, double *gather_ms,
+                     int64_t *n_steps);
 
 /* Device footprint in bytes of a run with these parameters. */
 int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt);

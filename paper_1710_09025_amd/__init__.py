@@ -238,11 +238,12 @@ class Pamc:
         _check(_capi.load().pamc_set_state(self._h, ctypes.byref(st)), "pamc_set_state")
 
     def phase_times(self):
-        """(sweep ms, resampling ms, steps) since the last call (timing=True)."""
-        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        _check(_capi.load().pamc_phase_times(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
-               "pamc_phase_times")
-        return a.value, b.value, n.value
+        """(sweep ms, resampling ms, stand-alone gather ms, steps) since the
+        last call (timing=True)."""
+        a, b, g, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(_capi.load().pamc_phase_times(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(g),
+                                             ctypes.byref(n)), "pamc_phase_times")
+        return a.value, b.value, g.value, n.value
 
     @property
     def stream_handle(self) -> int:

@@ -128,6 +128,7 @@ SIGNATURES = {
     "pamc_set_state": (ctypes.c_int, [P, ctypes.POINTER(State)]),
     "pamc_thresholds": (ctypes.c_int, [P, P, P]),
     "pamc_phase_times": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]),
     "pamc_footprint": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Options)]),
     "pamc_destroy": (None, [P]),

@@ -303,10 +303,10 @@ int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all)
     return const_cast<pamc_ctx *>(ctx)->run.thresholds(0, out, accept_all);
 }
 
-int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *other_ms, int64_t *n_steps)
+int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *resample_ms, double *gather_ms, int64_t *n_steps)
 {
     if (!ctx) return invalid("ctx is NULL");
-    return ctx->run.phase_times(sweep_ms, other_ms, n_steps);
+    return ctx->run.phase_times(sweep_ms, resample_ms, gather_ms, n_steps);
 }
 
 void pamc_destroy(pamc_ctx *ctx) { delete ctx; }

@@ -510,6 +510,14 @@ int Runner::upload_inst(int i)
     return PAMC_OK;
 }
 
+std::vector<Work> gather_items(uint32_t slot, int64_t Rcap, int row_bytes)
+{
+    const int g = std::max(1, std::min(1024, 32768 / row_bytes));
+    std::vector<Work> v;
+    for (int64_t r = 0; r < Rcap; r += g) v.push_back(Work{slot, (uint32_t)r, 0u, (uint32_t)g});
+    return v;
+}
+
 int Runner::set_shape(int i, int tile_rows, int rp)
 {
     if (i < 0 || i >= max_slots_ || !used_[i]) return PAMC_ERR_STATE;
@@ -539,7 +547,7 @@ int Runner::build_work(const std::vector<int> &active)
         return p;
     };
     std::map<std::tuple<int, int, int, int, int, int>, std::vector<Work>> groups;
-    std::vector<Work> rows, post;
+    std::vector<Work> rows, post, gath;
     std::vector<uint32_t> list;
     for (int i : active) {
         const HostInst &h = inst_[i];
@@ -550,6 +558,7 @@ int Runner::build_work(const std::vector<int> &active)
             rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
             post.push_back(Work{ii, (uint32_t)r, kRoleCopies, 0u});
         }
+        for (const Work &w : gather_items(ii, h.Rcap, h.row_bytes)) gath.push_back(w);
         int64_t fp2 = 1;
         while (fp2 < h.R) fp2 <<= 1;
         for (int64_t f = 0; f < fp2; f += 2048) post.push_back(Work{ii, (uint32_t)f, kRoleFamilies, 0u});
@@ -569,9 +578,11 @@ int Runner::build_work(const std::vector<int> &active)
         sweep_groups_.push_back(sg);
     }
     d_rows_ = (Work *)upload(rows.data(), rows.size() * sizeof(Work));
+    d_gather_ = (Work *)upload(gath.data(), gath.size() * sizeof(Work));
+    ngather_ = (int)gath.size();
     d_post_ = (Work *)upload(post.data(), post.size() * sizeof(Work));
     d_list_ = (uint32_t *)upload(list.data(), list.size() * 4);
-    if (!d_rows_ || !d_post_ || !d_list_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
+    if (!d_rows_ || !d_post_ || !d_list_ || !d_gather_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
     nrows_work_ = (int)rows.size();
     npost_ = (int)post.size();
     nlist_ = (int)list.size();
@@ -610,11 +621,12 @@ int Runner::launch_step_kernels()
 {
     for (auto &g : sweep_groups_)
         launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, stream_);
-    if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 2], stream_), "hipEventRecord");
+    if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 3], stream_), "hipEventRecord");
     launch_post(d_insts_, d_post_, npost_, stream_);
     launch_expand(d_insts_, d_rows_, nrows_work_, stream_);
+    if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 2], stream_), "hipEventRecord");
     if (!fuse_) {
-        launch_gather(d_insts_, d_rows_, nrows_work_, stream_);
+        launch_gather(d_insts_, d_gather_, ngather_, stream_);
         launch_flip(d_insts_, d_list_, nlist_, stream_);
     }
     return PAMC_OK;
@@ -624,13 +636,13 @@ int Runner::enqueue_step()
 {
     if (poisoned_) return PAMC_ERR_DEVICE;
     if (timing_) {
-        while (ev_pool_.size() < ev_used_ + 3) {
+        while (ev_pool_.size() < ev_used_ + 4) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e), "hipEventCreate");
             ev_pool_.push_back(e);
         }
-        ev_used_ += 3;
-        HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 3], stream_), "hipEventRecord");
+        ev_used_ += 4;
+        HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 4], stream_), "hipEventRecord");
     }
     if (graphs_) {
         if (!graph_exec_) {
@@ -655,24 +667,24 @@ int Runner::enqueue_step()
     return PAMC_OK;
 }
 
-int Runner::phase_times(double *sweep_ms, double *other_ms, int64_t *n_steps)
+int Runner::phase_times(double *sweep_ms, double *resample_ms, double *gather_ms, int64_t *n_steps)
 {
     if (!timing_) {
         set_error("timing is off for this run");
         return PAMC_ERR_STATE;
     }
     HIPCHK(hipStreamSynchronize(stream_), "timing sync");
-    double a = 0.0, b = 0.0;
-    for (size_t j = 0; j + 3 <= ev_used_; j += 3) {
-        float t1 = 0.f, t2 = 0.f;
-        HIPCHK(hipEventElapsedTime(&t1, ev_pool_[j], ev_pool_[j + 1]), "hipEventElapsedTime");
-        HIPCHK(hipEventElapsedTime(&t2, ev_pool_[j + 1], ev_pool_[j + 2]), "hipEventElapsedTime");
-        a += t1;
-        b += t2;
-    }
-    if (sweep_ms) *sweep_ms = a;
-    if (other_ms) *other_ms = b;
-    if (n_steps) *n_steps = (int64_t)(ev_used_ / 3);
+    double t[3] = {0.0, 0.0, 0.0};
+    for (size_t j = 0; j + 4 <= ev_used_; j += 4)
+        for (int p = 0; p < 3; ++p) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev_pool_[j + p], ev_pool_[j + p + 1]), "hipEventElapsedTime");
+            t[p] += ms;
+        }
+    if (sweep_ms) *sweep_ms = t[0];
+    if (resample_ms) *resample_ms = t[1];
+    if (gather_ms) *gather_ms = t[2];
+    if (n_steps) *n_steps = (int64_t)(ev_used_ / 4);
     ev_used_ = 0;
     return PAMC_OK;
 }
@@ -853,8 +865,7 @@ int Runner::materialise(int i)
     int st = read_ctl(i, ctl, status);
     if (st != PAMC_OK) return st;
     if (!ctl[2]) return PAMC_OK;
-    std::vector<Work> rows;
-    for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) rows.push_back(Work{(uint32_t)i, (uint32_t)r, 0u, 0u});
+    const std::vector<Work> rows = gather_items((uint32_t)i, h.Rcap, h.row_bytes);
     Work *d = (Work *)alloc_.get(rows.size() * sizeof(Work));
     uint32_t *l = (uint32_t *)alloc_.get(4);
     if (!d || !l) {

@@ -104,7 +104,7 @@ public:
     bool fused() const { return fuse_; }
     bool poisoned() const { return poisoned_; }
     // Sums of the recorded per-step event intervals since the last call.
-    int phase_times(double *sweep_ms, double *other_ms, int64_t *n_steps);
+    int phase_times(double *sweep_ms, double *resample_ms, double *gather_ms, int64_t *n_steps);
     bool timing() const { return timing_; }
 
 private:
@@ -137,8 +137,10 @@ private:
         int nwork;
     };
     std::vector<SweepGroup> sweep_groups_;
-    Work *d_rows_ = nullptr;   // 1024-row blocks (expand, gather)
+    Work *d_rows_ = nullptr;   // 1024-row blocks (expand)
     int nrows_work_ = 0;
+    Work *d_gather_ = nullptr; // row blocks of about 32 KB of spins (stand-alone gather)
+    int ngather_ = 0;
     Work *d_post_ = nullptr;   // post-launch workgroups with their roles
     int npost_ = 0;
     uint32_t *d_list_ = nullptr;
@@ -151,13 +153,17 @@ private:
     hipGraphExec_t graph_exec_ = nullptr;
     void drop_graph();
     int launch_step_kernels();
-    // timing: three events per enqueued step (before the sweeps, after the
-    // sweeps, after the step), reused from a pool
+    // timing: four events per enqueued step (before the sweeps, after the
+    // sweeps, after the resampling, after the stand-alone gather), reused
+    // from a pool
     bool timing_ = false;
     std::vector<hipEvent_t> ev_pool_;
     size_t ev_used_ = 0;
 };
 
 void set_error(const std::string &msg);
+// Work items of the stand-alone gather of instance slot i: blocks of about
+// 32 KB of spin rows, the row count in Work::pad.
+std::vector<Work> gather_items(uint32_t slot, int64_t Rcap, int row_bytes);
 
 }  // namespace pamc

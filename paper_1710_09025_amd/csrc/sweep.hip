@@ -477,13 +477,14 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
 // sites (two colours for even L, three for odd L).  Storage kLayoutCM: the
 // four sites of a Philox block are one aligned word of the row.  In LDS every
 // replica slot holds the row and its complement (0/1 swapped); a bond with
-// coupling -1 reads the neighbour from the complement, so byte-wise
-// s ^ nb_slot counts unsatisfied bonds directly.  A thread owns Philox block
-// g of every colour and keeps the 24 neighbour byte addresses of its four
-// sites in registers for all replicas and sweeps; each neighbour word is
-// assembled from four byte reads.  Energy: every bond joins two sites of
-// different colours, so U = (1/2) sum over all sites of their unsatisfied
-// bonds.
+// coupling -1 reads the neighbour from the complement, so every neighbour
+// byte read is s_nb ^ [J = -1], the bond is unsatisfied when it differs from
+// the site's own spin, and with m = the sum of the six bytes a site has
+// n = m unsatisfied bonds when s = 0 and 6 - m when s = 1.  A thread owns
+// Philox block g of every colour and keeps the 24 neighbour byte addresses
+// of its four sites in registers for all replicas and sweeps.  Energy:
+// every bond joins two sites of different colours, so U = (1/2) sum over all
+// sites of their unsatisfied bonds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void replica_barrier(int tpr)
 {
@@ -496,63 +497,47 @@ __device__ __forceinline__ void replica_barrier(int tpr)
     }
 }
 
-template <int NCOL>
 struct CMBlock {
-    const uint8_t *nb[24];  // neighbour bytes (spin or complement copy)
-    uint8_t *own;           // the four sites, spin copy
-    uint32_t vmask;         // 0x01 in bytes of real sites
-    uint32_t ctr;           // Philox counter word 0
+    uint32_t nb[24];  // LDS byte offsets of the neighbours, [direction][site]
+    uint32_t own;     // LDS byte offset of the four sites (spin copy)
+    uint32_t vmask;   // 0x01 in bytes of real sites
+    uint32_t ctr;     // Philox counter word 0
     bool has;
 };
 
-template <int NCOL>
-__device__ __forceinline__ uint32_t cm_count(const CMBlock<NCOL> &b, uint32_t own)
+// Per byte: unsatisfied bonds of the four sites, (m ^ 7 s) - s with m <= 6
+// the per-site sum of the neighbour bytes (no carries or borrows between
+// bytes).
+__device__ __forceinline__ uint32_t cm_count(const uint8_t *lds, const CMBlock &b, uint32_t own)
 {
-    uint32_t n = 0;
+    uint32_t m = 0;
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        uint32_t w = (uint32_t)b.nb[4 * d][0];
-        w |= (uint32_t)b.nb[4 * d + 1][0] << 8;
-        w |= (uint32_t)b.nb[4 * d + 2][0] << 16;
-        w |= (uint32_t)b.nb[4 * d + 3][0] << 24;
-        n += own ^ w;
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t t = (uint32_t)lds[b.nb[i]] + lds[b.nb[4 + i]] + lds[b.nb[8 + i]];
+        const uint32_t u = (uint32_t)lds[b.nb[12 + i]] + lds[b.nb[16 + i]] + lds[b.nb[20 + i]];
+        m += (t + u) << (8 * i);
     }
-    return n;
+    // 7 s per byte as (s rotated left by 3) - s: own has no bits above
+    // bit 24, so the rotation is a shift (and stays off the quarter-rate
+    // multiplier)
+    const uint32_t own7 = __builtin_amdgcn_alignbit(own, own, 29) - own;
+    return (m ^ own7) - own;
 }
 
-template <int NCOL>
-__device__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+// Sweeps of the replicas of the tile, RP at a time, each loaded into the
+// thread group's LDS slot (through the copy map) and stored back after its
+// N_S sweeps.  ALL: beta = 0, every move is accepted.
+template <int NCOL, bool ALL>
+__device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, const CMBlock (&blk)[NCOL],
+                                          const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows)
 {
     const int tpr = I.tpr;
     const int RP = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
-    const int slot_bytes = 2 * row_bytes;
-    uint32_t *thr = reinterpret_cast<uint32_t *>(lds + RP * slot_bytes);  // [8]
-    int *unsat = reinterpret_cast<int *>(thr + 8);
-    const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * slot_bytes;
-    CMBlock<NCOL> blk[NCOL];
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-        const int g = lane_r;
-        blk[c].has = g < I.gcs[c];
-        blk[c].ctr = ((uint32_t)c << 24) | (uint32_t)g;
-        const int gg = blk[c].has ? g : 0;
-        const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
-#pragma unroll
-        for (int i = 0; i < 24; ++i) blk[c].nb[i] = slot + d[i];
-        blk[c].vmask = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
-        blk[c].own = slot + I.cbase[c] + 4 * gg;
-    }
-    const uint4 th = I.thr[k];
-    const bool all = th.w != 0;
-    if (threadIdx.x < 8) thr[threadIdx.x] = threadIdx.x == 0 ? th.z : threadIdx.x == 1 ? th.y : threadIdx.x == 2 ? th.x : 0u;
-    for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) unsat[q] = 0;
-    const uint32_t key0 = I.key0, key1 = I.key1;
+    uint8_t *slot = lds + qsub * 2 * row_bytes;
     const int nvec = row_bytes >> 4;
-    __syncthreads();
-
+    const uint32_t key0 = I.key0, key1 = I.key1;
     for (int qb = 0; qb < nrows; qb += RP) {
         const int q = qb + qsub;
         const bool active = q < nrows;
@@ -571,25 +556,18 @@ __device__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nr
         for (int t = 0; t < I.NS; ++t) {
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
-                const CMBlock<NCOL> &b = blk[c];
+                const CMBlock &b = blk[c];
                 if (active && b.has) {
-                    const uint32_t own = *reinterpret_cast<const uint32_t *>(b.own);
-                    const uint32_t n = cm_count<NCOL>(b, own);
-                    uint32_t flip;
-                    if (all) {
-                        flip = 0x01010101u;
-                    } else {
+                    const uint32_t own = *reinterpret_cast<const uint32_t *>(lds + b.own);
+                    uint32_t flip = b.vmask;
+                    if constexpr (!ALL) {
+                        const uint32_t n = cm_count(lds, b, own);
                         const uint4 u = philox10(make_uint4(b.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
-                        flip = ((n + 0x05050505u) >> 3) & 0x01010101u;
-                        flip |= (u.x < thr[n & 7u] ? 1u : 0u);
-                        flip |= (u.y < thr[(n >> 8) & 7u] ? 1u : 0u) << 8;
-                        flip |= (u.z < thr[(n >> 16) & 7u] ? 1u : 0u) << 16;
-                        flip |= (u.w < thr[(n >> 24) & 7u] ? 1u : 0u) << 24;
+                        flip &= eo_flip(n, u, tab);
                     }
-                    flip &= b.vmask;
                     const uint32_t nw = own ^ flip;
-                    *reinterpret_cast<uint32_t *>(b.own) = nw;
-                    *reinterpret_cast<uint32_t *>(b.own + row_bytes) = nw ^ 0x01010101u;
+                    *reinterpret_cast<uint32_t *>(lds + b.own) = nw;
+                    *reinterpret_cast<uint32_t *>(lds + b.own + row_bytes) = nw ^ 0x01010101u;
                 }
                 replica_barrier(tpr);
             }
@@ -599,10 +577,10 @@ __device__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nr
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 if (!blk[c].has) continue;
-                const uint32_t own = *reinterpret_cast<const uint32_t *>(blk[c].own);
+                const uint32_t own = *reinterpret_cast<const uint32_t *>(lds + blk[c].own);
                 // padding bytes have no neighbours of their own: mask them
-                const uint32_t n = cm_count<NCOL>(blk[c], own) & (blk[c].vmask * 0xFFu);
-                part += (n & 0xFFu) + ((n >> 8) & 0xFFu) + ((n >> 16) & 0xFFu) + (n >> 24);
+                const uint32_t n = cm_count(lds, blk[c], own) & (blk[c].vmask * 0xFFu);
+                part = __builtin_amdgcn_sad_u8(n, 0u, part);
             }
             atomicAdd(&unsat[q], (int)part);
             const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
@@ -611,6 +589,44 @@ __device__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nr
         }
         replica_barrier(tpr);
     }
+}
+
+template <int NCOL>
+__device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+{
+    // thresholds by 4 n at a fixed LDS address (see eo_flip)
+    __shared__ uint32_t tab[8];
+    const int tpr = I.tpr;
+    const int RP = (int)blockDim.x / tpr;
+    const int row_bytes = I.row_bytes;
+    const int slot_bytes = 2 * row_bytes;
+    int *unsat = reinterpret_cast<int *>(lds + RP * slot_bytes + 32);
+    const TileIO io = tile_io(I);
+    const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
+    const uint32_t slot = (uint32_t)(qsub * slot_bytes);
+    CMBlock blk[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+        const int g = lane_r;
+        blk[c].has = g < I.gcs[c];
+        blk[c].ctr = ((uint32_t)c << 24) | (uint32_t)g;
+        const int gg = blk[c].has ? g : 0;
+        const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
+#pragma unroll
+        for (int i = 0; i < 24; ++i) blk[c].nb[i] = slot + d[i];
+        blk[c].vmask = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
+        blk[c].own = slot + (uint32_t)(I.cbase[c] + 4 * gg);
+    }
+    const uint4 th = I.thr[k];
+    const bool all = th.w != 0;
+    if (threadIdx.x < 8) tab[threadIdx.x] = threadIdx.x == 0 ? th.z : threadIdx.x == 1 ? th.y : threadIdx.x == 2 ? th.x : 0u;
+    for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) unsat[q] = 0;
+    __syncthreads();
+    const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
+    if (all)
+        cm_passes<NCOL, true>(I, k, lds, blk, tb, unsat, io, r0, nrows);
+    else
+        cm_passes<NCOL, false>(I, k, lds, blk, tb, unsat, io, r0, nrows);
     __syncthreads();
     // every bond was counted from both of its ends
     for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] >>= 1;
@@ -621,8 +637,10 @@ __device__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nr
     tile_family_count(I, io, r0, nrows);
 }
 
-template <int NCOL>
-__global__ __launch_bounds__(1024) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows)
+// MAXT: the largest workgroup the instantiation is built for (a 512-thread
+// bound leaves room for every neighbour address in registers).
+template <int NCOL, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
@@ -641,6 +659,8 @@ __global__ __launch_bounds__(1024) void k_sweep_cm(const Inst *insts, const Work
 // buffer receives source row map[d] (spins, energy, family).  Used when the
 // gather is not fused into the next sweep and to materialise a population
 // for export.  Runs after the step index has moved to the new population.
+// A work item is a block of w.pad destination rows (about 32 KB of spins);
+// each thread keeps four 16-byte loads in flight before its stores.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *work)
 {
@@ -649,21 +669,34 @@ __global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *w
     const int k = *I.k;
     if (k >= I.nT || I.status[0] || !*I.mapped) return;
     const int Rn = (int)I.Rk[k];
-    const int cur = *I.cur;
-    const int rows = min(kRowsPerBlock, Rn - (int)w.row0);
+    const int row0 = (int)w.row0;
+    const int rows = min((int)w.pad, Rn - row0);
     if (rows <= 0) return;
+    const int cur = *I.cur;
     const int per_row = I.row_bytes >> 4;
-    const uint8_t *src = I.spins[cur];
-    uint8_t *dst = I.spins[cur ^ 1];
-    for (int it = threadIdx.x; it < rows * per_row; it += blockDim.x) {
-        const int q = it / per_row, c = it - q * per_row;
-        const uint32_t d = w.row0 + q;
-        const uint32_t s = I.map[d];
-        *reinterpret_cast<uint4 *>(dst + (size_t)d * I.row_bytes + 16 * c) =
-            *reinterpret_cast<const uint4 *>(src + (size_t)s * I.row_bytes + 16 * c);
+    const int total = rows * per_row;
+    const uint4 *src = reinterpret_cast<const uint4 *>(I.spins[cur]);
+    uint4 *dst = reinterpret_cast<uint4 *>(I.spins[cur ^ 1]);
+    const int nt = (int)blockDim.x;
+    for (int base = threadIdx.x; base < total; base += 4 * nt) {
+        uint4 v[4];
+        size_t to[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int it = base + u * nt;
+            if (it < total) {
+                const int q = it / per_row, c = it - q * per_row;
+                const uint32_t d = (uint32_t)(row0 + q);
+                v[u] = src[(size_t)I.map[d] * per_row + c];
+                to[u] = (size_t)d * per_row + c;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * nt < total) dst[to[u]] = v[u];
     }
-    for (int q = threadIdx.x; q < rows; q += blockDim.x) {
-        const uint32_t d = w.row0 + q, s = I.map[d];
+    for (int q = threadIdx.x; q < rows; q += nt) {
+        const uint32_t d = (uint32_t)(row0 + q), s = I.map[d];
         I.E[cur ^ 1][d] = I.E[cur][s];
         I.fam[cur ^ 1][d] = I.fam[cur][s];
     }
@@ -692,10 +725,18 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
         const size_t lds = 2 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
-        if (variant == kSweepCM2)
-            k_sweep_cm<2><<<nwork, tpr * rp, lds, st>>>(insts, work, tile_rows);
-        else
-            k_sweep_cm<3><<<nwork, tpr * rp, lds, st>>>(insts, work, tile_rows);
+        const int nt = tpr * rp;
+        if (variant == kSweepCM2) {
+            if (nt <= 512)
+                k_sweep_cm<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+            else
+                k_sweep_cm<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+        } else {
+            if (nt <= 512)
+                k_sweep_cm<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+            else
+                k_sweep_cm<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+        }
         return;
     }
     const size_t lds = (size_t)tile_rows * row_bytes + 32 + 4 * (size_t)tile_rows;

@@ -165,12 +165,12 @@ int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
         st = run.set_shape(slot, c.first, c.second);
         if (st == PAMC_OK) st = run.enqueue_steps(1);
         if (st == PAMC_OK) st = run.sync();
-        double sw = 0.0, other = 0.0;
+        double sw = 0.0;
         int64_t n = 0;
-        if (st == PAMC_OK) st = run.phase_times(&sw, &other, &n);
+        if (st == PAMC_OK) st = run.phase_times(&sw, nullptr, nullptr, &n);
         if (st == PAMC_OK) st = run.enqueue_steps(2);
         if (st == PAMC_OK) st = run.sync();
-        if (st == PAMC_OK) st = run.phase_times(&sw, &other, &n);
+        if (st == PAMC_OK) st = run.phase_times(&sw, nullptr, nullptr, &n);
         if (st == PAMC_OK) st = run.inst_status(slot, nullptr, nullptr);
         if (st != PAMC_OK) return st;
         const double ns = sw * 1e6 / std::max<int64_t>(1, n) / attempts;
