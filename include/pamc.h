@@ -61,7 +61,12 @@ enum {
 enum { PAMC_SPINS_INT8 = 0, PAMC_SPINS_PACKED = 1 };
 
 typedef struct pamc_options {
-    int spin_format;         /* PAMC_SPINS_INT8 (default) or PAMC_SPINS_PACKED  */
+    int spin_format;         /* spin buffers in HBM: PAMC_SPINS_INT8 (default),
+                                one byte per site, or PAMC_SPINS_PACKED, one
+                                bit per site (rows 8x smaller; the sweeps
+                                expand a tile to bytes on chip and pack it
+                                when they write it back).  Results are
+                                identical for both                          */
     int64_t capacity;        /* rows reserved per buffer; 0 = R + ceil(8 sqrt R) + 64 */
     void *stream;            /* hipStream_t to run on; NULL = a library stream  */
     /* optional device allocator (e.g. a framework's caching allocator):
@@ -106,7 +111,8 @@ void pamc_default_options(pamc_options *opt);
  * couplings at beta = 0.5, timed by HIP events on opt's stream and device,
  * and the fastest sweep wins.  Results of a run never depend on the shape.
  * Choices are cached per process by (kernel, L, sweeps, capacity rounded up
- * to a power of two); a cached shape is returned without measuring.  The
+ * to a power of two, opt's spin format); a cached shape is returned without
+ * measuring.  The
  * throw-away run needs the device memory of one run of this size.
  * Outputs (each may be NULL): *tile_rows, *group_replicas (0 where the
  * kernel has a fixed value), *ns_per_attempt (sweep time per spin-flip
@@ -265,6 +271,8 @@ typedef struct pamc_server_options {
     int autotune;        /* 1: each request's sweep shape is chosen by
                             measurement at submission (pamc_autotune, cached
                             per process); 0: the fixed rule                 */
+    int spin_format;     /* PAMC_SPINS_INT8 or PAMC_SPINS_PACKED for every
+                            request (footprints follow it)                  */
 } pamc_server_options;
 
 typedef struct pamc_result {

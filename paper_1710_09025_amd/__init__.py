@@ -126,11 +126,12 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     return opt
 
 
-def autotune(L, R, sweeps, torch_stream=True):
+def autotune(L, R, sweeps, torch_stream=True, packed=False):
     """Sweep workgroup shape chosen by measurement (``pamc_autotune``):
     (tile_rows, group_replicas, sweep ns per attempt).  Cached per process."""
     keep = []
-    opt = _make_options(torch_stream=torch_stream, keep=keep)
+    opt = _make_options(torch_stream=torch_stream, keep=keep,
+                        spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
     t, g, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     _check(_capi.load().pamc_autotune(int(L), int(R), int(sweeps), ctypes.byref(opt), ctypes.byref(t),
                                       ctypes.byref(g), ctypes.byref(ns)), "pamc_autotune")
@@ -142,7 +143,7 @@ class Pamc:
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
-                 graphs=True, group_replicas=0, autotune=False):
+                 graphs=True, group_replicas=0, autotune=False, packed=False):
         lib = _capi.load()
         self.L = int(L)
         self.N = self.L ** 3
@@ -151,7 +152,8 @@ class Pamc:
         self.nT = len(self.beta)
         self._keep = []
         J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
-        opt = _make_options(capacity, overlap_steps, fuse_gather, torch_stream=torch_stream,
+        opt = _make_options(capacity, overlap_steps, fuse_gather,
+                            spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
                             tile_rows=tile_rows, graphs=graphs, group_replicas=group_replicas,
                             autotune=autotune)
@@ -259,7 +261,7 @@ class Pamc:
 class PamcBatch:
     """Many independent instances annealed together (``pamc_batch_*``)."""
 
-    def __init__(self, instances, fuse_gather=True, torch_stream=True, graphs=True, autotune=False):
+    def __init__(self, instances, fuse_gather=True, torch_stream=True, graphs=True, autotune=False, packed=False):
         lib = _capi.load()
         self._keep = []
         n = len(instances)
@@ -276,7 +278,7 @@ class PamcBatch:
             self.nT.append(len(b))
             self.N.append(L ** 3)
         opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs,
-                            autotune=autotune)
+                            autotune=autotune, spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
         h = ctypes.c_void_p()
         _check(lib.pamc_batch_create(n, arr, ctypes.byref(opt), ctypes.byref(h)), "pamc_batch_create")
         self._h = h
@@ -320,9 +322,10 @@ class PamcBatch:
 class PamcServer:
     """Request loop with continuous batching under an HBM budget."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 256, autotune: bool = False):
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 256, autotune: bool = False, packed: bool = False):
         lib = _capi.load()
-        opt = _capi.ServerOptions(int(max_active), -1, 1 if autotune else 0)
+        opt = _capi.ServerOptions(int(max_active), -1, 1 if autotune else 0,
+                                  _capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
         h = ctypes.c_void_p()
         _check(lib.pamc_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
                                       ctypes.byref(h)), "pamc_server_create")

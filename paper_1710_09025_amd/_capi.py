@@ -93,7 +93,8 @@ class Instance(ctypes.Structure):
 
 
 class ServerOptions(ctypes.Structure):
-    _fields_ = [("max_active", ctypes.c_int), ("device", ctypes.c_int), ("autotune", ctypes.c_int)]
+    _fields_ = [("max_active", ctypes.c_int), ("device", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("spin_format", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):

@@ -14,7 +14,9 @@ int cm_replicas_per_block(int tpr);
 // holds a multiple of this many rows
 int eo_replicas_per_pass(int L);
 
-void launch_init(const Inst *insts, const Work *work, int nwork, hipStream_t st);
+// lds_bytes: staging for packed rows (max(16384, row_bytes) when any instance
+// of the launch is packed, else 0)
+void launch_init(const Inst *insts, const Work *work, int nwork, size_t lds_bytes, hipStream_t st);
 void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st);
 // sweeps of one temperature step; the last workgroup of each instance also
 // measures the step and prepares its resampling table

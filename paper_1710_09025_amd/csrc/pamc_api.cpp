@@ -73,6 +73,8 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     h.layout = li.layout;
     h.variant = li.variant;
     h.row_bytes = li.row_bytes;
+    h.packed = opt.spin_format == PAMC_SPINS_PACKED ? 1 : 0;
+    h.srow_bytes = pamc::stored_row_bytes(li.row_bytes, h.packed != 0);
     h.tpr = li.tpr;
     h.R = R;
     h.Rcap = cap;
@@ -165,7 +167,7 @@ int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt)
     const pamc_options o = resolve(opt);
     const int64_t cap = o.capacity > 0 ? o.capacity : pamc::default_capacity(R);
     const int nov = (o.overlap_steps && o.n_overlap_steps > 0) ? o.n_overlap_steps : 1;
-    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov);
+    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED);
 }
 
 int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps, int sweeps,

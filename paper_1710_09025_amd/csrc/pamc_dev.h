@@ -53,7 +53,9 @@ struct StepRec {
 struct Inst {
     // problem
     int32_t L, N, ncol, layout;
-    int32_t row_bytes;  // bytes per replica row in the spin buffers (>= N, multiple of 16)
+    int32_t row_bytes;  // bytes per replica row in LDS, one byte per storage position (>= N, multiple of 16)
+    int32_t packed;     // 1: the spin buffers hold one bit per storage position
+    int32_t srow_bytes; // bytes per replica row in the spin buffers (row_bytes, or row_bytes / 8 rounded up to 16)
     int32_t nT, NS;
     uint32_t key0, key1;
     int32_t R;          // nominal population

@@ -119,7 +119,9 @@ __device__ void overlap_role(const Inst &I, int k, uint32_t p0, uint32_t *qh)
         __syncthreads();
     }
     const uint8_t *sp = I.spins[*I.cur];
-    const int words = I.row_bytes >> 4;
+    // 16-byte words of a stored row: bytes 0/1, or bits (both count the
+    // differing sites as the popcount of the XOR)
+    const int words = I.srow_bytes >> 4;
     int lpp = 1;  // lanes per pair, a power of two <= 64
     while (lpp < words && lpp < 64) lpp <<= 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -129,8 +131,8 @@ __device__ void overlap_role(const Inst &I, int k, uint32_t p0, uint32_t *qh)
         int diff = 0;
         if (q < npairs) {
             const int r = (int)p0 + q;
-            const uint4 *a = reinterpret_cast<const uint4 *>(sp + (size_t)r * I.row_bytes);
-            const uint4 *b = reinterpret_cast<const uint4 *>(sp + (size_t)(r + h) * I.row_bytes);
+            const uint4 *a = reinterpret_cast<const uint4 *>(sp + (size_t)r * I.srow_bytes);
+            const uint4 *b = reinterpret_cast<const uint4 *>(sp + (size_t)(r + h) * I.srow_bytes);
             for (int i = j; i < words; i += lpp) {
                 const uint4 x = a[i], y = b[i];
                 diff += __builtin_popcount(x.x ^ y.x) + __builtin_popcount(x.y ^ y.y) +

@@ -107,11 +107,11 @@ struct InstLayout {
         beta, rho, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, total;
 };
 
-InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
+InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool packed)
 {
     const int N = L * L * L;
     const LayoutInfo li = layout_for(L);
-    const int row_bytes = li.row_bytes;
+    const int row_bytes = stored_row_bytes(li.row_bytes, packed);
     const int ncol = li.ncol;
     const int nblk = (int)((Rcap + kRowsPerBlock - 1) / kRowsPerBlock);
     const int nlev = 3 * N + 1;
@@ -155,10 +155,12 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl)
 }
 }  // namespace
 
-size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl)
+int stored_row_bytes(int row_bytes, bool packed) { return packed ? (row_bytes + 127) / 128 * 16 : row_bytes; }
+
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed)
 {
     // R <= Rcap; use Rcap for the family counters as an upper bound
-    return layout_of(L, Rcap, Rcap, nT, n_ovl).total;
+    return layout_of(L, Rcap, Rcap, nT, n_ovl, packed).total;
 }
 
 Runner::~Runner()
@@ -284,7 +286,7 @@ int Runner::upload_inst(int i)
 {
     HostInst &h = inst_[i];
     const int L = h.L, N = h.N;
-    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n);
+    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n, h.packed != 0);
     h.bytes = lay.total;
     h.block = alloc_.get(lay.total);
     if (!h.block) {
@@ -300,6 +302,8 @@ int Runner::upload_inst(int i)
     d.ncol = h.ncol;
     d.layout = h.layout;
     d.row_bytes = h.row_bytes;
+    d.packed = h.packed;
+    d.srow_bytes = h.srow_bytes;
     d.nT = h.nT;
     d.NS = h.NS;
     d.key0 = (uint32_t)h.seed;
@@ -558,7 +562,7 @@ int Runner::build_work(const std::vector<int> &active)
             rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
             post.push_back(Work{ii, (uint32_t)r, kRoleCopies, 0u});
         }
-        for (const Work &w : gather_items(ii, h.Rcap, h.row_bytes)) gath.push_back(w);
+        for (const Work &w : gather_items(ii, h.Rcap, h.srow_bytes)) gath.push_back(w);
         int64_t fp2 = 1;
         while (fp2 < h.R) fp2 <<= 1;
         for (int64_t f = 0; f < fp2; f += 2048) post.push_back(Work{ii, (uint32_t)f, kRoleFamilies, 0u});
@@ -598,7 +602,10 @@ int Runner::init_instances(const std::vector<int> &slots)
     Work *d = (Work *)alloc_.get(w.size() * sizeof(Work));
     if (!d) return PAMC_ERR_NOMEM;
     HIPCHK(hipMemcpy(d, w.data(), w.size() * sizeof(Work), hipMemcpyHostToDevice), "upload init work");
-    launch_init(d_insts_, d, (int)w.size(), stream_);
+    size_t lds = 0;
+    for (int i : slots)
+        if (inst_[i].packed) lds = std::max(lds, (size_t)std::max(16384, inst_[i].row_bytes));
+    launch_init(d_insts_, d, (int)w.size(), lds, stream_);
     launch_energy(d_insts_, d, (int)w.size(), d_Jptr_, stream_);
     HIPCHK(hipGetLastError(), "init launch");
     HIPCHK(hipStreamSynchronize(stream_), "init sync");
@@ -865,7 +872,7 @@ int Runner::materialise(int i)
     int st = read_ctl(i, ctl, status);
     if (st != PAMC_OK) return st;
     if (!ctl[2]) return PAMC_OK;
-    const std::vector<Work> rows = gather_items((uint32_t)i, h.Rcap, h.row_bytes);
+    const std::vector<Work> rows = gather_items((uint32_t)i, h.Rcap, h.srow_bytes);
     Work *d = (Work *)alloc_.get(rows.size() * sizeof(Work));
     uint32_t *l = (uint32_t *)alloc_.get(4);
     if (!d || !l) {
@@ -916,12 +923,16 @@ int Runner::get_state(int i, pamc_state *stt)
     }
     const int cur = ctl[1];
     if (stt->spins) {
-        std::vector<uint8_t> buf((size_t)Rk * h.row_bytes);
+        std::vector<uint8_t> buf((size_t)Rk * h.srow_bytes);
         HIPCHK(hipMemcpy(buf.data(), h.dev.spins[cur], buf.size(), hipMemcpyDeviceToHost), "read spins");
         for (uint32_t r = 0; r < Rk; ++r) {
-            const uint8_t *row = buf.data() + (size_t)r * h.row_bytes;
+            const uint8_t *row = buf.data() + (size_t)r * h.srow_bytes;
             int8_t *o = stt->spins + (size_t)r * h.N;
-            for (int s = 0; s < h.N; ++s) o[s] = row[h.lex_pos[s]] ? 1 : -1;
+            for (int s = 0; s < h.N; ++s) {
+                const int p = h.lex_pos[s];
+                const int up = h.packed ? (row[p >> 3] >> (p & 7)) & 1 : row[p];
+                o[s] = up ? 1 : -1;
+            }
         }
     }
     if (stt->E) HIPCHK(hipMemcpy(stt->E, h.dev.E[cur], (size_t)Rk * 4, hipMemcpyDeviceToHost), "read E");
@@ -938,16 +949,21 @@ int Runner::set_state(int i, const pamc_state *st)
         return PAMC_ERR_INVALID;
     }
     const int64_t R = st->R;
-    std::vector<uint8_t> buf((size_t)R * h.row_bytes, 0);
+    std::vector<uint8_t> buf((size_t)R * h.srow_bytes, 0);
     for (int64_t r = 0; r < R; ++r) {
         const int8_t *in = st->spins + (size_t)r * h.N;
-        uint8_t *row = buf.data() + (size_t)r * h.row_bytes;
+        uint8_t *row = buf.data() + (size_t)r * h.srow_bytes;
         for (int s = 0; s < h.N; ++s) {
             if (in[s] != 1 && in[s] != -1) {
                 set_error("set_state: spins must be +-1");
                 return PAMC_ERR_INVALID;
             }
-            row[h.lex_pos[s]] = in[s] > 0 ? 1 : 0;
+            const int p = h.lex_pos[s];
+            if (h.packed) {
+                if (in[s] > 0) row[p >> 3] |= (uint8_t)(1u << (p & 7));
+            } else {
+                row[p] = in[s] > 0 ? 1 : 0;
+            }
         }
         if ((int64_t)st->family[r] >= h.R) {
             set_error("set_state: family id out of range");

@@ -22,6 +22,8 @@ namespace pamc {
 struct HostInst {
     int L = 0, N = 0, ncol = 0, layout = 0, variant = 0;
     int row_bytes = 0, tile_rows = 0;
+    int packed = 0;                    // spins stored one bit per position
+    int srow_bytes = 0;                // bytes per stored spin row
     int tpr = 0;                       // colour-major sweep: threads per replica
     int rp = 0;                        // colour-major sweep: replicas per workgroup
     int64_t R = 0, Rcap = 0;
@@ -53,7 +55,10 @@ struct Allocator {
 };
 
 // Footprint and table construction helpers.
-size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl);
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed);
+// Bytes per stored spin row: row_bytes, or one bit per position rounded up
+// to 16 bytes.
+int stored_row_bytes(int row_bytes, bool packed);
 int64_t default_capacity(int64_t R);
 // Storage layout for lattice size L, and the shape it implies.
 struct LayoutInfo {

@@ -60,6 +60,7 @@ struct pamc_server {
     int max_active = 256;
     int device = -1;
     bool autotune = false;  // sweep shapes chosen by measurement at submission
+    int spin_format = PAMC_SPINS_INT8;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<uint64_t> queue;
@@ -227,6 +228,7 @@ int pamc_server_create(size_t hbm_budget_bytes, const pamc_server_options *opt, 
     s->max_active = (opt && opt->max_active > 0) ? opt->max_active : 256;
     s->device = opt ? opt->device : -1;
     s->autotune = opt && opt->autotune;
+    s->spin_format = opt ? opt->spin_format : PAMC_SPINS_INT8;
     pamc_options o;
     pamc_default_options(&o);
     o.device = s->device;
@@ -250,11 +252,12 @@ int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_
     pamc_default_options(&o);
     o.device = s->device;
     o.autotune = s->autotune ? 1 : 0;
+    o.spin_format = s->spin_format;
     Request r;
     int st = pamc::make_inst(inst->L, inst->couplings, inst->R, inst->beta, inst->n_temps, inst->sweeps, inst->seed,
                              o, r.h);
     if (st != PAMC_OK) return st;
-    r.bytes = pamc::inst_device_bytes(inst->L, r.h.Rcap, inst->n_temps, r.h.ovl_n) + 4096;
+    r.bytes = pamc::inst_device_bytes(inst->L, r.h.Rcap, inst->n_temps, r.h.ovl_n, r.h.packed != 0) + 4096;
     r.n_temps = inst->n_temps;
     if (r.bytes > s->budget) {
         pamc::set_error("request needs " + std::to_string(r.bytes) + " bytes, more than the budget");

@@ -26,6 +26,34 @@ __device__ __forceinline__ const Inst &inst_ref(const Inst *insts, uint32_t i) {
 // Storage position of lexicographic site s in a replica row.
 __device__ __forceinline__ int storage_pos(const Inst &I, int s) { return I.pos[s]; }
 
+// Packed spin rows: bit p of a row (bit p & 7 of byte p >> 3) is the spin at
+// storage position p.  Kernels work on one byte per position in LDS; 16
+// stored bits are one 16-byte LDS vector.
+__device__ __forceinline__ uint32_t bits_to_bytes4(uint32_t nib)
+{
+    // bit i of the nibble lands on bit 8 i: nib + (nib << 7) + (nib << 14) + (nib << 21)
+    return (nib * 0x00204081u) & 0x01010101u;
+}
+__device__ __forceinline__ uint4 bits_to_bytes16(uint32_t b)
+{
+    return make_uint4(bits_to_bytes4(b & 15u), bits_to_bytes4((b >> 4) & 15u), bits_to_bytes4((b >> 8) & 15u),
+                      bits_to_bytes4((b >> 12) & 15u));
+}
+__device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t w)
+{
+    // byte i (0 or 1) lands on bit 24 + i of w * (2^24 + 2^17 + 2^10 + 2^3)
+    return (uint32_t)(((uint64_t)w * 0x01020408ull) >> 24) & 15u;
+}
+__device__ __forceinline__ uint32_t bytes_to_bits16(uint4 v)
+{
+    return bytes_to_bits4(v.x) | (bytes_to_bits4(v.y) << 4) | (bytes_to_bits4(v.z) << 8) | (bytes_to_bits4(v.w) << 12);
+}
+// Spin (0/1) at storage position p of a stored row.
+__device__ __forceinline__ int stored_spin(const Inst &I, const uint8_t *row, int p)
+{
+    return I.packed ? (row[p >> 3] >> (p & 7)) & 1 : row[p];
+}
+
 // ---------------------------------------------------------------------------
 // Initial replicas (Sec. II.B: random configurations at beta = 0).  Site s
 // of row r takes S = +1 when bit 31 of word (s & 3) of Philox at counter
@@ -33,19 +61,49 @@ __device__ __forceinline__ int storage_pos(const Inst &I, int s) { return I.pos[
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_init(const Inst *insts, const Work *work)
 {
+    extern __shared__ __align__(16) uint8_t stage[];
     const Work w = work[blockIdx.x];
     const Inst &I = inst_ref(insts, w.inst);
     const int nq = (I.N + 3) >> 2;
     const int rows = min(kRowsPerBlock, I.R - (int)w.row0);
-    uint8_t *sp = I.spins[0];
-    for (int it = threadIdx.x; it < rows * nq; it += blockDim.x) {
-        const int q = it / nq, b = it - q * nq;
-        const uint32_t r = w.row0 + q;
-        const uint4 v = philox10(make_uint4((uint32_t)b, r, 0u, kTagInit), I.key0, I.key1);
-        for (int j = 0; j < 4; ++j) {
-            const int s = 4 * b + j;
-            if (s >= I.N) break;
-            sp[(size_t)r * I.row_bytes + storage_pos(I, s)] = (uint8_t)(word_of(v, j) >> 31);
+    if (!I.packed) {
+        uint8_t *sp = I.spins[0];
+        for (int it = threadIdx.x; it < rows * nq; it += blockDim.x) {
+            const int q = it / nq, b = it - q * nq;
+            const uint32_t r = w.row0 + q;
+            const uint4 v = philox10(make_uint4((uint32_t)b, r, 0u, kTagInit), I.key0, I.key1);
+            for (int j = 0; j < 4; ++j) {
+                const int s = 4 * b + j;
+                if (s >= I.N) break;
+                sp[(size_t)r * I.row_bytes + storage_pos(I, s)] = (uint8_t)(word_of(v, j) >> 31);
+            }
+        }
+    } else {
+        // rows staged as bytes in LDS (16 KB, or one row), then packed
+        const int nvec = I.row_bytes >> 4;
+        const int rpi = max(1, 16384 / I.row_bytes);
+        uint4 *st16 = reinterpret_cast<uint4 *>(stage);
+        for (int q0 = 0; q0 < rows; q0 += rpi) {
+            const int nr = min(rpi, rows - q0);
+            for (int i = threadIdx.x; i < nr * nvec; i += blockDim.x) st16[i] = make_uint4(0u, 0u, 0u, 0u);
+            __syncthreads();
+            for (int it = threadIdx.x; it < nr * nq; it += blockDim.x) {
+                const int q = it / nq, b = it - q * nq;
+                const uint32_t r = w.row0 + q0 + q;
+                const uint4 v = philox10(make_uint4((uint32_t)b, r, 0u, kTagInit), I.key0, I.key1);
+                for (int j = 0; j < 4; ++j) {
+                    const int s = 4 * b + j;
+                    if (s >= I.N) break;
+                    stage[q * I.row_bytes + storage_pos(I, s)] = (uint8_t)(word_of(v, j) >> 31);
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < nr * nvec; i += blockDim.x) {
+                const int q = i / nvec, c = i - q * nvec;
+                uint16_t *dst = reinterpret_cast<uint16_t *>(I.spins[0] + (size_t)(w.row0 + q0 + q) * I.srow_bytes);
+                dst[c] = (uint16_t)bytes_to_bits16(st16[i]);
+            }
+            __syncthreads();
         }
     }
     for (int q = threadIdx.x; q < rows; q += blockDim.x) I.fam[0][w.row0 + q] = w.row0 + q;
@@ -69,15 +127,15 @@ __global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *w
     for (int q = wave; q < kRowsPerBlock; q += 4) {
         const int r = (int)w.row0 + q;
         if (r >= Rk) break;
-        const uint8_t *S = I.spins[cur] + (size_t)r * I.row_bytes;
+        const uint8_t *S = I.spins[cur] + (size_t)r * I.srow_bytes;
         int e = 0;
         for (int s = lane; s < N; s += 64) {
             const int x = s % L, y = (s / L) % L, z = s / (L * L);
-            const int ss = 2 * S[storage_pos(I, s)] - 1;
+            const int ss = 2 * stored_spin(I, S, storage_pos(I, s)) - 1;
             const int nb[3] = {(x + 1) % L + L * (y + L * z), x + L * ((y + 1) % L + L * z),
                                x + L * (y + L * ((z + 1) % L))};
             for (int d = 0; d < 3; ++d)
-                e -= J[d * N + s] * ss * (2 * S[storage_pos(I, nb[d])] - 1);
+                e -= J[d * N + s] * ss * (2 * stored_spin(I, S, storage_pos(I, nb[d])) - 1);
         }
         for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
         if (lane == 0) I.E[cur][r] = e;
@@ -96,6 +154,8 @@ struct TileIO {
     const uint32_t *fsrc;
     uint32_t *fdst;
     int32_t *Edst;
+    int packed;           // stored rows hold one bit per position
+    int srow;             // bytes per stored row
 };
 
 __device__ __forceinline__ TileIO tile_io(const Inst &I)
@@ -109,7 +169,24 @@ __device__ __forceinline__ TileIO tile_io(const Inst &I)
     io.fsrc = I.fam[cur];
     io.fdst = mapped ? I.fam[cur ^ 1] : nullptr;
     io.Edst = mapped ? I.E[cur ^ 1] : I.E[cur];
+    io.packed = I.packed;
+    io.srow = I.srow_bytes;
     return io;
+}
+
+// 16-byte LDS vector c of stored row `row`: a copy, or 16 stored bits
+// expanded to bytes.
+__device__ __forceinline__ uint4 stored_vec(const TileIO &io, const uint8_t *row, int c)
+{
+    if (io.packed) return bits_to_bytes16(reinterpret_cast<const uint16_t *>(row)[c]);
+    return reinterpret_cast<const uint4 *>(row)[c];
+}
+__device__ __forceinline__ void store_vec(const TileIO &io, uint8_t *row, int c, uint4 v)
+{
+    if (io.packed)
+        reinterpret_cast<uint16_t *>(row)[c] = (uint16_t)bytes_to_bits16(v);
+    else
+        reinterpret_cast<uint4 *>(row)[c] = v;
 }
 
 __device__ __forceinline__ void tile_load(const TileIO &io, uint8_t *tile, int r0, int nrows, int row_bytes)
@@ -119,8 +196,7 @@ __device__ __forceinline__ void tile_load(const TileIO &io, uint8_t *tile, int r
         const int q = it / per_row, c = it - q * per_row;
         const uint32_t r = (uint32_t)(r0 + q);
         const uint32_t sr = io.map ? io.map[r] : r;
-        const uint4 v = *reinterpret_cast<const uint4 *>(io.src + (size_t)sr * row_bytes + 16 * c);
-        *reinterpret_cast<uint4 *>(tile + q * row_bytes + 16 * c) = v;
+        *reinterpret_cast<uint4 *>(tile + q * row_bytes + 16 * c) = stored_vec(io, io.src + (size_t)sr * io.srow, c);
     }
 }
 
@@ -130,7 +206,7 @@ __device__ __forceinline__ void tile_store(const TileIO &io, const uint8_t *tile
     for (int it = threadIdx.x; it < nrows * per_row; it += blockDim.x) {
         const int q = it / per_row, c = it - q * per_row;
         const uint4 v = *reinterpret_cast<const uint4 *>(tile + q * row_bytes + 16 * c);
-        *reinterpret_cast<uint4 *>(io.dst + (size_t)(r0 + q) * row_bytes + 16 * c) = v;
+        store_vec(io, io.dst + (size_t)(r0 + q) * io.srow, c, v);
     }
     if (io.map)
         for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
@@ -544,10 +620,10 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
         const uint32_t r = (uint32_t)(r0 + q);
         if (active) {
             const uint32_t sr = io.map ? io.map[r] : r;
-            const uint4 *src = reinterpret_cast<const uint4 *>(io.src + (size_t)sr * row_bytes);
+            const uint8_t *src = io.src + (size_t)sr * io.srow;
             uint4 *sp = reinterpret_cast<uint4 *>(slot);
             for (int i = lane_r; i < nvec; i += tpr) {
-                const uint4 v = src[i];
+                const uint4 v = stored_vec(io, src, i);
                 sp[i] = v;
                 sp[nvec + i] = make_uint4(v.x ^ 0x01010101u, v.y ^ 0x01010101u, v.z ^ 0x01010101u, v.w ^ 0x01010101u);
             }
@@ -584,8 +660,8 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
             }
             atomicAdd(&unsat[q], (int)part);
             const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
-            uint4 *dst = reinterpret_cast<uint4 *>(io.dst + (size_t)r * row_bytes);
-            for (int i = lane_r; i < nvec; i += tpr) dst[i] = sp[i];
+            uint8_t *dst = io.dst + (size_t)r * io.srow;
+            for (int i = lane_r; i < nvec; i += tpr) store_vec(io, dst, i, sp[i]);
         }
         replica_barrier(tpr);
     }
@@ -673,7 +749,7 @@ __global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *w
     const int rows = min((int)w.pad, Rn - row0);
     if (rows <= 0) return;
     const int cur = *I.cur;
-    const int per_row = I.row_bytes >> 4;
+    const int per_row = I.srow_bytes >> 4;
     const int total = rows * per_row;
     const uint4 *src = reinterpret_cast<const uint4 *>(I.spins[cur]);
     uint4 *dst = reinterpret_cast<uint4 *>(I.spins[cur ^ 1]);
@@ -705,9 +781,9 @@ __global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *w
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-void launch_init(const Inst *insts, const Work *work, int nwork, hipStream_t st)
+void launch_init(const Inst *insts, const Work *work, int nwork, size_t lds_bytes, hipStream_t st)
 {
-    if (nwork) k_init<<<nwork, 256, 0, st>>>(insts, work);
+    if (nwork) k_init<<<nwork, 256, lds_bytes, st>>>(insts, work);
 }
 
 void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st)

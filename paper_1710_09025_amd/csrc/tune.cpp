@@ -11,7 +11,8 @@
 // and keeps the shape with the shortest sweep time measured by HIP events.
 // Every shape gives bit-identical results, so the choice only affects
 // speed.  Choices are cached for the life of the process, keyed by kernel,
-// L, sweeps per step and the capacity rounded up to a power of two.
+// L, sweeps per step, the capacity rounded up to a power of two and the
+// spin storage format.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -44,7 +45,7 @@ struct Choice {
 };
 
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int>, Choice> g_cache;
+std::map<std::tuple<int, int, int, int, int>, Choice> g_cache;
 
 int ceil_log2(int64_t v)
 {
@@ -119,7 +120,7 @@ std::vector<std::pair<int, int>> shape_candidates(const HostInst &h)
 
 int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
 {
-    const auto key = std::make_tuple(h.variant, h.L, h.NS, ceil_log2(h.Rcap));
+    const auto key = std::make_tuple(h.variant, h.L, h.NS, ceil_log2(h.Rcap), h.packed);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find(key);

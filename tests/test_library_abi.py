@@ -127,6 +127,19 @@ def test_invalid_sweep_shapes_are_rejected_on_the_host(lib, case):
     assert not h.value
 
 
+def test_packed_footprint_saves_the_spin_bytes(lib):
+    from paper_1710_09025_amd import _capi
+
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    a = lib.pamc_footprint(16, 500000, 301, ctypes.byref(opt))
+    opt.spin_format = _capi.SPINS_PACKED
+    b = lib.pamc_footprint(16, 500000, 301, ctypes.byref(opt))
+    cap = 500000 + int(np.ceil(8 * np.sqrt(500000))) + 64
+    # two buffers of cap rows shrink from 4096 to 512 bytes (256-byte carving slack)
+    assert abs((a - b) - 2 * cap * (4096 - 512)) <= 512
+
+
 @pytest.mark.parametrize("case", ["L", "coupling", "beta_order", "beta_nan", "R", "sweeps", "capacity"])
 def test_invalid_arguments_are_rejected_on_the_host(lib, case):
     from paper_1710_09025_amd import _capi
