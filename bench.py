@@ -71,7 +71,7 @@ def attempts_of(obs, N, sweeps):
     return float(np.sum(obs["R"][obs["measured"] == 1])) * N * sweeps
 
 
-def time_anneals(name, steps, warmup, autotune=True):
+def time_anneals(name, steps, warmup, autotune=True, packed=False):
     """Creates warmup + steps run handles up front (each temperature step a
     replayed hipGraph; sweep shapes chosen by the autotuner at creation,
     outside the timed region) and anneals them one after another for the
@@ -83,7 +83,7 @@ def time_anneals(name, steps, warmup, autotune=True):
 
     cfg, J, beta = workload_inputs(name)
     N = cfg["L"] ** 3
-    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune)
+    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune, packed=packed)
             for _ in range(warmup + steps)]
     shape = runs[0].sweep_shape()
     for r in runs[:warmup]:
@@ -99,7 +99,8 @@ def time_anneals(name, steps, warmup, autotune=True):
     for r in runs:
         r.close()
     del runs
-    timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, autotune=autotune)
+    timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, autotune=autotune,
+                 packed=packed)
     assert timed.sweep_shape() == shape
     assert timed.anneal() == 0
     sweep_ms, other_ms, _, nsteps = timed.phase_times()
@@ -114,7 +115,20 @@ def time_anneals(name, steps, warmup, autotune=True):
                 attempts_per_anneal=att, mean_R=Rbar, N=N, shape=shape)
 
 
-def gather_bench(name, n_steps):
+def footprint_gb(name, packed):
+    import ctypes
+
+    from paper_1710_09025_amd import _capi
+
+    cfg = pi.WORKLOADS[name]
+    lib = _capi.load()
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    opt.spin_format = _capi.SPINS_PACKED if packed else _capi.SPINS_INT8
+    return round(lib.pamc_footprint(cfg["L"], cfg["R"], cfg["n_temps"], ctypes.byref(opt)) / 1e9, 3)
+
+
+def gather_bench(name, n_steps, packed=False):
     """The stand-alone gather of surviving replicas (fuse_gather off) over the
     first n_steps temperature steps of a workload, timed with HIP events:
     algorithmic bytes per output replica = row read + row write + energy and
@@ -125,7 +139,7 @@ def gather_bench(name, n_steps):
 
     cfg, J, beta = workload_inputs(name)
     p = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, fuse_gather=False,
-             autotune=True)
+             autotune=True, packed=packed)
     assert p.anneal(n_steps) == 0
     sweep_ms, resample_ms, gather_ms, nsteps = p.phase_times()
     obs = p.observables()
@@ -134,11 +148,14 @@ def gather_bench(name, n_steps):
     p.close()
     torch.cuda.empty_cache()
     rb = ((cfg["L"] ** 3 + 15) // 16) * 16
+    if packed:
+        rb = (rb + 127) // 128 * 16
     # the gather after step k writes the R_{k+1} replicas of step k + 1
     rows = float(np.sum(obs["R"][1:n_steps])) + R_now
     per_row = 2 * rb + 2 * 8 + 4
     gbs = rows * per_row / (gather_ms / 1e3) / 1e9
-    return {"kernel": "k_gather", "steps": int(nsteps), "bytes_per_replica": per_row,
+    return {"kernel": "k_gather", "spins": "packed" if packed else "int8", "steps": int(nsteps),
+            "bytes_per_replica": per_row,
             "avg_launch_ms": round(gather_ms / nsteps, 4), "achieved_gbs": round(gbs, 1),
             "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
             "resample_ms_per_step": round(resample_ms / nsteps, 4),
@@ -371,19 +388,24 @@ def main():
     }
     if args.gather_steps:
         line["gather"] = {name: gather_bench(name, args.gather_steps) for name in (args.workload, "L16_R500000")}
+        line["gather"]["L16_R500000_packed"] = gather_bench("L16_R500000", args.gather_steps, packed=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
     if not args.no_extra:
         extra = {}
-        for name, k, w in (("L4_R1000", 5, 1), ("L16_R500000", 1, 0)):
-            if name == args.workload:
+        for name, k, w, packed in (("L4_R1000", 5, 1, False), ("L16_R500000", 1, 0, False),
+                                   ("L16_R500000", 1, 0, True)):
+            if name == args.workload and not packed:
                 continue
-            r = time_anneals(name, k, w)
-            extra[name] = {
+            r = time_anneals(name, k, w, packed=packed)
+            extra[name + ("_packed" if packed else "")] = {
                 "attempts_per_ns": round(r["attempts_per_anneal"] * k / (r["wall_s"] * 1e9), 3),
                 "sweep_attempts_per_ns": round(r["attempts_per_anneal"] / (r["sweep_ms"] * 1e6), 3),
                 "ms_per_anneal": round(r["wall_s"] / k * 1e3, 3),
                 "sweep_share": round(r["sweep_ms"] / (r["sweep_ms"] + r["other_ms"]), 4),
+                "spins": "packed" if packed else "int8",
+                "footprint_gb": footprint_gb(name, packed),
+                "sweep_shape": {"tile_rows": r["shape"][0], "group_replicas": r["shape"][1]},
             }
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)

@@ -92,10 +92,12 @@ typedef struct pamc_options {
                                 resampling kernels of every step (see
                                 pamc_phase_times); 0 (default): no events   */
     int group_replicas;      /* L other than 8 and 16 (colour-major sweep):
-                                replicas one sweep workgroup holds at once;
+                                replicas one sweep workgroup holds at once,
+                                an even number (they are swept in pairs);
                                 0 = the library's choice.  Its threads
-                                (threads per replica x group_replicas) must
-                                be whole 64-lane waves, at most 1024        */
+                                (threads per replica pair x group_replicas
+                                / 2) must be whole 64-lane waves, at most
+                                1024                                        */
     int autotune;            /* 1: when tile_rows and group_replicas are 0,
                                 pick them by timing the candidate shapes on
                                 a throw-away run first (see pamc_autotune);

@@ -551,16 +551,20 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
 // ---------------------------------------------------------------------------
 // Colour-major SWAR sweep for any L whose largest colour has at most 4096
 // sites (two colours for even L, three for odd L).  Storage kLayoutCM: the
-// four sites of a Philox block are one aligned word of the row.  In LDS every
-// replica slot holds the row and its complement (0/1 swapped); a bond with
-// coupling -1 reads the neighbour from the complement, so every neighbour
-// byte read is s_nb ^ [J = -1], the bond is unsatisfied when it differs from
-// the site's own spin, and with m = the sum of the six bytes a site has
-// n = m unsatisfied bonds when s = 0 and 6 - m when s = 1.  A thread owns
-// Philox block g of every colour and keeps the 24 neighbour byte addresses
-// of its four sites in registers for all replicas and sweeps.  Energy:
-// every bond joins two sites of different colours, so U = (1/2) sum over all
-// sites of their unsatisfied bonds.
+// four sites of a Philox block are one aligned word of the row.
+//
+// A thread group sweeps two replicas A, B at once from one LDS slot in which
+// their rows are byte-interleaved (position p of A at byte 2p, of B at
+// 2p + 1), followed by the interleaved complement (0/1 swapped).  A bond
+// with coupling -1 reads the neighbour from the complement, so each 16-bit
+// neighbour read returns s_nb ^ [J = -1] of both replicas; with m the
+// per-site sum of the six values a site has n = m unsatisfied bonds when
+// s = 0 and 6 - m when s = 1, i.e. (m ^ 7 s) - s per byte.  The four sites
+// of a Philox block are the words [A0 B0 A1 B1] and [A2 B2 A3 B3]; each
+// thread owns Philox block g of every colour, keeps its 24 neighbour
+// addresses in registers and runs the draws of A and B side by side.
+// Energy: every bond joins two sites of different colours, so
+// U = (1/2) sum over all sites of their unsatisfied bonds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void replica_barrier(int tpr)
 {
@@ -574,58 +578,79 @@ __device__ __forceinline__ void replica_barrier(int tpr)
 }
 
 struct CMBlock {
-    uint32_t nb[24];  // LDS byte offsets of the neighbours, [direction][site]
-    uint32_t own;     // LDS byte offset of the four sites (spin copy)
-    uint32_t vmask;   // 0x01 in bytes of real sites
+    uint32_t nb[24];  // LDS offsets of the neighbour byte pairs, [direction][site]
+    uint32_t own;     // LDS offset of the two words of the block (spin copy)
+    uint32_t vmask0;  // 0x01 in the bytes of real sites, words 0 and 1
+    uint32_t vmask1;
     uint32_t ctr;     // Philox counter word 0
     bool has;
 };
 
-// Per byte: unsatisfied bonds of the four sites, (m ^ 7 s) - s with m <= 6
-// the per-site sum of the neighbour bytes (no carries or borrows between
-// bytes).
-__device__ __forceinline__ uint32_t cm_count(const uint8_t *lds, const CMBlock &b, uint32_t own)
+// Byte-interleave of two replica words a, b: [a0 b0 a1 b1] and [a2 b2 a3 b3]
+// (v_perm selectors: bytes 0-3 of a, 4-7 of b).
+__device__ __forceinline__ uint32_t ilv_lo(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x05010400u); }
+__device__ __forceinline__ uint32_t ilv_hi(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07030602u); }
+// and back: from w0 = [a0 b0 a1 b1], w1 = [a2 b2 a3 b3]
+__device__ __forceinline__ uint32_t dil_a(uint32_t w0, uint32_t w1) { return __builtin_amdgcn_perm(w1, w0, 0x06040200u); }
+__device__ __forceinline__ uint32_t dil_b(uint32_t w0, uint32_t w1) { return __builtin_amdgcn_perm(w1, w0, 0x07050301u); }
+
+// 7 s - s trick per byte: (m ^ 7 s) - s, with 7 s as (s rotated left by 3) - s
+// (s has no bits above bit 24, so the rotation is a shift and stays off the
+// quarter-rate multiplier).
+__device__ __forceinline__ uint32_t unsat_from_sum(uint32_t m, uint32_t own)
 {
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t t = (uint32_t)lds[b.nb[i]] + lds[b.nb[4 + i]] + lds[b.nb[8 + i]];
-        const uint32_t u = (uint32_t)lds[b.nb[12 + i]] + lds[b.nb[16 + i]] + lds[b.nb[20 + i]];
-        m += (t + u) << (8 * i);
-    }
-    // 7 s per byte as (s rotated left by 3) - s: own has no bits above
-    // bit 24, so the rotation is a shift (and stays off the quarter-rate
-    // multiplier)
     const uint32_t own7 = __builtin_amdgcn_alignbit(own, own, 29) - own;
     return (m ^ own7) - own;
 }
 
-// Sweeps of the replicas of the tile, RP at a time, each loaded into the
-// thread group's LDS slot (through the copy map) and stored back after its
-// N_S sweeps.  ALL: beta = 0, every move is accepted.
+// Per byte of the two block words: unsatisfied bonds of the four sites of
+// A and B.
+__device__ __forceinline__ void cm_count(const uint8_t *lds, const CMBlock &b, uint2 own, uint32_t &n0, uint32_t &n1)
+{
+    uint32_t m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        auto rd = [&](int j) { return (uint32_t)*reinterpret_cast<const uint16_t *>(lds + b.nb[j]); };
+        m[i] = (rd(i) + rd(4 + i) + rd(8 + i)) + (rd(12 + i) + rd(16 + i) + rd(20 + i));
+    }
+    n0 = unsat_from_sum(m[0] | (m[1] << 16), own.x);
+    n1 = unsat_from_sum(m[2] | (m[3] << 16), own.y);
+}
+
+// Sweeps of the replicas of the tile, two per thread group at a time, each
+// pair loaded into the group's LDS slot (through the copy map) and stored
+// back after its N_S sweeps.  ALL: beta = 0, every move is accepted.  A
+// missing B (odd tail) is swept as zeros and never stored.
 template <int NCOL, bool ALL>
 __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, const CMBlock (&blk)[NCOL],
                                           const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows)
 {
     const int tpr = I.tpr;
-    const int RP = (int)blockDim.x / tpr;
+    const int RPG = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * 2 * row_bytes;
+    uint8_t *slot = lds + qsub * 4 * row_bytes;
     const int nvec = row_bytes >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
-    for (int qb = 0; qb < nrows; qb += RP) {
-        const int q = qb + qsub;
-        const bool active = q < nrows;
-        const uint32_t r = (uint32_t)(r0 + q);
-        if (active) {
-            const uint32_t sr = io.map ? io.map[r] : r;
-            const uint8_t *src = io.src + (size_t)sr * io.srow;
+    for (int qb = 0; qb < nrows; qb += 2 * RPG) {
+        const int qa = qb + 2 * qsub, qbb = qa + 1;
+        const bool act_a = qa < nrows, act_b = qbb < nrows;
+        const uint32_t ra = (uint32_t)(r0 + qa), rb = ra + 1u;
+        if (act_a) {
+            const uint8_t *src_a = io.src + (size_t)(io.map ? io.map[ra] : ra) * io.srow;
+            const uint8_t *src_b = act_b ? io.src + (size_t)(io.map ? io.map[rb] : rb) * io.srow : nullptr;
             uint4 *sp = reinterpret_cast<uint4 *>(slot);
             for (int i = lane_r; i < nvec; i += tpr) {
-                const uint4 v = stored_vec(io, src, i);
-                sp[i] = v;
-                sp[nvec + i] = make_uint4(v.x ^ 0x01010101u, v.y ^ 0x01010101u, v.z ^ 0x01010101u, v.w ^ 0x01010101u);
+                const uint4 va = stored_vec(io, src_a, i);
+                const uint4 vb = act_b ? stored_vec(io, src_b, i) : make_uint4(0u, 0u, 0u, 0u);
+                const uint4 w0 = make_uint4(ilv_lo(va.x, vb.x), ilv_hi(va.x, vb.x), ilv_lo(va.y, vb.y), ilv_hi(va.y, vb.y));
+                const uint4 w1 = make_uint4(ilv_lo(va.z, vb.z), ilv_hi(va.z, vb.z), ilv_lo(va.w, vb.w), ilv_hi(va.w, vb.w));
+                sp[2 * i] = w0;
+                sp[2 * i + 1] = w1;
+                sp[2 * nvec + 2 * i] = make_uint4(w0.x ^ 0x01010101u, w0.y ^ 0x01010101u, w0.z ^ 0x01010101u,
+                                                  w0.w ^ 0x01010101u);
+                sp[2 * nvec + 2 * i + 1] = make_uint4(w1.x ^ 0x01010101u, w1.y ^ 0x01010101u, w1.z ^ 0x01010101u,
+                                                      w1.w ^ 0x01010101u);
             }
         }
         replica_barrier(tpr);
@@ -633,35 +658,55 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 const CMBlock &b = blk[c];
-                if (active && b.has) {
-                    const uint32_t own = *reinterpret_cast<const uint32_t *>(lds + b.own);
-                    uint32_t flip = b.vmask;
+                if (act_a && b.has) {
+                    const uint2 own = *reinterpret_cast<const uint2 *>(lds + b.own);
+                    uint32_t f0 = b.vmask0, f1 = b.vmask1;
                     if constexpr (!ALL) {
-                        const uint32_t n = cm_count(lds, b, own);
-                        const uint4 u = philox10(make_uint4(b.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
-                        flip &= eo_flip(n, u, tab);
+                        uint32_t n0, n1;
+                        cm_count(lds, b, own, n0, n1);
+                        const uint4 ctr_a = make_uint4(b.ctr, ra, (uint32_t)k, kTagSweep | (uint32_t)t);
+                        const uint4 ua = philox10(ctr_a, key0, key1);
+                        const uint4 ub = philox10(make_uint4(b.ctr, rb, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                        f0 &= eo_flip(n0, make_uint4(ua.x, ub.x, ua.y, ub.y), tab);
+                        f1 &= eo_flip(n1, make_uint4(ua.z, ub.z, ua.w, ub.w), tab);
                     }
-                    const uint32_t nw = own ^ flip;
-                    *reinterpret_cast<uint32_t *>(lds + b.own) = nw;
-                    *reinterpret_cast<uint32_t *>(lds + b.own + row_bytes) = nw ^ 0x01010101u;
+                    const uint2 nw = make_uint2(own.x ^ f0, own.y ^ f1);
+                    *reinterpret_cast<uint2 *>(lds + b.own) = nw;
+                    *reinterpret_cast<uint2 *>(lds + b.own + 2 * row_bytes) =
+                        make_uint2(nw.x ^ 0x01010101u, nw.y ^ 0x01010101u);
                 }
                 replica_barrier(tpr);
             }
         }
-        if (active) {
-            uint32_t part = 0;
+        if (act_a) {
+            uint32_t pa = 0, pb = 0;
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 if (!blk[c].has) continue;
-                const uint32_t own = *reinterpret_cast<const uint32_t *>(lds + blk[c].own);
+                const uint2 own = *reinterpret_cast<const uint2 *>(lds + blk[c].own);
+                uint32_t n0, n1;
+                cm_count(lds, blk[c], own, n0, n1);
                 // padding bytes have no neighbours of their own: mask them
-                const uint32_t n = cm_count(lds, blk[c], own) & (blk[c].vmask * 0xFFu);
-                part = __builtin_amdgcn_sad_u8(n, 0u, part);
+                n0 &= blk[c].vmask0 * 0xFFu;
+                n1 &= blk[c].vmask1 * 0xFFu;
+                pa = __builtin_amdgcn_sad_u8(n0 & 0x00FF00FFu, 0u, pa);
+                pa = __builtin_amdgcn_sad_u8(n1 & 0x00FF00FFu, 0u, pa);
+                pb = __builtin_amdgcn_sad_u8(n0 & 0xFF00FF00u, 0u, pb);
+                pb = __builtin_amdgcn_sad_u8(n1 & 0xFF00FF00u, 0u, pb);
             }
-            atomicAdd(&unsat[q], (int)part);
+            atomicAdd(&unsat[qa], (int)pa);
+            if (act_b) atomicAdd(&unsat[qbb], (int)pb);
             const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
-            uint8_t *dst = io.dst + (size_t)r * io.srow;
-            for (int i = lane_r; i < nvec; i += tpr) store_vec(io, dst, i, sp[i]);
+            uint8_t *dst_a = io.dst + (size_t)ra * io.srow;
+            uint8_t *dst_b = io.dst + (size_t)rb * io.srow;
+            for (int i = lane_r; i < nvec; i += tpr) {
+                const uint4 w0 = sp[2 * i], w1 = sp[2 * i + 1];
+                store_vec(io, dst_a, i, make_uint4(dil_a(w0.x, w0.y), dil_a(w0.z, w0.w), dil_a(w1.x, w1.y),
+                                                   dil_a(w1.z, w1.w)));
+                if (act_b)
+                    store_vec(io, dst_b, i, make_uint4(dil_b(w0.x, w0.y), dil_b(w0.z, w0.w), dil_b(w1.x, w1.y),
+                                                       dil_b(w1.z, w1.w)));
+            }
         }
         replica_barrier(tpr);
     }
@@ -673,10 +718,10 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     // thresholds by 4 n at a fixed LDS address (see eo_flip)
     __shared__ uint32_t tab[8];
     const int tpr = I.tpr;
-    const int RP = (int)blockDim.x / tpr;
+    const int RPG = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
-    const int slot_bytes = 2 * row_bytes;
-    int *unsat = reinterpret_cast<int *>(lds + RP * slot_bytes + 32);
+    const int slot_bytes = 4 * row_bytes;
+    int *unsat = reinterpret_cast<int *>(lds + RPG * slot_bytes + 32);
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
     const uint32_t slot = (uint32_t)(qsub * slot_bytes);
@@ -688,10 +733,14 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
         blk[c].ctr = ((uint32_t)c << 24) | (uint32_t)g;
         const int gg = blk[c].has ? g : 0;
         const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
+        // byte offset o of the single-replica slot [row | complement] is
+        // byte pair 2 o of the interleaved slot
 #pragma unroll
-        for (int i = 0; i < 24; ++i) blk[c].nb[i] = slot + d[i];
-        blk[c].vmask = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
-        blk[c].own = slot + (uint32_t)(I.cbase[c] + 4 * gg);
+        for (int i = 0; i < 24; ++i) blk[c].nb[i] = slot + 2u * d[i];
+        const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
+        blk[c].vmask0 = ilv_lo(vm, vm);
+        blk[c].vmask1 = ilv_hi(vm, vm);
+        blk[c].own = slot + 2u * (uint32_t)(I.cbase[c] + 4 * gg);
     }
     const uint4 th = I.thr[k];
     const bool all = th.w != 0;
@@ -791,8 +840,8 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
     if (nwork) k_energy<<<nwork, 256, 0, st>>>(insts, work, Jraw);
 }
 
-// Workgroup shape of the colour-major sweep: tpr threads per replica and
-// max(1, 256 / tpr) replicas swept at once.
+// Default workgroup shape of the colour-major sweep: tpr threads per
+// replica pair and max(1, 256 / tpr) pairs swept at once.
 int cm_replicas_per_block(int tpr) { return tpr >= 256 ? 1 : 256 / tpr; }
 
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
@@ -800,7 +849,8 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
 {
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
-        const size_t lds = 2 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
+        // rp replica pairs, each an interleaved row and complement
+        const size_t lds = 4 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
         const int nt = tpr * rp;
         if (variant == kSweepCM2) {
             if (nt <= 512)
