@@ -63,7 +63,7 @@ def lib() -> ctypes.CDLL:
         P = ctypes.c_void_p
         i64, i32, u64, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
         L.orc_create.restype = P
-        L.orc_create.argtypes = [i32, P, i64, i64, P, i32, i32, u64, P]
+        L.orc_create.argtypes = [i32, P, i64, i64, P, i32, i32, u64, P, P]
         L.orc_destroy.argtypes = [P]
         L.orc_set_threads.argtypes = [P, i32]
         L.orc_run.argtypes = [P, i32]
@@ -119,7 +119,7 @@ class Oracle:
     """One PAMC run on the CPU.  ``couplings`` is int8 [3][L^3] of +-1."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
-                 threads=1):
+                 threads=1, pop_schedule=None):
         self.L = int(L)
         self.N = self.L ** 3
         self.R = int(R)
@@ -127,7 +127,11 @@ class Oracle:
         self.nT = len(self.beta)
         self.sweeps = int(sweeps)
         self.seed = int(seed)
-        self.capacity = int(capacity) if capacity is not None else default_capacity(self.R)
+        self._pop = None
+        if pop_schedule is not None:
+            self._pop = np.ascontiguousarray(pop_schedule, dtype=np.int64)
+        peak = int(self._pop.max()) if self._pop is not None else self.R
+        self.capacity = int(capacity) if capacity is not None else default_capacity(peak)
         J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
         self._J = J
         ov = None
@@ -137,7 +141,8 @@ class Oracle:
             self._ov = ov
         h = lib().orc_create(self.L, _ptr(J), self.R, self.capacity, _ptr(self.beta), self.nT,
                              self.sweeps, ctypes.c_uint64(self.seed & (2**64 - 1)),
-                             _ptr(ov) if ov is not None else None)
+                             _ptr(ov) if ov is not None else None,
+                             _ptr(self._pop) if self._pop is not None else None)
         if not h:
             raise ValueError("oracle: invalid arguments")
         self._h = ctypes.c_void_p(h)

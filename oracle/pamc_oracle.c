@@ -110,6 +110,7 @@ typedef struct {
     int nT, NS;
     uint64_t seed;
     double *beta;
+    int64_t *Rt;          /* [nT] nominal population at each beta_k, Rt[0] = R */
     int8_t *J;      /* [3][N]: bond (s, d) joins s and s + e_d            */
     int *nbr;       /* [N][6]: +x, -x, +y, -y, +z, -z                     */
     int8_t *Jn;     /* [N][6]: coupling of the bond to that neighbour     */
@@ -147,6 +148,7 @@ void orc_destroy(orc_t *o)
 {
     if (!o) return;
     free(o->beta);
+    free(o->Rt);
     free(o->J);
     free(o->nbr);
     free(o->Jn);
@@ -203,11 +205,18 @@ static void init_population(orc_t *o)
     o->lnZ = (double)o->N * log(2.0);
 }
 
+/* pop: NULL for a constant nominal population R, or the nominal population
+ * R(beta_k) of every step (pop[0] = R), Sec. III.D. */
 orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double *beta, int nT, int NS,
-                  uint64_t seed, const uint8_t *overlap_steps)
+                  uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
 {
     if (L < 2 || L > 32 || R < 1 || nT < 1 || NS < 1 || !J || !beta) return NULL;
     if (Rcap < R) return NULL;
+    if (pop) {
+        if (pop[0] != R) return NULL;
+        for (int i = 0; i < nT; ++i)
+            if (pop[i] < 1) return NULL;
+    }
     for (int i = 0; i < nT; ++i) {
         if (!(beta[i] >= 0.0) || !isfinite(beta[i])) return NULL;
         if (i > 0 && beta[i] < beta[i - 1]) return NULL;
@@ -225,6 +234,9 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
     o->nthreads = 1;
     int N = o->N;
     o->beta = (double *)malloc(sizeof(double) * nT);
+    o->Rt = (int64_t *)malloc(sizeof(int64_t) * nT);
+    if (o->Rt)
+        for (int i = 0; i < nT; ++i) o->Rt[i] = pop ? pop[i] : R;
     o->J = (int8_t *)malloc(3 * (size_t)N);
     o->nbr = (int *)malloc(sizeof(int) * 6 * (size_t)N);
     o->Jn = (int8_t *)malloc(6 * (size_t)N);
@@ -248,7 +260,7 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
     o->o_lnQ = (double *)calloc(nT, sizeof(double));
     o->o_lnZ = (double *)calloc(nT, sizeof(double));
     o->o_q = (int64_t *)calloc((size_t)nT * (2 * N + 1), sizeof(int64_t));
-    if (!o->beta || !o->J || !o->nbr || !o->Jn || !o->colour || !o->crank || !o->spin || !o->spin2 ||
+    if (!o->beta || !o->Rt || !o->J || !o->nbr || !o->Jn || !o->colour || !o->crank || !o->spin || !o->spin2 ||
         !o->E || !o->E2 || !o->fam || !o->fam2 || !o->ncopy || !o->ovl || !o->o_R || !o->o_sumE ||
         !o->o_sumE2 || !o->o_Emin || !o->o_Emax || !o->o_S || !o->o_T || !o->o_lnQ || !o->o_lnZ ||
         !o->o_q) {
@@ -425,10 +437,11 @@ static int measure(orc_t *o)
 }
 
 /* Resampling from beta_k to beta_{k+1} (Sec. II.B).  The mean number of
- * copies of replica i is tau_i = R exp[-(beta'-beta) E_i] / sum_j exp[...],
- * so that the expected new population is the nominal R; replica i gets
- * floor(tau_i) copies plus one more with probability frac(tau_i).  Copies
- * keep source order (families stay contiguous). */
+ * copies of replica i is tau_i = R' exp[-(beta'-beta) E_i] / sum_j exp[...],
+ * so that the expected new population is the nominal R' = R(beta_{k+1})
+ * (constant unless a population schedule was given, Sec. III.D); replica i
+ * gets floor(tau_i) copies plus one more with probability frac(tau_i).
+ * Copies keep source order (families stay contiguous). */
 static int resample(orc_t *o)
 {
     int k = o->k, N = o->N;
@@ -467,7 +480,7 @@ static int resample(orc_t *o)
     double S = pairwise_tree(leaf, P);
 
     for (int64_t m = 0; m <= M; ++m) {
-        double tau = ((double)o->R * w[m]) / S;
+        double tau = ((double)o->Rt[k + 1] * w[m]) / S;
         double fl = floor(tau);
         B[m] = (uint32_t)fl;
         F[m] = (uint32_t)floor((tau - fl) * 4294967296.0);

@@ -59,6 +59,57 @@ def linear_beta(beta_max: float, n_temps: int) -> np.ndarray:
     return np.array([beta_max * k / (n_temps - 1) for k in range(n_temps)], dtype=np.float64)
 
 
+def lblt_beta(beta_max: float, n_temps: int, T_N: float = 1.0) -> np.ndarray:
+    """Linear-in-beta linear-in-T schedule (Sec. III.B): the first half of
+    the temperatures, from beta = 0 down to T_N, equally spaced in beta, the
+    second half from T_N to T_min = 1/beta_max equally spaced in T.  The two
+    halves meet at step k_N = (n_temps - 1) // 2 with beta = 1/T_N (3D
+    optimum T_N = 1.0, Fig. 3(d)); requires T_N > 1/beta_max."""
+    if n_temps < 3:
+        return linear_beta(beta_max, n_temps)
+    kN = (n_temps - 1) // 2
+    bN, Tmin = 1.0 / T_N, 1.0 / beta_max
+    if not bN < beta_max:
+        raise ValueError("T_N must lie above 1/beta_max")
+    beta = np.empty(n_temps)
+    for k in range(kN + 1):
+        beta[k] = bN * k / kN
+    n2 = n_temps - 1 - kN
+    for j in range(1, n2 + 1):
+        beta[kN + j] = 1.0 / (T_N + (Tmin - T_N) * j / n2)
+    return beta
+
+
+def tspl_beta(beta_max: float, n_temps: int, alpha1: float = float(np.exp(-0.0734)),
+              alpha2: float = float(np.exp(2.15)), beta0: float = 1.63) -> np.ndarray:
+    """Two-stage power-law schedule, Eq. (5): beta(tau) = a tau^alpha1 below
+    tau_0 and b tau^alpha2 above, tau = k / (n_temps - 1).  b = beta_max
+    fixes the final temperature, tau_0 = (beta0 / beta_max)^(1/alpha2) puts
+    the switch-over at beta0, a = beta0 / tau_0^alpha1 makes it continuous.
+    Defaults are the paper's parameters for 3D."""
+    if n_temps == 1:
+        return np.zeros(1)
+    tau0 = (beta0 / beta_max) ** (1.0 / alpha2)
+    a = beta0 / tau0 ** alpha1
+    tau = np.arange(n_temps, dtype=np.float64) / (n_temps - 1)
+    return np.where(tau < tau0, a * tau ** alpha1, beta_max * tau ** alpha2)
+
+
+def clipped_exponential_population(beta: np.ndarray, R_mean: int, beta0: float = 0.9, r: float = 33.8,
+                                   S: float = float(np.exp(-2.52))) -> np.ndarray:
+    """Nominal population R(beta_k) of the clipped exponential schedule,
+    Eq. (6): R_0 up to beta0, then falling to R_0 / r at beta_max with
+    slope S (the paper's 3D parameters by default).  R_0 is scaled so that
+    the mean over the steps is R_mean (comparable to a uniform run); the
+    entries are rounded to integers >= 1."""
+    beta = np.asarray(beta, dtype=np.float64)
+    bmax = beta[-1]
+    a = np.exp(bmax * S) - np.exp(beta0 * S)
+    f = np.where(beta <= beta0, 1.0, a / ((r - 1.0) * (np.exp(beta * S) - np.exp(beta0 * S)) + a))
+    R0 = R_mean * len(beta) / f.sum()
+    return np.maximum(1, np.rint(R0 * f)).astype(np.int64)
+
+
 def random_spins(R: int, N: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(np.uint64(seed)))
     return (2 * rng.integers(0, 2, size=(R, N), dtype=np.int8) - 1).astype(np.int8)

@@ -559,3 +559,69 @@ def test_overlap_at_beta_zero_has_mean_q2_one_over_N():
     q2 = o.observables()["q2"][0]
     # q^2 of two independent random configurations: mean 1/N, var ~ 2/N^2
     assert abs(q2 - 1 / N) < 5 * math.sqrt(2.0 / (R / 2)) / N
+
+
+# --------------------------------------------------------------------------
+# Annealing schedules and the population schedule (Sec. III.B, Eqs. (5)-(6))
+# --------------------------------------------------------------------------
+def test_lblt_schedule_is_linear_in_beta_then_in_T():
+    b = pi.lblt_beta(5.0, 201, T_N=1.0)
+    kN = 100
+    assert b[0] == 0.0 and b[-1] == pytest.approx(5.0, rel=1e-15) and b[kN] == pytest.approx(1.0, rel=1e-15)
+    assert np.allclose(np.diff(b[: kN + 1]), 1.0 / kN, rtol=1e-12)
+    T = 1.0 / b[kN:]
+    assert np.allclose(np.diff(T), (0.2 - 1.0) / 100, rtol=1e-9)
+    assert np.all(np.diff(b) > 0)
+
+
+def test_tspl_schedule_endpoints_and_switch_over():
+    a1, a2, b0, bmax, nT = np.exp(-0.0734), np.exp(2.15), 1.63, 5.0, 301
+    b = pi.tspl_beta(bmax, nT)
+    assert b[0] == 0.0 and b[-1] == pytest.approx(bmax, rel=1e-15)
+    assert np.all(np.diff(b) > 0)
+    tau0 = (b0 / bmax) ** (1 / a2)
+    # both branches give beta0 at tau0 (continuity), each is its power law
+    a = b0 / tau0 ** a1
+    tau = np.arange(nT) / (nT - 1)
+    lo = tau < tau0
+    assert np.allclose(b[lo], a * tau[lo] ** a1, rtol=1e-14)
+    assert np.allclose(b[~lo], bmax * tau[~lo] ** a2, rtol=1e-14)
+    assert a * tau0 ** a1 == pytest.approx(b0, rel=1e-14) and bmax * tau0 ** a2 == pytest.approx(b0, rel=1e-14)
+
+
+def test_clipped_exponential_population():
+    beta = pi.linear_beta(5.0, 201)
+    R = pi.clipped_exponential_population(beta, 10000)
+    R0 = R[0]
+    assert np.all(R[beta <= 0.9] == R0)
+    assert np.all(np.diff(R) <= 0)
+    assert R[-1] == pytest.approx(R0 / 33.8, abs=1.0)
+    assert R.mean() == pytest.approx(10000, rel=1e-3)
+
+
+def test_resampling_targets_the_scheduled_population():
+    """With a population schedule the resampling to beta_{k+1} targets
+    R(beta_{k+1}): tau_r = R(beta') w_r / sum w."""
+    L, N, R, R1 = 3, 27, 400, 250
+    J = pi.pm_j_couplings(L, 9)
+    spins = pi.random_spins(R, N, 6)
+    o = oracle.Oracle(L, J, R, [0.0, 0.4], 2, 11, pop_schedule=[R, R1])
+    o.set_state(0, spins, np.arange(R, dtype=np.uint32), N * math.log(2))
+    E = o.energies(spins).astype(np.float64)  # beta_0 = 0: the sweeps flip every spin twice
+    assert o.run(1) == oracle.OK
+    n = np.bincount(o.get_state()["family"], minlength=R)
+    w = np.exp(-0.4 * (E - E.min()))
+    tau = R1 * w / w.sum()
+    assert np.all((n == np.floor(tau + 1e-9)) | (n == np.ceil(tau - 1e-9)))
+    assert abs(n.sum() - R1) < 6 * math.sqrt(R1)
+
+
+def test_population_follows_its_schedule():
+    L = 4
+    J = pi.pm_j_couplings(L, 2)
+    beta = pi.linear_beta(4.0, 101)
+    pop = pi.clipped_exponential_population(beta, 2000)
+    o = oracle.Oracle(L, J, int(pop[0]), beta, 1, 78, threads=8, pop_schedule=pop)
+    assert o.run() == oracle.OK
+    Rk = o.records()["R"]
+    assert np.all(np.abs(Rk - pop) < 6 * np.sqrt(pop) + 1)
