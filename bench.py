@@ -270,6 +270,52 @@ def batch_bench(n_inst, plain_per_L):
     }
 
 
+def schedule_bench(name, kind):
+    """One anneal of a workload under the paper's LBLT or TSPL schedule
+    (Sec. III.B), or TSPL with the clipped exponential population schedule
+    (Sec. III.D; same mean population), timed like the main line."""
+    import torch
+
+    from paper_1710_09025_amd import Pamc
+
+    cfg, J, _ = workload_inputs(name)
+    nT = cfg["n_temps"]
+    beta = pi.lblt_beta(cfg["beta_max"], nT) if kind == "lblt" else pi.tspl_beta(cfg["beta_max"], nT)
+    pop = pi.clipped_exponential_population(beta, cfg["R"]) if kind == "tspl_dynamic_R" else None
+    R = int(pop[0]) if pop is not None else cfg["R"]
+    p = Pamc(cfg["L"], J, R, beta, cfg["sweeps"], cfg["seed"], autotune=True, pop_schedule=pop)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    assert p.anneal() == 0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    obs = p.observables()
+    p.close()
+    torch.cuda.empty_cache()
+    att = attempts_of(obs, cfg["L"] ** 3, cfg["sweeps"])
+    return {"schedule": kind, "attempts_per_ns": round(att / ((t1 - t0) * 1e9), 3),
+            "ms_per_anneal": round((t1 - t0) * 1e3, 3), "final_rho_s": round(float(obs["rho_s"][-1]), 3),
+            "final_S_f": round(float(obs["S_f"][-1]), 4), "peak_R": int(np.max(obs["R"]))}
+
+
+def rho_f_bench(L=8, R=20000, n_temps=201, runs=16):
+    """rho_f = R var(beta F) from independent runs of one instance (Eq. (4)),
+    annealed together as one batch."""
+    import torch
+
+    from paper_1710_09025_amd import free_energy_variance
+
+    J = pi.pm_j_couplings(L, 2)
+    beta = pi.linear_beta(5.0, n_temps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = free_energy_variance(L, J, R, beta, 10, [7000 + i for i in range(runs)], autotune=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return {"L": L, "R": R, "n_temps": n_temps, "runs": runs, "rho_f_final": round(float(res["rho_f"][-1]), 4),
+            "rho_f_max": round(float(np.max(res["rho_f"])), 4), "seconds": round(t1 - t0, 3)}
+
+
 def warm_serving_shapes(sweeps=10):
     """Tunes the sweep shapes of the serving size classes before the stream
     (as a deployment would ship a tuning cache): every L of the request mix
@@ -407,6 +453,9 @@ def main():
                 "footprint_gb": footprint_gb(name, packed),
                 "sweep_shape": {"tile_rows": r["shape"][0], "group_replicas": r["shape"][1]},
             }
+        for kind in ("lblt", "tspl", "tspl_dynamic_R"):
+            extra[f"{args.workload}_{kind}"] = schedule_bench(args.workload, kind)
+        extra["rho_f"] = rho_f_bench()
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
         if args.serve:

@@ -102,6 +102,13 @@ typedef struct pamc_options {
                                 pick them by timing the candidate shapes on
                                 a throw-away run first (see pamc_autotune);
                                 0 (default): a fixed rule                   */
+    const int64_t *pop_schedule; /* NULL: the nominal population is R at every
+                                step.  Else [n_temps] nominal populations
+                                R(beta_k) (Sec. III.D), pop_schedule[0] = R,
+                                all >= 1: the resampling to beta_{k+1}
+                                targets pop_schedule[k+1], and the default
+                                capacity follows the largest entry.  Read
+                                during pamc_create only.                     */
 } pamc_options;
 
 /* Fills *opt with the defaults described above. */
@@ -251,6 +258,7 @@ typedef struct pamc_instance {
     int n_temps;
     int sweeps;
     uint64_t seed;
+    const int64_t *pop_schedule; /* NULL or [n_temps], as in pamc_options */
 } pamc_instance;
 
 typedef struct pamc_batch pamc_batch;

@@ -101,7 +101,7 @@ def _torch_available() -> bool:
 
 def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
                   torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0,
-                  graphs=True, group_replicas=0, autotune=False):
+                  graphs=True, group_replicas=0, autotune=False, pop_schedule=None):
     lib = _capi.load()
     opt = _capi.Options()
     lib.pamc_default_options(ctypes.byref(opt))
@@ -114,6 +114,10 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     opt.group_replicas = int(group_replicas)
     opt.autotune = 1 if autotune else 0
     opt.graphs = 1 if graphs else 0
+    if pop_schedule is not None:
+        pop = np.ascontiguousarray(pop_schedule, dtype=np.int64)
+        keep.append(pop)
+        opt.pop_schedule = pop.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     if overlap_steps is not None:
         ov = np.ascontiguousarray(overlap_steps, dtype=np.int32)
         keep.append(ov)
@@ -138,12 +142,38 @@ def autotune(L, R, sweeps, torch_stream=True, packed=False):
     return t.value, g.value, ns.value
 
 
+def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None, packed=False, autotune=False):
+    """rho_f = R var(beta F) (Sec. II.B, Eq. (4)) from independent runs of one
+    instance: the runs (one per seed, at least two; the paper asks for ten or
+    more) are annealed together as one batch, and per temperature step the
+    sample variance (ddof 1) of beta F = -ln Z across runs is multiplied by
+    the nominal population R(beta_k).  Returns a dict of arrays over steps:
+    beta, mean_betaF, var_betaF, rho_f, and the per-run beta F [runs, steps]."""
+    seeds = [int(x) for x in seeds]
+    if len(seeds) < 2:
+        raise ValueError("rho_f needs at least two independent runs")
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    inst = [dict(L=L, couplings=couplings, R=R, beta=beta, sweeps=sweeps, seed=sd, pop_schedule=pop_schedule)
+            for sd in seeds]
+    b = PamcBatch(inst, packed=packed, autotune=autotune)
+    try:
+        st = b.anneal()
+        if st != _capi.OK:
+            raise PamcError(st, "free_energy_variance")
+        bf = np.stack([b.observables(i)["betaF"] for i in range(len(seeds))])
+    finally:
+        b.close()
+    nominal = np.full(len(beta), float(R)) if pop_schedule is None else np.asarray(pop_schedule, dtype=np.float64)
+    var = bf.var(axis=0, ddof=1)
+    return {"beta": beta, "mean_betaF": bf.mean(axis=0), "var_betaF": var, "rho_f": nominal * var, "betaF": bf}
+
+
 class Pamc:
     """One population-annealing run on the GPU (``pamc_create``)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
-                 graphs=True, group_replicas=0, autotune=False, packed=False):
+                 graphs=True, group_replicas=0, autotune=False, packed=False, pop_schedule=None):
         lib = _capi.load()
         self.L = int(L)
         self.N = self.L ** 3
@@ -156,7 +186,7 @@ class Pamc:
                             spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
                             tile_rows=tile_rows, graphs=graphs, group_replicas=group_replicas,
-                            autotune=autotune)
+                            autotune=autotune, pop_schedule=pop_schedule)
         self._opt = opt
         h = ctypes.c_void_p()
         _check(lib.pamc_create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),
@@ -273,8 +303,12 @@ class PamcBatch:
             J = np.ascontiguousarray(d["couplings"], dtype=np.int8).reshape(3, L ** 3)
             b = np.ascontiguousarray(d["beta"], dtype=np.float64)
             self._keep += [J, b]
+            pop = None
+            if d.get("pop_schedule") is not None:
+                pop = np.ascontiguousarray(d["pop_schedule"], dtype=np.int64)
+                self._keep.append(pop)
             arr[i] = _capi.Instance(L, _ptr(J).value, int(d["R"]), _ptr(b).value, len(b), int(d["sweeps"]),
-                                    int(d["seed"]) & (2**64 - 1))
+                                    int(d["seed"]) & (2**64 - 1), _ptr(pop).value if pop is not None else None)
             self.nT.append(len(b))
             self.N.append(L ** 3)
         opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs,
@@ -333,12 +367,13 @@ class PamcServer:
         self._keep = {}
         self._nT = {}
 
-    def submit(self, L, couplings, R, beta, sweeps, seed) -> int:
+    def submit(self, L, couplings, R, beta, sweeps, seed, pop_schedule=None) -> int:
         L = int(L)
         J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, L ** 3)
         b = np.ascontiguousarray(beta, dtype=np.float64)
+        pop = None if pop_schedule is None else np.ascontiguousarray(pop_schedule, dtype=np.int64)
         inst = _capi.Instance(L, _ptr(J).value, int(R), _ptr(b).value, len(b), int(sweeps),
-                              int(seed) & (2**64 - 1))
+                              int(seed) & (2**64 - 1), _ptr(pop).value if pop is not None else None)
         rid = ctypes.c_uint64()
         _check(_capi.load().pamc_server_submit(self._h, ctypes.byref(inst), ctypes.byref(rid)), "submit")
         self._nT[rid.value] = len(b)

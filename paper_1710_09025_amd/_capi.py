@@ -41,6 +41,7 @@ class Options(ctypes.Structure):
         ("timing", ctypes.c_int),
         ("group_replicas", ctypes.c_int),
         ("autotune", ctypes.c_int),
+        ("pop_schedule", ctypes.POINTER(ctypes.c_int64)),
     ]
 
 
@@ -89,6 +90,7 @@ class Instance(ctypes.Structure):
         ("n_temps", ctypes.c_int),
         ("sweeps", ctypes.c_int),
         ("seed", ctypes.c_uint64),
+        ("pop_schedule", ctypes.c_void_p),
     ]
 
 

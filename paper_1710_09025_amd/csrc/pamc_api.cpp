@@ -1,6 +1,7 @@
 // pamc_api.cpp -- the extern "C" boundary declared in include/pamc.h.
 // Argument validation, handle bookkeeping and status codes; the work is
 // done by pamc::Runner and the gfx950 kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -61,7 +62,15 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
         if (!std::isfinite(beta[k]) || beta[k] < 0.0) return invalid("beta must be finite and >= 0");
         if (k > 0 && beta[k] < beta[k - 1]) return invalid("beta must be non-decreasing");
     }
-    const int64_t cap = opt.capacity > 0 ? opt.capacity : pamc::default_capacity(R);
+    int64_t peak = R;
+    if (opt.pop_schedule) {
+        if (opt.pop_schedule[0] != R) return invalid("pop_schedule[0] must equal R");
+        for (int k = 0; k < nT; ++k) {
+            if (opt.pop_schedule[k] < 1) return invalid("pop_schedule entries must be >= 1");
+            peak = std::max(peak, (int64_t)opt.pop_schedule[k]);
+        }
+    }
+    const int64_t cap = opt.capacity > 0 ? opt.capacity : pamc::default_capacity(peak);
     if (cap < R) return invalid("capacity must be >= R");
     if (cap >= ((int64_t)1 << 31) - 1024) return invalid("capacity must stay below 2^31");
     if (opt.spin_format != PAMC_SPINS_INT8 && opt.spin_format != PAMC_SPINS_PACKED)
@@ -82,6 +91,9 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     h.NS = NS;
     h.seed = seed;
     h.beta.assign(beta, beta + nT);
+    h.pop.assign((size_t)nT, (double)R);
+    if (opt.pop_schedule)
+        for (int k = 0; k < nT; ++k) h.pop[(size_t)k] = (double)opt.pop_schedule[k];
     h.J.assign(J, J + 3 * N);
     h.ovl_slot.assign(nT, -1);
     h.ovl_n = 0;
@@ -169,6 +181,12 @@ int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt)
     const pamc_options o = resolve(opt);
     const int64_t cap = o.capacity > 0 ? o.capacity : pamc::default_capacity(R);
     const int nov = (o.overlap_steps && o.n_overlap_steps > 0) ? o.n_overlap_steps : 1;
+    if (o.capacity <= 0 && o.pop_schedule) {
+        int64_t peak = R;
+        for (int k = 0; k < n_temps; ++k) peak = std::max(peak, (int64_t)o.pop_schedule[k]);
+        const int64_t c = pamc::default_capacity(peak);
+        return (int64_t)pamc::inst_device_bytes(L, c, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED);
+    }
     return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED);
 }
 
@@ -253,6 +271,7 @@ int pamc_autotune(int L, int64_t R, int sweeps, const pamc_options *opt, int *ti
     o.tile_rows = 0;
     o.group_replicas = 0;
     o.autotune = 0;
+    o.pop_schedule = nullptr;
     // seeded +-J couplings (splitmix64): the sweep's speed does not depend
     // on their values
     const int N = L * L * L;
@@ -325,7 +344,9 @@ int pamc_batch_create(int n, const pamc_instance *inst, const pamc_options *opt,
     std::vector<HostInst> v((size_t)n);
     for (int i = 0; i < n; ++i) {
         const pamc_instance &p = inst[i];
-        int st = pamc::make_inst(p.L, p.couplings, p.R, p.beta, p.n_temps, p.sweeps, p.seed, o, v[(size_t)i]);
+        pamc_options oi = o;
+        oi.pop_schedule = p.pop_schedule;
+        int st = pamc::make_inst(p.L, p.couplings, p.R, p.beta, p.n_temps, p.sweeps, p.seed, oi, v[(size_t)i]);
         if (st != PAMC_OK) {
             pamc::set_error("instance " + std::to_string(i) + ": " + pamc_last_error());
             return st;

@@ -85,6 +85,7 @@ struct Inst {
     const uint4 *thr;   // [nT] (T(dE=4), T(8), T(12), accept_all)
     const double *beta; // [nT]
     const double *rho;  // [nT] exp(-2 (beta_{k+1} - beta_k)), host libm
+    const double *Rt;   // [nT] nominal population R(beta_k) the resampling targets
     const double *nlnn; // [>= Rcap + 1] n ln n, host libm (shared)
     const uint4 *site;  // lex layout: [N] {nb+x|nb-x<<16, nb+y|nb-y<<16, nb+z|nb-z<<16, jmask}
     const uint16_t *grp;// lex layout: [ncol][gmax][4] sites of each Philox block (0xFFFF: none)

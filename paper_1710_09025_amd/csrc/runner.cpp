@@ -104,7 +104,7 @@ struct Carve {
 
 struct InstLayout {
     size_t ctl, status, sync, spins0, spins1, E0, E1, f0, f1, map, loff, bsum, boff, hist, BF, cnt, fpart, thr,
-        beta, rho, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, total;
+        beta, rho, Rt, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, total;
 };
 
 InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool packed)
@@ -140,6 +140,7 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
     l.thr = c.take((size_t)nT * 16);
     l.beta = c.take((size_t)nT * 8);
     l.rho = c.take((size_t)nT * 8);
+    l.Rt = c.take((size_t)nT * 8);
     l.site = c.take((size_t)N * 16);
     l.grp = c.take((size_t)ncol * gmax * 4 * 2);
     l.jeo = c.take((size_t)2 * (N / 8 + 1) * 6 * 4);
@@ -333,6 +334,7 @@ int Runner::upload_inst(int i)
     d.thr = (const uint4 *)(b + lay.thr);
     d.beta = (const double *)(b + lay.beta);
     d.rho = (const double *)(b + lay.rho);
+    d.Rt = (const double *)(b + lay.Rt);
     d.nlnn = d_nlnn_;
     d.site = (const uint4 *)(b + lay.site);
     d.grp = (const uint16_t *)(b + lay.grp);
@@ -493,6 +495,8 @@ int Runner::upload_inst(int i)
     HIPCHK(hipMemcpyAsync(b + lay.beta, h.beta.data(), h.beta.size() * 8, hipMemcpyHostToDevice, stream_),
            "upload beta");
     HIPCHK(hipMemcpyAsync(b + lay.rho, rho.data(), rho.size() * 8, hipMemcpyHostToDevice, stream_), "upload rho");
+    HIPCHK(hipMemcpyAsync(b + lay.Rt, h.pop.data(), h.pop.size() * 8, hipMemcpyHostToDevice, stream_),
+           "upload nominal populations");
     HIPCHK(hipMemcpyAsync(b + lay.site, site.data(), site.size() * 4, hipMemcpyHostToDevice, stream_),
            "upload site");
     HIPCHK(hipMemcpyAsync(b + lay.grp, grp.data(), grp.size() * 2, hipMemcpyHostToDevice, stream_), "upload grp");

@@ -30,6 +30,7 @@ struct HostInst {
     int nT = 0, NS = 0;
     uint64_t seed = 0;
     std::vector<double> beta;
+    std::vector<double> pop;           // [nT] nominal population R(beta_k)
     std::vector<int8_t> J;             // [3][N]
     std::vector<int32_t> ovl_slot;     // [nT]
     int ovl_n = 0;

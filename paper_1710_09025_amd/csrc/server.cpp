@@ -253,6 +253,7 @@ int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_
     o.device = s->device;
     o.autotune = s->autotune ? 1 : 0;
     o.spin_format = s->spin_format;
+    o.pop_schedule = inst->pop_schedule;
     Request r;
     int st = pamc::make_inst(inst->L, inst->couplings, inst->R, inst->beta, inst->n_temps, inst->sweeps, inst->seed,
                              o, r.h);

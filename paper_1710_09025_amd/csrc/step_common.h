@@ -3,7 +3,7 @@
 // summation tree, counting with one atomic per distinct address of a wave,
 // the end-of-launch detection of the last workgroup of an instance, and the
 // measurement of a temperature step (paper Sec. II.B: reweighting factors
-// exp[-(beta'-beta) E_i] normalised to the nominal population).
+// exp[-(beta'-beta) E_i] normalised to the nominal population R(beta')).
 #pragma once
 #include "pamc_dev.h"
 
@@ -214,7 +214,7 @@ __device__ void measure_step(const Inst &I, int k)
             P,
             [&](int m) { return m < nl ? (double)I.hist[lmin + m] * level_weight(pw, (uint32_t)m) : 0.0; },
             tree, roots);
-        const double Rd = (double)I.R;
+        const double Rd = I.Rt[k + 1];  // nominal population at beta_{k+1}
         for (int m = threadIdx.x; m < nl; m += blockDim.x) {
             const double tau = (Rd * level_weight(pw, (uint32_t)m)) / S;
             const double fl = __builtin_floor(tau);

@@ -147,6 +147,7 @@ int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
     o.tile_rows = 0;
     o.group_replicas = 0;
     o.autotune = 0;
+    o.pop_schedule = nullptr;
     o.fuse_gather = 1;
     const int nT = 1 + 3 * (int)cand.size();
     const std::vector<double> beta((size_t)nT, 0.5);

@@ -140,7 +140,8 @@ def test_packed_footprint_saves_the_spin_bytes(lib):
     assert abs((a - b) - 2 * cap * (4096 - 512)) <= 512
 
 
-@pytest.mark.parametrize("case", ["L", "coupling", "beta_order", "beta_nan", "R", "sweeps", "capacity"])
+@pytest.mark.parametrize("case", ["L", "coupling", "beta_order", "beta_nan", "R", "sweeps", "capacity",
+                                  "pop_first", "pop_zero"])
 def test_invalid_arguments_are_rejected_on_the_host(lib, case):
     from paper_1710_09025_amd import _capi
 
@@ -163,6 +164,13 @@ def test_invalid_arguments_are_rejected_on_the_host(lib, case):
         NS = 0
     elif case == "capacity":
         opt.capacity = 50
+    elif case in ("pop_first", "pop_zero"):
+        pop = np.full(len(beta), R, dtype=np.int64)
+        if case == "pop_first":
+            pop[0] = R + 1
+        else:
+            pop[3] = 0
+        opt.pop_schedule = pop.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     h = ctypes.c_void_p()
     st = lib.pamc_create(L, J.ctypes.data_as(ctypes.c_void_p), R, beta.ctypes.data_as(ctypes.c_void_p),
                          len(beta), NS, 1, ctypes.byref(opt), ctypes.byref(h))
