@@ -115,10 +115,11 @@ typedef struct pamc_options {
 void pamc_default_options(pamc_options *opt);
 
 /* Sweep workgroup shape for lattice size L, population R and `sweeps`
- * sweeps per step, chosen by measurement: each candidate shape runs three
- * temperature steps (one warm-up) of a throw-away run with seeded +-J
- * couplings at beta = 0.5, timed by HIP events on opt's stream and device,
- * and the fastest sweep wins.  Results of a run never depend on the shape.
+ * sweeps per step, chosen by measurement: after eight burn-in steps, each
+ * candidate shape runs four temperature steps (one warm-up) of a
+ * throw-away run with seeded +-J couplings at beta = 2, timed by HIP events
+ * on opt's stream and device, and the shape with the fastest timed step
+ * wins.  Results of a run never depend on the shape.
  * Choices are cached per process by (kernel, L, sweeps, capacity rounded up
  * to a power of two, opt's spin format); a cached shape is returned without
  * measuring.  The
