@@ -621,8 +621,12 @@ void Runner::drop_graph()
 {
     if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
+    if (chunk_exec_) (void)hipGraphExecDestroy(chunk_exec_);
+    if (chunk_graph_) (void)hipGraphDestroy(chunk_graph_);
     graph_exec_ = nullptr;
     graph_ = nullptr;
+    chunk_exec_ = nullptr;
+    chunk_graph_ = nullptr;
 }
 
 // The kernels of one temperature step, for every active instance.  Their
@@ -671,10 +675,35 @@ int Runner::enqueue_step()
     }
     if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 1], stream_), "hipEventRecord");
     HIPCHK(hipGetLastError(), "step launch");
+    count_enqueued(1);
+    return PAMC_OK;
+}
+
+void Runner::count_enqueued(int steps)
+{
     for (int i : active_) {
         HostInst &h = inst_[i];
-        if (h.k_enq < h.nT) h.k_enq++;
+        h.k_enq = std::min(h.nT, h.k_enq + steps);
     }
+}
+
+// kChunkSteps steps as one graph launch (the step kernels read the step
+// index from the device, so consecutive steps are the same kernel
+// sequence; steps past an instance's last temperature do nothing).
+int Runner::enqueue_chunk()
+{
+    if (poisoned_) return PAMC_ERR_DEVICE;
+    if (!chunk_exec_) {
+        HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        for (int s = 0; s < kChunkSteps; ++s) launch_step_kernels();
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(stream_, &g), "hipStreamEndCapture");
+        chunk_graph_ = g;
+        HIPCHK(hipGraphInstantiate(&chunk_exec_, chunk_graph_, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    HIPCHK(hipGraphLaunch(chunk_exec_, stream_), "hipGraphLaunch");
+    HIPCHK(hipGetLastError(), "chunk launch");
+    count_enqueued(kChunkSteps);
     return PAMC_OK;
 }
 
@@ -702,12 +731,19 @@ int Runner::phase_times(double *sweep_ms, double *resample_ms, double *gather_ms
 
 int Runner::enqueue_steps(int n)
 {
-    for (int s = 0; s < n; ++s) {
-        bool any = false;
-        for (int i : active_)
-            if (inst_[i].k_enq < inst_[i].nT) any = true;
-        if (!any) break;
-        int st = enqueue_step();
+    // steps left for the active instance that is furthest from its end
+    int left = 0;
+    for (int i : active_) left = std::max(left, inst_[i].nT - inst_[i].k_enq);
+    n = std::min(n, left);
+    while (n > 0) {
+        int st;
+        if (graphs_ && n >= kChunkSteps) {
+            st = enqueue_chunk();
+            n -= kChunkSteps;
+        } else {
+            st = enqueue_step();
+            --n;
+        }
         if (st != PAMC_OK) return st;
     }
     return PAMC_OK;

@@ -153,12 +153,18 @@ private:
     int nlist_ = 0;
     std::vector<void *> work_allocs_;
     std::vector<int> active_;
-    // one captured temperature step, replayed for every step
+    // one captured temperature step, replayed for every step, and a
+    // captured chunk of kChunkSteps steps for runs of whole chunks
+    static constexpr int kChunkSteps = 16;
     bool graphs_ = true;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;
+    hipGraph_t chunk_graph_ = nullptr;
+    hipGraphExec_t chunk_exec_ = nullptr;
     void drop_graph();
     int launch_step_kernels();
+    int enqueue_chunk();
+    void count_enqueued(int steps);
     // timing: four events per enqueued step (before the sweeps, after the
     // sweeps, after the resampling, after the stand-alone gather), reused
     // from a pool

@@ -288,3 +288,15 @@ def test_server_rejects_requests_above_budget():
         srv.submit(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"])
     assert e.value.status == -8
     srv.close()
+
+
+def test_chunked_graphs_equal_direct_launches():
+    """37 temperatures: two replays of the 16-step graph and five single-step
+    replays give the state of direct launches."""
+    inst = instance(5, 900, 37, 3, 4.0, disorder_seed=41, seed=42)
+    a, _ = gpu_run(inst, graphs=True)
+    b, _ = gpu_run(inst, graphs=False)
+    compare_state(a.get_state(), b.get_state(), "chunked graphs vs direct")
+    oa, ob = a.observables(), b.observables()
+    for key in ("R", "sum_E", "lnZ", "S_f"):
+        np.testing.assert_array_equal(oa[key], ob[key])
