@@ -93,11 +93,11 @@ typedef struct pamc_options {
                                 pamc_phase_times); 0 (default): no events   */
     int group_replicas;      /* L other than 8 and 16 (colour-major sweep):
                                 replicas one sweep workgroup holds at once,
-                                an even number (they are swept in pairs);
-                                0 = the library's choice.  Its threads
-                                (threads per replica pair x group_replicas
-                                / 2) must be whole 64-lane waves, at most
-                                1024                                        */
+                                a multiple of four (they are swept in
+                                fours); 0 = the library's choice.  Its
+                                threads (threads per replica quad x
+                                group_replicas / 4) must be whole 64-lane
+                                waves, at most 1024                         */
     int autotune;            /* 1: when tile_rows and group_replicas are 0,
                                 pick them by timing the candidate shapes on
                                 a throw-away run first (see pamc_autotune);

@@ -8,8 +8,8 @@ namespace pamc {
 
 enum SweepVariant { kSweepLex = 0, kSweepEO8 = 1, kSweepEO16 = 2, kSweepCM2 = 3, kSweepCM3 = 4 };
 
-// default number of replica pairs a colour-major workgroup sweeps at once
-// (tpr threads per pair)
+// default number of replica quads a colour-major workgroup sweeps at once
+// (tpr threads per quad)
 int cm_replicas_per_block(int tpr);
 // replicas swept at once by an even/odd-x workgroup (L = 8 or 16); its tile
 // holds a multiple of this many rows
@@ -21,7 +21,7 @@ void launch_init(const Inst *insts, const Work *work, int nwork, size_t lds_byte
 void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t *const *Jraw, hipStream_t st);
 // sweeps of one temperature step; the last workgroup of each instance also
 // measures the step and prepares its resampling table
-// (tpr, rp: threads per replica pair and replica pairs per workgroup of the
+// (tpr, rp: threads per replica quad and replica quads per workgroup of the
 // colour-major kernel; unused by the others)
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
                   int rp, hipStream_t st);

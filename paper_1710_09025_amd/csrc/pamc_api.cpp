@@ -112,9 +112,9 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     if (opt.group_replicas < 0 || opt.group_replicas > 1024) return invalid("group_replicas out of range");
     const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3;
     if (opt.tile_rows > 0 || (cm && opt.group_replicas > 0)) {
-        // the colour-major kernel sweeps replicas in pairs
-        if (cm && opt.group_replicas % 2) return invalid("group_replicas must be even for this lattice");
-        const int rp = cm && opt.group_replicas > 0 ? opt.group_replicas / 2 : h.rp;
+        // the colour-major kernel sweeps replicas in fours
+        if (cm && opt.group_replicas % 4) return invalid("group_replicas must be a multiple of four for this lattice");
+        const int rp = cm && opt.group_replicas > 0 ? opt.group_replicas / 4 : h.rp;
         // without an explicit tile: the default number of passes per workgroup
         int tr = opt.tile_rows > 0 ? opt.tile_rows : (cm ? h.tile_rows / h.rp * rp : h.tile_rows);
         // the even/odd-x kernel sweeps a fixed number of replicas per pass
@@ -259,7 +259,7 @@ int pamc_sweep_shape(const pamc_ctx *ctx, int *tile_rows, int *group_replicas)
     if (!ctx) return invalid("ctx is NULL");
     const HostInst &h = ctx->run.inst(0);
     if (tile_rows) *tile_rows = h.tile_rows;
-    if (group_replicas) *group_replicas = 2 * h.rp;
+    if (group_replicas) *group_replicas = 4 * h.rp;
     return PAMC_OK;
 }
 
@@ -292,7 +292,7 @@ int pamc_autotune(int L, int64_t R, int sweeps, const pamc_options *opt, int *ti
     st = pamc::tune_shape(h, o, ns_per_attempt);
     if (st != PAMC_OK) return st;
     if (tile_rows) *tile_rows = h.tile_rows;
-    if (group_replicas) *group_replicas = 2 * h.rp;
+    if (group_replicas) *group_replicas = 4 * h.rp;
     return PAMC_OK;
 }
 

@@ -79,7 +79,7 @@ LayoutInfo layout_for(int L)
     } else {
         tpr = (li.gmax + 63) / 64 * 64;
     }
-    if (tpr <= 1024 && 2 * rb <= 65535 && 4 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= 65536) {
+    if (tpr <= 1024 && 2 * rb <= 65535 && 8 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= 65536) {
         li.layout = kLayoutCM;
         li.variant = li.ncol == 2 ? kSweepCM2 : kSweepCM3;
         li.row_bytes = rb;

@@ -25,7 +25,7 @@ struct HostInst {
     int packed = 0;                    // spins stored one bit per position
     int srow_bytes = 0;                // bytes per stored spin row
     int tpr = 0;                       // colour-major sweep: threads per replica
-    int rp = 0;                        // colour-major sweep: replica pairs per workgroup
+    int rp = 0;                        // colour-major sweep: replica quads per workgroup
     int64_t R = 0, Rcap = 0;
     int nT = 0, NS = 0;
     uint64_t seed = 0;

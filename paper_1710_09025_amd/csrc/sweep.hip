@@ -551,20 +551,22 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
 // ---------------------------------------------------------------------------
 // Colour-major SWAR sweep for any L whose largest colour has at most 4096
 // sites (two colours for even L, three for odd L).  Storage kLayoutCM: the
-// four sites of a Philox block are one aligned word of the row.
+// four sites of a Philox block are consecutive storage positions.
 //
-// A thread group sweeps two replicas A, B at once from one LDS slot in which
-// their rows are byte-interleaved (position p of A at byte 2p, of B at
-// 2p + 1), followed by the interleaved complement (0/1 swapped).  A bond
-// with coupling -1 reads the neighbour from the complement, so each 16-bit
-// neighbour read returns s_nb ^ [J = -1] of both replicas; with m the
-// per-site sum of the six values a site has n = m unsatisfied bonds when
-// s = 0 and 6 - m when s = 1, i.e. (m ^ 7 s) - s per byte.  The four sites
-// of a Philox block are the words [A0 B0 A1 B1] and [A2 B2 A3 B3]; each
-// thread owns Philox block g of every colour, keeps its 24 neighbour
-// addresses in registers and runs the draws of A and B side by side.
-// Energy: every bond joins two sites of different colours, so
-// U = (1/2) sum over all sites of their unsatisfied bonds.
+// A thread group sweeps four replicas A, B, C, D at once from one LDS slot
+// in which the byte lanes of a word are the replicas: storage position p of
+// the four is the word [A B C D] at plane(p) row_bytes + 4 (p >> 2), with
+// plane(p) = p & 3 (threads of neighbouring Philox blocks read neighbouring
+// words), followed by the same four planes of the complement (0/1 swapped).
+// A bond with coupling -1 reads the neighbour from the complement, so one
+// 32-bit neighbour read returns s_nb ^ [J = -1] of all four replicas; with m
+// the per-site sum of the six words a site has n = m unsatisfied bonds when
+// s = 0 and 6 - m when s = 1, i.e. (m ^ 7 s) - s per byte.  Each thread owns
+// Philox block g of every colour, keeps the 24 neighbour addresses of its
+// four sites in registers and runs the four replicas' draws side by side;
+// site i of the block takes word i of each replica's draw.  Energy: every
+// bond joins two sites of different colours, so U = (1/2) sum over all
+// sites of their unsatisfied bonds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void replica_barrier(int tpr)
 {
@@ -578,49 +580,53 @@ __device__ __forceinline__ void replica_barrier(int tpr)
 }
 
 struct CMBlock {
-    uint32_t nb[24];  // LDS offsets of the neighbour byte pairs, [direction][site]
-    uint32_t own;     // LDS offset of the two words of the block (spin copy)
-    uint32_t vmask0;  // 0x01 in the bytes of real sites, words 0 and 1
-    uint32_t vmask1;
+    uint32_t nb[24];  // LDS offsets of the neighbour words, [direction][site]
+    uint32_t own;     // LDS offset of site 0's word (site i at + i row_bytes)
+    uint32_t vbits;   // bit i set when site i of the block is a real site
     uint32_t ctr;     // Philox counter word 0
     bool has;
 };
 
-// Byte-interleave of two replica words a, b: [a0 b0 a1 b1] and [a2 b2 a3 b3]
-// (v_perm selectors: bytes 0-3 of a, 4-7 of b).
-__device__ __forceinline__ uint32_t ilv_lo(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x05010400u); }
-__device__ __forceinline__ uint32_t ilv_hi(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07030602u); }
-// and back: from w0 = [a0 b0 a1 b1], w1 = [a2 b2 a3 b3]
-__device__ __forceinline__ uint32_t dil_a(uint32_t w0, uint32_t w1) { return __builtin_amdgcn_perm(w1, w0, 0x06040200u); }
-__device__ __forceinline__ uint32_t dil_b(uint32_t w0, uint32_t w1) { return __builtin_amdgcn_perm(w1, w0, 0x07050301u); }
+// Byte offset, in a replica-quad slot, of storage position p (p < row_bytes;
+// the complement's positions follow at 4 row_bytes).
+__device__ __forceinline__ uint32_t quad_pos(uint32_t p, uint32_t row_bytes)
+{
+    return (p & 3u) * row_bytes + 4u * (p >> 2);
+}
 
-// 7 s - s trick per byte: (m ^ 7 s) - s, with 7 s as (s rotated left by 3) - s
-// (s has no bits above bit 24, so the rotation is a shift and stays off the
-// quarter-rate multiplier).
+// 4 x 4 byte transpose: word k of the result holds byte k of w0, w1, w2, w3
+// (v_perm selectors: bytes 0-3 of the second operand, 4-7 of the first).
+// It is its own inverse.
+__device__ __forceinline__ void transpose4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t (&o)[4])
+{
+    const uint32_t a_lo = __builtin_amdgcn_perm(w1, w0, 0x05010400u);  // [w0.0 w1.0 w0.1 w1.1]
+    const uint32_t a_hi = __builtin_amdgcn_perm(w1, w0, 0x07030602u);  // [w0.2 w1.2 w0.3 w1.3]
+    const uint32_t b_lo = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+    const uint32_t b_hi = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+    o[0] = __builtin_amdgcn_perm(b_lo, a_lo, 0x05040100u);
+    o[1] = __builtin_amdgcn_perm(b_lo, a_lo, 0x07060302u);
+    o[2] = __builtin_amdgcn_perm(b_hi, a_hi, 0x05040100u);
+    o[3] = __builtin_amdgcn_perm(b_hi, a_hi, 0x07060302u);
+}
+
+// Per byte (replica): unsatisfied bonds, (m ^ 7 s) - s, with 7 s as (s
+// rotated left by 3) - s (s has no bits above bit 24, so the rotation is a
+// shift and stays off the quarter-rate multiplier).
 __device__ __forceinline__ uint32_t unsat_from_sum(uint32_t m, uint32_t own)
 {
     const uint32_t own7 = __builtin_amdgcn_alignbit(own, own, 29) - own;
     return (m ^ own7) - own;
 }
 
-// Per byte of the two block words: unsatisfied bonds of the four sites of
-// A and B.
-__device__ __forceinline__ void cm_count(const uint8_t *lds, const CMBlock &b, uint2 own, uint32_t &n0, uint32_t &n1)
+__device__ __forceinline__ uint32_t lds_word(const uint8_t *lds, uint32_t a)
 {
-    uint32_t m[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        auto rd = [&](int j) { return (uint32_t)*reinterpret_cast<const uint16_t *>(lds + b.nb[j]); };
-        m[i] = (rd(i) + rd(4 + i) + rd(8 + i)) + (rd(12 + i) + rd(16 + i) + rd(20 + i));
-    }
-    n0 = unsat_from_sum(m[0] | (m[1] << 16), own.x);
-    n1 = unsat_from_sum(m[2] | (m[3] << 16), own.y);
+    return *reinterpret_cast<const uint32_t *>(lds + a);
 }
 
-// Sweeps of the replicas of the tile, two per thread group at a time, each
-// pair loaded into the group's LDS slot (through the copy map) and stored
-// back after its N_S sweeps.  ALL: beta = 0, every move is accepted.  A
-// missing B (odd tail) is swept as zeros and never stored.
+// Sweeps of the replicas of the tile, four per thread group at a time, each
+// quad loaded into the group's LDS slot (through the copy map) and stored
+// back after its N_S sweeps.  ALL: beta = 0, every move is accepted.
+// Missing replicas of the last quad are swept as zeros and never stored.
 template <int NCOL, bool ALL>
 __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, const CMBlock (&blk)[NCOL],
                                           const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows)
@@ -629,28 +635,39 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
     const int RPG = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * 4 * row_bytes;
+    uint8_t *slot = lds + qsub * 8 * row_bytes;
     const int nvec = row_bytes >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
-    for (int qb = 0; qb < nrows; qb += 2 * RPG) {
-        const int qa = qb + 2 * qsub, qbb = qa + 1;
-        const bool act_a = qa < nrows, act_b = qbb < nrows;
-        const uint32_t ra = (uint32_t)(r0 + qa), rb = ra + 1u;
-        if (act_a) {
-            const uint8_t *src_a = io.src + (size_t)(io.map ? io.map[ra] : ra) * io.srow;
-            const uint8_t *src_b = act_b ? io.src + (size_t)(io.map ? io.map[rb] : rb) * io.srow : nullptr;
+    for (int qb = 0; qb < nrows; qb += 4 * RPG) {
+        const int q0 = qb + 4 * qsub;
+        const bool act = q0 < nrows;
+        const uint32_t r0q = (uint32_t)(r0 + q0);
+        if (act) {
+            const uint8_t *src[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t r = r0q + j;
+                src[j] = q0 + j < nrows ? io.src + (size_t)(io.map ? io.map[r] : r) * io.srow : nullptr;
+            }
+            // 16 bytes of a row are four blocks: their plane-k words are 16
+            // contiguous bytes of plane k
             uint4 *sp = reinterpret_cast<uint4 *>(slot);
             for (int i = lane_r; i < nvec; i += tpr) {
-                const uint4 va = stored_vec(io, src_a, i);
-                const uint4 vb = act_b ? stored_vec(io, src_b, i) : make_uint4(0u, 0u, 0u, 0u);
-                const uint4 w0 = make_uint4(ilv_lo(va.x, vb.x), ilv_hi(va.x, vb.x), ilv_lo(va.y, vb.y), ilv_hi(va.y, vb.y));
-                const uint4 w1 = make_uint4(ilv_lo(va.z, vb.z), ilv_hi(va.z, vb.z), ilv_lo(va.w, vb.w), ilv_hi(va.w, vb.w));
-                sp[2 * i] = w0;
-                sp[2 * i + 1] = w1;
-                sp[2 * nvec + 2 * i] = make_uint4(w0.x ^ 0x01010101u, w0.y ^ 0x01010101u, w0.z ^ 0x01010101u,
-                                                  w0.w ^ 0x01010101u);
-                sp[2 * nvec + 2 * i + 1] = make_uint4(w1.x ^ 0x01010101u, w1.y ^ 0x01010101u, w1.z ^ 0x01010101u,
-                                                      w1.w ^ 0x01010101u);
+                uint4 v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = src[j] ? stored_vec(io, src[j], i) : make_uint4(0u, 0u, 0u, 0u);
+                uint32_t ox[4], oy[4], oz[4], ow[4];
+                transpose4(v[0].x, v[1].x, v[2].x, v[3].x, ox);
+                transpose4(v[0].y, v[1].y, v[2].y, v[3].y, oy);
+                transpose4(v[0].z, v[1].z, v[2].z, v[3].z, oz);
+                transpose4(v[0].w, v[1].w, v[2].w, v[3].w, ow);
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) {
+                    const uint4 w = make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]);
+                    sp[pl * nvec + i] = w;
+                    sp[(4 + pl) * nvec + i] =
+                        make_uint4(w.x ^ 0x01010101u, w.y ^ 0x01010101u, w.z ^ 0x01010101u, w.w ^ 0x01010101u);
+                }
             }
         }
         replica_barrier(tpr);
@@ -658,54 +675,74 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 const CMBlock &b = blk[c];
-                if (act_a && b.has) {
-                    const uint2 own = *reinterpret_cast<const uint2 *>(lds + b.own);
-                    uint32_t f0 = b.vmask0, f1 = b.vmask1;
-                    if constexpr (!ALL) {
-                        uint32_t n0, n1;
-                        cm_count(lds, b, own, n0, n1);
-                        const uint4 ctr_a = make_uint4(b.ctr, ra, (uint32_t)k, kTagSweep | (uint32_t)t);
-                        const uint4 ua = philox10(ctr_a, key0, key1);
-                        const uint4 ub = philox10(make_uint4(b.ctr, rb, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
-                        f0 &= eo_flip(n0, make_uint4(ua.x, ub.x, ua.y, ub.y), tab);
-                        f1 &= eo_flip(n1, make_uint4(ua.z, ub.z, ua.w, ub.w), tab);
+                if (act && b.has) {
+                    uint32_t own[4], flip[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        own[i] = lds_word(lds, b.own + i * row_bytes);
+                        flip[i] = ((b.vbits >> i) & 1u) * 0x01010101u;
                     }
-                    const uint2 nw = make_uint2(own.x ^ f0, own.y ^ f1);
-                    *reinterpret_cast<uint2 *>(lds + b.own) = nw;
-                    *reinterpret_cast<uint2 *>(lds + b.own + 2 * row_bytes) =
-                        make_uint2(nw.x ^ 0x01010101u, nw.y ^ 0x01010101u);
+                    if constexpr (!ALL) {
+                        uint4 u[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            u[j] = philox10(make_uint4(b.ctr, r0q + j, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const uint32_t m = (lds_word(lds, b.nb[i]) + lds_word(lds, b.nb[4 + i]) +
+                                                lds_word(lds, b.nb[8 + i])) +
+                                               (lds_word(lds, b.nb[12 + i]) + lds_word(lds, b.nb[16 + i]) +
+                                                lds_word(lds, b.nb[20 + i]));
+                            const uint32_t n = unsat_from_sum(m, own[i]);
+                            flip[i] &= eo_flip(n, make_uint4(word_of(u[0], i), word_of(u[1], i), word_of(u[2], i),
+                                                             word_of(u[3], i)),
+                                               tab);
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t nw = own[i] ^ flip[i];
+                        *reinterpret_cast<uint32_t *>(lds + b.own + i * row_bytes) = nw;
+                        *reinterpret_cast<uint32_t *>(lds + b.own + (4 + i) * row_bytes) = nw ^ 0x01010101u;
+                    }
                 }
                 replica_barrier(tpr);
             }
         }
-        if (act_a) {
-            uint32_t pa = 0, pb = 0;
+        if (act) {
+            // per byte (replica) at most 4 sites x 3 colours x 6 bonds = 72:
+            // the sum stays inside its byte
+            uint32_t acc = 0;
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 if (!blk[c].has) continue;
-                const uint2 own = *reinterpret_cast<const uint2 *>(lds + blk[c].own);
-                uint32_t n0, n1;
-                cm_count(lds, blk[c], own, n0, n1);
-                // padding bytes have no neighbours of their own: mask them
-                n0 &= blk[c].vmask0 * 0xFFu;
-                n1 &= blk[c].vmask1 * 0xFFu;
-                pa = __builtin_amdgcn_sad_u8(n0 & 0x00FF00FFu, 0u, pa);
-                pa = __builtin_amdgcn_sad_u8(n1 & 0x00FF00FFu, 0u, pa);
-                pb = __builtin_amdgcn_sad_u8(n0 & 0xFF00FF00u, 0u, pb);
-                pb = __builtin_amdgcn_sad_u8(n1 & 0xFF00FF00u, 0u, pb);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (!((blk[c].vbits >> i) & 1u)) continue;
+                    const uint32_t m = (lds_word(lds, blk[c].nb[i]) + lds_word(lds, blk[c].nb[4 + i]) +
+                                        lds_word(lds, blk[c].nb[8 + i])) +
+                                       (lds_word(lds, blk[c].nb[12 + i]) + lds_word(lds, blk[c].nb[16 + i]) +
+                                        lds_word(lds, blk[c].nb[20 + i]));
+                    acc += unsat_from_sum(m, lds_word(lds, blk[c].own + i * row_bytes));
+                }
             }
-            atomicAdd(&unsat[qa], (int)pa);
-            if (act_b) atomicAdd(&unsat[qbb], (int)pb);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (q0 + j < nrows) atomicAdd(&unsat[q0 + j], (int)((acc >> (8 * j)) & 0xFFu));
             const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
-            uint8_t *dst_a = io.dst + (size_t)ra * io.srow;
-            uint8_t *dst_b = io.dst + (size_t)rb * io.srow;
             for (int i = lane_r; i < nvec; i += tpr) {
-                const uint4 w0 = sp[2 * i], w1 = sp[2 * i + 1];
-                store_vec(io, dst_a, i, make_uint4(dil_a(w0.x, w0.y), dil_a(w0.z, w0.w), dil_a(w1.x, w1.y),
-                                                   dil_a(w1.z, w1.w)));
-                if (act_b)
-                    store_vec(io, dst_b, i, make_uint4(dil_b(w0.x, w0.y), dil_b(w0.z, w0.w), dil_b(w1.x, w1.y),
-                                                       dil_b(w1.z, w1.w)));
+                uint4 w[4];
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) w[pl] = sp[pl * nvec + i];
+                uint32_t ox[4], oy[4], oz[4], ow[4];
+                transpose4(w[0].x, w[1].x, w[2].x, w[3].x, ox);
+                transpose4(w[0].y, w[1].y, w[2].y, w[3].y, oy);
+                transpose4(w[0].z, w[1].z, w[2].z, w[3].z, oz);
+                transpose4(w[0].w, w[1].w, w[2].w, w[3].w, ow);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (q0 + j < nrows)
+                        store_vec(io, io.dst + (size_t)(r0q + j) * io.srow, i, make_uint4(ox[j], oy[j], oz[j], ow[j]));
             }
         }
         replica_barrier(tpr);
@@ -720,11 +757,12 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
-    const int slot_bytes = 4 * row_bytes;
+    const int slot_bytes = 8 * row_bytes;
     int *unsat = reinterpret_cast<int *>(lds + RPG * slot_bytes + 32);
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
     const uint32_t slot = (uint32_t)(qsub * slot_bytes);
+    const uint32_t rb = (uint32_t)row_bytes;
     CMBlock blk[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) {
@@ -733,14 +771,17 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
         blk[c].ctr = ((uint32_t)c << 24) | (uint32_t)g;
         const int gg = blk[c].has ? g : 0;
         const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
-        // byte offset o of the single-replica slot [row | complement] is
-        // byte pair 2 o of the interleaved slot
+        // byte offset o of the single-replica slot [row | complement]: row
+        // position o, or complement position o - row_bytes
 #pragma unroll
-        for (int i = 0; i < 24; ++i) blk[c].nb[i] = slot + 2u * d[i];
+        for (int i = 0; i < 24; ++i) {
+            const uint32_t o = d[i];
+            blk[c].nb[i] = slot + (o < rb ? quad_pos(o, rb) : 4u * rb + quad_pos(o - rb, rb));
+        }
         const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
-        blk[c].vmask0 = ilv_lo(vm, vm);
-        blk[c].vmask1 = ilv_hi(vm, vm);
-        blk[c].own = slot + 2u * (uint32_t)(I.cbase[c] + 4 * gg);
+        blk[c].vbits = (vm & 1u) | ((vm >> 7) & 2u) | ((vm >> 14) & 4u) | ((vm >> 21) & 8u);
+        // position cbase + 4 g is a multiple of four: site 0 is in plane 0
+        blk[c].own = slot + (uint32_t)(I.cbase[c] + 4 * gg);
     }
     const uint4 th = I.thr[k];
     const bool all = th.w != 0;
@@ -765,7 +806,7 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
 // MAXT: the largest workgroup the instantiation is built for (a 512-thread
 // bound leaves room for every neighbour address in registers).
 template <int NCOL, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows)
+__global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
@@ -841,7 +882,7 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
 }
 
 // Default workgroup shape of the colour-major sweep: tpr threads per
-// replica pair and max(1, 256 / tpr) pairs swept at once.
+// replica quad and max(1, 256 / tpr) quads swept at once.
 int cm_replicas_per_block(int tpr) { return tpr >= 256 ? 1 : 256 / tpr; }
 
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
@@ -849,8 +890,8 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
 {
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
-        // rp replica pairs, each an interleaved row and complement
-        const size_t lds = 4 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
+        // rp replica quads, each four planes of the row and of the complement
+        const size_t lds = 8 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
         const int nt = tpr * rp;
         if (variant == kSweepCM2) {
             if (nt <= 512)

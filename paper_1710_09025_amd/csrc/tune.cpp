@@ -2,7 +2,7 @@
 //
 // How fast the sweep runs depends on how many replica rows one workgroup
 // holds (tile_rows) and, for the colour-major kernel, on how many replica
-// pairs it sweeps at once: a small population needs small
+// quads it sweeps at once: a small population needs small
 // tiles to spread over the 256 compute units, a large one amortises the tile
 // load, the energy epilogue and the measurement tail over more rows.  The
 // tuner runs each candidate shape on a throw-away run of the instance (its
@@ -40,7 +40,7 @@ bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kS
 
 int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
 {
-    if (is_cm(h)) return 4 * (int64_t)h.row_bytes * rp + 32 + 4 * (int64_t)tile_rows;
+    if (is_cm(h)) return 8 * (int64_t)h.row_bytes * rp + 32 + 4 * (int64_t)tile_rows;
     return (int64_t)tile_rows * h.row_bytes + 32 + 4 * (int64_t)tile_rows;
 }
 
@@ -71,7 +71,7 @@ bool shape_valid(const HostInst &h, int tile_rows, int rp, const char **why)
     } else if (is_eo(h) && tile_rows % eo_replicas_per_pass(h.L) != 0) {
         w = "tile_rows must be a multiple of the replicas one pass sweeps";
     } else if (is_cm(h) && (rp < 1 || (h.tpr * rp) % 64 != 0 || h.tpr * rp > 1024)) {
-        w = "group_replicas must be even and make whole waves of at most 1024 threads";
+        w = "group_replicas must be a multiple of four and make whole waves of at most 1024 threads";
     } else if (sweep_lds(h, tile_rows, is_cm(h) ? rp : 0) > kMaxLds) {
         w = "the workgroup's tile does not fit in LDS";
     }
@@ -92,8 +92,8 @@ void default_shape(HostInst &h, int gmax)
         h.rp = 0;
     } else if (is_cm(h)) {
         h.rp = cm_replicas_per_block(h.tpr);
-        const int64_t m = std::max<int64_t>(1, std::min<int64_t>(4, h.Rcap / (target * 2 * h.rp)));
-        h.tile_rows = (int)(m * 2 * h.rp);
+        const int64_t m = std::max<int64_t>(1, std::min<int64_t>(4, h.Rcap / (target * 4 * h.rp)));
+        h.tile_rows = (int)(m * 4 * h.rp);
     } else {
         // per-site kernel: about 512 Philox blocks of work per workgroup
         int tr = (512 + gmax - 1) / gmax;
@@ -118,8 +118,8 @@ std::vector<std::pair<int, int>> shape_candidates(const HostInst &h)
         for (int rp = 1; h.tpr * rp <= 1024; rp *= 2) {
             if ((h.tpr * rp) % 64 != 0) continue;
             for (int m : kPasses)
-                if (shape_valid(h, 2 * m * rp, rp, nullptr) && 2 * m * rp <= 2 * h.Rcap)
-                    c.emplace_back(2 * m * rp, rp);
+                if (shape_valid(h, 4 * m * rp, rp, nullptr) && 4 * m * rp <= 2 * h.Rcap)
+                    c.emplace_back(4 * m * rp, rp);
         }
     } else {
         for (int t = 1; t <= 4096; t *= 2)

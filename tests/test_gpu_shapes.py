@@ -24,13 +24,13 @@ def same_run(a, b, what):
 
 
 # (L, shapes as (tile_rows, group_replicas)): colour-major with two and three
-# colours (8 threads per replica pair at L = 4, 128 at L = 10; odd tiles leave
-# a pair without its second replica), even/odd-x (L = 8, 16), per-site
-# (L = 24); ragged tiles and single-pass workgroups
+# colours (8 threads per replica quad at L = 4, 128 at L = 10; tiles that are
+# not multiples of four leave a quad partly empty), even/odd-x (L = 8, 16),
+# per-site (L = 24); ragged tiles and single-pass workgroups
 SHAPES = [
-    (4, [(16, 16), (40, 16), (128, 64), (1000, 256)]),
-    (5, [(8, 8), (40, 16), (64, 64)]),
-    (10, [(2, 2), (3, 2), (16, 8)]),
+    (4, [(32, 32), (40, 32), (128, 64), (1000, 256)]),
+    (5, [(16, 16), (40, 16), (128, 128)]),
+    (10, [(4, 4), (7, 4), (16, 8), (6, 16)]),
     (8, [(8, 0), (16, 0), (64, 0)]),
     (16, [(2, 0), (4, 0), (14, 0)]),
     (24, [(1, 0), (3, 0)]),

@@ -117,9 +117,9 @@ def test_invalid_sweep_shapes_are_rejected_on_the_host(lib, case):
     elif case == "lds":
         opt.tile_rows = 64          # 64 rows of 4096 bytes exceed the workgroup's LDS
     elif case == "group_waves":
-        opt.group_replicas = 3      # odd: replicas are swept in pairs
+        opt.group_replicas = 6      # not a multiple of four: replicas are swept in fours
     else:
-        opt.group_replicas = 32     # 128 threads per replica pair: 2048 threads
+        opt.group_replicas = 64     # 128 threads per replica quad: 2048 threads
     h = ctypes.c_void_p()
     st = lib.pamc_create(L, J.ctypes.data_as(ctypes.c_void_p), 100, beta.ctypes.data_as(ctypes.c_void_p),
                          len(beta), 1, 1, ctypes.byref(opt), ctypes.byref(h))
