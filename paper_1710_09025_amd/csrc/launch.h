@@ -8,6 +8,14 @@ namespace pamc {
 
 enum SweepVariant { kSweepLex = 0, kSweepEO8 = 1, kSweepEO16 = 2, kSweepCM2 = 3, kSweepCM3 = 4 };
 
+// Dynamic LDS a sweep workgroup may take: gfx950 gives one workgroup up to
+// 160 KB, of which 12 KB stay for the kernels' static LDS (the step
+// measurement's reduction trees).
+constexpr int kMaxSweepLds = 160 * 1024 - 12 * 1024;
+// Lets every sweep kernel launch with up to kMaxSweepLds bytes of dynamic
+// LDS (above the 64 KB default); returns the HIP status.
+hipError_t sweep_kernels_init();
+
 // default number of replica quads a colour-major workgroup sweeps at once
 // (tpr threads per quad)
 int cm_replicas_per_block(int tpr);

@@ -50,7 +50,8 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // L = 8, 16: even/odd-x rows (SWAR words aligned to rows).  Otherwise the
 // colour-major layout when its largest colour fits a workgroup of 1024
-// threads and the slot offsets fit 16 bits; else lexicographic.
+// threads, the slot offsets fit 16 bits and a replica quad's slot fits the
+// workgroup's LDS (even L up to 20, odd L up to 21); else lexicographic.
 LayoutInfo layout_for(int L)
 {
     LayoutInfo li{};
@@ -79,7 +80,7 @@ LayoutInfo layout_for(int L)
     } else {
         tpr = (li.gmax + 63) / 64 * 64;
     }
-    if (tpr <= 1024 && 2 * rb <= 65535 && 8 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= 65536) {
+    if (tpr <= 1024 && 2 * rb <= 65535 && 8 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= kMaxSweepLds) {
         li.layout = kLayoutCM;
         li.variant = li.ncol == 2 ? kSweepCM2 : kSweepCM3;
         li.row_bytes = rb;
@@ -202,6 +203,7 @@ int Runner::setup(const pamc_options &opt, int max_slots)
     max_slots_ = max_slots;
     if (opt.device >= 0) HIPCHK(hipSetDevice(opt.device), "hipSetDevice");
     HIPCHK(hipGetDevice(&device_), "hipGetDevice");
+    HIPCHK(sweep_kernels_init(), "hipFuncSetAttribute (sweep LDS)");
     if (opt.stream) {
         stream_ = (hipStream_t)opt.stream;
     } else {

@@ -871,6 +871,21 @@ __global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *w
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+hipError_t sweep_kernels_init()
+{
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&k_sweep_lex),         reinterpret_cast<const void *>(&k_sweep_eo<8>),
+        reinterpret_cast<const void *>(&k_sweep_eo<16>),      reinterpret_cast<const void *>(&k_sweep_cm<2, 512>),
+        reinterpret_cast<const void *>(&k_sweep_cm<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<3, 512>),
+        reinterpret_cast<const void *>(&k_sweep_cm<3, 1024>),
+    };
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 void launch_init(const Inst *insts, const Work *work, int nwork, size_t lds_bytes, hipStream_t st)
 {
     if (nwork) k_init<<<nwork, 256, lds_bytes, st>>>(insts, work);

@@ -30,7 +30,7 @@ int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int
 
 namespace {
 
-constexpr int64_t kMaxLds = 65536;  // dynamic LDS of one sweep workgroup
+constexpr int64_t kMaxLds = kMaxSweepLds;  // dynamic LDS of one sweep workgroup
 constexpr int kTimedSteps = 3;      // timed steps per candidate shape (after one warm-up)
 constexpr int kBurnIn = 8;          // steps before the first candidate
 constexpr double kTuneBeta = 2.0;   // inside the low-temperature part where an anneal spends most steps

@@ -1,8 +1,8 @@
 """Degenerate and extreme cases against the oracle, bit for bit (through
 the C ABI, on the GPU): a single replica, a single temperature, a single
 sweep, no change of temperature, and the largest lattices of each sweep
-kernel (L = 20 and 23 run the 1024-thread colour-major workgroups, L = 32
-the per-site kernel)."""
+kernel (L = 20 and 21 run the largest colour-major workgroups, 1024 and 896
+threads; L = 23 and 32 the per-site kernel)."""
 import numpy as np
 import pytest
 
@@ -57,6 +57,6 @@ def test_constant_beta_keeps_every_replica():
     assert np.all(p.observables()["R"] == 300)
 
 
-@pytest.mark.parametrize("L,R", [(20, 3), (23, 3), (32, 2)])
+@pytest.mark.parametrize("L,R", [(20, 3), (21, 3), (23, 3), (32, 2)])
 def test_largest_lattices(L, R):
     both(L, R, pi.linear_beta(3.0, 3), 1, 310 + L, 320 + L)
