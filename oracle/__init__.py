@@ -14,6 +14,10 @@ The C sources follow the paper step by step:
   perturbation.
 * ``enumerate.c`` -- exact enumeration of every configuration of tiny
   lattices (Eq. (1)): density of states and overlap distribution.
+
+Couplings are int8 +-1, or int32 fixed-point real couplings J = j 2^-20
+(the paper's Gaussian case study, Sec. II.A); the dtype of the array picks
+the model.  Energies of real-coupling runs are int64 in units of 2^-20.
 """
 from __future__ import annotations
 
@@ -64,6 +68,16 @@ def lib() -> ctypes.CDLL:
         i64, i32, u64, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
         L.orc_create.restype = P
         L.orc_create.argtypes = [i32, P, i64, i64, P, i32, i32, u64, P, P]
+        L.orc_create_real.restype = P
+        L.orc_create_real.argtypes = [i32, P, i64, i64, P, i32, i32, u64, P, P]
+        L.orc_records_wide.argtypes = [P, P]
+        L.orc_get_state64.argtypes = [P, P, P, P]
+        L.orc_energies64.argtypes = [P, P, i64, P]
+        L.orc_sweep_rows64.argtypes = [P, i32, i64, P, P, P]
+        L.orc_exp_f32.restype = ctypes.c_float
+        L.orc_exp_f32.argtypes = [ctypes.c_float]
+        L.orc_real_accept.argtypes = [ctypes.c_float, i64, ctypes.c_uint32]
+        L.enum_energies_real.argtypes = [i32, P, P]
         L.orc_destroy.argtypes = [P]
         L.orc_set_threads.argtypes = [P, i32]
         L.orc_run.argtypes = [P, i32]
@@ -108,6 +122,21 @@ def philox4x32_10(counter, key) -> np.ndarray:
     return out
 
 
+def exp_f32(x: float) -> float:
+    """The oracle's binary32 exponential (acceptance with real couplings)."""
+    return float(lib().orc_exp_f32(ctypes.c_float(x)))
+
+
+def real_accept(bq: float, dE: int, u: int) -> bool:
+    """Acceptance of a move with dE > 0 (units of 2^-20) at binary32 bq."""
+    return bool(lib().orc_real_accept(ctypes.c_float(bq), int(dE), ctypes.c_uint32(u)))
+
+
+def real_beta(beta: float) -> np.float32:
+    """beta 2^-20 rounded to binary32."""
+    return np.float32(beta * 2.0 ** -20)
+
+
 def thresholds(beta: float):
     T = np.zeros(3, dtype=np.uint32)
     flag = ctypes.c_int(0)
@@ -116,7 +145,8 @@ def thresholds(beta: float):
 
 
 class Oracle:
-    """One PAMC run on the CPU.  ``couplings`` is int8 [3][L^3] of +-1."""
+    """One PAMC run on the CPU.  ``couplings`` is int8 [3][L^3] of +-1, or
+    int32 [3][L^3] of fixed-point real couplings (J = j 2^-20, |J| < 8)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  threads=1, pop_schedule=None):
@@ -132,14 +162,17 @@ class Oracle:
             self._pop = np.ascontiguousarray(pop_schedule, dtype=np.int64)
         peak = int(self._pop.max()) if self._pop is not None else self.R
         self.capacity = int(capacity) if capacity is not None else default_capacity(peak)
-        J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
+        self.real = np.asarray(couplings).dtype == np.int32
+        dt = np.int32 if self.real else np.int8
+        J = np.ascontiguousarray(couplings, dtype=dt).reshape(3, self.N)
         self._J = J
+        create = lib().orc_create_real if self.real else lib().orc_create
         ov = None
         if overlap_steps is not None:
             ov = np.zeros(self.nT, dtype=np.uint8)
             ov[np.asarray(overlap_steps, dtype=np.int64)] = 1
             self._ov = ov
-        h = lib().orc_create(self.L, _ptr(J), self.R, self.capacity, _ptr(self.beta), self.nT,
+        h = create(self.L, _ptr(J), self.R, self.capacity, _ptr(self.beta), self.nT,
                              self.sweeps, ctypes.c_uint64(self.seed & (2**64 - 1)),
                              _ptr(ov) if ov is not None else None,
                              _ptr(self._pop) if self._pop is not None else None)
@@ -178,13 +211,17 @@ class Oracle:
         return lib().orc_lnZ(self._h)
 
     def records(self):
+        """Per-step records; sumE2 is a Python int per step (exact)."""
         ints = np.zeros((self.nT, 5), dtype=np.int64)
         dbl = np.zeros((self.nT, 4), dtype=np.float64)
         q = np.zeros((self.nT, 2 * self.N + 1), dtype=np.int64)
         lib().orc_records(self._h, _ptr(ints), _ptr(dbl), _ptr(q))
-        return {"R": ints[:, 0], "sumE": ints[:, 1], "sumE2": ints[:, 2], "Emin": ints[:, 3],
-                "Emax": ints[:, 4], "S": dbl[:, 0], "T": dbl[:, 1], "lnQ": dbl[:, 2],
-                "lnZ": dbl[:, 3], "qhist": q}
+        wide = np.zeros((self.nT, 6), dtype=np.int64)
+        lib().orc_records_wide(self._h, _ptr(wide))
+        sumE2 = [int(np.uint64(lo)) + (int(hi) << 64) for lo, hi in zip(wide[:, 2], wide[:, 3])]
+        return {"R": ints[:, 0], "sumE": wide[:, 1], "sumE2": np.array(sumE2, dtype=object),
+                "Emin": wide[:, 4], "Emax": wide[:, 5], "S": dbl[:, 0], "T": dbl[:, 1],
+                "lnQ": dbl[:, 2], "lnZ": dbl[:, 3], "qhist": q}
 
     def observables(self):
         out = np.zeros((self.nT, 12), dtype=np.float64)
@@ -197,9 +234,10 @@ class Oracle:
     def get_state(self):
         Rk = self.population
         spins = np.zeros((Rk, self.N), dtype=np.int8)
-        E = np.zeros(Rk, dtype=np.int32)
+        E = np.zeros(Rk, dtype=np.int64 if self.real else np.int32)
         fam = np.zeros(Rk, dtype=np.uint32)
-        lib().orc_get_state(self._h, _ptr(spins), _ptr(E), _ptr(fam))
+        get = lib().orc_get_state64 if self.real else lib().orc_get_state
+        get(self._h, _ptr(spins), _ptr(E), _ptr(fam))
         return {"step": self.step, "R": Rk, "spins": spins, "E": E, "family": fam, "lnZ": self.lnZ}
 
     def set_state(self, step, spins, family, lnZ):
@@ -216,8 +254,9 @@ class Oracle:
         their row indices; returns (spins after, energies)."""
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         sp = np.array(spins, dtype=np.int8, order="C", copy=True)
-        E = np.zeros(len(rows), dtype=np.int32)
-        st = lib().orc_sweep_rows(self._h, int(step), len(rows), _ptr(rows), _ptr(sp), _ptr(E))
+        E = np.zeros(len(rows), dtype=np.int64 if self.real else np.int32)
+        sweep = lib().orc_sweep_rows64 if self.real else lib().orc_sweep_rows
+        st = sweep(self._h, int(step), len(rows), _ptr(rows), _ptr(sp), _ptr(E))
         if st != OK:
             raise ValueError(f"oracle sweep_rows failed: {st}")
         return sp, E
@@ -228,8 +267,9 @@ class Oracle:
 
     def energies(self, spins):
         spins = np.ascontiguousarray(spins, dtype=np.int8)
-        E = np.zeros(spins.shape[0], dtype=np.int32)
-        lib().orc_energies(self._h, _ptr(spins), int(spins.shape[0]), _ptr(E))
+        E = np.zeros(spins.shape[0], dtype=np.int64 if self.real else np.int32)
+        en = lib().orc_energies64 if self.real else lib().orc_energies
+        en(self._h, _ptr(spins), int(spins.shape[0]), _ptr(E))
         return E
 
     def colouring(self):
@@ -262,6 +302,34 @@ def all_energies(L, couplings) -> np.ndarray:
     if lib().enum_energies(int(L), _ptr(J), _ptr(E)) != 0:
         raise ValueError("enumeration too large")
     return E
+
+
+def all_energies_real(L, couplings) -> np.ndarray:
+    """Energies (int64, units of 2^-20) of all 2^N configurations of an
+    instance with fixed-point real couplings; bit s of the index is S_s = +1."""
+    N = L ** 3
+    J = np.ascontiguousarray(couplings, dtype=np.int32).reshape(3, N)
+    E = np.zeros(2 ** N, dtype=np.int64)
+    if lib().enum_energies_real(int(L), _ptr(J), _ptr(E)) != 0:
+        raise ValueError("enumeration too large")
+    return E
+
+
+def exact_thermo_real(E_fixed: np.ndarray, N: int, beta):
+    """Exact ln Z, <E>, C_V at each beta from every configuration's energy."""
+    E = E_fixed.astype(np.float64) * 2.0 ** -20
+    out = {"lnZ": [], "mean_E": [], "C_V": []}
+    for b in np.atleast_1d(beta):
+        a = -b * E
+        amax = a.max()
+        w = np.exp(a - amax)
+        Z = w.sum()
+        m1 = (w * E).sum() / Z
+        m2 = (w * E * E).sum() / Z
+        out["lnZ"].append(amax + np.log(Z))
+        out["mean_E"].append(m1)
+        out["C_V"].append(b * b * (m2 - m1 * m1) / N)
+    return {k: np.array(v) for k, v in out.items()}
 
 
 def overlap_distribution(L, couplings, beta) -> np.ndarray:

@@ -148,3 +148,47 @@ int enum_overlap(int L, const int8_t *J, double beta, double *P)
     free(w);
     return 0;
 }
+
+/* Energies, in units of 2^-20, of all 2^N configurations of an instance with
+ * real couplings Jq [3][N] (J = Jq 2^-20): configuration c has S_s = +1 when
+ * bit s of c is set.  Each energy is the plain sum over the 3N bonds,
+ * Eq. (1).  N <= 24. */
+int enum_energies_real(int L, const int32_t *Jq, int64_t *E)
+{
+    int N = L * L * L;
+    if (N > 24) return -1;
+    int nb = 3 * N;
+    int *a = (int *)malloc(sizeof(int) * nb), *b = (int *)malloc(sizeof(int) * nb);
+    int64_t *j = (int64_t *)malloc(sizeof(int64_t) * nb);
+    if (!a || !b || !j) {
+        free(a);
+        free(b);
+        free(j);
+        return -2;
+    }
+    int n = 0;
+    for (int d = 0; d < 3; ++d)
+        for (int z = 0; z < L; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    int s = x + L * (y + L * z);
+                    int xx = d == 0 ? (x + 1) % L : x, yy = d == 1 ? (y + 1) % L : y, zz = d == 2 ? (z + 1) % L : z;
+                    a[n] = s;
+                    b[n] = xx + L * (yy + L * zz);
+                    j[n] = Jq[d * N + s];
+                    ++n;
+                }
+    uint64_t total = (uint64_t)1 << N;
+    for (uint64_t c = 0; c < total; ++c) {
+        int64_t e = 0;
+        for (int i = 0; i < nb; ++i) {
+            int sa = ((c >> a[i]) & 1) ? 1 : -1, sb = ((c >> b[i]) & 1) ? 1 : -1;
+            e -= j[i] * sa * sb;
+        }
+        E[c] = e;
+    }
+    free(a);
+    free(b);
+    free(j);
+    return 0;
+}

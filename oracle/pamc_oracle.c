@@ -7,6 +7,11 @@
  * and the CPU-baseline leg of the benchmark load it.  It shares no code,
  * header, table or constant generator with the GPU library.
  *
+ * Couplings are either +-1 or real, the paper's own case study (Sec. II.A:
+ * Gaussian, mean 0, variance 1), held in fixed point as J = j 2^-20 with an
+ * integer j, |J| < 8, so that energies are exact integers in units of 2^-20
+ * and every sum is independent of its order.
+ *
  * Paper: A. Barzegar, C. Pattison, W. Wang, H. G. Katzgraber, "Optimization
  * of population annealing Monte Carlo for large-scale spin-glass simulations"
  * (arXiv:1710.09025).  Passages followed:
@@ -36,6 +41,11 @@
  *   relative to E_min as a fixed product of powers of exp(-2 dbeta); a
  *   pairwise summation tree for the normaliser and for the family term;
  *   the order sweep -> measure -> resample at every beta_k, beta_0 included.
+ * For real couplings: the fixed-point couplings above; Metropolis acceptance
+ *   u < floor(e 2^32) with e = exp(-beta dE) evaluated in binary32 by the
+ *   function orc_exp_f32 below; per-replica weights relative to E_min as a
+ *   fixed product of exp(-dbeta 2^(b-20)) over the set bits b of E - E_min;
+ *   the normaliser summed by the pairwise tree over replica rows.
  *
  * Spins are stored as int8 +-1, replica-major, sites in lexicographic order
  * s = x + L (y + L z).
@@ -111,13 +121,16 @@ typedef struct {
     uint64_t seed;
     double *beta;
     int64_t *Rt;          /* [nT] nominal population at each beta_k, Rt[0] = R */
-    int8_t *J;      /* [3][N]: bond (s, d) joins s and s + e_d            */
+    int gauss;      /* 1: real couplings in fixed point (units of 2^-20)  */
+    int8_t *J;      /* [3][N]: bond (s, d) joins s and s + e_d (+-1)      */
+    int32_t *Jq;    /* [3][N]: the same for real couplings, J = Jq 2^-20  */
     int *nbr;       /* [N][6]: +x, -x, +y, -y, +z, -z                     */
     int8_t *Jn;     /* [N][6]: coupling of the bond to that neighbour     */
+    int32_t *Jnq;   /* [N][6]: the same for real couplings                */
     int *colour;    /* [N]                                                */
     int *crank;     /* [N]: rank of s among sites of its colour           */
     int8_t *spin, *spin2;
-    int32_t *E, *E2;
+    int64_t *E, *E2; /* energies (units of 2^-20 for real couplings)       */
     uint32_t *fam, *fam2;
     uint32_t *ncopy;
     int64_t Rk;
@@ -126,8 +139,9 @@ typedef struct {
     uint8_t *ovl;   /* [nT]: measure the overlap at this step             */
     int nthreads;
     /* per-step records */
-    int64_t *o_R, *o_sumE, *o_sumE2;
-    int32_t *o_Emin, *o_Emax;
+    int64_t *o_R, *o_sumE;
+    __int128 *o_sumE2;
+    int64_t *o_Emin, *o_Emax;
     double *o_S, *o_T, *o_lnQ, *o_lnZ;
     int64_t *o_q; /* [nT][2N+1] */
 } orc_t;
@@ -150,8 +164,10 @@ void orc_destroy(orc_t *o)
     free(o->beta);
     free(o->Rt);
     free(o->J);
+    free(o->Jq);
     free(o->nbr);
     free(o->Jn);
+    free(o->Jnq);
     free(o->colour);
     free(o->crank);
     free(o->spin);
@@ -175,12 +191,18 @@ void orc_destroy(orc_t *o)
     free(o);
 }
 
-/* Energy of one replica, Eq. (1): each of the 3N bonds counted once. */
-static int32_t energy(const orc_t *o, const int8_t *S)
+/* Coupling of bond (s, d), in units of 2^-20 for real couplings. */
+static int64_t coupling(const orc_t *o, int d, int s)
 {
-    int32_t e = 0;
+    return o->gauss ? (int64_t)o->Jq[d * o->N + s] : (int64_t)o->J[d * o->N + s];
+}
+
+/* Energy of one replica, Eq. (1): each of the 3N bonds counted once. */
+static int64_t energy(const orc_t *o, const int8_t *S)
+{
+    int64_t e = 0;
     for (int s = 0; s < o->N; ++s)
-        for (int d = 0; d < 3; ++d) e -= o->J[d * o->N + s] * S[s] * S[o->nbr[s * 6 + 2 * d]];
+        for (int d = 0; d < 3; ++d) e -= coupling(o, d, s) * S[s] * S[o->nbr[s * 6 + 2 * d]];
     return e;
 }
 
@@ -207,10 +229,10 @@ static void init_population(orc_t *o)
 
 /* pop: NULL for a constant nominal population R, or the nominal population
  * R(beta_k) of every step (pop[0] = R), Sec. III.D. */
-orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double *beta, int nT, int NS,
-                  uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
+static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64_t Rcap, const double *beta,
+                     int nT, int NS, uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
 {
-    if (L < 2 || L > 32 || R < 1 || nT < 1 || NS < 1 || !J || !beta) return NULL;
+    if (L < 2 || L > 32 || R < 1 || nT < 1 || NS < 1 || (!J && !Jq) || !beta) return NULL;
     if (Rcap < R) return NULL;
     if (pop) {
         if (pop[0] != R) return NULL;
@@ -225,6 +247,7 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
     if (!o) return NULL;
     o->L = L;
     o->N = L * L * L;
+    o->gauss = Jq != NULL;
     o->ncol = (L % 2 == 0) ? 2 : 3;
     o->R = R;
     o->Rcap = Rcap;
@@ -237,30 +260,32 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
     o->Rt = (int64_t *)malloc(sizeof(int64_t) * nT);
     if (o->Rt)
         for (int i = 0; i < nT; ++i) o->Rt[i] = pop ? pop[i] : R;
-    o->J = (int8_t *)malloc(3 * (size_t)N);
+    o->J = (int8_t *)calloc(3 * (size_t)N, 1);
+    o->Jq = (int32_t *)calloc(3 * (size_t)N, sizeof(int32_t));
     o->nbr = (int *)malloc(sizeof(int) * 6 * (size_t)N);
-    o->Jn = (int8_t *)malloc(6 * (size_t)N);
+    o->Jn = (int8_t *)calloc(6 * (size_t)N, 1);
+    o->Jnq = (int32_t *)calloc(6 * (size_t)N, sizeof(int32_t));
     o->colour = (int *)malloc(sizeof(int) * N);
     o->crank = (int *)malloc(sizeof(int) * N);
     o->spin = (int8_t *)malloc((size_t)Rcap * N);
     o->spin2 = (int8_t *)malloc((size_t)Rcap * N);
-    o->E = (int32_t *)malloc(sizeof(int32_t) * Rcap);
-    o->E2 = (int32_t *)malloc(sizeof(int32_t) * Rcap);
+    o->E = (int64_t *)malloc(sizeof(int64_t) * Rcap);
+    o->E2 = (int64_t *)malloc(sizeof(int64_t) * Rcap);
     o->fam = (uint32_t *)malloc(sizeof(uint32_t) * Rcap);
     o->fam2 = (uint32_t *)malloc(sizeof(uint32_t) * Rcap);
     o->ncopy = (uint32_t *)malloc(sizeof(uint32_t) * Rcap);
     o->ovl = (uint8_t *)calloc(nT, 1);
     o->o_R = (int64_t *)calloc(nT, sizeof(int64_t));
     o->o_sumE = (int64_t *)calloc(nT, sizeof(int64_t));
-    o->o_sumE2 = (int64_t *)calloc(nT, sizeof(int64_t));
-    o->o_Emin = (int32_t *)calloc(nT, sizeof(int32_t));
-    o->o_Emax = (int32_t *)calloc(nT, sizeof(int32_t));
+    o->o_sumE2 = (__int128 *)calloc(nT, sizeof(__int128));
+    o->o_Emin = (int64_t *)calloc(nT, sizeof(int64_t));
+    o->o_Emax = (int64_t *)calloc(nT, sizeof(int64_t));
     o->o_S = (double *)calloc(nT, sizeof(double));
     o->o_T = (double *)calloc(nT, sizeof(double));
     o->o_lnQ = (double *)calloc(nT, sizeof(double));
     o->o_lnZ = (double *)calloc(nT, sizeof(double));
     o->o_q = (int64_t *)calloc((size_t)nT * (2 * N + 1), sizeof(int64_t));
-    if (!o->beta || !o->Rt || !o->J || !o->nbr || !o->Jn || !o->colour || !o->crank || !o->spin || !o->spin2 ||
+    if (!o->beta || !o->Rt || !o->J || !o->Jq || !o->nbr || !o->Jn || !o->Jnq || !o->colour || !o->crank || !o->spin || !o->spin2 ||
         !o->E || !o->E2 || !o->fam || !o->fam2 || !o->ncopy || !o->ovl || !o->o_R || !o->o_sumE ||
         !o->o_sumE2 || !o->o_Emin || !o->o_Emax || !o->o_S || !o->o_T || !o->o_lnQ || !o->o_lnZ ||
         !o->o_q) {
@@ -268,12 +293,31 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
         return NULL;
     }
     memcpy(o->beta, beta, sizeof(double) * nT);
-    for (int i = 0; i < 3 * N; ++i) {
-        if (J[i] != 1 && J[i] != -1) {
+    if (J) {
+        for (int i = 0; i < 3 * N; ++i) {
+            if (J[i] != 1 && J[i] != -1) {
+                orc_destroy(o);
+                return NULL;
+            }
+            o->J[i] = J[i];
+        }
+    } else {
+        /* |J| < 8; the largest |E| (the sum of |j|) times the capacity stays
+         * below 2^62, so sums of energies fit int64 and the variance numerator
+         * R sum E^2 - (sum E)^2 fits int128 */
+        int64_t A = 0;
+        for (int i = 0; i < 3 * N; ++i) {
+            if (Jq[i] <= -(1 << 23) || Jq[i] >= (1 << 23)) {
+                orc_destroy(o);
+                return NULL;
+            }
+            o->Jq[i] = Jq[i];
+            A += Jq[i] < 0 ? -(int64_t)Jq[i] : (int64_t)Jq[i];
+        }
+        if (A > 0 && (__int128)A * Rcap >= ((__int128)1 << 62)) {
             orc_destroy(o);
             return NULL;
         }
-        o->J[i] = J[i];
     }
     if (overlap_steps)
         memcpy(o->ovl, overlap_steps, nT);
@@ -306,12 +350,34 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
                 jn[3] = o->J[1 * N + ym];
                 jn[4] = o->J[2 * N + s];
                 jn[5] = o->J[2 * N + zm];
+                int32_t *jq = o->Jnq + 6 * s;
+                jq[0] = o->Jq[0 * N + s];
+                jq[1] = o->Jq[0 * N + xm];
+                jq[2] = o->Jq[1 * N + s];
+                jq[3] = o->Jq[1 * N + ym];
+                jq[4] = o->Jq[2 * N + s];
+                jq[5] = o->Jq[2 * N + zm];
                 int c = colour_of(L, x, y, z);
                 o->colour[s] = c;
                 o->crank[s] = count[c]++;
             }
     init_population(o);
     return o;
+}
+
+orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double *beta, int nT, int NS,
+                  uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
+{
+    if (!J) return NULL;
+    return create(L, J, NULL, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
+}
+
+/* Real couplings: Jq int32 [3][N], J = Jq 2^-20, |J| < 8. */
+orc_t *orc_create_real(int L, const int32_t *Jq, int64_t R, int64_t Rcap, const double *beta, int nT, int NS,
+                       uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
+{
+    if (!Jq) return NULL;
+    return create(L, NULL, Jq, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
 }
 
 void orc_set_threads(orc_t *o, int n) { o->nthreads = n < 1 ? 1 : n; }
@@ -330,28 +396,72 @@ void orc_thresholds(double b, uint32_t T[3], int *accept_all)
     }
 }
 
+/* exp(x) in binary32 for -23 <= x <= 0 (acceptance with real couplings).
+ * Cody-Waite reduction x = n ln 2 + r, n = rint(x log2(e)), with ln 2 split
+ * into a head of 16 significant bits (n ln2_hi is exact) and a tail; then
+ * the Taylor polynomial of degree 7 in r (|r| <= ln(2)/2, truncation error
+ * below 2^-27) by Horner's rule with fused multiply-adds, scaled by 2^n.
+ * Every step is a correctly rounded binary32 operation, so any IEEE
+ * implementation of the same steps returns the same bits. */
+float orc_exp_f32(float x)
+{
+    const float log2e = 1.44269504f;
+    const float ln2_hi = 0.693145751953125f;
+    const float ln2_lo = 1.42860677e-06f;
+    float n = rintf(x * log2e);
+    float r = fmaf(-n, ln2_hi, x);
+    r = fmaf(-n, ln2_lo, r);
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)n);
+}
+
+/* Metropolis acceptance of a move with dE > 0 (units of 2^-20) at
+ * bq = beta 2^-20 rounded to binary32: x = -(bq dE) in binary32; rejected
+ * for x < -23 (exp(x) 2^32 < 1); else accepted when e = exp(x) >= 1 or
+ * u < floor(e 2^32). */
+int orc_real_accept(float bq, int64_t dE, uint32_t u)
+{
+    float x = -(bq * (float)dE);
+    if (x < -23.0f) return 0;
+    float e = orc_exp_f32(x);
+    if (e >= 1.0f) return 1;
+    return u < (uint32_t)(e * 4294967296.0f);
+}
+
+/* beta_k 2^-20 rounded to binary32 (the scale is exact in binary64). */
+static float real_beta(double b) { return (float)(b * 0x1p-20); }
+
 /* N_S Metropolis sweeps of one replica at step k (Sec. II.B; checkerboard
  * order of Sec. III.A): colours ascending; inside a colour sites share no
  * bond, so visiting them lexicographically equals updating them at once.
  * S is the replica's configuration, *E its energy, r its row index (which
  * keys the draws together with k). */
-static void sweep_one(const orc_t *o, int8_t *S, int32_t *Ep, int64_t r, int k, const uint32_t T[3],
+static void sweep_one(const orc_t *o, int8_t *S, int64_t *Ep, int64_t r, int k, const uint32_t T[3],
                       int accept_all)
 {
-    int32_t E = *Ep;
+    int64_t E = *Ep;
+    const float bq = real_beta(o->beta[k]);
     for (int t = 0; t < o->NS; ++t)
         for (int c = 0; c < o->ncol; ++c)
             for (int s = 0; s < o->N; ++s) {
                 if (o->colour[s] != c) continue;
                 const int *nb = o->nbr + 6 * s;
-                const int8_t *jn = o->Jn + 6 * s;
-                int h = 0;
-                for (int d = 0; d < 6; ++d) h += jn[d] * S[nb[d]];
-                int dE = 2 * S[s] * h;
+                int64_t h = 0;
+                for (int d = 0; d < 6; ++d)
+                    h += (o->gauss ? (int64_t)o->Jnq[6 * s + d] : (int64_t)o->Jn[6 * s + d]) * S[nb[d]];
+                int64_t dE = 2 * S[s] * h;
                 int i = o->crank[s];
                 uint32_t u = draw(o->seed, ((uint32_t)c << 24) | (uint32_t)(i >> 2), (uint32_t)r,
                                   (uint32_t)k, TAG_SWEEP | (uint32_t)t, i & 3);
-                int accept = accept_all || dE <= 0 || u < T[dE / 4 - 1];
+                int accept = accept_all || dE <= 0 ||
+                             (o->gauss ? orc_real_accept(bq, dE, u) : u < T[dE / 4 - 1]);
                 if (accept) {
                     S[s] = (int8_t)-S[s];
                     E += dE;
@@ -387,12 +497,13 @@ static int64_t pow2_at_least(int64_t n)
 static int measure(orc_t *o)
 {
     int k = o->k, N = o->N;
-    int64_t sumE = 0, sumE2 = 0;
-    int32_t Emin = o->E[0], Emax = o->E[0];
+    int64_t sumE = 0;
+    __int128 sumE2 = 0;
+    int64_t Emin = o->E[0], Emax = o->E[0];
     for (int64_t r = 0; r < o->Rk; ++r) {
         int64_t e = o->E[r];
         sumE += e;
-        sumE2 += e * e;
+        sumE2 += (__int128)e * e;
         if (o->E[r] < Emin) Emin = o->E[r];
         if (o->E[r] > Emax) Emax = o->E[r];
     }
@@ -436,6 +547,83 @@ static int measure(orc_t *o)
     return ORC_OK;
 }
 
+/* Stable copy of the population by the copy numbers o->ncopy (source order,
+ * so families stay contiguous), then swap of the buffers. */
+static void copy_population(orc_t *o)
+{
+    int N = o->N;
+    int64_t d = 0;
+    for (int64_t r = 0; r < o->Rk; ++r)
+        for (uint32_t j = 0; j < o->ncopy[r]; ++j, ++d) {
+            memcpy(o->spin2 + d * N, o->spin + r * N, (size_t)N);
+            o->E2[d] = o->E[r];
+            o->fam2[d] = o->fam[r];
+        }
+    int8_t *ts = o->spin;
+    o->spin = o->spin2;
+    o->spin2 = ts;
+    int64_t *te = o->E;
+    o->E = o->E2;
+    o->E2 = te;
+    uint32_t *tf = o->fam;
+    o->fam = o->fam2;
+    o->fam2 = tf;
+}
+
+/* Resampling with real couplings (Sec. II.B): replica i's weight relative to
+ * the lowest energy is w_i = exp(-dbeta (E_i - E_min)); with D_i = E_i - E_min
+ * in units of 2^-20 it is the product, over the set bits b of D_i in
+ * ascending order, of pw[b] = exp(-dbeta 2^(b-20)) (libm).  S is the
+ * pairwise tree over the replica rows 0 .. P-1 (P the smallest power of two
+ * >= R_k, zero leaves beyond R_k); tau_i = R' w_i / S and the copy numbers
+ * follow as for +-1 couplings. */
+static int resample_real(orc_t *o, double dbeta)
+{
+    int k = o->k;
+    int64_t Emin = o->o_Emin[k];
+    double pw[40];
+    for (int b = 0; b < 40; ++b) pw[b] = exp(-dbeta * ldexp(1.0, b - 20));
+    int64_t P = pow2_at_least(o->Rk);
+    double *w = (double *)malloc(sizeof(double) * (size_t)o->Rk);
+    double *leaf = (double *)calloc((size_t)P, sizeof(double));
+    if (!w || !leaf) {
+        free(w);
+        free(leaf);
+        return ORC_ERR_NOMEM;
+    }
+    for (int64_t r = 0; r < o->Rk; ++r) {
+        int64_t D = o->E[r] - Emin;
+        double x = 1.0;
+        for (int b = 0; b < 40; ++b)
+            if ((D >> b) & 1) x = x * pw[b];
+        w[r] = x;
+        leaf[r] = x;
+    }
+    double S = pairwise_tree(leaf, P);
+    int64_t Rn = 0;
+    for (int64_t r = 0; r < o->Rk; ++r) {
+        double tau = ((double)o->Rt[k + 1] * w[r]) / S;
+        double fl = floor(tau);
+        uint32_t B = (uint32_t)fl;
+        uint32_t F = (uint32_t)floor((tau - fl) * 4294967296.0);
+        uint32_t u = draw(o->seed, 0u, (uint32_t)r, (uint32_t)k, TAG_RESAMPLE, 0);
+        o->ncopy[r] = B + (u < F ? 1u : 0u);
+        Rn += o->ncopy[r];
+    }
+    free(w);
+    free(leaf);
+    if (Rn > o->Rcap) return ORC_ERR_CAPACITY;
+    if (Rn == 0) return ORC_ERR_EXTINCT;
+    copy_population(o);
+    /* free-energy perturbation as for +-1 couplings, E_min in energy units */
+    double lnQ = (-dbeta * ((double)Emin * 0x1p-20)) + log(S) - log((double)o->Rk);
+    o->o_S[k] = S;
+    o->o_lnQ[k] = lnQ;
+    o->lnZ = o->lnZ + lnQ;
+    o->Rk = Rn;
+    return ORC_OK;
+}
+
 /* Resampling from beta_k to beta_{k+1} (Sec. II.B).  The mean number of
  * copies of replica i is tau_i = R' exp[-(beta'-beta) E_i] / sum_j exp[...],
  * so that the expected new population is the nominal R' = R(beta_{k+1})
@@ -446,7 +634,8 @@ static int resample(orc_t *o)
 {
     int k = o->k, N = o->N;
     double dbeta = o->beta[k + 1] - o->beta[k];
-    int32_t Emin = o->o_Emin[k], Emax = o->o_Emax[k];
+    if (o->gauss) return resample_real(o, dbeta);
+    int64_t Emin = o->o_Emin[k], Emax = o->o_Emax[k];
     int64_t M = (Emax - Emin) / 2; /* energies differ by multiples of 2 */
     int64_t P = pow2_at_least(M + 1);
     int64_t *hist = (int64_t *)calloc((size_t)(M + 1), sizeof(int64_t));
@@ -511,7 +700,7 @@ static int resample(orc_t *o)
     int8_t *ts = o->spin;
     o->spin = o->spin2;
     o->spin2 = ts;
-    int32_t *te = o->E;
+    int64_t *te = o->E;
     o->E = o->E2;
     o->E2 = te;
     uint32_t *tf = o->fam;
@@ -562,6 +751,22 @@ int64_t orc_population(const orc_t *o) { return o->Rk; }
 int orc_num_spins(const orc_t *o) { return o->N; }
 double orc_lnZ(const orc_t *o) { return o->lnZ; }
 
+/* Per-step records with the exact sum of E^2 as two 64-bit halves:
+ * ints[k][6] = R_k, sum E, low and high 64 bits of sum E^2, E_min, E_max. */
+int orc_records_wide(const orc_t *o, int64_t *ints)
+{
+    for (int k = 0; k < o->nT; ++k) {
+        unsigned __int128 v = (unsigned __int128)o->o_sumE2[k];
+        ints[6 * k + 0] = o->o_R[k];
+        ints[6 * k + 1] = o->o_sumE[k];
+        ints[6 * k + 2] = (int64_t)(uint64_t)v;
+        ints[6 * k + 3] = (int64_t)(uint64_t)(v >> 64);
+        ints[6 * k + 4] = o->o_Emin[k];
+        ints[6 * k + 5] = o->o_Emax[k];
+    }
+    return ORC_OK;
+}
+
 /* Per-step records: ints[k][5] = R_k, sum E, sum E^2, E_min, E_max;
  * dbl[k][4] = S_k (normaliser), family term T_k, ln Q_k, ln Z_k. */
 int orc_records(const orc_t *o, int64_t *ints, double *dbl, int64_t *qhist)
@@ -569,7 +774,7 @@ int orc_records(const orc_t *o, int64_t *ints, double *dbl, int64_t *qhist)
     for (int k = 0; k < o->nT; ++k) {
         ints[5 * k + 0] = o->o_R[k];
         ints[5 * k + 1] = o->o_sumE[k];
-        ints[5 * k + 2] = o->o_sumE2[k];
+        ints[5 * k + 2] = (int64_t)o->o_sumE2[k];
         ints[5 * k + 3] = o->o_Emin[k];
         ints[5 * k + 4] = o->o_Emax[k];
         dbl[4 * k + 0] = o->o_S[k];
@@ -585,7 +790,16 @@ int orc_records(const orc_t *o, int64_t *ints, double *dbl, int64_t *qhist)
 int orc_get_state(const orc_t *o, int8_t *spins, int32_t *E, uint32_t *fam)
 {
     memcpy(spins, o->spin, (size_t)o->Rk * o->N);
-    memcpy(E, o->E, sizeof(int32_t) * (size_t)o->Rk);
+    for (int64_t r = 0; r < o->Rk; ++r) E[r] = (int32_t)o->E[r];
+    memcpy(fam, o->fam, sizeof(uint32_t) * (size_t)o->Rk);
+    return ORC_OK;
+}
+
+/* The same with 64-bit energies (units of 2^-20 for real couplings). */
+int orc_get_state64(const orc_t *o, int8_t *spins, int64_t *E, uint32_t *fam)
+{
+    memcpy(spins, o->spin, (size_t)o->Rk * o->N);
+    memcpy(E, o->E, sizeof(int64_t) * (size_t)o->Rk);
     memcpy(fam, o->fam, sizeof(uint32_t) * (size_t)o->Rk);
     return ORC_OK;
 }
@@ -614,6 +828,12 @@ int orc_set_state(orc_t *o, int k, int64_t Rk, const int8_t *spins, const uint32
 /* Energy of arbitrary configurations of this instance (Eq. (1)). */
 int orc_energies(const orc_t *o, const int8_t *spins, int64_t n, int32_t *E)
 {
+    for (int64_t r = 0; r < n; ++r) E[r] = (int32_t)energy(o, spins + r * o->N);
+    return ORC_OK;
+}
+
+int orc_energies64(const orc_t *o, const int8_t *spins, int64_t n, int64_t *E)
+{
     for (int64_t r = 0; r < n; ++r) E[r] = energy(o, spins + r * o->N);
     return ORC_OK;
 }
@@ -640,7 +860,9 @@ int orc_neighbours(const orc_t *o, int32_t *nb)
  * S_f, rho_s, and the overlap Binder cumulant g_SG (NaN when the overlap was
  * not measured at k).  Definitions:
  *   <E> = sum E / R_k;  C_V = beta^2 var(E) / N with the variance taken
- *   exactly in integers, (R_k sum E^2 - (sum E)^2) / R_k^2;
+ *   exactly in integers, (R_k sum E^2 - (sum E)^2) / R_k^2 (for real
+ *   couplings the integer sums are in units of 2^-20 and 2^-40, scaled
+ *   after the division);
  *   beta F = -ln Z;  f = -ln Z / (beta N) (NaN at beta = 0);
  *   S_f = ln R_k - (1/R_k) sum_i n_i ln n_i  (= -sum_i nu_i ln nu_i);
  *   rho_s = R_k / e^{S_f} with the local R_k;
@@ -659,9 +881,11 @@ int orc_observables(const orc_t *o, double *out, double *ovl_out)
         v[0] = b;
         if (Rk <= 0) continue;
         double R = (double)Rk;
-        double meanE = (double)o->o_sumE[k] / R;
-        __int128 num = (__int128)Rk * (__int128)o->o_sumE2[k] - (__int128)o->o_sumE[k] * (__int128)o->o_sumE[k];
-        double var = (double)num / (R * R);
+        /* energies in units of 2^-20 for real couplings (exact scalings) */
+        double sc = o->gauss ? 0x1p-20 : 1.0;
+        double meanE = ((double)o->o_sumE[k] * sc) / R;
+        __int128 num = (__int128)Rk * o->o_sumE2[k] - (__int128)o->o_sumE[k] * (__int128)o->o_sumE[k];
+        double var = ((double)num / (R * R)) * (sc * sc);
         v[1] = R;
         v[2] = meanE;
         v[3] = meanE / (double)N;
@@ -705,7 +929,20 @@ int orc_observables(const orc_t *o, double *out, double *ovl_out)
  * spins[i][N] (int8 +-1) is overwritten by its configuration after the N_S
  * sweeps of step k; E[i] receives its energy.  The handle's population is
  * untouched. */
+int orc_sweep_rows64(orc_t *o, int k, int64_t n, const int64_t *rows, int8_t *spins, int64_t *E);
+
 int orc_sweep_rows(orc_t *o, int k, int64_t n, const int64_t *rows, int8_t *spins, int32_t *E)
+{
+    int64_t *E64 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!E64) return ORC_ERR_NOMEM;
+    int st = orc_sweep_rows64(o, k, n, rows, spins, E64);
+    for (int64_t i = 0; i < n; ++i) E[i] = (int32_t)E64[i];
+    free(E64);
+    return st;
+}
+
+/* The same with 64-bit energies (units of 2^-20 for real couplings). */
+int orc_sweep_rows64(orc_t *o, int k, int64_t n, const int64_t *rows, int8_t *spins, int64_t *E)
 {
     if (k < 0 || k >= o->nT || n < 0) return ORC_ERR_INVALID;
     uint32_t T[3];

@@ -4,8 +4,8 @@ This module holds no part of the method's arithmetic: it only draws problem
 instances (couplings), builds temperature schedules and the workload
 descriptions, so that the GPU library, the oracle, the tests and the
 benchmark all see the same inputs.  The paper's own disorder instances are not
-published; +-J couplings with probability 1/2 each from a seeded generator
-stand in for them.
+published; +-J couplings with probability 1/2 each, or Gaussian couplings
+in fixed point, from a seeded generator stand in for them.
 """
 from __future__ import annotations
 
@@ -18,6 +18,23 @@ def pm_j_couplings(L: int, disorder_seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(np.uint64(disorder_seed)))
     bits = rng.integers(0, 2, size=(3, N), dtype=np.int8)
     return (2 * bits - 1).astype(np.int8)
+
+
+# Real couplings are carried in fixed point, J = j 2^-20 with int32 j and
+# |J| < 8, so that energies are exact integers (units of 2^-20).
+REAL_SCALE_BITS = 20
+REAL_LIMIT = (1 << 23) - 1
+
+
+def gaussian_couplings(L: int, disorder_seed: int) -> np.ndarray:
+    """Gaussian couplings (mean 0, variance 1; the paper's case study,
+    Sec. II.A) rounded to the fixed-point grid, int32 [3][L^3] of j with
+    J = j 2^-20; the rare draws with |J| >= 8 are clipped."""
+    N = L ** 3
+    rng = np.random.Generator(np.random.PCG64(np.uint64(disorder_seed)))
+    g = rng.standard_normal(size=(3, N))
+    j = np.rint(g * float(1 << REAL_SCALE_BITS))
+    return np.clip(j, -REAL_LIMIT, REAL_LIMIT).astype(np.int32)
 
 
 def ferro_couplings(L: int) -> np.ndarray:
@@ -46,9 +63,10 @@ def gauge_transform(L: int, couplings: np.ndarray, eps: np.ndarray) -> np.ndarra
     x, y, z = idx % L, (idx // L) % L, idx // (L * L)
     nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z),
           x + L * (y + L * ((z + 1) % L))]
-    J = np.array(couplings, dtype=np.int8).reshape(3, N).copy()
+    dt = np.int32 if np.asarray(couplings).dtype == np.int32 else np.int8
+    J = np.array(couplings, dtype=dt).reshape(3, N).copy()
     for d in range(3):
-        J[d] = (eps * J[d] * eps[nb[d]]).astype(np.int8)
+        J[d] = (eps.astype(np.int64) * J[d] * eps[nb[d]]).astype(dt)
     return J
 
 
