@@ -1,12 +1,15 @@
 /*
- * pamc.h -- population annealing Monte Carlo for 3D +-J Edwards-Anderson spin
- * glasses on AMD Instinct MI355X (gfx950).
+ * pamc.h -- population annealing Monte Carlo for 3D Edwards-Anderson spin
+ * glasses (+-J or real, e.g. Gaussian, couplings) on AMD Instinct MI355X
+ * (gfx950).
  *
  * The operation is the one of Barzegar, Pattison, Wang and Katzgraber,
  * "Optimization of population annealing Monte Carlo for large-scale
  * spin-glass simulations" (arXiv:1710.09025):
  *   - Sec. II.A, Eq. (1): H = -sum_<ij> J_ij S_i S_j on the periodic L^3
- *     lattice, N = L^3 Ising spins, couplings J_ij = +-1;
+ *     lattice, N = L^3 Ising spins, couplings J_ij = +-1 (pamc_create) or
+ *     real (pamc_create_real: the paper's Gaussian case study, held in fixed
+ *     point, J = j 2^-20 with int32 j, |J| < 8);
  *   - Sec. II.B: R replicas start at random at beta_0 = 0; at each of the
  *     n_temps inverse temperatures beta_k the library runs `sweeps`
  *     Metropolis sweeps on every replica (one sweep = N attempted flips,
@@ -109,6 +112,9 @@ typedef struct pamc_options {
                                 targets pop_schedule[k+1], and the default
                                 capacity follows the largest entry.  Read
                                 during pamc_create only.                     */
+    int real_couplings;      /* pamc_footprint and pamc_autotune only (they
+                                take no couplings): 1 = size or tune a run
+                                with real couplings                         */
 } pamc_options;
 
 /* Fills *opt with the defaults described above. */
@@ -148,6 +154,23 @@ typedef struct pamc_ctx pamc_ctx;
 int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps,
                 int sweeps, uint64_t seed, const pamc_options *opt, pamc_ctx **out);
 
+/* The same with real couplings (Sec. II.A: the paper's case study draws them
+ * from a Gaussian of mean 0 and variance 1), in fixed point:
+ *   couplings  int32 [3][N], J = couplings[d*N + s] * 2^-20 with
+ *              |couplings| < 2^23 (|J| < 8), same bond order as pamc_create;
+ *   L          even L <= 20 or odd L <= 21 (the colour-major sweep);
+ *   capacity   at most 2^29, and times the sum of |couplings| below 2^62.
+ * Energies are exact integers in units of 2^-20 (the E_min, E_max, sum_E,
+ * sum_E2 fields of pamc_step_obs and pamc_state.E_fixed); mean_E, e, C_V,
+ * lnQ and the free energies are in energy units.  Metropolis acceptance of
+ * a move with dE > 0: u < floor(e 2^32) with e = exp(-beta dE) evaluated by
+ * a fixed binary32 recipe (Cody-Waite reduction, degree-7 Taylor polynomial
+ * with fused multiply-adds); resampling weights per replica as the product
+ * over the set bits b of E - E_min of exp(-dbeta 2^(b-20)).  Errors as for
+ * pamc_create. */
+int pamc_create_real(int L, const int32_t *couplings, int64_t R, const double *beta, int n_temps,
+                     int sweeps, uint64_t seed, const pamc_options *opt, pamc_ctx **out);
+
 /* Runs up to n_steps temperature steps (n_steps < 0: to the end); a step k
  * is the sweeps at beta_k, the measurements, and for k < n_temps - 1 the
  * resampling to beta_{k+1}.  Returns PAMC_OK when the requested steps (or
@@ -166,9 +189,11 @@ int pamc_sync(pamc_ctx *ctx);
 typedef struct pamc_step_obs {
     double beta;
     int64_t R;          /* population R_k                                  */
-    int64_t sum_E;      /* sum of energies (exact)                         */
-    int64_t sum_E2;     /* sum of squared energies (exact)                 */
-    int32_t E_min, E_max;
+    int64_t sum_E;      /* sum of energies (exact; units of 2^-20 for real
+                           couplings)                                      */
+    int64_t sum_E2;     /* sum of squared energies (exact): low 64 bits    */
+    int64_t sum_E2_hi;  /*   and high 64 bits (0 for +-1 couplings)        */
+    int64_t E_min, E_max;
     double mean_E;      /* sum_E / R_k                                     */
     double e;           /* mean_E / N                                      */
     double C_V;         /* beta^2 var(E) / N, var from the exact sums      */
@@ -197,15 +222,17 @@ int pamc_overlap_hist(const pamc_ctx *ctx, int step, int64_t *hist);
 int pamc_step_sums(const pamc_ctx *ctx, double *S, double *T, int n);
 
 /* Population state.  spins: int8 [R_k][N] of +-1 in lexicographic site
- * order; E: int32 [R_k]; family: uint32 [R_k] (index of the initial
- * replica each row descends from, non-decreasing). */
+ * order; E: int32 [R_k] (+-1 couplings); family: uint32 [R_k] (index of the
+ * initial replica each row descends from, non-decreasing); E_fixed: int64
+ * [R_k] energies in units of 2^-20 (real couplings). */
 typedef struct pamc_state {
     int step;        /* next step to run, 0 .. n_temps                    */
     int64_t R;       /* R_k                                               */
     double lnZ;      /* ln Z_k                                            */
     int8_t *spins;
-    int32_t *E;
+    int32_t *E;      /* +-1 couplings only; untouched for real couplings  */
     uint32_t *family;
+    int64_t *E_fixed;/* real couplings only; untouched for +-1 couplings  */
 } pamc_state;
 
 /* Reads the current step and population size (no copies). */
@@ -223,7 +250,8 @@ int pamc_get_state(pamc_ctx *ctx, pamc_state *st);
 int pamc_set_state(pamc_ctx *ctx, const pamc_state *st);
 
 /* Metropolis thresholds of every step: out[k][0..2] for dE = 4, 8, 12,
- * accept_all[k] = 1 when beta_k = 0 (every move accepted). */
+ * accept_all[k] = 1 when beta_k = 0 (every move accepted).  PAMC_ERR_STATE
+ * for real couplings (their acceptance is evaluated per move). */
 int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all);
 
 /* Device time of the steps run since the previous call (options.timing =
@@ -239,7 +267,8 @@ int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all);
 int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *resample_ms, double *gather_ms,
                      int64_t *n_steps);
 
-/* Device footprint in bytes of a run with these parameters. */
+/* Device footprint in bytes of a run with these parameters; -1 for
+ * arguments no run accepts. */
 int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt);
 
 void pamc_destroy(pamc_ctx *ctx);
@@ -260,6 +289,9 @@ typedef struct pamc_instance {
     int sweeps;
     uint64_t seed;
     const int64_t *pop_schedule; /* NULL or [n_temps], as in pamc_options */
+    const int32_t *real_couplings; /* NULL: couplings (+-1) above; else
+                                 [3][L^3] real couplings as in
+                                 pamc_create_real (couplings is ignored) */
 } pamc_instance;
 
 typedef struct pamc_batch pamc_batch;

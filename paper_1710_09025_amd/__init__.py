@@ -1,5 +1,10 @@
-"""Population annealing Monte Carlo for 3D +-J Edwards-Anderson spin glasses
-on AMD Instinct MI355X (gfx950).
+"""Population annealing Monte Carlo for 3D Edwards-Anderson spin glasses on
+AMD Instinct MI355X (gfx950).
+
+Couplings are int8 +-1, or int32 fixed-point real couplings J = j 2^-20
+with |J| < 8 (the paper's Gaussian case study, Sec. II.A); the dtype of the
+array picks the model.  Energies of real-coupling runs (E_min, E_max, sum_E,
+sum_E2, state energies) are exact integers in units of 2^-20.
 
 Python binding of the C ABI in ``include/pamc.h``: it marshals arguments and
 results; every step of the method runs in the HIP kernels of ``libpamc.so``.
@@ -53,8 +58,19 @@ def _ptr(a: np.ndarray):
 def _obs_to_dict(arr) -> dict:
     out = {}
     for name in OBS_FIELDS:
-        out[name] = np.array([getattr(o, name) for o in arr])
+        if name == "sum_E2":
+            # exact: low and high 64-bit halves of the 128-bit sum
+            out[name] = np.array([(o.sum_E2 & (2**64 - 1)) + (o.sum_E2_hi << 64) for o in arr], dtype=object)
+        else:
+            out[name] = np.array([getattr(o, name) for o in arr])
     return out
+
+
+def _couplings(L, couplings):
+    """(array, real): int32 fixed-point real couplings, else int8 +-1."""
+    real = np.asarray(couplings).dtype == np.int32
+    J = np.ascontiguousarray(couplings, dtype=np.int32 if real else np.int8).reshape(3, int(L) ** 3)
+    return J, real
 
 
 class _TorchGlue:
@@ -130,12 +146,13 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     return opt
 
 
-def autotune(L, R, sweeps, torch_stream=True, packed=False):
+def autotune(L, R, sweeps, torch_stream=True, packed=False, real=False):
     """Sweep workgroup shape chosen by measurement (``pamc_autotune``):
     (tile_rows, group_replicas, sweep ns per attempt).  Cached per process."""
     keep = []
     opt = _make_options(torch_stream=torch_stream, keep=keep,
                         spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
+    opt.real_couplings = 1 if real else 0
     t, g, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     _check(_capi.load().pamc_autotune(int(L), int(R), int(sweeps), ctypes.byref(opt), ctypes.byref(t),
                                       ctypes.byref(g), ctypes.byref(ns)), "pamc_autotune")
@@ -169,7 +186,8 @@ def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None
 
 
 class Pamc:
-    """One population-annealing run on the GPU (``pamc_create``)."""
+    """One population-annealing run on the GPU (``pamc_create``, or
+    ``pamc_create_real`` for int32 real couplings)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
@@ -181,7 +199,7 @@ class Pamc:
         self.beta = np.ascontiguousarray(beta, dtype=np.float64)
         self.nT = len(self.beta)
         self._keep = []
-        J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, self.N)
+        J, self.real = _couplings(self.L, couplings)
         opt = _make_options(capacity, overlap_steps, fuse_gather,
                             spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
@@ -189,9 +207,10 @@ class Pamc:
                             autotune=autotune, pop_schedule=pop_schedule)
         self._opt = opt
         h = ctypes.c_void_p()
-        _check(lib.pamc_create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),
-                               ctypes.c_uint64(int(seed) & (2**64 - 1)), ctypes.byref(opt),
-                               ctypes.byref(h)), "pamc_create")
+        create = lib.pamc_create_real if self.real else lib.pamc_create
+        _check(create(self.L, _ptr(J), self.R, _ptr(self.beta), self.nT, int(sweeps),
+                      ctypes.c_uint64(int(seed) & (2**64 - 1)), ctypes.byref(opt), ctypes.byref(h)),
+               "pamc_create_real" if self.real else "pamc_create")
         self._h = h
 
     def close(self):
@@ -254,11 +273,12 @@ class Pamc:
         return t.value, g.value
 
     def get_state(self) -> dict:
+        """Energies are int32 (+-1 couplings) or int64 in units of 2^-20."""
         k, Rk = self.shape()
         spins = np.zeros((Rk, self.N), dtype=np.int8)
-        E = np.zeros(Rk, dtype=np.int32)
+        E = np.zeros(Rk, dtype=np.int64 if self.real else np.int32)
         fam = np.zeros(Rk, dtype=np.uint32)
-        st = _capi.State(0, 0, 0.0, _ptr(spins).value, _ptr(E).value, _ptr(fam).value)
+        st = _state(spins, E, fam, self.real)
         _check(_capi.load().pamc_get_state(self._h, ctypes.byref(st)), "pamc_get_state")
         return {"step": st.step, "R": st.R, "lnZ": st.lnZ, "spins": spins[: st.R], "E": E[: st.R],
                 "family": fam[: st.R]}
@@ -266,7 +286,7 @@ class Pamc:
     def set_state(self, step, spins, family, lnZ):
         spins = np.ascontiguousarray(spins, dtype=np.int8)
         family = np.ascontiguousarray(family, dtype=np.uint32)
-        st = _capi.State(int(step), spins.shape[0], float(lnZ), _ptr(spins).value, None, _ptr(family).value)
+        st = _capi.State(int(step), spins.shape[0], float(lnZ), _ptr(spins).value, None, _ptr(family).value, None)
         _check(_capi.load().pamc_set_state(self._h, ctypes.byref(st)), "pamc_set_state")
 
     def phase_times(self):
@@ -288,6 +308,12 @@ class Pamc:
         return T, acc
 
 
+def _state(spins, E, fam, real):
+    """A pamc_state over caller buffers: E goes to E_fixed for real couplings."""
+    return _capi.State(0, 0, 0.0, _ptr(spins).value, None if real else _ptr(E).value, _ptr(fam).value,
+                       _ptr(E).value if real else None)
+
+
 class PamcBatch:
     """Many independent instances annealed together (``pamc_batch_*``)."""
 
@@ -298,19 +324,23 @@ class PamcBatch:
         arr = (_capi.Instance * n)()
         self.nT = []
         self.N = []
+        self.real = []
         for i, d in enumerate(instances):
             L = int(d["L"])
-            J = np.ascontiguousarray(d["couplings"], dtype=np.int8).reshape(3, L ** 3)
+            J, real = _couplings(L, d["couplings"])
             b = np.ascontiguousarray(d["beta"], dtype=np.float64)
             self._keep += [J, b]
             pop = None
             if d.get("pop_schedule") is not None:
                 pop = np.ascontiguousarray(d["pop_schedule"], dtype=np.int64)
                 self._keep.append(pop)
-            arr[i] = _capi.Instance(L, _ptr(J).value, int(d["R"]), _ptr(b).value, len(b), int(d["sweeps"]),
-                                    int(d["seed"]) & (2**64 - 1), _ptr(pop).value if pop is not None else None)
+            arr[i] = _capi.Instance(L, None if real else _ptr(J).value, int(d["R"]), _ptr(b).value, len(b),
+                                    int(d["sweeps"]), int(d["seed"]) & (2**64 - 1),
+                                    _ptr(pop).value if pop is not None else None,
+                                    _ptr(J).value if real else None)
             self.nT.append(len(b))
             self.N.append(L ** 3)
+            self.real.append(real)
         opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs,
                             autotune=autotune, spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
         h = ctypes.c_void_p()
@@ -346,9 +376,9 @@ class PamcBatch:
         _check(_capi.load().pamc_batch_shape(self._h, int(i), ctypes.byref(k), ctypes.byref(R)), "shape")
         N = self.N[i]
         spins = np.zeros((R.value, N), dtype=np.int8)
-        E = np.zeros(R.value, dtype=np.int32)
+        E = np.zeros(R.value, dtype=np.int64 if self.real[i] else np.int32)
         fam = np.zeros(R.value, dtype=np.uint32)
-        st = _capi.State(0, 0, 0.0, _ptr(spins).value, _ptr(E).value, _ptr(fam).value)
+        st = _state(spins, E, fam, self.real[i])
         _check(_capi.load().pamc_batch_get_state(self._h, int(i), ctypes.byref(st)), "pamc_batch_get_state")
         return {"step": st.step, "R": st.R, "lnZ": st.lnZ, "spins": spins, "E": E, "family": fam}
 
@@ -369,11 +399,12 @@ class PamcServer:
 
     def submit(self, L, couplings, R, beta, sweeps, seed, pop_schedule=None) -> int:
         L = int(L)
-        J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, L ** 3)
+        J, real = _couplings(L, couplings)
         b = np.ascontiguousarray(beta, dtype=np.float64)
         pop = None if pop_schedule is None else np.ascontiguousarray(pop_schedule, dtype=np.int64)
-        inst = _capi.Instance(L, _ptr(J).value, int(R), _ptr(b).value, len(b), int(sweeps),
-                              int(seed) & (2**64 - 1), _ptr(pop).value if pop is not None else None)
+        inst = _capi.Instance(L, None if real else _ptr(J).value, int(R), _ptr(b).value, len(b), int(sweeps),
+                              int(seed) & (2**64 - 1), _ptr(pop).value if pop is not None else None,
+                              _ptr(J).value if real else None)
         rid = ctypes.c_uint64()
         _check(_capi.load().pamc_server_submit(self._h, ctypes.byref(inst), ctypes.byref(rid)), "submit")
         self._nT[rid.value] = len(b)

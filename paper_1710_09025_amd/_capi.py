@@ -42,6 +42,7 @@ class Options(ctypes.Structure):
         ("group_replicas", ctypes.c_int),
         ("autotune", ctypes.c_int),
         ("pop_schedule", ctypes.POINTER(ctypes.c_int64)),
+        ("real_couplings", ctypes.c_int),
     ]
 
 
@@ -51,8 +52,9 @@ class StepObs(ctypes.Structure):
         ("R", ctypes.c_int64),
         ("sum_E", ctypes.c_int64),
         ("sum_E2", ctypes.c_int64),
-        ("E_min", ctypes.c_int32),
-        ("E_max", ctypes.c_int32),
+        ("sum_E2_hi", ctypes.c_int64),
+        ("E_min", ctypes.c_int64),
+        ("E_max", ctypes.c_int64),
         ("mean_E", ctypes.c_double),
         ("e", ctypes.c_double),
         ("C_V", ctypes.c_double),
@@ -78,6 +80,7 @@ class State(ctypes.Structure):
         ("spins", ctypes.c_void_p),
         ("E", ctypes.c_void_p),
         ("family", ctypes.c_void_p),
+        ("E_fixed", ctypes.c_void_p),
     ]
 
 
@@ -91,6 +94,7 @@ class Instance(ctypes.Structure):
         ("sweeps", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("pop_schedule", ctypes.c_void_p),
+        ("real_couplings", ctypes.c_void_p),
     ]
 
 
@@ -119,6 +123,8 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_double)]),
     "pamc_create": (ctypes.c_int, [ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_uint64, ctypes.POINTER(Options), ctypes.POINTER(P)]),
+    "pamc_create_real": (ctypes.c_int, [ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint64, ctypes.POINTER(Options), ctypes.POINTER(P)]),
     "pamc_anneal": (ctypes.c_int, [P, ctypes.c_int]),
     "pamc_anneal_async": (ctypes.c_int, [P, ctypes.c_int]),
     "pamc_sync": (ctypes.c_int, [P]),

@@ -6,7 +6,16 @@
 
 namespace pamc {
 
-enum SweepVariant { kSweepLex = 0, kSweepEO8 = 1, kSweepEO16 = 2, kSweepCM2 = 3, kSweepCM3 = 4 };
+// CM: colour-major, +-1 couplings; CQ: colour-major, real couplings
+enum SweepVariant {
+    kSweepLex = 0,
+    kSweepEO8 = 1,
+    kSweepEO16 = 2,
+    kSweepCM2 = 3,
+    kSweepCM3 = 4,
+    kSweepCQ2 = 5,
+    kSweepCQ3 = 6
+};
 
 // Dynamic LDS a sweep workgroup may take: gfx950 gives one workgroup up to
 // 160 KB, of which 12 KB stay for the kernels' static LDS (the step
@@ -33,6 +42,9 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
 // colour-major kernel; unused by the others)
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
                   int rp, hipStream_t st);
+// resampling weights and their normaliser (instances with real couplings;
+// work items are 1024-row blocks)
+void launch_weights(const Inst *insts, const Work *work, int nwork, hipStream_t st);
 // copy counts, family entropy, overlap; the last workgroup of each instance
 // finishes the prefix sum and advances the step
 void launch_post(const Inst *insts, const Work *work, int nwork, hipStream_t st);

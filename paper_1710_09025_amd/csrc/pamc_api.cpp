@@ -28,8 +28,8 @@ struct pamc_batch {
 };
 
 namespace pamc {
-int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
-              const pamc_options &opt, HostInst &h);
+int make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
+              uint64_t seed, const pamc_options &opt, HostInst &h);
 bool shape_valid(const HostInst &h, int tile_rows, int rp, const char **why);
 void default_shape(HostInst &h, int gmax);
 int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt);
@@ -45,19 +45,30 @@ int invalid(const std::string &m)
 
 }  // namespace
 
-// Validates one instance and fills the host description.
-int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
-              const pamc_options &opt, HostInst &h)
+// Validates one instance and fills the host description.  Exactly one of J
+// (+-1 couplings) and Jq (real couplings, units of 2^-20) is used: Jq when
+// it is not NULL.
+int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
+                    uint64_t seed, const pamc_options &opt, HostInst &h)
 {
     if (L < 2 || L > 32) return invalid("L must be in [2, 32]");
-    if (!J) return invalid("couplings is NULL");
+    if (!J && !Jq) return invalid("couplings is NULL");
     if (!beta) return invalid("beta is NULL");
     if (R < 1) return invalid("R must be >= 1");
     if (nT < 1) return invalid("n_temps must be >= 1");
     if (NS < 1) return invalid("sweeps must be >= 1");
     const int N = L * L * L;
-    for (int i = 0; i < 3 * N; ++i)
-        if (J[i] != 1 && J[i] != -1) return invalid("couplings must be +1 or -1");
+    const bool real = Jq != nullptr;
+    int64_t absJ = 0;  // sum of |j|: bounds |E| (units of 2^-20)
+    if (real) {
+        for (int i = 0; i < 3 * N; ++i) {
+            if (Jq[i] <= -(1 << 23) || Jq[i] >= (1 << 23)) return invalid("real couplings must satisfy |J| < 8");
+            absJ += Jq[i] < 0 ? -(int64_t)Jq[i] : (int64_t)Jq[i];
+        }
+    } else {
+        for (int i = 0; i < 3 * N; ++i)
+            if (J[i] != 1 && J[i] != -1) return invalid("couplings must be +1 or -1");
+    }
     for (int k = 0; k < nT; ++k) {
         if (!std::isfinite(beta[k]) || beta[k] < 0.0) return invalid("beta must be finite and >= 0");
         if (k > 0 && beta[k] < beta[k - 1]) return invalid("beta must be non-decreasing");
@@ -75,7 +86,12 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     if (cap >= ((int64_t)1 << 31) - 1024) return invalid("capacity must stay below 2^31");
     if (opt.spin_format != PAMC_SPINS_INT8 && opt.spin_format != PAMC_SPINS_PACKED)
         return invalid("unknown spin format");
-    const pamc::LayoutInfo li = pamc::layout_for(L);
+    if (real && (__int128)absJ * cap >= ((__int128)1 << 62))
+        return invalid("capacity times the sum of |couplings| must stay below 2^62");
+    // the normaliser's tree folds at most 2^19 roots of 1024-row blocks
+    if (real && cap > ((int64_t)1 << 29)) return invalid("real couplings: capacity must stay at or below 2^29");
+    const pamc::LayoutInfo li = pamc::layout_for(L, real);
+    if (li.layout < 0) return invalid("real couplings need even L <= 20 or odd L <= 21");
     h.L = L;
     h.N = N;
     h.ncol = li.ncol;
@@ -94,7 +110,11 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     h.pop.assign((size_t)nT, (double)R);
     if (opt.pop_schedule)
         for (int k = 0; k < nT; ++k) h.pop[(size_t)k] = (double)opt.pop_schedule[k];
-    h.J.assign(J, J + 3 * N);
+    h.real = real ? 1 : 0;
+    if (real)
+        h.Jq.assign(Jq, Jq + 3 * N);
+    else
+        h.J.assign(J, J + 3 * N);
     h.ovl_slot.assign(nT, -1);
     h.ovl_n = 0;
     if (opt.overlap_steps && opt.n_overlap_steps > 0) {
@@ -110,7 +130,8 @@ int pamc::make_inst(int L, const int8_t *J, int64_t R, const double *beta, int n
     pamc::default_shape(h, li.gmax);
     if (opt.tile_rows < 0 || opt.tile_rows > 4096) return invalid("tile_rows out of range");
     if (opt.group_replicas < 0 || opt.group_replicas > 1024) return invalid("group_replicas out of range");
-    const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3;
+    const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM3 || h.variant == pamc::kSweepCQ2 ||
+                    h.variant == pamc::kSweepCQ3;
     if (opt.tile_rows > 0 || (cm && opt.group_replicas > 0)) {
         // the colour-major kernel sweeps replicas in fours
         if (cm && opt.group_replicas % 4) return invalid("group_replicas must be a multiple of four for this lattice");
@@ -179,25 +200,32 @@ int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt)
 {
     if (L < 2 || L > 32 || R < 1 || n_temps < 1) return -1;
     const pamc_options o = resolve(opt);
+    if (o.real_couplings && pamc::layout_for(L, true).layout < 0) return -1;
     const int64_t cap = o.capacity > 0 ? o.capacity : pamc::default_capacity(R);
     const int nov = (o.overlap_steps && o.n_overlap_steps > 0) ? o.n_overlap_steps : 1;
     if (o.capacity <= 0 && o.pop_schedule) {
         int64_t peak = R;
         for (int k = 0; k < n_temps; ++k) peak = std::max(peak, (int64_t)o.pop_schedule[k]);
         const int64_t c = pamc::default_capacity(peak);
-        return (int64_t)pamc::inst_device_bytes(L, c, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED);
+        return (int64_t)pamc::inst_device_bytes(L, c, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED,
+                                                o.real_couplings != 0);
     }
-    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED);
+    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED,
+                                            o.real_couplings != 0);
 }
 
-int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps, int sweeps,
-                uint64_t seed, const pamc_options *opt, pamc_ctx **out)
+}  // extern "C"
+
+namespace {
+
+int create_one(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int n_temps, int sweeps,
+               uint64_t seed, const pamc_options *opt, pamc_ctx **out)
 {
     if (!out) return invalid("out is NULL");
     *out = nullptr;
     const pamc_options o = resolve(opt);
     std::vector<HostInst> v(1);
-    int st = pamc::make_inst(L, couplings, R, beta, n_temps, sweeps, seed, o, v[0]);
+    int st = pamc::make_inst(L, J, Jq, R, beta, n_temps, sweeps, seed, o, v[0]);
     if (st != PAMC_OK) return st;
     std::unique_ptr<pamc_ctx> c(new (std::nothrow) pamc_ctx());
     if (!c) return PAMC_ERR_NOMEM;
@@ -211,6 +239,30 @@ int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, i
     if (st != PAMC_OK) return st;
     *out = c.release();
     return PAMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps, int sweeps,
+                uint64_t seed, const pamc_options *opt, pamc_ctx **out)
+{
+    if (!couplings) {
+        if (out) *out = nullptr;
+        return invalid("couplings is NULL");
+    }
+    return create_one(L, couplings, nullptr, R, beta, n_temps, sweeps, seed, opt, out);
+}
+
+int pamc_create_real(int L, const int32_t *couplings, int64_t R, const double *beta, int n_temps, int sweeps,
+                     uint64_t seed, const pamc_options *opt, pamc_ctx **out)
+{
+    if (!couplings) {
+        if (out) *out = nullptr;
+        return invalid("couplings is NULL");
+    }
+    return create_one(L, nullptr, couplings, R, beta, n_temps, sweeps, seed, opt, out);
 }
 
 int pamc_anneal_async(pamc_ctx *ctx, int n_steps)
@@ -272,22 +324,24 @@ int pamc_autotune(int L, int64_t R, int sweeps, const pamc_options *opt, int *ti
     o.group_replicas = 0;
     o.autotune = 0;
     o.pop_schedule = nullptr;
-    // seeded +-J couplings (splitmix64): the sweep's speed does not depend
-    // on their values
+    // seeded couplings (splitmix64): +-1, or real ones spread over
+    // (-2, 2); the sweep's speed does not depend on their values
     const int N = L * L * L;
     std::vector<int8_t> J((size_t)3 * N);
+    std::vector<int32_t> Jq(o.real_couplings ? (size_t)3 * N : 0);
     uint64_t x = 0x2545F4914F6CDD1Dull;
-    for (auto &j : J) {
+    for (size_t i = 0; i < J.size(); ++i) {
         x += 0x9E3779B97F4A7C15ull;
         uint64_t z = x;
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         z ^= z >> 31;
-        j = (z >> 63) ? 1 : -1;
+        J[i] = (z >> 63) ? 1 : -1;
+        if (!Jq.empty()) Jq[i] = (int32_t)(z >> 42) - (1 << 21);
     }
     const double beta[2] = {0.0, 0.5};
     HostInst h;
-    int st = pamc::make_inst(L, J.data(), R, beta, 2, sweeps, 1, o, h);
+    int st = pamc::make_inst(L, J.data(), Jq.empty() ? nullptr : Jq.data(), R, beta, 2, sweeps, 1, o, h);
     if (st != PAMC_OK) return st;
     st = pamc::tune_shape(h, o, ns_per_attempt);
     if (st != PAMC_OK) return st;
@@ -346,7 +400,8 @@ int pamc_batch_create(int n, const pamc_instance *inst, const pamc_options *opt,
         const pamc_instance &p = inst[i];
         pamc_options oi = o;
         oi.pop_schedule = p.pop_schedule;
-        int st = pamc::make_inst(p.L, p.couplings, p.R, p.beta, p.n_temps, p.sweeps, p.seed, oi, v[(size_t)i]);
+        int st = pamc::make_inst(p.L, p.real_couplings ? nullptr : p.couplings, p.real_couplings, p.R, p.beta,
+                                 p.n_temps, p.sweeps, p.seed, oi, v[(size_t)i]);
         if (st != PAMC_OK) {
             pamc::set_error("instance " + std::to_string(i) + ": " + pamc_last_error());
             return st;

@@ -40,14 +40,27 @@ constexpr int kRowsPerBlock = 1024;  // rows handled per block by row kernels
 constexpr int kOvlPairs = 256;       // replica pairs per overlap workgroup
 constexpr int kOvlLdsBins = 8194;    // overlap histograms up to this many bins (L <= 16) are built in LDS
 
-// Per-step integer record written on the device.
+// Per-step integer record written on the device.  Energies are in units of
+// 2^-20 for real couplings.
 struct StepRec {
-    int64_t R;      // R_k
-    int64_t sumE;   // sum of E
-    int64_t sumE2;  // sum of E^2
-    int32_t Emin, Emax;
-    double S;       // resampling normaliser (NaN at the last step)
-    double T;       // family term sum n ln n
+    int64_t R;        // R_k
+    int64_t sumE;     // sum of E
+    uint64_t sumE2;   // sum of E^2: low 64 bits of the exact 128-bit sum
+    int64_t sumE2_hi; //   and its high 64 bits
+    int64_t Emin, Emax;
+    double S;         // resampling normaliser (NaN at the last step)
+    double T;         // family term sum n ln n
+};
+
+// Energy moments of a step's population with real couplings, accumulated
+// with atomics by the sweep workgroups (one update per tile) and read and
+// reset by the step measurement.  Sums are exact: E^2 as a 128-bit integer.
+struct EMoments {
+    long long emin, emax;
+    unsigned long long sum;      // sum of E, two's complement
+    unsigned long long sq_lo;    // sum of E^2, low 64 bits
+    unsigned long long sq_hi;    //   high 64 bits (carries added)
+    unsigned long long pad[3];
 };
 
 struct Inst {
@@ -64,6 +77,7 @@ struct Inst {
     int32_t nlev;       // 3N + 1 energy levels
     int32_t fam_pow2;   // smallest power of two >= R (family tree leaves)
     int32_t ovl_n;      // number of overlap steps
+    int32_t real;       // 1: real couplings in fixed point, J = j 2^-20 (int32 j, |J| < 8)
     // double-buffered population
     uint8_t *spins[2];
     int32_t *E[2];
@@ -73,7 +87,7 @@ struct Inst {
     uint32_t *loff;     // [Rcap] first destination of each row inside its row block
     uint32_t *bsum;     // [nblk]
     uint32_t *boff;     // [nblk]
-    uint32_t *sync;     // [2] workgroups finished in the current sweep / post launch
+    uint32_t *sync;     // [4] workgroups finished in the current sweep / post / weights launch
     int32_t sweep_tiles;  // workgroups of this instance in a sweep launch
     int32_t post_blocks;  // workgroups of this instance in a post launch
     int32_t tile_rows;    // replica rows per sweep workgroup
@@ -101,6 +115,15 @@ struct Inst {
     int32_t ncs[3];     // sites per colour
     int32_t gcs[3];     // Philox blocks per colour, ceil(ncs / 4)
     int32_t gmax;
+    // real couplings (CM layout)
+    int64_t *Eq[2];     // energies, units of 2^-20
+    double *wrep;       // [Rcap] resampling weight of each row
+    double *wpart;      // [nblk] pairwise-tree roots of the 1024-row blocks
+    EMoments *emom;     // energy moments of the step being swept
+    const int32_t *cmj; // [ncol][gmax][24] coupling of each neighbour bond, in cmdesc order
+    const float *bq;    // [nT] beta_k 2^-20 rounded to binary32
+    const double *gpw;  // [nT][40] exp(-(beta_{k+1} - beta_k) 2^(b-20)), host libm
+    int64_t Jtot;       // sum of all couplings
     // progress and records
     int32_t *k;         // current step (device scalar)
     int32_t *cur;       // buffer holding the current population (0/1)

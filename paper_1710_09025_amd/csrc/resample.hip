@@ -19,6 +19,54 @@
 
 namespace pamc {
 
+// Resampling weights with real couplings (Sec. II.B), for rows
+// [row0, row0 + 1024) of one instance after the sweeps of step k:
+// w_r = exp(-dbeta (E_r - E_min)) as the product over the set bits b of
+// E_r - E_min (units of 2^-20) of exp(-dbeta 2^(b-20)), in ascending b.  The
+// block's 1024 leaves (zero beyond R_k) form an aligned subtree of the
+// pairwise tree over rows 0 .. P-1 (P the smallest power of two >= R_k); the
+// last workgroup of the instance folds the block roots (zero for blocks
+// beyond R_k) into the normaliser S.  For P < 1024 the block tree adds only
+// zeros above the P-leaf subtree, which leaves its sum unchanged.
+__global__ __launch_bounds__(512) void k_weights(const Inst *insts, const Work *work)
+{
+    __shared__ double pw[40];
+    __shared__ double a[512];
+    __shared__ double roots[512];
+    const Work w = work[blockIdx.x];
+    const Inst &I = insts[w.inst];
+    const int k = *I.k;
+    if (!inst_live(I, k) || k >= I.nT - 1) return;
+    const int Rk = (int)I.Rk[k];
+    const int t = threadIdx.x;
+    if (t < 40) pw[t] = I.gpw[(size_t)k * 40 + t];
+    __syncthreads();
+    const long long Emin = I.rec[k].Emin;
+    const int64_t *E = I.Eq[*I.cur];
+    double l[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int r = (int)w.row0 + 2 * t + j;
+        if (r < Rk) {
+            const double x = weight64(pw, (uint64_t)(E[r] - Emin));
+            I.wrep[r] = x;
+            l[j] = x;
+        }
+    }
+    a[t] = l[0] + l[1];
+    __syncthreads();
+    const double root = lds_pairwise(a, 512);
+    if (t == 0) I.wpart[w.row0 / kRowsPerBlock] = root;
+    if (last_workgroup(&I.sync[2], I.nblk)) {
+        int P = 1;
+        while (P < Rk) P <<= 1;
+        const int nroot = P > kRowsPerBlock ? P / kRowsPerBlock : 1;
+        const double S = tree_sum<512>(
+            nroot, [&](int b) { return b * kRowsPerBlock < Rk ? I.wpart[b] : 0.0; }, a, roots);
+        if (t == 0) I.rec[k].S = S;
+    }
+}
+
 // Exclusive scan over the workgroup (1024 threads, 16 waves).
 __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t *sh, uint32_t *total)
 {
@@ -54,10 +102,17 @@ __device__ void copies_role(const Inst &I, int k, uint32_t row0, uint32_t *sh)
     const int r = (int)row0 + (int)threadIdx.x;
     uint32_t n = 0;
     if (r < Rk) {
-        const int m = (I.E[*I.cur][r] - I.rec[k].Emin) >> 1;
-        const uint2 bf = I.BF[m];
         const uint32_t u = philox10(make_uint4(0u, (uint32_t)r, (uint32_t)k, kTagResample), I.key0, I.key1).x;
-        n = bf.x + (u < bf.y ? 1u : 0u);
+        if (I.real) {
+            // per-replica weight from the weights launch
+            const double tau = (I.Rt[k + 1] * I.wrep[r]) / I.rec[k].S;
+            const double fl = __builtin_floor(tau);
+            n = (uint32_t)fl + (u < (uint32_t)__builtin_floor((tau - fl) * 4294967296.0) ? 1u : 0u);
+        } else {
+            const int m = (int)((I.E[*I.cur][r] - I.rec[k].Emin) >> 1);
+            const uint2 bf = I.BF[m];
+            n = bf.x + (u < bf.y ? 1u : 0u);
+        }
     }
     uint32_t total;
     const uint32_t off = block_exscan(n, sh, &total);
@@ -253,6 +308,10 @@ __global__ void k_flip(const Inst *insts, const uint32_t *list)
 }
 
 // ---------------------------------------------------------------------------
+void launch_weights(const Inst *insts, const Work *work, int nwork, hipStream_t st)
+{
+    if (nwork) k_weights<<<nwork, 512, 0, st>>>(insts, work);
+}
 void launch_post(const Inst *insts, const Work *work, int nwork, hipStream_t st)
 {
     if (nwork) k_post<<<nwork, 1024, 0, st>>>(insts, work);

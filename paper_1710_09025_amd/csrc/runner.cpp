@@ -52,7 +52,9 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // colour-major layout when its largest colour fits a workgroup of 1024
 // threads, the slot offsets fit 16 bits and a replica quad's slot fits the
 // workgroup's LDS (even L up to 20, odd L up to 21); else lexicographic.
-LayoutInfo layout_for(int L)
+// Real couplings: the colour-major layout wherever it fits (a quad slot of
+// four planes), L = 8 and 16 included; no kernel beyond it.
+LayoutInfo layout_for(int L, bool real)
 {
     LayoutInfo li{};
     const int N = L * L * L;
@@ -63,7 +65,7 @@ LayoutInfo layout_for(int L)
     li.gmax = 1;
     for (int c = 0; c < 3; ++c) li.gmax = std::max(li.gmax, (li.ncs[c] + 3) / 4);
     li.row_bytes = (N + 15) & ~15;
-    if (L == 8 || L == 16) {
+    if (!real && (L == 8 || L == 16)) {
         li.layout = kLayoutEO;
         li.variant = L == 8 ? kSweepEO8 : kSweepEO16;
         return li;
@@ -79,6 +81,18 @@ LayoutInfo layout_for(int L)
         while (tpr < li.gmax) tpr <<= 1;
     } else {
         tpr = (li.gmax + 63) / 64 * 64;
+    }
+    if (real) {
+        if (tpr <= 1024 && 2 * rb <= 65535 && 4 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 8 * 64 <= kMaxSweepLds) {
+            li.layout = kLayoutCM;
+            li.variant = li.ncol == 2 ? kSweepCQ2 : kSweepCQ3;
+            li.row_bytes = rb;
+            li.tpr = tpr;
+        } else {
+            li.layout = -1;
+            li.variant = -1;
+        }
+        return li;
     }
     if (tpr <= 1024 && 2 * rb <= 65535 && 8 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= kMaxSweepLds) {
         li.layout = kLayoutCM;
@@ -105,13 +119,14 @@ struct Carve {
 
 struct InstLayout {
     size_t ctl, status, sync, spins0, spins1, E0, E1, f0, f1, map, loff, bsum, boff, hist, BF, cnt, fpart, thr,
-        beta, rho, Rt, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, total;
+        beta, rho, Rt, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, Eq0, Eq1, wrep, wpart, emom, cmj,
+        bq, gpw, total;
 };
 
-InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool packed)
+InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool packed, bool real)
 {
     const int N = L * L * L;
-    const LayoutInfo li = layout_for(L);
+    const LayoutInfo li = layout_for(L, real);
     const int row_bytes = stored_row_bytes(li.row_bytes, packed);
     const int ncol = li.ncol;
     const int nblk = (int)((Rcap + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -123,11 +138,11 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
     InstLayout l{};
     l.ctl = c.take(16);
     l.status = c.take(8);
-    l.sync = c.take(8);
+    l.sync = c.take(16);
     l.spins0 = c.take((size_t)Rcap * row_bytes);
     l.spins1 = c.take((size_t)Rcap * row_bytes);
-    l.E0 = c.take((size_t)Rcap * 4);
-    l.E1 = c.take((size_t)Rcap * 4);
+    l.E0 = c.take(real ? 16 : (size_t)Rcap * 4);
+    l.E1 = c.take(real ? 16 : (size_t)Rcap * 4);
     l.f0 = c.take((size_t)Rcap * 4);
     l.f1 = c.take((size_t)Rcap * 4);
     l.map = c.take((size_t)Rcap * 4);
@@ -145,13 +160,23 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
     l.site = c.take((size_t)N * 16);
     l.grp = c.take((size_t)ncol * gmax * 4 * 2);
     l.jeo = c.take((size_t)2 * (N / 8 + 1) * 6 * 4);
-    l.J = c.take((size_t)3 * N);
+    l.J = c.take((size_t)3 * N * (real ? 4 : 1));
     l.pos = c.take((size_t)N * 2);
     l.cmdesc = li.layout == kLayoutCM ? c.take((size_t)ncol * gmax * 32 * 2) : c.take(16);
     l.Rk = c.take((size_t)(nT + 1) * 4);
     l.rec = c.take((size_t)nT * sizeof(StepRec));
     l.ovl_slot = c.take((size_t)nT * 4);
     l.qhist = c.take((size_t)std::max(1, n_ovl) * (2 * N + 1) * 4);
+    // real couplings: 64-bit energies, per-row weights, block roots, moments,
+    // couplings per neighbour word and the per-step scalars
+    l.Eq0 = c.take(real ? (size_t)Rcap * 8 : 16);
+    l.Eq1 = c.take(real ? (size_t)Rcap * 8 : 16);
+    l.wrep = c.take(real ? (size_t)Rcap * 8 : 16);
+    l.wpart = c.take(real ? (size_t)nblk * 8 : 16);
+    l.emom = c.take(sizeof(EMoments));
+    l.cmj = c.take(real ? (size_t)ncol * gmax * 24 * 4 : 16);
+    l.bq = c.take((size_t)nT * 4);
+    l.gpw = c.take(real ? (size_t)nT * 40 * 8 : 16);
     l.total = c.off;
     return l;
 }
@@ -159,10 +184,10 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
 
 int stored_row_bytes(int row_bytes, bool packed) { return packed ? (row_bytes + 127) / 128 * 16 : row_bytes; }
 
-size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed)
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bool real)
 {
     // R <= Rcap; use Rcap for the family counters as an upper bound
-    return layout_of(L, Rcap, Rcap, nT, n_ovl, packed).total;
+    return layout_of(L, Rcap, Rcap, nT, n_ovl, packed, real).total;
 }
 
 Runner::~Runner()
@@ -289,7 +314,7 @@ int Runner::upload_inst(int i)
 {
     HostInst &h = inst_[i];
     const int L = h.L, N = h.N;
-    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n, h.packed != 0);
+    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n, h.packed != 0, h.real != 0);
     h.bytes = lay.total;
     h.block = alloc_.get(lay.total);
     if (!h.block) {
@@ -352,6 +377,17 @@ int Runner::upload_inst(int i)
     d.qhist = (uint32_t *)(b + lay.qhist);
     d.status = (uint32_t *)(b + lay.status);
     d.sync = (uint32_t *)(b + lay.sync);
+    d.real = h.real;
+    d.Eq[0] = (int64_t *)(b + lay.Eq0);
+    d.Eq[1] = (int64_t *)(b + lay.Eq1);
+    d.wrep = (double *)(b + lay.wrep);
+    d.wpart = (double *)(b + lay.wpart);
+    d.emom = (EMoments *)(b + lay.emom);
+    d.cmj = (const int32_t *)(b + lay.cmj);
+    d.bq = (const float *)(b + lay.bq);
+    d.gpw = (const double *)(b + lay.gpw);
+    d.Jtot = 0;
+    for (int32_t v : h.Jq) d.Jtot += v;
     d.tile_rows = h.tile_rows;
     d.sweep_tiles = (int32_t)((h.Rcap + h.tile_rows - 1) / h.tile_rows);
     {
@@ -395,9 +431,10 @@ int Runner::upload_inst(int i)
         d.gcs[c] = (ncs[c] + 3) / 4;
     }
     d.gmax = std::max(d.gcs[0], std::max(d.gcs[1], d.gcs[2]));
-    auto J = [&](int dir, int s) { return (int)h.J[(size_t)dir * N + s]; };
+    // coupling of bond (dir, s): +-1, or j (units of 2^-20) for real couplings
+    auto J = [&](int dir, int s) { return h.real ? (int)h.Jq[(size_t)dir * N + s] : (int)h.J[(size_t)dir * N + s]; };
     auto site_of = [L](int x, int y, int z) { return ((x % L + L) % L) + L * (((y % L + L) % L) + L * ((z % L + L) % L)); };
-    const LayoutInfo li = layout_for(L);
+    const LayoutInfo li = layout_for(L, h.real != 0);
     for (int c = 0; c < 3; ++c) d.cbase[c] = li.cbase[c];
     d.tpr = li.tpr;
     // storage position of each site
@@ -414,6 +451,7 @@ int Runner::upload_inst(int i)
         pos16[s] = (uint16_t)h.lex_pos[s];
     }
     std::vector<uint16_t> cmdesc;
+    std::vector<int32_t> cmj;
     std::vector<uint32_t> site((size_t)N * 4, 0u);
     std::vector<uint16_t> grp((size_t)h.ncol * d.gmax * 4, (uint16_t)0xFFFF);
     std::vector<uint32_t> jeo((size_t)2 * (N / 8 + 1) * 6, 0u);
@@ -439,10 +477,12 @@ int Runner::upload_inst(int i)
                 }
     } else if (h.layout == kLayoutCM) {
         // per colour, Philox block and site: the LDS offsets of its six
-        // neighbours, in the complemented copy (+row_bytes) for a -1 bond
+        // neighbours, in the complemented copy (+row_bytes) for a -1 bond;
+        // for real couplings the plain copy, with the couplings alongside
         std::vector<int> site_at((size_t)3 * N, -1);
         for (int s = 0; s < N; ++s) site_at[(size_t)col[s] * N + rank[s]] = s;
         cmdesc.assign((size_t)h.ncol * d.gmax * 32, 0);
+        if (h.real) cmj.assign((size_t)h.ncol * d.gmax * 24, 0);
         for (int c = 0; c < h.ncol; ++c)
             for (int g = 0; g < d.gcs[c]; ++g) {
                 uint16_t *e = cmdesc.data() + ((size_t)c * d.gmax + g) * 32;
@@ -460,8 +500,14 @@ int Runner::upload_inst(int i)
                     const int nb[6] = {site_of(x + 1, y, z), site_of(x - 1, y, z), site_of(x, y + 1, z),
                                        site_of(x, y - 1, z), site_of(x, y, z + 1), site_of(x, y, z - 1)};
                     const int jv[6] = {J(0, s), J(0, nb[1]), J(1, s), J(1, nb[3]), J(2, s), J(2, nb[5])};
-                    for (int dd = 0; dd < 6; ++dd)
-                        e[4 * dd + bb] = (uint16_t)(h.lex_pos[nb[dd]] + (jv[dd] < 0 ? h.row_bytes : 0));
+                    for (int dd = 0; dd < 6; ++dd) {
+                        if (h.real) {
+                            e[4 * dd + bb] = (uint16_t)h.lex_pos[nb[dd]];
+                            cmj[((size_t)c * d.gmax + g) * 24 + 4 * dd + bb] = jv[dd];
+                        } else {
+                            e[4 * dd + bb] = (uint16_t)(h.lex_pos[nb[dd]] + (jv[dd] < 0 ? h.row_bytes : 0));
+                        }
+                    }
                 }
                 e[24] = (uint16_t)(vmask & 0xFFFFu);
                 e[25] = (uint16_t)(vmask >> 16);
@@ -489,6 +535,21 @@ int Runner::upload_inst(int i)
                 (void)H;
             }
     }
+    // real couplings: beta_k 2^-20 in binary32 and the weight factors
+    // exp(-(beta_{k+1} - beta_k) 2^(b-20)), b < 40, host libm
+    std::vector<float> bq((size_t)h.nT);
+    for (int k = 0; k < h.nT; ++k) bq[(size_t)k] = (float)(h.beta[k] * 0x1p-20);
+    std::vector<double> gpw;
+    if (h.real) {
+        gpw.assign((size_t)h.nT * 40, 1.0);
+        for (int k = 0; k + 1 < h.nT; ++k) {
+            const double db = h.beta[k + 1] - h.beta[k];
+            for (int bb = 0; bb < 40; ++bb) gpw[(size_t)k * 40 + bb] = std::exp(-db * std::ldexp(1.0, bb - 20));
+        }
+    }
+    EMoments em{};
+    em.emin = std::numeric_limits<long long>::max();
+    em.emax = std::numeric_limits<long long>::min();
     std::vector<uint32_t> Rk0((size_t)h.nT + 1, 0u);
     Rk0[0] = (uint32_t)h.R;
     int32_t ctl[4] = {0, 0, 0, 0};
@@ -503,7 +564,18 @@ int Runner::upload_inst(int i)
            "upload site");
     HIPCHK(hipMemcpyAsync(b + lay.grp, grp.data(), grp.size() * 2, hipMemcpyHostToDevice, stream_), "upload grp");
     HIPCHK(hipMemcpyAsync(b + lay.jeo, jeo.data(), jeo.size() * 4, hipMemcpyHostToDevice, stream_), "upload jeo");
-    HIPCHK(hipMemcpyAsync(b + lay.J, h.J.data(), h.J.size(), hipMemcpyHostToDevice, stream_), "upload J");
+    if (h.real)
+        HIPCHK(hipMemcpyAsync(b + lay.J, h.Jq.data(), h.Jq.size() * 4, hipMemcpyHostToDevice, stream_), "upload J");
+    else
+        HIPCHK(hipMemcpyAsync(b + lay.J, h.J.data(), h.J.size(), hipMemcpyHostToDevice, stream_), "upload J");
+    HIPCHK(hipMemcpyAsync(b + lay.bq, bq.data(), bq.size() * 4, hipMemcpyHostToDevice, stream_), "upload bq");
+    HIPCHK(hipMemcpyAsync(b + lay.emom, &em, sizeof(em), hipMemcpyHostToDevice, stream_), "upload moments");
+    if (!gpw.empty())
+        HIPCHK(hipMemcpyAsync(b + lay.gpw, gpw.data(), gpw.size() * 8, hipMemcpyHostToDevice, stream_),
+               "upload weight factors");
+    if (!cmj.empty())
+        HIPCHK(hipMemcpyAsync(b + lay.cmj, cmj.data(), cmj.size() * 4, hipMemcpyHostToDevice, stream_),
+               "upload couplings per neighbour word");
     HIPCHK(hipMemcpyAsync(b + lay.pos, pos16.data(), pos16.size() * 2, hipMemcpyHostToDevice, stream_), "upload pos");
     if (!cmdesc.empty())
         HIPCHK(hipMemcpyAsync(b + lay.cmdesc, cmdesc.data(), cmdesc.size() * 2, hipMemcpyHostToDevice, stream_),
@@ -557,7 +629,7 @@ int Runner::build_work(const std::vector<int> &active)
         return p;
     };
     std::map<std::tuple<int, int, int, int, int, int>, std::vector<Work>> groups;
-    std::vector<Work> rows, post, gath;
+    std::vector<Work> rows, post, gath, wblk;
     std::vector<uint32_t> list;
     for (int i : active) {
         const HostInst &h = inst_[i];
@@ -567,6 +639,7 @@ int Runner::build_work(const std::vector<int> &active)
         for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) {
             rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
             post.push_back(Work{ii, (uint32_t)r, kRoleCopies, 0u});
+            if (h.real) wblk.push_back(Work{ii, (uint32_t)r, 0u, 0u});
         }
         for (const Work &w : gather_items(ii, h.Rcap, h.srow_bytes)) gath.push_back(w);
         int64_t fp2 = 1;
@@ -592,6 +665,12 @@ int Runner::build_work(const std::vector<int> &active)
     ngather_ = (int)gath.size();
     d_post_ = (Work *)upload(post.data(), post.size() * sizeof(Work));
     d_list_ = (uint32_t *)upload(list.data(), list.size() * 4);
+    d_wblk_ = nullptr;
+    nwblk_ = (int)wblk.size();
+    if (nwblk_) {
+        d_wblk_ = (Work *)upload(wblk.data(), wblk.size() * sizeof(Work));
+        if (!d_wblk_) return dev_fail(hipErrorOutOfMemory, "upload weight work");
+    }
     if (!d_rows_ || !d_post_ || !d_list_ || !d_gather_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
     nrows_work_ = (int)rows.size();
     npost_ = (int)post.size();
@@ -639,6 +718,7 @@ int Runner::launch_step_kernels()
     for (auto &g : sweep_groups_)
         launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, stream_);
     if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 3], stream_), "hipEventRecord");
+    launch_weights(d_insts_, d_wblk_, nwblk_, stream_);
     launch_post(d_insts_, d_post_, npost_, stream_);
     launch_expand(d_insts_, d_rows_, nrows_work_, stream_);
     if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 2], stream_), "hipEventRecord");
@@ -823,14 +903,18 @@ int Runner::observables(int i, pamc_step_obs *out, int n)
         o.measured = 1;
         o.R = r.R;
         o.sum_E = r.sumE;
-        o.sum_E2 = r.sumE2;
+        o.sum_E2 = (int64_t)r.sumE2;
+        o.sum_E2_hi = r.sumE2_hi;
         o.E_min = r.Emin;
         o.E_max = r.Emax;
         const double Rd = (double)r.R;
-        o.mean_E = (double)r.sumE / Rd;
+        // energies in units of 2^-20 for real couplings (exact scalings)
+        const double sc = h.real ? 0x1p-20 : 1.0;
+        o.mean_E = ((double)r.sumE * sc) / Rd;
         o.e = o.mean_E / (double)N;
-        const __int128 num = (__int128)r.R * (__int128)r.sumE2 - (__int128)r.sumE * (__int128)r.sumE;
-        const double var = (double)num / (Rd * Rd);
+        const __int128 sum2 = (__int128)(((unsigned __int128)(uint64_t)r.sumE2_hi << 64) | r.sumE2);
+        const __int128 num = (__int128)r.R * sum2 - (__int128)r.sumE * (__int128)r.sumE;
+        const double var = ((double)num / (Rd * Rd)) * (sc * sc);
         o.C_V = (o.beta * o.beta) * var / (double)N;
         o.lnZ = lnZ;
         o.betaF = -lnZ;
@@ -839,7 +923,7 @@ int Runner::observables(int i, pamc_step_obs *out, int n)
         o.rho_s = Rd / std::exp(o.S_f);
         if (k < h.nT - 1 && k + 1 < kdone + (status[0] ? 0 : 1)) {
             const double db = h.beta[k + 1] - h.beta[k];
-            o.lnQ = (-db * (double)r.Emin) + std::log(r.S) - std::log(Rd);
+            o.lnQ = (-db * ((double)r.Emin * sc)) + std::log(r.S) - std::log(Rd);
             lnZ = lnZ + o.lnQ;
         }
         const int slot = h.ovl_slot[k];
@@ -977,7 +1061,12 @@ int Runner::get_state(int i, pamc_state *stt)
             }
         }
     }
-    if (stt->E) HIPCHK(hipMemcpy(stt->E, h.dev.E[cur], (size_t)Rk * 4, hipMemcpyDeviceToHost), "read E");
+    if (h.real) {
+        if (stt->E_fixed)
+            HIPCHK(hipMemcpy(stt->E_fixed, h.dev.Eq[cur], (size_t)Rk * 8, hipMemcpyDeviceToHost), "read E");
+    } else if (stt->E) {
+        HIPCHK(hipMemcpy(stt->E, h.dev.E[cur], (size_t)Rk * 4, hipMemcpyDeviceToHost), "read E");
+    }
     if (stt->family)
         HIPCHK(hipMemcpy(stt->family, h.dev.fam[cur], (size_t)Rk * 4, hipMemcpyDeviceToHost), "read family");
     return PAMC_OK;
@@ -1041,6 +1130,10 @@ int Runner::set_state(int i, const pamc_state *st)
 int Runner::thresholds(int i, uint32_t *out, uint8_t *acc)
 {
     const HostInst &h = inst_[i];
+    if (h.real) {
+        set_error("thresholds: runs with real couplings take their acceptance per move (no table)");
+        return PAMC_ERR_STATE;
+    }
     std::vector<uint32_t> thr((size_t)h.nT * 4);
     HIPCHK(hipMemcpy(thr.data(), h.dev.thr, thr.size() * 4, hipMemcpyDeviceToHost), "read thr");
     for (int k = 0; k < h.nT; ++k) {

@@ -23,6 +23,7 @@ struct HostInst {
     int L = 0, N = 0, ncol = 0, layout = 0, variant = 0;
     int row_bytes = 0, tile_rows = 0;
     int packed = 0;                    // spins stored one bit per position
+    int real = 0;                      // real couplings in fixed point (Jq)
     int srow_bytes = 0;                // bytes per stored spin row
     int tpr = 0;                       // colour-major sweep: threads per replica
     int rp = 0;                        // colour-major sweep: replica quads per workgroup
@@ -31,7 +32,8 @@ struct HostInst {
     uint64_t seed = 0;
     std::vector<double> beta;
     std::vector<double> pop;           // [nT] nominal population R(beta_k)
-    std::vector<int8_t> J;             // [3][N]
+    std::vector<int8_t> J;             // [3][N] +-1 couplings
+    std::vector<int32_t> Jq;           // [3][N] real couplings, J = Jq 2^-20
     std::vector<int32_t> ovl_slot;     // [nT]
     int ovl_n = 0;
     int k_enq = 0;                     // steps enqueued so far
@@ -56,21 +58,23 @@ struct Allocator {
 };
 
 // Footprint and table construction helpers.
-size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed);
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bool real = false);
 // Bytes per stored spin row: row_bytes, or one bit per position rounded up
 // to 16 bytes.
 int stored_row_bytes(int row_bytes, bool packed);
 int64_t default_capacity(int64_t R);
 // Storage layout for lattice size L, and the shape it implies.
 struct LayoutInfo {
-    int layout, variant, ncol;
+    int layout, variant, ncol;  // layout < 0: no kernel for this lattice
     int ncs[3];       // sites per colour
     int cbase[3];     // colour-major: first byte of each colour
     int row_bytes;    // bytes per replica row (multiple of 16)
     int gmax;         // Philox blocks of the largest colour
     int tpr;          // colour-major: threads per replica
 };
-LayoutInfo layout_for(int L);
+// Real couplings use the colour-major layout for every L it covers (L = 8
+// and 16 included).
+LayoutInfo layout_for(int L, bool real = false);
 
 class Runner {
 public:
@@ -145,6 +149,8 @@ private:
     std::vector<SweepGroup> sweep_groups_;
     Work *d_rows_ = nullptr;   // 1024-row blocks (expand)
     int nrows_work_ = 0;
+    Work *d_wblk_ = nullptr;   // 1024-row blocks of instances with real couplings (weights)
+    int nwblk_ = 0;
     Work *d_gather_ = nullptr; // row blocks of about 32 KB of spins (stand-alone gather)
     int ngather_ = 0;
     Work *d_post_ = nullptr;   // post-launch workgroups with their roles

@@ -21,8 +21,8 @@
 #include "runner.h"
 
 namespace pamc {
-int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
-              const pamc_options &opt, HostInst &h);
+int make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
+              uint64_t seed, const pamc_options &opt, HostInst &h);
 }
 
 using pamc::HostInst;
@@ -255,10 +255,12 @@ int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_
     o.spin_format = s->spin_format;
     o.pop_schedule = inst->pop_schedule;
     Request r;
-    int st = pamc::make_inst(inst->L, inst->couplings, inst->R, inst->beta, inst->n_temps, inst->sweeps, inst->seed,
-                             o, r.h);
+    int st = pamc::make_inst(inst->L, inst->real_couplings ? nullptr : inst->couplings, inst->real_couplings,
+                             inst->R, inst->beta, inst->n_temps, inst->sweeps, inst->seed, o, r.h);
     if (st != PAMC_OK) return st;
-    r.bytes = pamc::inst_device_bytes(inst->L, r.h.Rcap, inst->n_temps, r.h.ovl_n, r.h.packed != 0) + 4096;
+    r.bytes = pamc::inst_device_bytes(inst->L, r.h.Rcap, inst->n_temps, r.h.ovl_n, r.h.packed != 0,
+                                      r.h.real != 0) +
+              4096;
     r.n_temps = inst->n_temps;
     if (r.bytes > s->budget) {
         pamc::set_error("request needs " + std::to_string(r.bytes) + " bytes, more than the budget");

@@ -124,6 +124,52 @@ __device__ __forceinline__ double level_weight(const double *pw, uint32_t m)
     return x;
 }
 
+// w = product over the set bits b of D (< 2^40), ascending, of pw[b].
+__device__ __forceinline__ double weight64(const double *pw, uint64_t D)
+{
+    double x = 1.0;
+    for (int b = 0; D != 0; ++b, D >>= 1)
+        if (D & 1u) x = x * pw[b];
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Metropolis acceptance with real couplings.  exp(x) in binary32 for
+// -23 <= x <= 0 by a fixed recipe of correctly rounded steps: Cody-Waite
+// reduction x = n ln 2 + r, n = rint(x log2 e), with ln 2 split into a head
+// of 16 significant bits (n times it is exact) and a tail; the Taylor
+// polynomial of degree 7 in r (|r| <= ln(2)/2) by Horner's rule with fused
+// multiply-adds; scaling by 2^n.  Any IEEE implementation of the same steps
+// returns the same bits, so decisions are reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float exp_recipe(float x)
+{
+    const float n = __builtin_rintf(x * 1.44269504f);
+    float r = __builtin_fmaf(-n, 0.693145751953125f, x);
+    r = __builtin_fmaf(-n, 1.42860677e-06f, r);
+    float p = 1.0f / 5040.0f;
+    p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+    p = __builtin_fmaf(p, r, 0.5f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    return __builtin_ldexpf(p, (int)n);
+}
+
+// A move with dE > 0 (units of 2^-20) at bq = beta 2^-20 (binary32) is
+// accepted when x = -(bq dE) >= -23 and e = exp(x) >= 1 or u < floor(e 2^32).
+// The argument of the recipe is clamped to [-24, 0], which leaves every
+// decision unchanged and keeps its conversions in range for any dE.
+__device__ __forceinline__ bool real_accept(float bq, int32_t dE, uint32_t u)
+{
+    const float x = -(bq * (float)dE);
+    const float e = exp_recipe(__builtin_fminf(__builtin_fmaxf(x, -24.0f), 0.0f));
+    const uint32_t T = (uint32_t)((e < 1.0f ? e : 0.0f) * 4294967296.0f);
+    return x >= -23.0f && (e >= 1.0f || u < T);
+}
+
 // Adds one count per valid lane to arr[idx], one atomic per distinct index
 // of the wave: at low temperature most replicas share a few energies (and
 // sorted families share ids), and per-lane atomics on one address would
@@ -196,7 +242,8 @@ __device__ void measure_step(const Inst &I, int k)
     if (threadIdx.x == 0) {
         rec->R = I.Rk[k];
         rec->sumE = s1;
-        rec->sumE2 = s2;
+        rec->sumE2 = (uint64_t)s2;
+        rec->sumE2_hi = 0;
         rec->Emin = 2 * lmin - N3;
         rec->Emax = 2 * lmax - N3;
         rec->S = __builtin_nan("");
@@ -229,6 +276,34 @@ __device__ void measure_step(const Inst &I, int k)
     for (int m = threadIdx.x; m < I.nlev; m += blockDim.x) I.hist[m] = 0u;
     // the sweep of this step moved the population to the other buffer
     if (threadIdx.x == 0 && *I.mapped) {
+        *I.cur ^= 1;
+        *I.mapped = 0;
+    }
+}
+
+// Measurement of step k with real couplings, by the last sweep workgroup:
+// the energy moments the tiles accumulated (exact integers) go to the step
+// record and are reset for the next step; the weights and the normaliser
+// follow in the weights launch.  Moves the buffer roles on when the sweep
+// wrote the other buffer.
+__device__ __forceinline__ void measure_step_real(const Inst &I, int k)
+{
+    if (threadIdx.x != 0) return;
+    EMoments *m = I.emom;
+    StepRec *rec = I.rec + k;
+    rec->R = I.Rk[k];
+    rec->sumE = (int64_t)m->sum;
+    rec->sumE2 = m->sq_lo;
+    rec->sumE2_hi = (int64_t)m->sq_hi;
+    rec->Emin = m->emin;
+    rec->Emax = m->emax;
+    rec->S = __builtin_nan("");
+    m->emin = 0x7FFFFFFFFFFFFFFFll;
+    m->emax = -0x7FFFFFFFFFFFFFFFll - 1;
+    m->sum = 0ull;
+    m->sq_lo = 0ull;
+    m->sq_hi = 0ull;
+    if (*I.mapped) {
         *I.cur ^= 1;
         *I.mapped = 0;
     }

@@ -124,6 +124,27 @@ __global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *w
     const int8_t *J = Jraw[w.inst];
     const int L = I.L, N = I.N;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (I.real) {
+        // real couplings: int32 [3][N] in units of 2^-20, 64-bit sums
+        const int32_t *Jq = reinterpret_cast<const int32_t *>(J);
+        for (int q = wave; q < kRowsPerBlock; q += 4) {
+            const int r = (int)w.row0 + q;
+            if (r >= Rk) break;
+            const uint8_t *S = I.spins[cur] + (size_t)r * I.srow_bytes;
+            long long e = 0;
+            for (int s = lane; s < N; s += 64) {
+                const int x = s % L, y = (s / L) % L, z = s / (L * L);
+                const int ss = 2 * stored_spin(I, S, storage_pos(I, s)) - 1;
+                const int nb[3] = {(x + 1) % L + L * (y + L * z), x + L * ((y + 1) % L + L * z),
+                                   x + L * (y + L * ((z + 1) % L))};
+                for (int d = 0; d < 3; ++d)
+                    e -= (long long)Jq[d * N + s] * (ss * (2 * stored_spin(I, S, storage_pos(I, nb[d])) - 1));
+            }
+            for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+            if (lane == 0) I.Eq[cur][r] = e;
+        }
+        return;
+    }
     for (int q = wave; q < kRowsPerBlock; q += 4) {
         const int r = (int)w.row0 + q;
         if (r >= Rk) break;
@@ -154,6 +175,7 @@ struct TileIO {
     const uint32_t *fsrc;
     uint32_t *fdst;
     int32_t *Edst;
+    int64_t *Eqdst;       // real couplings: 64-bit energies
     int packed;           // stored rows hold one bit per position
     int srow;             // bytes per stored row
 };
@@ -169,6 +191,7 @@ __device__ __forceinline__ TileIO tile_io(const Inst &I)
     io.fsrc = I.fam[cur];
     io.fdst = mapped ? I.fam[cur ^ 1] : nullptr;
     io.Edst = mapped ? I.E[cur ^ 1] : I.E[cur];
+    io.Eqdst = I.real ? (mapped ? I.Eq[cur ^ 1] : I.Eq[cur]) : nullptr;
     io.packed = I.packed;
     io.srow = I.srow_bytes;
     return io;
@@ -821,6 +844,278 @@ __global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const In
 }
 
 // ---------------------------------------------------------------------------
+// Colour-major sweep with real couplings (Sec. II.A: Gaussian J in fixed
+// point, J = j 2^-20).  Same replica quads as the +-1 kernel, without the
+// complement planes: one 32-bit read of a neighbour word returns that
+// neighbour's spin in all four replicas, and its XOR with the site's own
+// word is sigma = [S != S_nb] per byte.  With S S_nb = 1 - 2 sigma,
+//   dE = 2 S sum_d J_d S_d = 2 sum_d J_d - 4 sum_d sigma_d J_d,
+// formed per replica with 24-bit multiply-adds of sigma (0/1) and j.  Each
+// thread keeps the 24 neighbour addresses and the 24 couplings of its block
+// of every colour in registers.  Energy: every bond is seen from both of its
+// sites, so E = -sum_b J_b + sum over sites of sum_d sigma_d J_d.
+// ---------------------------------------------------------------------------
+struct CQBlock {
+    uint32_t nb[24];  // LDS offsets of the neighbour words, [direction][site]
+    int32_t j[24];    // coupling of each of those bonds (units of 2^-20)
+    int32_t j2[4];    // twice the sum of the six couplings of each site
+    uint32_t own;     // LDS offset of site 0's word (site i at + i row_bytes)
+    uint32_t vmask[4];// 0x01010101 for a real site, 0 for padding
+    uint32_t ctr;     // Philox counter word 0
+    bool has;
+};
+
+// sum_d sigma_d J_d of site i of block b for the four replicas (bytes of the
+// XOR words), given the site's own word.
+__device__ __forceinline__ void cq_field(const uint8_t *lds, const CQBlock &b, int i, uint32_t own, int32_t (&a)[4])
+{
+    a[0] = a[1] = a[2] = a[3] = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const uint32_t x = own ^ lds_word(lds, b.nb[4 * d + i]);
+        const int32_t jj = b.j[4 * d + i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = __mul24((int)((x >> (8 * r)) & 1u), jj) + a[r];
+    }
+}
+
+template <int NCOL, bool ALL>
+__device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, const CQBlock (&blk)[NCOL], float bq,
+                                          unsigned long long *eacc, const TileIO &io, int r0, int nrows)
+{
+    const int tpr = I.tpr;
+    const int RPG = (int)blockDim.x / tpr;
+    const int row_bytes = I.row_bytes;
+    const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
+    uint8_t *slot = lds + qsub * 4 * row_bytes;
+    const int nvec = row_bytes >> 4;
+    const uint32_t key0 = I.key0, key1 = I.key1;
+    for (int qb = 0; qb < nrows; qb += 4 * RPG) {
+        const int q0 = qb + 4 * qsub;
+        const bool act = q0 < nrows;
+        const uint32_t r0q = (uint32_t)(r0 + q0);
+        if (act) {
+            const uint8_t *src[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t r = r0q + j;
+                src[j] = q0 + j < nrows ? io.src + (size_t)(io.map ? io.map[r] : r) * io.srow : nullptr;
+            }
+            uint4 *sp = reinterpret_cast<uint4 *>(slot);
+            for (int i = lane_r; i < nvec; i += tpr) {
+                uint4 v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = src[j] ? stored_vec(io, src[j], i) : make_uint4(0u, 0u, 0u, 0u);
+                uint32_t ox[4], oy[4], oz[4], ow[4];
+                transpose4(v[0].x, v[1].x, v[2].x, v[3].x, ox);
+                transpose4(v[0].y, v[1].y, v[2].y, v[3].y, oy);
+                transpose4(v[0].z, v[1].z, v[2].z, v[3].z, oz);
+                transpose4(v[0].w, v[1].w, v[2].w, v[3].w, ow);
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) sp[pl * nvec + i] = make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]);
+            }
+        }
+        replica_barrier(tpr);
+        for (int t = 0; t < I.NS; ++t) {
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                const CQBlock &b = blk[c];
+                if (act && b.has) {
+                    uint32_t own[4], flip[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        own[i] = lds_word(lds, b.own + i * row_bytes);
+                        flip[i] = b.vmask[i];
+                    }
+                    if constexpr (!ALL) {
+                        uint4 u[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            u[j] = philox10(make_uint4(b.ctr, r0q + j, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            int32_t a[4];
+                            cq_field(lds, b, i, own[i], a);
+                            uint32_t acc = 0;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int32_t dE = b.j2[i] - 4 * a[r];
+                                const bool ok = dE <= 0 || real_accept(bq, dE, word_of(u[r], i));
+                                acc |= (ok ? 1u : 0u) << (8 * r);
+                            }
+                            flip[i] &= acc;
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        *reinterpret_cast<uint32_t *>(lds + b.own + i * row_bytes) = own[i] ^ flip[i];
+                }
+                replica_barrier(tpr);
+            }
+        }
+        if (act) {
+            // per replica, sum over the thread's sites of sum_d sigma_d J_d:
+            // at most 12 sites x 6 bonds x 2^23 < 2^30
+            int32_t e[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                if (!blk[c].has) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int32_t a[4];
+                    cq_field(lds, blk[c], i, lds_word(lds, blk[c].own + i * row_bytes), a);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) e[r] += a[r];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (q0 + j < nrows) atomicAdd(&eacc[q0 + j], (unsigned long long)(long long)e[j]);
+            const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
+            for (int i = lane_r; i < nvec; i += tpr) {
+                uint4 w[4];
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) w[pl] = sp[pl * nvec + i];
+                uint32_t ox[4], oy[4], oz[4], ow[4];
+                transpose4(w[0].x, w[1].x, w[2].x, w[3].x, ox);
+                transpose4(w[0].y, w[1].y, w[2].y, w[3].y, oy);
+                transpose4(w[0].z, w[1].z, w[2].z, w[3].z, oz);
+                transpose4(w[0].w, w[1].w, w[2].w, w[3].w, ow);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (q0 + j < nrows)
+                        store_vec(io, io.dst + (size_t)(r0q + j) * io.srow, i, make_uint4(ox[j], oy[j], oz[j], ow[j]));
+            }
+        }
+        replica_barrier(tpr);
+    }
+}
+
+// Energies of the tile's rows (E = -sum_b J_b + the accumulated sums) and
+// their moments, added to the step's accumulators once per workgroup: min,
+// max, sum E (two's complement) and sum E^2 as an exact 128-bit integer
+// (low word added first; its carry goes into the high word).
+__device__ __forceinline__ void tile_moments_real(const Inst &I, const TileIO &io, const unsigned long long *eacc,
+                                                  int r0, int nrows)
+{
+    __shared__ long long smin[16], smax[16];
+    __shared__ unsigned long long ssum[16], slo[16], shi[16];
+    long long lmin = 0x7FFFFFFFFFFFFFFFll, lmax = -0x7FFFFFFFFFFFFFFFll - 1;
+    unsigned long long s1 = 0ull, lo = 0ull, hi = 0ull;
+    for (int q = threadIdx.x; q < nrows; q += blockDim.x) {
+        const long long E = (long long)eacc[q] - I.Jtot;
+        io.Eqdst[r0 + q] = E;
+        lmin = E < lmin ? E : lmin;
+        lmax = E > lmax ? E : lmax;
+        s1 += (unsigned long long)E;
+        const unsigned __int128 e2 = (unsigned __int128)((__int128)E * (__int128)E);
+        const unsigned long long l2 = (unsigned long long)e2;
+        const unsigned long long nl = lo + l2;
+        hi += (unsigned long long)(e2 >> 64) + (nl < lo ? 1ull : 0ull);
+        lo = nl;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long omin = __shfl_xor(lmin, off), omax = __shfl_xor(lmax, off);
+        const unsigned long long os = __shfl_xor(s1, off), ol = __shfl_xor(lo, off), oh = __shfl_xor(hi, off);
+        lmin = omin < lmin ? omin : lmin;
+        lmax = omax > lmax ? omax : lmax;
+        s1 += os;
+        const unsigned long long nl = lo + ol;
+        hi += oh + (nl < lo ? 1ull : 0ull);
+        lo = nl;
+    }
+    const int wave = threadIdx.x >> 6, nw = ((int)blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smin[wave] = lmin;
+        smax[wave] = lmax;
+        ssum[wave] = s1;
+        slo[wave] = lo;
+        shi[wave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < nw; ++v) {
+            lmin = smin[v] < lmin ? smin[v] : lmin;
+            lmax = smax[v] > lmax ? smax[v] : lmax;
+            s1 += ssum[v];
+            const unsigned long long nl = lo + slo[v];
+            hi += shi[v] + (nl < lo ? 1ull : 0ull);
+            lo = nl;
+        }
+        EMoments *m = I.emom;
+        atomicMin(&m->emin, lmin);
+        atomicMax(&m->emax, lmax);
+        atomicAdd(&m->sum, s1);
+        const unsigned long long old = atomicAdd(&m->sq_lo, lo);
+        atomicAdd(&m->sq_hi, hi + (old + lo < old ? 1ull : 0ull));
+    }
+}
+
+template <int NCOL>
+__device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+{
+    const int tpr = I.tpr;
+    const int RPG = (int)blockDim.x / tpr;
+    const int row_bytes = I.row_bytes;
+    unsigned long long *eacc = reinterpret_cast<unsigned long long *>(lds + RPG * 4 * row_bytes + 32);
+    const TileIO io = tile_io(I);
+    const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
+    const uint32_t slot = (uint32_t)(qsub * 4 * row_bytes);
+    const uint32_t rb = (uint32_t)row_bytes;
+    CQBlock blk[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+        const int g = lane_r;
+        blk[c].has = g < I.gcs[c];
+        blk[c].ctr = ((uint32_t)c << 24) | (uint32_t)g;
+        const int gg = blk[c].has ? g : 0;
+        const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
+        const int32_t *jd = I.cmj + ((size_t)c * I.gmax + gg) * 24;
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+            blk[c].nb[i] = slot + quad_pos((uint32_t)d[i], rb);
+            blk[c].j[i] = jd[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            blk[c].j2[i] = 2 * (blk[c].j[i] + blk[c].j[4 + i] + blk[c].j[8 + i] + blk[c].j[12 + i] + blk[c].j[16 + i] +
+                                blk[c].j[20 + i]);
+        const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) blk[c].vmask[i] = ((vm >> (8 * i)) & 1u) * 0x01010101u;
+        blk[c].own = slot + (uint32_t)(I.cbase[c] + 4 * gg);
+    }
+    const float bq = I.bq[k];
+    const bool all = I.thr[k].w != 0;
+    for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) eacc[q] = 0ull;
+    __syncthreads();
+    if (all)
+        cq_passes<NCOL, true>(I, k, lds, blk, bq, eacc, io, r0, nrows);
+    else
+        cq_passes<NCOL, false>(I, k, lds, blk, bq, eacc, io, r0, nrows);
+    __syncthreads();
+    if (io.map)
+        for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
+    tile_moments_real(I, io, eacc, r0, nrows);
+    tile_family_count(I, io, r0, nrows);
+}
+
+template <int NCOL, int MAXT>
+__global__ __launch_bounds__(MAXT, 2) void k_sweep_cq(const Inst *insts, const Work *work, int tile_rows)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k >= I.nT || I.status[0]) return;
+    const int Rk = (int)I.Rk[k];
+    const int r0 = (int)w.row0;
+    const int nrows = min(tile_rows, Rk - r0);
+    if (nrows > 0) sweep_tile_cq<NCOL>(I, k, lds, r0, nrows, tile_rows);
+    if (last_workgroup(&I.sync[0], I.sweep_tiles)) measure_step_real(I, k);
+}
+
+// ---------------------------------------------------------------------------
 // Stand-alone gather of surviving replicas: destination row d of the other
 // buffer receives source row map[d] (spins, energy, family).  Used when the
 // gather is not fused into the next sweep and to materialise a population
@@ -863,7 +1158,10 @@ __global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *w
     }
     for (int q = threadIdx.x; q < rows; q += nt) {
         const uint32_t d = (uint32_t)(row0 + q), s = I.map[d];
-        I.E[cur ^ 1][d] = I.E[cur][s];
+        if (I.real)
+            I.Eq[cur ^ 1][d] = I.Eq[cur][s];
+        else
+            I.E[cur ^ 1][d] = I.E[cur][s];
         I.fam[cur ^ 1][d] = I.fam[cur][s];
     }
 }
@@ -877,7 +1175,9 @@ hipError_t sweep_kernels_init()
         reinterpret_cast<const void *>(&k_sweep_lex),         reinterpret_cast<const void *>(&k_sweep_eo<8>),
         reinterpret_cast<const void *>(&k_sweep_eo<16>),      reinterpret_cast<const void *>(&k_sweep_cm<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_cm<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<3, 512>),
-        reinterpret_cast<const void *>(&k_sweep_cm<3, 1024>),
+        reinterpret_cast<const void *>(&k_sweep_cm<3, 1024>), reinterpret_cast<const void *>(&k_sweep_cq<2, 512>),
+        reinterpret_cast<const void *>(&k_sweep_cq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cq<3, 512>),
+        reinterpret_cast<const void *>(&k_sweep_cq<3, 1024>),
     };
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
@@ -918,6 +1218,23 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
                 k_sweep_cm<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
             else
                 k_sweep_cm<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+        }
+        return;
+    }
+    if (variant == kSweepCQ2 || variant == kSweepCQ3) {
+        // rp replica quads of four planes, and a 64-bit energy per tile row
+        const size_t lds = 4 * (size_t)row_bytes * rp + 32 + 8 * (size_t)tile_rows;
+        const int nt = tpr * rp;
+        if (variant == kSweepCQ2) {
+            if (nt <= 512)
+                k_sweep_cq<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+            else
+                k_sweep_cq<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+        } else {
+            if (nt <= 512)
+                k_sweep_cq<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+            else
+                k_sweep_cq<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
         }
         return;
     }

@@ -25,8 +25,8 @@
 
 namespace pamc {
 
-int make_inst(int L, const int8_t *J, int64_t R, const double *beta, int nT, int NS, uint64_t seed,
-              const pamc_options &opt, HostInst &h);
+int make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
+              uint64_t seed, const pamc_options &opt, HostInst &h);
 
 namespace {
 
@@ -35,11 +35,16 @@ constexpr int kTimedSteps = 3;      // timed steps per candidate shape (after on
 constexpr int kBurnIn = 8;          // steps before the first candidate
 constexpr double kTuneBeta = 2.0;   // inside the low-temperature part where an anneal spends most steps
 
-bool is_cm(const HostInst &h) { return h.variant == kSweepCM2 || h.variant == kSweepCM3; }
+bool is_cm(const HostInst &h)
+{
+    return h.variant == kSweepCM2 || h.variant == kSweepCM3 || h.variant == kSweepCQ2 || h.variant == kSweepCQ3;
+}
+bool is_cq(const HostInst &h) { return h.variant == kSweepCQ2 || h.variant == kSweepCQ3; }
 bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kSweepEO16; }
 
 int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
 {
+    if (is_cq(h)) return 4 * (int64_t)h.row_bytes * rp + 32 + 8 * (int64_t)tile_rows;
     if (is_cm(h)) return 8 * (int64_t)h.row_bytes * rp + 32 + 4 * (int64_t)tile_rows;
     return (int64_t)tile_rows * h.row_bytes + 32 + 4 * (int64_t)tile_rows;
 }
@@ -163,7 +168,8 @@ int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
     const int nT = 1 + kBurnIn + (1 + kTimedSteps) * (int)cand.size();
     const std::vector<double> beta((size_t)nT, kTuneBeta);
     HostInst t;
-    int st = make_inst(h.L, h.J.data(), h.R, beta.data(), nT, h.NS, h.seed, o, t);
+    int st = make_inst(h.L, h.real ? nullptr : h.J.data(), h.real ? h.Jq.data() : nullptr, h.R, beta.data(), nT,
+                       h.NS, h.seed, o, t);
     if (st != PAMC_OK) return st;
     Runner run;
     st = run.setup(o, 1);

@@ -127,6 +127,43 @@ def test_invalid_sweep_shapes_are_rejected_on_the_host(lib, case):
     assert not h.value
 
 
+@pytest.mark.parametrize("case", ["range", "lattice", "capacity", "null"])
+def test_invalid_real_couplings_are_rejected_on_the_host(lib, case):
+    from paper_1710_09025_amd import _capi
+
+    L = 22 if case == "lattice" else 6
+    J = np.zeros((3, L ** 3), dtype=np.int32)
+    R = 100
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    if case == "range":
+        J[2, 7] = 1 << 23           # |J| = 8
+    elif case == "capacity":
+        opt.capacity = (1 << 29) + 1
+    beta = np.linspace(0, 1, 3)
+    h = ctypes.c_void_p()
+    ptr = None if case == "null" else J.ctypes.data_as(ctypes.c_void_p)
+    st = lib.pamc_create_real(L, ptr, R, beta.ctypes.data_as(ctypes.c_void_p), len(beta), 1, 1,
+                              ctypes.byref(opt), ctypes.byref(h))
+    assert st == _capi.ERR_INVALID, lib.pamc_last_error()
+    assert not h.value
+
+
+def test_real_footprint_adds_64_bit_energies_and_weights(lib):
+    from paper_1710_09025_amd import _capi
+
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    a = lib.pamc_footprint(8, 100000, 201, ctypes.byref(opt))
+    opt.real_couplings = 1
+    b = lib.pamc_footprint(8, 100000, 201, ctypes.byref(opt))
+    cap = 100000 + int(np.ceil(8 * np.sqrt(100000))) + 64
+    # two 8-byte energy buffers and the weights replace two 4-byte buffers
+    assert b - a >= cap * (3 * 8 - 2 * 4)
+    # no kernel for real couplings at L = 22
+    assert lib.pamc_footprint(22, 1000, 11, ctypes.byref(opt)) == -1
+
+
 def test_packed_footprint_saves_the_spin_bytes(lib):
     from paper_1710_09025_amd import _capi
 
