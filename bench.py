@@ -45,10 +45,23 @@ HBM_PEAK_GBS = 8000.0
 # acceptance = 4 x (extract + compare + select) + 2 (downhill mask) + 1
 # (apply) = 15; 67 / 4 = 16.75.
 ALU_OPS_PER_ATTEMPT = 16.75
+# The same with real (Gaussian, fixed-point) couplings, per attempt: Philox
+# 40 / 4 = 10; the local field over six neighbours, each an XOR shared by the
+# four replicas of a word (1/4) + extract + 24-bit multiply-add, and dE from
+# it = 6 x 2.25 + 1 = 14.5; the acceptance: binary32 conversion and product
+# (2), the exp recipe (scale, round, 2 reduction FMAs, 7 Horner FMAs,
+# convert, ldexp = 13), the threshold (scale, convert = 2) and four compares
+# (dE <= 0, x >= -23, e >= 1, u < T) = 21; applying the flip = 2: 47.5.
+ALU_OPS_PER_ATTEMPT_REAL = 47.5
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_counters.json")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_1710_09025_amd", "csrc", f)
                  for f in ("sweep.hip", "step_common.h", "pamc_dev.h")]
+
+
+def log(msg: str):
+    """Progress of the legs on stderr (the JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def source_hash() -> str:
@@ -60,9 +73,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def workload_inputs(name):
+def workload_inputs(name, real=False):
     cfg = pi.WORKLOADS[name]
-    J = pi.pm_j_couplings(cfg["L"], cfg["disorder_seed"])
+    gen = pi.gaussian_couplings if real else pi.pm_j_couplings
+    J = gen(cfg["L"], cfg["disorder_seed"])
     beta = pi.linear_beta(cfg["beta_max"], cfg["n_temps"])
     return cfg, J, beta
 
@@ -71,7 +85,7 @@ def attempts_of(obs, N, sweeps):
     return float(np.sum(obs["R"][obs["measured"] == 1])) * N * sweeps
 
 
-def time_anneals(name, steps, warmup, autotune=True, packed=False):
+def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False):
     """Creates warmup + steps run handles up front (each temperature step a
     replayed hipGraph; sweep shapes chosen by the autotuner at creation,
     outside the timed region) and anneals them one after another for the
@@ -81,7 +95,7 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False):
 
     from paper_1710_09025_amd import Pamc
 
-    cfg, J, beta = workload_inputs(name)
+    cfg, J, beta = workload_inputs(name, real)
     N = cfg["L"] ** 3
     runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune, packed=packed)
             for _ in range(warmup + steps)]
@@ -112,7 +126,7 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False):
     att = attempts_of(obs, N, cfg["sweeps"])
     Rbar = float(np.mean(obs["R"]))
     return dict(cfg=cfg, wall_s=t1 - t0, sweep_ms=sweep_ms, other_ms=other_ms, nsteps=nsteps,
-                attempts_per_anneal=att, mean_R=Rbar, N=N, shape=shape)
+                attempts_per_anneal=att, mean_R=Rbar, N=N, shape=shape, real=real)
 
 
 def footprint_gb(name, packed):
@@ -162,26 +176,35 @@ def gather_bench(name, n_steps, packed=False):
             "sweep_ms_per_step": round(sweep_ms / nsteps, 4)}
 
 
+def sweep_kernel_name(L, real):
+    if real:
+        return f"k_sweep_cq<{2 if L % 2 == 0 else 3}, 512>"
+    return f"k_sweep_eo<{L}>" if L in (8, 16) else "k_sweep_cm / k_sweep_lex"
+
+
 def roofline(res):
     sweep_s = res["sweep_ms"] / 1e3
-    ops = ALU_OPS_PER_ATTEMPT * res["attempts_per_anneal"]
+    real = res.get("real", False)
+    opa = ALU_OPS_PER_ATTEMPT_REAL if real else ALU_OPS_PER_ATTEMPT
+    ops = opa * res["attempts_per_anneal"]
     achieved = ops / sweep_s / 1e12
     traffic = None
+    key = res["cfg"].get("name", "") + ("_gaussian" if real else "")
     if os.path.exists(COUNTERS_FILE):
         try:
             c = json.load(open(COUNTERS_FILE))
-            w = c.get("workloads", {}).get(res["cfg"].get("name", ""), None)
+            w = c.get("workloads", {}).get(key, None)
             if c.get("sweep_source_sha256_16") == source_hash() and w:
                 traffic = w["hbm_bytes_per_launch"]
         except Exception:
             traffic = None
     rb = ((res["N"] + 15) // 16) * 16
-    alg_bytes = 2.0 * res["mean_R"] * rb + 16.0 * res["mean_R"]  # tile in + out, map/E/family
+    # tile in + out, map / energy / family
+    alg_bytes = 2.0 * res["mean_R"] * rb + (20.0 if real else 16.0) * res["mean_R"]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
             "unit": "Tops/s (int32 VALU)", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
-            "kernel": f"k_sweep_eo<{res['cfg']['L']}> (N_S sweeps of every replica at one temperature)"
-                      if res["cfg"]["L"] in (8, 16) else "k_sweep_lex",
-            "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
+            "kernel": sweep_kernel_name(res["cfg"]["L"], real) + " (N_S sweeps of every replica at one temperature)",
+            "ops_per_attempt": opa,
             "sweep_shape": {"tile_rows": res["shape"][0], "group_replicas": res["shape"][1]},
             "avg_launch_ms": round(res["sweep_ms"] / max(1, res["nsteps"]), 4),
             "hbm_gbs_algorithmic": round(alg_bytes / (res["sweep_ms"] / max(1, res["nsteps"]) / 1e3) / 1e9, 1),
@@ -189,10 +212,10 @@ def roofline(res):
                                           / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(name, n_steps):
+def cpu_baseline(name, n_steps, real=False):
     import oracle
 
-    cfg, J, beta = workload_inputs(name)
+    cfg, J, beta = workload_inputs(name, real)
     threads = min(16, os.cpu_count() or 1)
     o = oracle.Oracle(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], threads=threads)
     t0 = time.perf_counter()
@@ -368,6 +391,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed anneals")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="L8_R100000", choices=sorted(pi.WORKLOADS))
+    ap.add_argument("--couplings", default="pm1", choices=("pm1", "gaussian"),
+                    help="couplings of the benchmark instance: +-1, or Gaussian in fixed point")
     ap.add_argument("--cpu-steps", type=int, default=16, help="temperature steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -406,8 +431,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    res = time_anneals(args.workload, args.steps, args.warmup)
+    real = args.couplings == "gaussian"
+    res = time_anneals(args.workload, args.steps, args.warmup, real=real)
     res["cfg"]["name"] = args.workload
+    log(f"{args.workload} ({args.couplings}) timed")
     total_attempts = res["attempts_per_anneal"] * args.steps
     value = total_attempts / (res["wall_s"] * 1e9)
     cfg = res["cfg"]
@@ -423,8 +450,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
-        "data": "synthetic: +-J couplings and Philox-initialised replicas from fixed seeds",
-        "config": {"workload": f"3D EA +-J L={cfg['L']} periodic, R={cfg['R']}, n_temps={cfg['n_temps']} "
+        "data": f"synthetic: {'Gaussian' if real else '+-J'} couplings and Philox-initialised replicas from "
+                "fixed seeds",
+        "config": {"workload": f"3D EA {'Gaussian' if real else '+-J'} L={cfg['L']} periodic, R={cfg['R']}, n_temps={cfg['n_temps']} "
                                f"beta linear 0->{cfg['beta_max']}, N_S={cfg['sweeps']}, one instance",
                    "L": cfg["L"], "R": cfg["R"], "n_temps": cfg["n_temps"], "sweeps": cfg["sweeps"],
                    "step": "one complete anneal", "spins": "int8"},
@@ -432,11 +460,14 @@ def main():
         "sweep_share": round(res["sweep_ms"] / (res["sweep_ms"] + res["other_ms"]), 4),
         "roofline": roofline(res),
     }
-    if args.gather_steps:
+    if args.gather_steps and not real:
         line["gather"] = {name: gather_bench(name, args.gather_steps) for name in (args.workload, "L16_R500000")}
         line["gather"]["L16_R500000_packed"] = gather_bench("L16_R500000", args.gather_steps, packed=True)
+        log("gather legs done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps if not real else max(1, args.cpu_steps // 4),
+                                            real)
+        log("cpu baseline done")
     if not args.no_extra:
         extra = {}
         for name, k, w, packed in (("L4_R1000", 5, 1, False), ("L16_R500000", 1, 0, False),
@@ -444,6 +475,7 @@ def main():
             if name == args.workload and not packed:
                 continue
             r = time_anneals(name, k, w, packed=packed)
+            log(f"{name}{' packed' if packed else ''} done")
             extra[name + ("_packed" if packed else "")] = {
                 "attempts_per_ns": round(r["attempts_per_anneal"] * k / (r["wall_s"] * 1e9), 3),
                 "sweep_attempts_per_ns": round(r["attempts_per_anneal"] / (r["sweep_ms"] * 1e6), 3),
@@ -453,16 +485,33 @@ def main():
                 "footprint_gb": footprint_gb(name, packed),
                 "sweep_shape": {"tile_rows": r["shape"][0], "group_replicas": r["shape"][1]},
             }
+        if not real:
+            # the paper's own case study: Gaussian couplings, same workload
+            g = time_anneals(args.workload, 3, 1, real=True)
+            g["cfg"]["name"] = args.workload
+            extra[args.workload + "_gaussian"] = {
+                "attempts_per_ns": round(g["attempts_per_anneal"] * 3 / (g["wall_s"] * 1e9), 3),
+                "sweep_attempts_per_ns": round(g["attempts_per_anneal"] / (g["sweep_ms"] * 1e6), 3),
+                "ms_per_anneal": round(g["wall_s"] / 3 * 1e3, 3),
+                "sweep_share": round(g["sweep_ms"] / (g["sweep_ms"] + g["other_ms"]), 4),
+                "roofline": roofline(g),
+                "cpu_baseline": cpu_baseline(args.workload, 3, real=True),
+            }
+            log("gaussian leg done")
         for kind in ("lblt", "tspl", "tspl_dynamic_R"):
             extra[f"{args.workload}_{kind}"] = schedule_bench(args.workload, kind)
+            log(f"schedule {kind} done")
         extra["rho_f"] = rho_f_bench()
+        log("rho_f done")
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
+            log("batch done")
         if args.serve:
             warm = warm_serving_shapes()
             sat = serve_bench(args.serve, args.serve_rate, args.serve_budget_gb)
             sat["shape_tuning_before_stream_s"] = round(warm, 2)
             extra["serving"] = sat
+            log("serving done")
             if args.serve_light:
                 extra["serving_at_0.8x_saturation"] = serve_bench(
                     args.serve_light, 0.8 * sat["instances_per_s"], args.serve_budget_gb)

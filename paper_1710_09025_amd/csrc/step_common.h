@@ -160,12 +160,12 @@ __device__ __forceinline__ float exp_recipe(float x)
 
 // A move with dE > 0 (units of 2^-20) at bq = beta 2^-20 (binary32) is
 // accepted when x = -(bq dE) >= -23 and e = exp(x) >= 1 or u < floor(e 2^32).
-// The argument of the recipe is clamped to [-24, 0], which leaves every
-// decision unchanged and keeps its conversions in range for any dE.
+// The recipe's argument is x clamped to [-24, 0] (dE <= 0 taken as 0): every
+// decision is unchanged and its conversions stay in range for any dE.
 __device__ __forceinline__ bool real_accept(float bq, int32_t dE, uint32_t u)
 {
-    const float x = -(bq * (float)dE);
-    const float e = exp_recipe(__builtin_fminf(__builtin_fmaxf(x, -24.0f), 0.0f));
+    const float x = -(bq * (float)max(dE, 0));
+    const float e = exp_recipe(__builtin_fmaxf(x, -24.0f));
     const uint32_t T = (uint32_t)((e < 1.0f ? e : 0.0f) * 4294967296.0f);
     return x >= -23.0f && (e >= 1.0f || u < T);
 }

@@ -846,11 +846,13 @@ __global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const In
 // ---------------------------------------------------------------------------
 // Colour-major sweep with real couplings (Sec. II.A: Gaussian J in fixed
 // point, J = j 2^-20).  Same replica quads as the +-1 kernel, without the
-// complement planes: one 32-bit read of a neighbour word returns that
-// neighbour's spin in all four replicas, and its XOR with the site's own
-// word is sigma = [S != S_nb] per byte.  With S S_nb = 1 - 2 sigma,
+// complement planes, and with each spin held in LDS as a byte 0x00 / 0xFF
+// (converted on load and store): one 32-bit read of a neighbour word returns
+// that neighbour's spin in all four replicas, and its XOR with the site's own
+// word is, per byte, 0 or -1 for sigma = [S != S_nb] = 0 or 1.  With
+// S S_nb = 1 - 2 sigma,
 //   dE = 2 S sum_d J_d S_d = 2 sum_d J_d - 4 sum_d sigma_d J_d,
-// formed per replica with 24-bit multiply-adds of sigma (0/1) and j.  Each
+// where sigma_d J_d is the sign-extended byte ANDed with j.  Each
 // thread keeps the 24 neighbour addresses and the 24 couplings of its block
 // of every colour in registers.  Energy: every bond is seen from both of its
 // sites, so E = -sum_b J_b + sum over sites of sum_d sigma_d J_d.
@@ -860,13 +862,13 @@ struct CQBlock {
     int32_t j[24];    // coupling of each of those bonds (units of 2^-20)
     int32_t j2[4];    // twice the sum of the six couplings of each site
     uint32_t own;     // LDS offset of site 0's word (site i at + i row_bytes)
-    uint32_t vmask[4];// 0x01010101 for a real site, 0 for padding
+    uint32_t vbits;   // bit i set when site i of the block is a real site
     uint32_t ctr;     // Philox counter word 0
     bool has;
 };
 
 // sum_d sigma_d J_d of site i of block b for the four replicas (bytes of the
-// XOR words), given the site's own word.
+// XOR words, 0x00 or 0xFF), given the site's own word.
 __device__ __forceinline__ void cq_field(const uint8_t *lds, const CQBlock &b, int i, uint32_t own, int32_t (&a)[4])
 {
     a[0] = a[1] = a[2] = a[3] = 0;
@@ -875,8 +877,19 @@ __device__ __forceinline__ void cq_field(const uint8_t *lds, const CQBlock &b, i
         const uint32_t x = own ^ lds_word(lds, b.nb[4 * d + i]);
         const int32_t jj = b.j[4 * d + i];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = __mul24((int)((x >> (8 * r)) & 1u), jj) + a[r];
+        for (int r = 0; r < 4; ++r) a[r] += (int32_t)(int8_t)(uint8_t)(x >> (8 * r)) & jj;
     }
+}
+
+// 0/1 spin bytes to 0x00/0xFF (255 b per byte, no carries) and back.
+__device__ __forceinline__ uint32_t spin_ff(uint32_t w) { return (w << 8) - w; }
+__device__ __forceinline__ uint4 spin_ff4(uint4 v)
+{
+    return make_uint4(spin_ff(v.x), spin_ff(v.y), spin_ff(v.z), spin_ff(v.w));
+}
+__device__ __forceinline__ uint4 spin_01(uint4 v)
+{
+    return make_uint4(v.x & 0x01010101u, v.y & 0x01010101u, v.z & 0x01010101u, v.w & 0x01010101u);
 }
 
 template <int NCOL, bool ALL>
@@ -912,7 +925,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
                 transpose4(v[0].z, v[1].z, v[2].z, v[3].z, oz);
                 transpose4(v[0].w, v[1].w, v[2].w, v[3].w, ow);
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) sp[pl * nvec + i] = make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]);
+                for (int pl = 0; pl < 4; ++pl) sp[pl * nvec + i] = spin_ff4(make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]));
             }
         }
         replica_barrier(tpr);
@@ -925,7 +938,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         own[i] = lds_word(lds, b.own + i * row_bytes);
-                        flip[i] = b.vmask[i];
+                        flip[i] = (b.vbits >> i) & 1u ? 0xFFFFFFFFu : 0u;
                     }
                     if constexpr (!ALL) {
                         uint4 u[4];
@@ -941,7 +954,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
                             for (int r = 0; r < 4; ++r) {
                                 const int32_t dE = b.j2[i] - 4 * a[r];
                                 const bool ok = dE <= 0 || real_accept(bq, dE, word_of(u[r], i));
-                                acc |= (ok ? 1u : 0u) << (8 * r);
+                                acc |= (ok ? 0xFFu : 0u) << (8 * r);
                             }
                             flip[i] &= acc;
                         }
@@ -975,7 +988,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
             for (int i = lane_r; i < nvec; i += tpr) {
                 uint4 w[4];
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) w[pl] = sp[pl * nvec + i];
+                for (int pl = 0; pl < 4; ++pl) w[pl] = spin_01(sp[pl * nvec + i]);
                 uint32_t ox[4], oy[4], oz[4], ow[4];
                 transpose4(w[0].x, w[1].x, w[2].x, w[3].x, ox);
                 transpose4(w[0].y, w[1].y, w[2].y, w[3].y, oy);
@@ -1081,8 +1094,7 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
             blk[c].j2[i] = 2 * (blk[c].j[i] + blk[c].j[4 + i] + blk[c].j[8 + i] + blk[c].j[12 + i] + blk[c].j[16 + i] +
                                 blk[c].j[20 + i]);
         const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) blk[c].vmask[i] = ((vm >> (8 * i)) & 1u) * 0x01010101u;
+        blk[c].vbits = (vm & 1u) | ((vm >> 7) & 2u) | ((vm >> 14) & 4u) | ((vm >> 21) & 8u);
         blk[c].own = slot + (uint32_t)(I.cbase[c] + 4 * gg);
     }
     const float bq = I.bq[k];
