@@ -78,6 +78,10 @@ def lib() -> ctypes.CDLL:
         L.orc_exp_f32.argtypes = [ctypes.c_float]
         L.orc_real_accept.argtypes = [ctypes.c_float, i64, ctypes.c_uint32]
         L.enum_energies_real.argtypes = [i32, P, P]
+        L.orc_set_icm.argtypes = [P, i32]
+        L.orc_icm_perm.restype = ctypes.c_uint32
+        L.orc_icm_perm.argtypes = [u64, ctypes.c_uint32, ctypes.c_uint32, i32, i32]
+        L.orc_icm_pair.argtypes = [P, P, P, ctypes.c_uint32, i32, i32]
         L.orc_destroy.argtypes = [P]
         L.orc_set_threads.argtypes = [P, i32]
         L.orc_run.argtypes = [P, i32]
@@ -137,6 +141,11 @@ def real_beta(beta: float) -> np.float32:
     return np.float32(beta * 2.0 ** -20)
 
 
+def icm_perm(seed: int, i: int, n: int, step: int, round_: int) -> int:
+    """The oracle's keyed permutation of [0, n) used to pair replicas."""
+    return int(lib().orc_icm_perm(ctypes.c_uint64(seed & (2**64 - 1)), i, n, step, round_))
+
+
 def thresholds(beta: float):
     T = np.zeros(3, dtype=np.uint32)
     flag = ctypes.c_int(0)
@@ -149,7 +158,7 @@ class Oracle:
     int32 [3][L^3] of fixed-point real couplings (J = j 2^-20, |J| < 8)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
-                 threads=1, pop_schedule=None):
+                 threads=1, pop_schedule=None, icm_rounds=0):
         self.L = int(L)
         self.N = self.L ** 3
         self.R = int(R)
@@ -180,6 +189,7 @@ class Oracle:
             raise ValueError("oracle: invalid arguments")
         self._h = ctypes.c_void_p(h)
         lib().orc_set_threads(self._h, int(threads))
+        lib().orc_set_icm(self._h, int(icm_rounds))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -264,6 +274,14 @@ class Oracle:
     def measure_resample(self) -> int:
         """Measure and resample the current population without sweeping it."""
         return lib().orc_measure_resample(self._h)
+
+    def icm_pair(self, a, b, pair_index, step, round_):
+        """One cluster update of the configurations a, b (int8 +-1, copied);
+        returns (a', b', island size)."""
+        sa = np.array(a, dtype=np.int8, order="C", copy=True)
+        sb = np.array(b, dtype=np.int8, order="C", copy=True)
+        n = lib().orc_icm_pair(self._h, _ptr(sa), _ptr(sb), int(pair_index), int(step), int(round_))
+        return sa, sb, n
 
     def energies(self, spins):
         spins = np.ascontiguousarray(spins, dtype=np.int8)

@@ -29,6 +29,12 @@
  *                        energy by free-energy perturbation.
  *   Sec. III.A           checkerboard spin selection on bipartite lattices.
  *   Sec. III.D           rho_s uses the local population size R at each beta.
+ *   Sec. IV (Houdayer)   isoenergetic cluster moves (ICM): after a
+ *                        resampling, N_S/2 sweeps, then R updates of random
+ *                        replica pairs, then N_S/2 sweeps; an update builds
+ *                        the overlap of the pair, takes an island of the
+ *                        sector with fewer sites and flips it in both
+ *                        replicas (their summed energy is unchanged).
  *   Sec. V.A, Eq. (9)    observables are population averages; the spin
  *                        overlap is measured only at selected temperatures.
  *
@@ -46,6 +52,13 @@
  *   function orc_exp_f32 below; per-replica weights relative to E_min as a
  *   fixed product of exp(-dbeta 2^(b-20)) over the set bits b of E - E_min;
  *   the normaliser summed by the pairwise tree over replica rows.
+ * For ICM: the R updates as two rounds of floor(R_k/2) disjoint pairs, rows
+ *   paired by a keyed pseudo-random permutation (a four-round Feistel
+ *   network on 2h-bit words whose round function is Philox, cycle-walked
+ *   into [0, R_k)); the island is the one containing a uniformly drawn site
+ *   of the smaller sector (ties: the sector where the replicas differ; an
+ *   empty sector is no move); ICM at every step k >= 1, after
+ *   floor(N_S/2) sweeps; family ids stay with their rows.
  *
  * Spins are stored as int8 +-1, replica-major, sites in lexicographic order
  * s = x + L (y + L z).
@@ -71,6 +84,7 @@ enum {
 #define TAG_INIT 0x10000000u
 #define TAG_SWEEP 0x20000000u
 #define TAG_RESAMPLE 0x30000000u
+#define TAG_ICM 0x40000000u
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
@@ -138,6 +152,7 @@ typedef struct {
     double lnZ;
     uint8_t *ovl;   /* [nT]: measure the overlap at this step             */
     int nthreads;
+    int icm_rounds;  /* ICM rounds of disjoint pairs per step (0: none)   */
     /* per-step records */
     int64_t *o_R, *o_sumE;
     __int128 *o_sumE2;
@@ -444,11 +459,11 @@ static float real_beta(double b) { return (float)(b * 0x1p-20); }
  * S is the replica's configuration, *E its energy, r its row index (which
  * keys the draws together with k). */
 static void sweep_one(const orc_t *o, int8_t *S, int64_t *Ep, int64_t r, int k, const uint32_t T[3],
-                      int accept_all)
+                      int accept_all, int t0, int t1)
 {
     int64_t E = *Ep;
     const float bq = real_beta(o->beta[k]);
-    for (int t = 0; t < o->NS; ++t)
+    for (int t = t0; t < t1; ++t)
         for (int c = 0; c < o->ncol; ++c)
             for (int s = 0; s < o->N; ++s) {
                 if (o->colour[s] != c) continue;
@@ -470,10 +485,112 @@ static void sweep_one(const orc_t *o, int8_t *S, int64_t *Ep, int64_t r, int k, 
     *Ep = E;
 }
 
-static void sweep_replica(orc_t *o, int64_t r, const uint32_t T[3], int accept_all)
+/* Sweeps t0 .. t1-1 of replica r at the current step. */
+static void sweep_replica(orc_t *o, int64_t r, const uint32_t T[3], int accept_all, int t0, int t1)
 {
-    sweep_one(o, o->spin + r * o->N, &o->E[r], r, o->k, T, accept_all);
+    sweep_one(o, o->spin + r * o->N, &o->E[r], r, o->k, T, accept_all, t0, t1);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Isoenergetic cluster moves (Sec. IV)                                      */
+/* ------------------------------------------------------------------------ */
+/* Keyed pseudo-random permutation of [0, n): a balanced Feistel network on
+ * 2h-bit words (4^h >= n) of four rounds, (l, r) -> (r, l ^ F_j(r)), with
+ * F_j(r) = word 0 of Philox at counter (r, j, k, TAG_ICM | round) masked to
+ * h bits, applied repeatedly from i until the value falls in [0, n) (cycle
+ * walking; it ends because i itself lies on the cycle). */
+uint32_t orc_icm_perm(uint64_t seed, uint32_t i, uint32_t n, int k, int round)
+{
+    int h = 0;
+    while (((uint64_t)1 << (2 * h)) < (uint64_t)n) ++h;
+    const uint32_t mask = h == 0 ? 0u : (uint32_t)(((uint64_t)1 << h) - 1);
+    uint32_t x = i;
+    do {
+        uint32_t l = h == 0 ? 0u : x >> h, r = x & mask;
+        for (int j = 0; j < 4; ++j) {
+            uint32_t f = draw(seed, r, (uint32_t)j, (uint32_t)k, TAG_ICM | (uint32_t)round, 0) & mask;
+            uint32_t t = l ^ f;
+            l = r;
+            r = t;
+        }
+        x = h == 0 ? 0u : ((l << h) | r);
+    } while (x >= n);
+    return x;
+}
+
+/* One ICM update of the pair (Sa, Sb), pair index j of round `round` at step
+ * k: the sector of sites where the replicas differ (q = -1) or agree
+ * (q = +1), whichever has fewer sites (the differing one on a tie); the
+ * m-th site of that sector in lexicographic order with
+ * m = floor(u * count / 2^32), u = word 0 of Philox at counter
+ * (j, 4, k, TAG_ICM | round); its island, the sites of the sector connected
+ * to it by lattice bonds, flipped in both replicas.  Returns the island
+ * size (0: empty sector). */
+int orc_icm_pair(const orc_t *o, int8_t *Sa, int8_t *Sb, uint32_t j, int k, int round)
+{
+    const int N = o->N;
+    int ndiff = 0;
+    for (int s = 0; s < N; ++s) ndiff += Sa[s] != Sb[s];
+    const int want_diff = ndiff <= N - ndiff;
+    const int cnt = want_diff ? ndiff : N - ndiff;
+    if (cnt == 0) return 0;
+    const uint32_t u = draw(o->seed, j, 4u, (uint32_t)k, TAG_ICM | (uint32_t)round, 0);
+    const int m = (int)(((uint64_t)u * (uint64_t)cnt) >> 32);
+    int s0 = -1;
+    for (int s = 0, seen = 0; s < N; ++s)
+        if ((Sa[s] != Sb[s]) == want_diff) {
+            if (seen == m) {
+                s0 = s;
+                break;
+            }
+            ++seen;
+        }
+    uint8_t *in = (uint8_t *)calloc((size_t)N, 1);
+    int *queue = (int *)malloc(sizeof(int) * (size_t)N);
+    if (!in || !queue) {
+        free(in);
+        free(queue);
+        return -1;
+    }
+    int head = 0, tail = 0;
+    queue[tail++] = s0;
+    in[s0] = 1;
+    while (head < tail) {
+        const int s = queue[head++];
+        for (int d = 0; d < 6; ++d) {
+            const int t = o->nbr[6 * s + d];
+            if (!in[t] && (Sa[t] != Sb[t]) == want_diff) {
+                in[t] = 1;
+                queue[tail++] = t;
+            }
+        }
+    }
+    for (int q = 0; q < tail; ++q) {
+        Sa[queue[q]] = (int8_t)-Sa[queue[q]];
+        Sb[queue[q]] = (int8_t)-Sb[queue[q]];
+    }
+    free(in);
+    free(queue);
+    return tail;
+}
+
+/* The ICM rounds of the current step: round rd pairs rows
+ * perm(2j) and perm(2j+1), j < floor(R_k/2); energies are recomputed. */
+static int icm_step(orc_t *o)
+{
+    const uint32_t n = (uint32_t)o->Rk;
+    for (int rd = 0; rd < o->icm_rounds; ++rd)
+        for (uint32_t j = 0; j < n / 2; ++j) {
+            const uint32_t a = orc_icm_perm(o->seed, 2 * j, n, o->k, rd);
+            const uint32_t b = orc_icm_perm(o->seed, 2 * j + 1, n, o->k, rd);
+            if (orc_icm_pair(o, o->spin + (size_t)a * o->N, o->spin + (size_t)b * o->N, j, o->k, rd) < 0)
+                return ORC_ERR_NOMEM;
+        }
+    for (int64_t r = 0; r < o->Rk; ++r) o->E[r] = energy(o, o->spin + r * o->N);
+    return ORC_OK;
+}
+
+void orc_set_icm(orc_t *o, int rounds) { o->icm_rounds = rounds < 0 ? 0 : rounds; }
 
 /* Pairwise summation tree over n leaves (n a power of two): level by level,
  * node i of the next level is left child 2i plus right child 2i+1. */
@@ -727,10 +844,22 @@ int orc_run(orc_t *o, int n_steps)
         uint32_t T[3];
         int all;
         orc_thresholds(o->beta[o->k], T, &all);
+        /* with ICM (steps after a resampling): N_S/2 sweeps, the cluster
+         * updates, the remaining sweeps */
+        const int icm = o->icm_rounds > 0 && o->k >= 1;
+        const int t_mid = icm ? o->NS / 2 : o->NS;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(o->nthreads)
 #endif
-        for (int64_t r = 0; r < o->Rk; ++r) sweep_replica(o, r, T, all);
+        for (int64_t r = 0; r < o->Rk; ++r) sweep_replica(o, r, T, all, 0, t_mid);
+        if (icm) {
+            int sti = icm_step(o);
+            if (sti != ORC_OK) return sti;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(o->nthreads)
+#endif
+            for (int64_t r = 0; r < o->Rk; ++r) sweep_replica(o, r, T, all, t_mid, o->NS);
+        }
         int st = measure(o);
         if (st != ORC_OK) return st;
         if (o->k < o->nT - 1) {
@@ -954,7 +1083,7 @@ int orc_sweep_rows64(orc_t *o, int k, int64_t n, const int64_t *rows, int8_t *sp
     for (int64_t i = 0; i < n; ++i) {
         int8_t *S = spins + i * o->N;
         E[i] = energy(o, S);
-        sweep_one(o, S, &E[i], rows[i], k, T, all);
+        sweep_one(o, S, &E[i], rows[i], k, T, all, 0, o->NS);
     }
     return ORC_OK;
 }
