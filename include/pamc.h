@@ -115,6 +115,18 @@ typedef struct pamc_options {
     int real_couplings;      /* pamc_footprint and pamc_autotune only (they
                                 take no couplings): 1 = size or tune a run
                                 with real couplings                         */
+    int icm_rounds;          /* isoenergetic cluster moves (Sec. IV): 0
+                                (default) = none; n in [1, 8] = at every step
+                                after a resampling, floor(sweeps/2) sweeps,
+                                then n rounds that update floor(R_k/2)
+                                disjoint random replica pairs each (the
+                                paper's R updates per step: n = 2), then the
+                                remaining sweeps.  An update flips, in both
+                                replicas, the island of the smaller overlap
+                                sector that holds a randomly drawn site.
+                                Needs PAMC_SPINS_INT8.  Family ids stay with
+                                their rows, so S_f and rho_s no longer
+                                measure equilibration (use rho_f)          */
 } pamc_options;
 
 /* Fills *opt with the defaults described above. */

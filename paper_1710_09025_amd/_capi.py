@@ -43,6 +43,7 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("pop_schedule", ctypes.POINTER(ctypes.c_int64)),
         ("real_couplings", ctypes.c_int),
+        ("icm_rounds", ctypes.c_int),
     ]
 
 

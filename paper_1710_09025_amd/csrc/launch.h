@@ -39,12 +39,18 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
 // sweeps of one temperature step; the last workgroup of each instance also
 // measures the step and prepares its resampling table
 // (tpr, rp: threads per replica quad and replica quads per workgroup of the
-// colour-major kernel; unused by the others)
+// colour-major kernel; unused by the others).  phase 0: all N_S sweeps;
+// with cluster moves, phase 1: the first floor(N_S/2) sweeps (no energies,
+// no measurement), phase 2: the rest with energies and the measurement.
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
-                  int rp, hipStream_t st);
+                  int rp, int phase, hipStream_t st);
 // resampling weights and their normaliser (instances with real couplings;
 // work items are 1024-row blocks)
 void launch_weights(const Inst *insts, const Work *work, int nwork, hipStream_t st);
+// one round of isoenergetic cluster moves (work items: instance, pair
+// index); N: the largest lattice of the launch (sizes the LDS)
+void launch_icm(const Inst *insts, const Work *work, int nwork, int N, int round, hipStream_t st);
+hipError_t icm_kernels_init();
 // copy counts, family entropy, overlap; the last workgroup of each instance
 // finishes the prefix sum and advances the step
 void launch_post(const Inst *insts, const Work *work, int nwork, hipStream_t st);

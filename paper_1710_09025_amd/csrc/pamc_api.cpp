@@ -86,6 +86,9 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
     if (cap >= ((int64_t)1 << 31) - 1024) return invalid("capacity must stay below 2^31");
     if (opt.spin_format != PAMC_SPINS_INT8 && opt.spin_format != PAMC_SPINS_PACKED)
         return invalid("unknown spin format");
+    if (opt.icm_rounds < 0 || opt.icm_rounds > 8) return invalid("icm_rounds must be in [0, 8]");
+    if (opt.icm_rounds > 0 && opt.spin_format == PAMC_SPINS_PACKED)
+        return invalid("cluster moves need int8 spin storage");
     if (real && (__int128)absJ * cap >= ((__int128)1 << 62))
         return invalid("capacity times the sum of |couplings| must stay below 2^62");
     // the normaliser's tree folds at most 2^19 roots of 1024-row blocks
@@ -111,6 +114,7 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
     if (opt.pop_schedule)
         for (int k = 0; k < nT; ++k) h.pop[(size_t)k] = (double)opt.pop_schedule[k];
     h.real = real ? 1 : 0;
+    h.icm = opt.icm_rounds;
     if (real)
         h.Jq.assign(Jq, Jq + 3 * N);
     else

@@ -19,6 +19,7 @@ namespace pamc {
 constexpr uint32_t kTagInit = 0x10000000u;
 constexpr uint32_t kTagSweep = 0x20000000u;
 constexpr uint32_t kTagResample = 0x30000000u;
+constexpr uint32_t kTagIcm = 0x40000000u;
 
 // Spin storage layouts inside one replica row.
 enum Layout : int32_t {
@@ -78,6 +79,7 @@ struct Inst {
     int32_t fam_pow2;   // smallest power of two >= R (family tree leaves)
     int32_t ovl_n;      // number of overlap steps
     int32_t real;       // 1: real couplings in fixed point, J = j 2^-20 (int32 j, |J| < 8)
+    int32_t icm;        // cluster-move rounds per step (0: none)
     // double-buffered population
     uint8_t *spins[2];
     int32_t *E[2];

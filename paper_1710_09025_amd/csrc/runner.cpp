@@ -229,6 +229,7 @@ int Runner::setup(const pamc_options &opt, int max_slots)
     if (opt.device >= 0) HIPCHK(hipSetDevice(opt.device), "hipSetDevice");
     HIPCHK(hipGetDevice(&device_), "hipGetDevice");
     HIPCHK(sweep_kernels_init(), "hipFuncSetAttribute (sweep LDS)");
+    HIPCHK(icm_kernels_init(), "hipFuncSetAttribute (cluster-move LDS)");
     if (opt.stream) {
         stream_ = (hipStream_t)opt.stream;
     } else {
@@ -378,6 +379,7 @@ int Runner::upload_inst(int i)
     d.status = (uint32_t *)(b + lay.status);
     d.sync = (uint32_t *)(b + lay.sync);
     d.real = h.real;
+    d.icm = h.icm;
     d.Eq[0] = (int64_t *)(b + lay.Eq0);
     d.Eq[1] = (int64_t *)(b + lay.Eq1);
     d.wrep = (double *)(b + lay.wrep);
@@ -628,13 +630,20 @@ int Runner::build_work(const std::vector<int> &active)
         if (bytes && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
         return p;
     };
-    std::map<std::tuple<int, int, int, int, int, int>, std::vector<Work>> groups;
-    std::vector<Work> rows, post, gath, wblk;
+    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<Work>> groups;
+    std::vector<Work> rows, post, gath, wblk, icm;
+    icm_rounds_ = 0;
+    icm_N_ = 0;
     std::vector<uint32_t> list;
     for (int i : active) {
         const HostInst &h = inst_[i];
         const uint32_t ii = (uint32_t)i;
-        auto &g = groups[std::make_tuple(h.variant, h.L, h.tile_rows, h.row_bytes, h.tpr, h.rp)];
+        auto &g = groups[std::make_tuple(h.variant, h.L, h.tile_rows, h.row_bytes, h.tpr, h.rp, h.icm > 0 ? 1 : 0)];
+        if (h.icm > 0) {
+            for (int64_t j = 0; j < h.Rcap / 2; ++j) icm.push_back(Work{ii, (uint32_t)j, 0u, 0u});
+            icm_rounds_ = std::max(icm_rounds_, h.icm);
+            icm_N_ = std::max(icm_N_, h.N);
+        }
         for (int64_t r = 0; r < h.Rcap; r += h.tile_rows) g.push_back(Work{ii, (uint32_t)r, 0u, 0u});
         for (int64_t r = 0; r < h.Rcap; r += kRowsPerBlock) {
             rows.push_back(Work{ii, (uint32_t)r, 0u, 0u});
@@ -655,6 +664,7 @@ int Runner::build_work(const std::vector<int> &active)
         sg.row_bytes = std::get<3>(kv.first);
         sg.tpr = std::get<4>(kv.first);
         sg.rp = std::get<5>(kv.first);
+        sg.icm = std::get<6>(kv.first);
         sg.nwork = (int)kv.second.size();
         sg.work = (Work *)upload(kv.second.data(), kv.second.size() * sizeof(Work));
         if (!sg.work) return dev_fail(hipErrorOutOfMemory, "upload sweep work");
@@ -665,6 +675,12 @@ int Runner::build_work(const std::vector<int> &active)
     ngather_ = (int)gath.size();
     d_post_ = (Work *)upload(post.data(), post.size() * sizeof(Work));
     d_list_ = (uint32_t *)upload(list.data(), list.size() * 4);
+    d_icm_ = nullptr;
+    nicm_ = (int)icm.size();
+    if (nicm_) {
+        d_icm_ = (Work *)upload(icm.data(), icm.size() * sizeof(Work));
+        if (!d_icm_) return dev_fail(hipErrorOutOfMemory, "upload pair work");
+    }
     d_wblk_ = nullptr;
     nwblk_ = (int)wblk.size();
     if (nwblk_) {
@@ -715,8 +731,18 @@ void Runner::drop_graph()
 // population size live on the device), so the sequence can be captured once.
 int Runner::launch_step_kernels()
 {
+    // runs with cluster moves split their sweeps around the ICM rounds
     for (auto &g : sweep_groups_)
-        launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, stream_);
+        if (!g.icm) launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, 0, stream_);
+    if (nicm_) {
+        for (auto &g : sweep_groups_)
+            if (g.icm)
+                launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, 1, stream_);
+        for (int rd = 0; rd < icm_rounds_; ++rd) launch_icm(d_insts_, d_icm_, nicm_, icm_N_, rd, stream_);
+        for (auto &g : sweep_groups_)
+            if (g.icm)
+                launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, 2, stream_);
+    }
     if (timing_) HIPCHK(hipEventRecord(ev_pool_[ev_used_ - 3], stream_), "hipEventRecord");
     launch_weights(d_insts_, d_wblk_, nwblk_, stream_);
     launch_post(d_insts_, d_post_, npost_, stream_);

@@ -24,6 +24,7 @@ struct HostInst {
     int row_bytes = 0, tile_rows = 0;
     int packed = 0;                    // spins stored one bit per position
     int real = 0;                      // real couplings in fixed point (Jq)
+    int icm = 0;                       // cluster-move rounds per step
     int srow_bytes = 0;                // bytes per stored spin row
     int tpr = 0;                       // colour-major sweep: threads per replica
     int rp = 0;                        // colour-major sweep: replica quads per workgroup
@@ -142,7 +143,7 @@ private:
 
     // work lists for the current active set
     struct SweepGroup {
-        int variant, tile_rows, row_bytes, tpr, rp;
+        int variant, tile_rows, row_bytes, tpr, rp, icm;
         Work *work;
         int nwork;
     };
@@ -151,6 +152,8 @@ private:
     int nrows_work_ = 0;
     Work *d_wblk_ = nullptr;   // 1024-row blocks of instances with real couplings (weights)
     int nwblk_ = 0;
+    Work *d_icm_ = nullptr;    // replica pairs of instances with cluster moves
+    int nicm_ = 0, icm_rounds_ = 0, icm_N_ = 0;
     Work *d_gather_ = nullptr; // row blocks of about 32 KB of spins (stand-alone gather)
     int ngather_ = 0;
     Work *d_post_ = nullptr;   // post-launch workgroups with their roles

@@ -262,10 +262,31 @@ __device__ __forceinline__ void tile_family_count(const Inst &I, const TileIO &i
     }
 }
 
-// End of a sweep workgroup: the last one of the instance measures the step.
-__device__ __forceinline__ void sweep_done(const Inst &I, int k)
+// A sweep launch runs the whole step (phase 0) or, for runs with cluster
+// moves, the first floor(N_S/2) sweeps (phase 1: through the copy map, no
+// energies) and later the remaining ones (phase 2: in place, with energies
+// and the measurement).
+__device__ __forceinline__ int phase_t0(const Inst &I, int phase) { return phase == 2 ? I.NS / 2 : 0; }
+__device__ __forceinline__ int phase_t1(const Inst &I, int phase) { return phase == 1 ? I.NS / 2 : I.NS; }
+
+// End of phase 1 in the last workgroup: the population now lives in the
+// buffer the tiles were written to.
+__device__ __forceinline__ void phase1_done(const Inst &I)
 {
-    if (last_workgroup(&I.sync[0], I.sweep_tiles)) measure_step<256>(I, k);
+    const bool last = last_workgroup(&I.sync[0], I.sweep_tiles);
+    if (last && threadIdx.x == 0 && *I.mapped) {
+        *I.cur ^= 1;
+        *I.mapped = 0;
+    }
+}
+
+// End of a sweep workgroup: the last one of the instance measures the step.
+__device__ __forceinline__ void sweep_done(const Inst &I, int k, int phase)
+{
+    if (phase == 1)
+        phase1_done(I);
+    else if (last_workgroup(&I.sync[0], I.sweep_tiles))
+        measure_step<256>(I, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -274,9 +295,9 @@ __device__ __forceinline__ void sweep_done(const Inst &I, int k)
 // consecutive sites of one colour) of one replica of the tile; per site the
 // six neighbours and the couplings come from a per-site record.
 // ---------------------------------------------------------------------------
-__device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows);
+__device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows, int phase);
 
-__global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work *work, int tile_rows)
+__global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work *work, int tile_rows, int phase)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
@@ -286,11 +307,11 @@ __global__ __launch_bounds__(256) void k_sweep_lex(const Inst *insts, const Work
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_lex(I, k, lds, r0, nrows, tile_rows);
-    sweep_done(I, k);
+    if (nrows > 0) sweep_tile_lex(I, k, lds, r0, nrows, tile_rows, phase);
+    sweep_done(I, k, phase);
 }
 
-__device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+__device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows, int phase)
 {
     const int row_bytes = I.row_bytes;
     int *unsat = reinterpret_cast<int *>(lds + tile_rows * row_bytes);
@@ -302,7 +323,8 @@ __device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int n
     const uint32_t key0 = I.key0, key1 = I.key1;
     __syncthreads();
 
-    for (int t = 0; t < I.NS; ++t) {
+    const int t1 = phase_t1(I, phase);
+    for (int t = phase_t0(I, phase); t < t1; ++t) {
         for (int c = 0; c < I.ncol; ++c) {
             const int G = I.gcs[c];
             const int items = nrows * G;
@@ -336,6 +358,10 @@ __device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int n
         }
     }
 
+    if (phase == 1) {
+        tile_store(io, lds, r0, nrows, row_bytes);
+        return;
+    }
     // energies: E = 2U - 3N with U the unsatisfied bonds (s, s + e_d)
     for (int it = threadIdx.x; it < nrows * I.N; it += blockDim.x) {
         const int q = it / I.N, s = it - q * I.N;
@@ -470,7 +496,7 @@ __device__ __forceinline__ uint32_t eo_flip(uint32_t n, uint4 u, const uint8_t *
 // results are never stored.
 template <int L, bool ALL>
 __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, const EOGroup (&gr)[2][EOShape<L>::GPT],
-                                          const uint8_t *tab, int *unsat, int r0, int nrows)
+                                          const uint8_t *tab, int *unsat, int r0, int nrows, int phase)
 {
     using SH = EOShape<L>;
     const int qsub = threadIdx.x / SH::TPR;
@@ -478,7 +504,8 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
     for (int qb = 0; qb < nrows; qb += SH::RP) {
         const int q0 = qb + qsub;
         uint8_t *row = lds + q0 * SH::N;
-        for (int t = 0; t < I.NS; ++t) {
+        const int t1 = phase_t1(I, phase);
+        for (int t = phase_t0(I, phase); t < t1; ++t) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -503,6 +530,7 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
         }
         // energy: every bond joins a colour-0 and a colour-1 site, so the
         // unsatisfied bonds are the sum of n over colour-0 sites.
+        if (phase == 1) continue;
 #pragma unroll
         for (int j = 0; j < SH::RPT; ++j) {
             const uint8_t *rj = row + j * SH::RSTRIDE;
@@ -520,10 +548,10 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
 }
 
 template <int L>
-__device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows);
+__device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows, int phase);
 
 template <int L>
-__global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work *work, int tile_rows)
+__global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work *work, int tile_rows, int phase)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
@@ -533,14 +561,14 @@ __global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work 
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_eo<L>(I, k, lds, r0, nrows, tile_rows);
-    sweep_done(I, k);
+    if (nrows > 0) sweep_tile_eo<L>(I, k, lds, r0, nrows, tile_rows, phase);
+    sweep_done(I, k, phase);
 }
 
 // The tile holds tile_rows rows (a multiple of EOShape<L>::RP) of N bytes,
 // then tile_rows unsatisfied-bond counters.
 template <int L>
-__device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+__device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows, int phase)
 {
     using SH = EOShape<L>;
     // thresholds by 4 n at a fixed LDS address: T(dE = 12, 8, 4) for
@@ -563,10 +591,11 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
     __syncthreads();
     const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
     if (all)
-        eo_sweeps<L, true>(I, k, lds, gr, tb, unsat, r0, nrows);
+        eo_sweeps<L, true>(I, k, lds, gr, tb, unsat, r0, nrows, phase);
     else
-        eo_sweeps<L, false>(I, k, lds, gr, tb, unsat, r0, nrows);
+        eo_sweeps<L, false>(I, k, lds, gr, tb, unsat, r0, nrows, phase);
     tile_store(io, lds, r0, nrows, SH::N);
+    if (phase == 1) return;
     tile_energy_out(I, io, unsat, r0, nrows);
     tile_family_count(I, io, r0, nrows);
 }
@@ -652,7 +681,8 @@ __device__ __forceinline__ uint32_t lds_word(const uint8_t *lds, uint32_t a)
 // Missing replicas of the last quad are swept as zeros and never stored.
 template <int NCOL, bool ALL>
 __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, const CMBlock (&blk)[NCOL],
-                                          const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows)
+                                          const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows,
+                                          int phase)
 {
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
@@ -694,7 +724,8 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
             }
         }
         replica_barrier(tpr);
-        for (int t = 0; t < I.NS; ++t) {
+        const int t1 = phase_t1(I, phase);
+        for (int t = phase_t0(I, phase); t < t1; ++t) {
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 const CMBlock &b = blk[c];
@@ -732,7 +763,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                 replica_barrier(tpr);
             }
         }
-        if (act) {
+        if (act && phase != 1) {
             // per byte (replica) at most 4 sites x 3 colours x 6 bonds = 72:
             // the sum stays inside its byte
             uint32_t acc = 0;
@@ -752,6 +783,8 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (q0 + j < nrows) atomicAdd(&unsat[q0 + j], (int)((acc >> (8 * j)) & 0xFFu));
+        }
+        if (act) {
             const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
             for (int i = lane_r; i < nvec; i += tpr) {
                 uint4 w[4];
@@ -773,7 +806,8 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 }
 
 template <int NCOL>
-__device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+__device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows,
+                                              int phase)
 {
     // thresholds by 4 n at a fixed LDS address (see eo_flip)
     __shared__ uint32_t tab[8];
@@ -813,14 +847,15 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     __syncthreads();
     const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
     if (all)
-        cm_passes<NCOL, true>(I, k, lds, blk, tb, unsat, io, r0, nrows);
+        cm_passes<NCOL, true>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
     else
-        cm_passes<NCOL, false>(I, k, lds, blk, tb, unsat, io, r0, nrows);
+        cm_passes<NCOL, false>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
     __syncthreads();
     // every bond was counted from both of its ends
     for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] >>= 1;
     if (io.map)
         for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
+    if (phase == 1) return;
     __syncthreads();
     tile_energy_out(I, io, unsat, r0, nrows);
     tile_family_count(I, io, r0, nrows);
@@ -829,7 +864,8 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
 // MAXT: the largest workgroup the instantiation is built for (a 512-thread
 // bound leaves room for every neighbour address in registers).
 template <int NCOL, int MAXT>
-__global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows)
+__global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows,
+                                                                       int phase)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
@@ -839,8 +875,11 @@ __global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const In
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_cm<NCOL>(I, k, lds, r0, nrows, tile_rows);
-    if (last_workgroup(&I.sync[0], I.sweep_tiles)) measure_step<512>(I, k);
+    if (nrows > 0) sweep_tile_cm<NCOL>(I, k, lds, r0, nrows, tile_rows, phase);
+    if (phase == 1)
+        phase1_done(I);
+    else if (last_workgroup(&I.sync[0], I.sweep_tiles))
+        measure_step<512>(I, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,7 +933,7 @@ __device__ __forceinline__ uint4 spin_01(uint4 v)
 
 template <int NCOL, bool ALL>
 __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, const CQBlock (&blk)[NCOL], float bq,
-                                          unsigned long long *eacc, const TileIO &io, int r0, int nrows)
+                                          unsigned long long *eacc, const TileIO &io, int r0, int nrows, int phase)
 {
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
@@ -929,7 +968,8 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
             }
         }
         replica_barrier(tpr);
-        for (int t = 0; t < I.NS; ++t) {
+        const int t1 = phase_t1(I, phase);
+        for (int t = phase_t0(I, phase); t < t1; ++t) {
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 const CQBlock &b = blk[c];
@@ -966,7 +1006,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
                 replica_barrier(tpr);
             }
         }
-        if (act) {
+        if (act && phase != 1) {
             // per replica, sum over the thread's sites of sum_d sigma_d J_d:
             // at most 12 sites x 6 bonds x 2^23 < 2^30
             int32_t e[4] = {0, 0, 0, 0};
@@ -984,6 +1024,8 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (q0 + j < nrows) atomicAdd(&eacc[q0 + j], (unsigned long long)(long long)e[j]);
+        }
+        if (act) {
             const uint4 *sp = reinterpret_cast<const uint4 *>(slot);
             for (int i = lane_r; i < nvec; i += tpr) {
                 uint4 w[4];
@@ -1065,7 +1107,8 @@ __device__ __forceinline__ void tile_moments_real(const Inst &I, const TileIO &i
 }
 
 template <int NCOL>
-__device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows)
+__device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows,
+                                              int phase)
 {
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
@@ -1102,18 +1145,19 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
     for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) eacc[q] = 0ull;
     __syncthreads();
     if (all)
-        cq_passes<NCOL, true>(I, k, lds, blk, bq, eacc, io, r0, nrows);
+        cq_passes<NCOL, true>(I, k, lds, blk, bq, eacc, io, r0, nrows, phase);
     else
-        cq_passes<NCOL, false>(I, k, lds, blk, bq, eacc, io, r0, nrows);
+        cq_passes<NCOL, false>(I, k, lds, blk, bq, eacc, io, r0, nrows, phase);
     __syncthreads();
     if (io.map)
         for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
+    if (phase == 1) return;
     tile_moments_real(I, io, eacc, r0, nrows);
     tile_family_count(I, io, r0, nrows);
 }
 
 template <int NCOL, int MAXT>
-__global__ __launch_bounds__(MAXT, 2) void k_sweep_cq(const Inst *insts, const Work *work, int tile_rows)
+__global__ __launch_bounds__(MAXT, 2) void k_sweep_cq(const Inst *insts, const Work *work, int tile_rows, int phase)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
@@ -1123,8 +1167,11 @@ __global__ __launch_bounds__(MAXT, 2) void k_sweep_cq(const Inst *insts, const W
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_cq<NCOL>(I, k, lds, r0, nrows, tile_rows);
-    if (last_workgroup(&I.sync[0], I.sweep_tiles)) measure_step_real(I, k);
+    if (nrows > 0) sweep_tile_cq<NCOL>(I, k, lds, r0, nrows, tile_rows, phase);
+    if (phase == 1)
+        phase1_done(I);
+    else if (last_workgroup(&I.sync[0], I.sweep_tiles))
+        measure_step_real(I, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1213,7 +1260,7 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
 int cm_replicas_per_block(int tpr) { return tpr >= 256 ? 1 : 256 / tpr; }
 
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
-                  int rp, hipStream_t st)
+                  int rp, int phase, hipStream_t st)
 {
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
@@ -1222,14 +1269,14 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
         const int nt = tpr * rp;
         if (variant == kSweepCM2) {
             if (nt <= 512)
-                k_sweep_cm<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cm<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
             else
-                k_sweep_cm<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cm<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
         } else {
             if (nt <= 512)
-                k_sweep_cm<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cm<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
             else
-                k_sweep_cm<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cm<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
         }
         return;
     }
@@ -1239,22 +1286,22 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
         const int nt = tpr * rp;
         if (variant == kSweepCQ2) {
             if (nt <= 512)
-                k_sweep_cq<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cq<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
             else
-                k_sweep_cq<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cq<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
         } else {
             if (nt <= 512)
-                k_sweep_cq<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cq<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
             else
-                k_sweep_cq<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows);
+                k_sweep_cq<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
         }
         return;
     }
     const size_t lds = (size_t)tile_rows * row_bytes + 32 + 4 * (size_t)tile_rows;
     switch (variant) {
-    case kSweepLex: k_sweep_lex<<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;
-    case kSweepEO8: k_sweep_eo<8><<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;
-    case kSweepEO16: k_sweep_eo<16><<<nwork, 256, lds, st>>>(insts, work, tile_rows); break;
+    case kSweepLex: k_sweep_lex<<<nwork, 256, lds, st>>>(insts, work, tile_rows, phase); break;
+    case kSweepEO8: k_sweep_eo<8><<<nwork, 256, lds, st>>>(insts, work, tile_rows, phase); break;
+    case kSweepEO16: k_sweep_eo<16><<<nwork, 256, lds, st>>>(insts, work, tile_rows, phase); break;
     default: break;
     }
 }

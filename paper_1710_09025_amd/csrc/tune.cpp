@@ -165,6 +165,7 @@ int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
     o.autotune = 0;
     o.pop_schedule = nullptr;
     o.fuse_gather = 1;
+    o.icm_rounds = 0;  // the shape concerns the sweep alone
     const int nT = 1 + kBurnIn + (1 + kTimedSteps) * (int)cand.size();
     const std::vector<double> beta((size_t)nT, kTuneBeta);
     HostInst t;

@@ -149,6 +149,27 @@ def test_invalid_real_couplings_are_rejected_on_the_host(lib, case):
     assert not h.value
 
 
+@pytest.mark.parametrize("case", ["packed", "rounds"])
+def test_invalid_cluster_move_options_are_rejected_on_the_host(lib, case):
+    from paper_1710_09025_amd import _capi
+
+    L = 4
+    J = np.ones((3, L ** 3), dtype=np.int8)
+    beta = np.linspace(0, 1, 3)
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    if case == "packed":
+        opt.icm_rounds = 2
+        opt.spin_format = _capi.SPINS_PACKED
+    else:
+        opt.icm_rounds = 9
+    h = ctypes.c_void_p()
+    st = lib.pamc_create(L, J.ctypes.data_as(ctypes.c_void_p), 100, beta.ctypes.data_as(ctypes.c_void_p),
+                         len(beta), 2, 1, ctypes.byref(opt), ctypes.byref(h))
+    assert st == _capi.ERR_INVALID, lib.pamc_last_error()
+    assert not h.value
+
+
 def test_real_footprint_adds_64_bit_energies_and_weights(lib):
     from paper_1710_09025_amd import _capi
 
