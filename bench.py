@@ -85,7 +85,7 @@ def attempts_of(obs, N, sweeps):
     return float(np.sum(obs["R"][obs["measured"] == 1])) * N * sweeps
 
 
-def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False):
+def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, icm_rounds=0):
     """Creates warmup + steps run handles up front (each temperature step a
     replayed hipGraph; sweep shapes chosen by the autotuner at creation,
     outside the timed region) and anneals them one after another for the
@@ -97,8 +97,8 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False):
 
     cfg, J, beta = workload_inputs(name, real)
     N = cfg["L"] ** 3
-    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune, packed=packed)
-            for _ in range(warmup + steps)]
+    runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune, packed=packed,
+                 icm_rounds=icm_rounds) for _ in range(warmup + steps)]
     shape = runs[0].sweep_shape()
     for r in runs[:warmup]:
         assert r.anneal() == 0
@@ -114,7 +114,7 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False):
         r.close()
     del runs
     timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, autotune=autotune,
-                 packed=packed)
+                 packed=packed, icm_rounds=icm_rounds)
     assert timed.sweep_shape() == shape
     assert timed.anneal() == 0
     sweep_ms, other_ms, _, nsteps = timed.phase_times()
@@ -321,9 +321,9 @@ def schedule_bench(name, kind):
             "final_S_f": round(float(obs["S_f"][-1]), 4), "peak_R": int(np.max(obs["R"]))}
 
 
-def rho_f_bench(L=8, R=20000, n_temps=201, runs=16):
+def rho_f_bench(L=8, R=20000, n_temps=201, runs=16, icm_rounds=0):
     """rho_f = R var(beta F) from independent runs of one instance (Eq. (4)),
-    annealed together as one batch."""
+    annealed together as one batch (with cluster moves when icm_rounds > 0)."""
     import torch
 
     from paper_1710_09025_amd import free_energy_variance
@@ -332,11 +332,39 @@ def rho_f_bench(L=8, R=20000, n_temps=201, runs=16):
     beta = pi.linear_beta(5.0, n_temps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = free_energy_variance(L, J, R, beta, 10, [7000 + i for i in range(runs)], autotune=True)
+    res = free_energy_variance(L, J, R, beta, 10, [7000 + i for i in range(runs)], autotune=True,
+                               icm_rounds=icm_rounds)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return {"L": L, "R": R, "n_temps": n_temps, "runs": runs, "rho_f_final": round(float(res["rho_f"][-1]), 4),
-            "rho_f_max": round(float(np.max(res["rho_f"])), 4), "seconds": round(t1 - t0, 3)}
+    return {"L": L, "R": R, "n_temps": n_temps, "runs": runs, "icm_rounds": icm_rounds,
+            "rho_f_final": round(float(res["rho_f"][-1]), 4), "rho_f_max": round(float(np.max(res["rho_f"])), 4),
+            "seconds": round(t1 - t0, 3)}
+
+
+def icm_bench(name, rounds=2):
+    """One anneal of a workload with isoenergetic cluster moves (Sec. IV):
+    rounds x floor(R_k/2) pair updates per step between the two halves of
+    the sweeps, timed like the main line; the attempts counted are the
+    Metropolis ones, so the rate shows the cost of the cluster moves."""
+    import torch
+
+    from paper_1710_09025_amd import Pamc
+
+    cfg, J, beta = workload_inputs(name)
+    p = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=True, icm_rounds=rounds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    assert p.anneal() == 0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    obs = p.observables()
+    p.close()
+    torch.cuda.empty_cache()
+    att = attempts_of(obs, cfg["L"] ** 3, cfg["sweeps"])
+    pairs = rounds * int(np.sum(obs["R"][1:] // 2))
+    return {"icm_rounds": rounds, "attempts_per_ns": round(att / ((t1 - t0) * 1e9), 3),
+            "ms_per_anneal": round((t1 - t0) * 1e3, 3), "pair_updates": pairs,
+            "pair_updates_per_us": round(pairs / ((t1 - t0) * 1e6), 3)}
 
 
 def warm_serving_shapes(sweeps=10):
@@ -393,6 +421,8 @@ def main():
     ap.add_argument("--workload", default="L8_R100000", choices=sorted(pi.WORKLOADS))
     ap.add_argument("--couplings", default="pm1", choices=("pm1", "gaussian"),
                     help="couplings of the benchmark instance: +-1, or Gaussian in fixed point")
+    ap.add_argument("--icm-rounds", type=int, default=0,
+                    help="isoenergetic cluster-move rounds per step in the main line (0: none)")
     ap.add_argument("--cpu-steps", type=int, default=16, help="temperature steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -432,7 +462,7 @@ def main():
     torch.cuda.set_device(0)
 
     real = args.couplings == "gaussian"
-    res = time_anneals(args.workload, args.steps, args.warmup, real=real)
+    res = time_anneals(args.workload, args.steps, args.warmup, real=real, icm_rounds=args.icm_rounds)
     res["cfg"]["name"] = args.workload
     log(f"{args.workload} ({args.couplings}) timed")
     total_attempts = res["attempts_per_anneal"] * args.steps
@@ -455,7 +485,7 @@ def main():
         "config": {"workload": f"3D EA {'Gaussian' if real else '+-J'} L={cfg['L']} periodic, R={cfg['R']}, n_temps={cfg['n_temps']} "
                                f"beta linear 0->{cfg['beta_max']}, N_S={cfg['sweeps']}, one instance",
                    "L": cfg["L"], "R": cfg["R"], "n_temps": cfg["n_temps"], "sweeps": cfg["sweeps"],
-                   "step": "one complete anneal", "spins": "int8"},
+                   "step": "one complete anneal", "spins": "int8", "icm_rounds": args.icm_rounds},
         "sweep_attempts_per_ns": round(res["attempts_per_anneal"] / (res["sweep_ms"] * 1e6), 3),
         "sweep_share": round(res["sweep_ms"] / (res["sweep_ms"] + res["other_ms"]), 4),
         "roofline": roofline(res),
@@ -502,7 +532,9 @@ def main():
             extra[f"{args.workload}_{kind}"] = schedule_bench(args.workload, kind)
             log(f"schedule {kind} done")
         extra["rho_f"] = rho_f_bench()
-        log("rho_f done")
+        extra[f"{args.workload}_icm"] = icm_bench(args.workload)
+        extra["rho_f_icm"] = rho_f_bench(icm_rounds=2)
+        log("rho_f and cluster moves done")
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
             log("batch done")

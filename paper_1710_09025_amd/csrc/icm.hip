@@ -19,6 +19,8 @@
 // repeatedly until the value falls in [0, R_k) (cycle walking).  The drawn
 // site is the m-th site of the sector in lexicographic order,
 // m = floor(u count / 2^32), u = word 0 of Philox at (j, 4, k, TAG_ICM | rd).
+#include <algorithm>
+
 #include "launch.h"
 #include "pamc_dev.h"
 #include "step_common.h"
@@ -46,114 +48,106 @@ __device__ uint32_t icm_perm(uint32_t key0, uint32_t key1, uint32_t i, uint32_t 
 }
 
 // LDS of one pair: the sector flag of every lexicographic site (bytes), the
-// visited bits, and the island queue (site indices, N <= 32768).
-__host__ __device__ inline size_t icm_lds_bytes(int N)
+// visited bits, the island queue (site indices, N <= 32768) and its tail.
+__host__ __device__ inline int icm_pair_bytes(int N)
 {
-    return (size_t)((N + 15) & ~15) + 4 * (size_t)((N + 31) / 32) + 2 * (size_t)N + 16;
+    return ((N + 15) & ~15) + 4 * ((N + 31) / 32) + ((2 * N + 15) & ~15) + 16;
 }
 
-// Exclusive scan over the workgroup (a multiple of 64 threads, <= 1024).
-__device__ __forceinline__ int icm_exscan(int v, int *sh, int *total)
+__device__ __forceinline__ void wave_sync()
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
-    int x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[wave] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < nw; ++i) {
-            const int t = sh[i];
-            sh[i] = acc;
-            acc += t;
-        }
-        sh[16] = acc;
-    }
-    __syncthreads();
-    *total = sh[16];
-    const int r = sh[wave] + x - v;
-    __syncthreads();
-    return r;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One ICM round: work item = (instance, pair index j).
-__global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work, int round)
+__device__ __forceinline__ int wave_sum(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// One ICM round.  Each wave of the workgroup updates one pair (work item =
+// instance, pair index j) on its own slice of LDS, so the island search
+// synchronises only inside its wave.
+__global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work, int nwork, int round, int pair_bytes)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t rows[2];
-    __shared__ int sh[17];
-    __shared__ int sh_tail;
-    const Work w = work[blockIdx.x];
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int item = (int)blockIdx.x * ((int)blockDim.x >> 6) + wave;
+    if (item >= nwork) return;
+    const Work w = work[item];
     const Inst &I = insts[w.inst];
     const int k = *I.k;
     if (!inst_live(I, k) || k == 0 || round >= I.icm) return;
     const uint32_t n = I.Rk[k];
     const uint32_t j = w.row0;
     if (j >= n / 2) return;
-    const int N = I.N, L = I.L, t = (int)threadIdx.x, bd = (int)blockDim.x;
-    uint8_t *member = lds;
-    uint32_t *vis = reinterpret_cast<uint32_t *>(lds + ((N + 15) & ~15));
-    uint16_t *queue = reinterpret_cast<uint16_t *>(lds + ((N + 15) & ~15) + 4 * ((N + 31) / 32));
-    if (t == 0) {
-        rows[0] = icm_perm(I.key0, I.key1, 2 * j, n, k, round);
-        rows[1] = icm_perm(I.key0, I.key1, 2 * j + 1, n, k, round);
-    }
-    __syncthreads();
+    const int N = I.N, L = I.L;
+    uint8_t *base = lds + (size_t)wave * pair_bytes;
+    uint8_t *member = base;
+    uint32_t *vis = reinterpret_cast<uint32_t *>(base + ((N + 15) & ~15));
+    uint16_t *queue = reinterpret_cast<uint16_t *>(base + ((N + 15) & ~15) + 4 * ((N + 31) / 32));
+    int *tailp = reinterpret_cast<int *>(base + pair_bytes - 16);
+    // the pair's rows: pi(2j) on lane 0, pi(2j + 1) on lane 1
+    uint32_t row = 0;
+    if (lane < 2) row = icm_perm(I.key0, I.key1, 2 * j + (uint32_t)lane, n, k, round);
+    const uint32_t ra = __shfl(row, 0), rb = __shfl(row, 1);
     uint8_t *sp = I.spins[*I.cur];
-    uint8_t *A = sp + (size_t)rows[0] * I.srow_bytes;
-    uint8_t *B = sp + (size_t)rows[1] * I.srow_bytes;
+    uint8_t *A = sp + (size_t)ra * I.srow_bytes;
+    uint8_t *B = sp + (size_t)rb * I.srow_bytes;
     // sites where the replicas differ
     int nd = 0;
-    for (int s = t; s < N; s += bd) {
+    for (int s = lane; s < N; s += 64) {
         const int p = I.pos[s];
         const uint8_t d = A[p] != B[p] ? 1 : 0;
         member[s] = d;
         nd += d;
     }
-    for (int i = t; i < (N + 31) / 32; i += bd) vis[i] = 0u;
-    int total;
-    (void)icm_exscan(nd, sh, &total);
-    nd = total;
+    for (int i = lane; i < (N + 31) / 32; i += 64) vis[i] = 0u;
+    nd = wave_sum(nd);
     const bool want = nd <= N - nd;
     const int cnt = want ? nd : N - nd;
-    if (cnt == 0) return;  // empty sector: no move (uniform over the workgroup)
+    if (cnt == 0) return;  // empty sector: no move (uniform over the wave)
     if (!want)
-        for (int s = t; s < N; s += bd) member[s] ^= 1u;
-    __syncthreads();
-    // the m-th site of the sector, found through per-thread chunk counts
+        for (int s = lane; s < N; s += 64) member[s] ^= 1u;
+    wave_sync();
+    // the m-th site of the sector, through per-lane chunk counts
     const uint32_t u = philox10(make_uint4(j, 4u, (uint32_t)k, kTagIcm | (uint32_t)round), I.key0, I.key1).x;
     const int m = (int)(((uint64_t)u * (uint64_t)cnt) >> 32);
-    const int chunk = (N + bd - 1) / bd;
-    const int s_begin = min(N, t * chunk), s_end = min(N, s_begin + chunk);
+    const int chunk = (N + 63) / 64;
+    const int s_begin = min(N, lane * chunk), s_end = min(N, s_begin + chunk);
     int c = 0;
     for (int s = s_begin; s < s_end; ++s) c += member[s];
-    const int off = icm_exscan(c, sh, &total);
-    if (off <= m && m < off + c) {
-        int seen = off;
+    int incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    const int excl = incl - c;
+    if (excl <= m && m < incl) {
+        int seen = excl;
         for (int s = s_begin; s < s_end; ++s)
             if (member[s]) {
                 if (seen == m) {
                     queue[0] = (uint16_t)s;
                     vis[s >> 5] = 1u << (s & 31);
+                    *tailp = 1;
                     break;
                 }
                 ++seen;
             }
     }
-    if (t == 0) sh_tail = 1;
-    __syncthreads();
+    wave_sync();
     // breadth-first growth of the island, one frontier per iteration; the
     // queue only grows and holds each site once, so this ends within N
     // iterations
     int head = 0;
     while (true) {
-        const int tail = sh_tail;
+        const int tail = *reinterpret_cast<volatile int *>(tailp);
         if (head >= tail) break;
-        __syncthreads();
-        for (int idx = head + t; idx < tail; idx += bd) {
+        wave_sync();
+        for (int idx = head + lane; idx < tail; idx += 64) {
             const int s = queue[idx];
             const int x = s % L, yz = s / L, y = yz % L, z = yz / L;
             const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
@@ -167,15 +161,15 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
                 if (!member[q]) continue;
                 const uint32_t bit = 1u << (q & 31);
                 if (atomicOr(&vis[q >> 5], bit) & bit) continue;
-                queue[atomicAdd(&sh_tail, 1)] = (uint16_t)q;
+                queue[atomicAdd(tailp, 1)] = (uint16_t)q;
             }
         }
         head = tail;
-        __syncthreads();
+        wave_sync();
     }
     // flip the island in both replicas
-    const int size = sh_tail;
-    for (int idx = t; idx < size; idx += bd) {
+    const int size = *reinterpret_cast<volatile int *>(tailp);
+    for (int idx = lane; idx < size; idx += 64) {
         const int p = I.pos[queue[idx]];
         A[p] ^= 1u;
         B[p] ^= 1u;
@@ -190,7 +184,11 @@ hipError_t icm_kernels_init()
 
 void launch_icm(const Inst *insts, const Work *work, int nwork, int N, int round, hipStream_t st)
 {
-    if (nwork) k_icm<<<nwork, 256, icm_lds_bytes(N), st>>>(insts, work, round);
+    if (!nwork) return;
+    // one wave per pair, up to four pairs per workgroup within the LDS limit
+    const int pb = icm_pair_bytes(N);
+    const int ppw = std::max(1, std::min(4, kMaxSweepLds / pb));
+    k_icm<<<(nwork + ppw - 1) / ppw, 64 * ppw, (size_t)ppw * pb, st>>>(insts, work, nwork, round, pb);
 }
 
 }  // namespace pamc
