@@ -321,7 +321,7 @@ def schedule_bench(name, kind):
             "final_S_f": round(float(obs["S_f"][-1]), 4), "peak_R": int(np.max(obs["R"]))}
 
 
-def rho_f_bench(L=8, R=20000, n_temps=201, runs=16, icm_rounds=0):
+def rho_f_bench(L=8, R=20000, n_temps=201, runs=128, icm_rounds=0, icm_beta_min=0.0):
     """rho_f = R var(beta F) from independent runs of one instance (Eq. (4)),
     annealed together as one batch (with cluster moves when icm_rounds > 0)."""
     import torch
@@ -333,10 +333,10 @@ def rho_f_bench(L=8, R=20000, n_temps=201, runs=16, icm_rounds=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = free_energy_variance(L, J, R, beta, 10, [7000 + i for i in range(runs)], autotune=True,
-                               icm_rounds=icm_rounds)
+                               icm_rounds=icm_rounds, icm_beta_min=icm_beta_min)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return {"L": L, "R": R, "n_temps": n_temps, "runs": runs, "icm_rounds": icm_rounds,
+    return {"L": L, "R": R, "n_temps": n_temps, "runs": runs, "icm_rounds": icm_rounds, "icm_beta_min": icm_beta_min,
             "rho_f_final": round(float(res["rho_f"][-1]), 4), "rho_f_max": round(float(np.max(res["rho_f"])), 4),
             "seconds": round(t1 - t0, 3)}
 
@@ -534,6 +534,8 @@ def main():
         extra["rho_f"] = rho_f_bench()
         extra[f"{args.workload}_icm"] = icm_bench(args.workload)
         extra["rho_f_icm"] = rho_f_bench(icm_rounds=2)
+        # only below T = 1, around and below the spin-glass transition
+        extra["rho_f_icm_low_T"] = rho_f_bench(icm_rounds=2, icm_beta_min=1.0)
         log("rho_f and cluster moves done")
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)

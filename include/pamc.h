@@ -127,6 +127,10 @@ typedef struct pamc_options {
                                 Needs PAMC_SPINS_INT8.  Family ids stay with
                                 their rows, so S_f and rho_s no longer
                                 measure equilibration (use rho_f)          */
+    double icm_beta_min;     /* cluster moves only at steps with beta_k >=
+                                icm_beta_min (the paper restricts them to a
+                                low-temperature window in 3D); 0 = every
+                                step after a resampling                     */
 } pamc_options;
 
 /* Fills *opt with the defaults described above. */

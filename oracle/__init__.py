@@ -78,7 +78,7 @@ def lib() -> ctypes.CDLL:
         L.orc_exp_f32.argtypes = [ctypes.c_float]
         L.orc_real_accept.argtypes = [ctypes.c_float, i64, ctypes.c_uint32]
         L.enum_energies_real.argtypes = [i32, P, P]
-        L.orc_set_icm.argtypes = [P, i32]
+        L.orc_set_icm.argtypes = [P, i32, dbl]
         L.orc_icm_perm.restype = ctypes.c_uint32
         L.orc_icm_perm.argtypes = [u64, ctypes.c_uint32, ctypes.c_uint32, i32, i32]
         L.orc_icm_pair.argtypes = [P, P, P, ctypes.c_uint32, i32, i32]
@@ -158,7 +158,7 @@ class Oracle:
     int32 [3][L^3] of fixed-point real couplings (J = j 2^-20, |J| < 8)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
-                 threads=1, pop_schedule=None, icm_rounds=0):
+                 threads=1, pop_schedule=None, icm_rounds=0, icm_beta_min=0.0):
         self.L = int(L)
         self.N = self.L ** 3
         self.R = int(R)
@@ -189,7 +189,7 @@ class Oracle:
             raise ValueError("oracle: invalid arguments")
         self._h = ctypes.c_void_p(h)
         lib().orc_set_threads(self._h, int(threads))
-        lib().orc_set_icm(self._h, int(icm_rounds))
+        lib().orc_set_icm(self._h, int(icm_rounds), ctypes.c_double(icm_beta_min))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -57,8 +57,10 @@
  *   network on 2h-bit words whose round function is Philox, cycle-walked
  *   into [0, R_k)); the island is the one containing a uniformly drawn site
  *   of the smaller sector (ties: the sector where the replicas differ; an
- *   empty sector is no move); ICM at every step k >= 1, after
- *   floor(N_S/2) sweeps; family ids stay with their rows.
+ *   empty sector is no move); ICM at every step k >= 1 (optionally only
+ *   where beta_k >= a given minimum, the low-temperature window in which
+ *   the paper finds the moves efficient in 3D), after floor(N_S/2) sweeps;
+ *   family ids stay with their rows.
  *
  * Spins are stored as int8 +-1, replica-major, sites in lexicographic order
  * s = x + L (y + L z).
@@ -153,6 +155,7 @@ typedef struct {
     uint8_t *ovl;   /* [nT]: measure the overlap at this step             */
     int nthreads;
     int icm_rounds;  /* ICM rounds of disjoint pairs per step (0: none)   */
+    double icm_beta_min; /* ICM only at steps with beta_k >= this        */
     /* per-step records */
     int64_t *o_R, *o_sumE;
     __int128 *o_sumE2;
@@ -590,7 +593,11 @@ static int icm_step(orc_t *o)
     return ORC_OK;
 }
 
-void orc_set_icm(orc_t *o, int rounds) { o->icm_rounds = rounds < 0 ? 0 : rounds; }
+void orc_set_icm(orc_t *o, int rounds, double beta_min)
+{
+    o->icm_rounds = rounds < 0 ? 0 : rounds;
+    o->icm_beta_min = beta_min;
+}
 
 /* Pairwise summation tree over n leaves (n a power of two): level by level,
  * node i of the next level is left child 2i plus right child 2i+1. */
@@ -846,7 +853,7 @@ int orc_run(orc_t *o, int n_steps)
         orc_thresholds(o->beta[o->k], T, &all);
         /* with ICM (steps after a resampling): N_S/2 sweeps, the cluster
          * updates, the remaining sweeps */
-        const int icm = o->icm_rounds > 0 && o->k >= 1;
+        const int icm = o->icm_rounds > 0 && o->k >= 1 && o->beta[o->k] >= o->icm_beta_min;
         const int t_mid = icm ? o->NS / 2 : o->NS;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(o->nthreads)

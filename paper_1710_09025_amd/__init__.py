@@ -117,7 +117,8 @@ def _torch_available() -> bool:
 
 def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
                   torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0,
-                  graphs=True, group_replicas=0, autotune=False, pop_schedule=None, icm_rounds=0):
+                  graphs=True, group_replicas=0, autotune=False, pop_schedule=None, icm_rounds=0,
+                  icm_beta_min=0.0):
     lib = _capi.load()
     opt = _capi.Options()
     lib.pamc_default_options(ctypes.byref(opt))
@@ -131,6 +132,7 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     opt.autotune = 1 if autotune else 0
     opt.graphs = 1 if graphs else 0
     opt.icm_rounds = int(icm_rounds)
+    opt.icm_beta_min = float(icm_beta_min)
     if pop_schedule is not None:
         pop = np.ascontiguousarray(pop_schedule, dtype=np.int64)
         keep.append(pop)
@@ -161,7 +163,7 @@ def autotune(L, R, sweeps, torch_stream=True, packed=False, real=False):
 
 
 def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None, packed=False, autotune=False,
-                         icm_rounds=0):
+                         icm_rounds=0, icm_beta_min=0.0):
     """rho_f = R var(beta F) (Sec. II.B, Eq. (4)) from independent runs of one
     instance: the runs (one per seed, at least two; the paper asks for ten or
     more) are annealed together as one batch, and per temperature step the
@@ -174,7 +176,7 @@ def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None
     beta = np.ascontiguousarray(beta, dtype=np.float64)
     inst = [dict(L=L, couplings=couplings, R=R, beta=beta, sweeps=sweeps, seed=sd, pop_schedule=pop_schedule)
             for sd in seeds]
-    b = PamcBatch(inst, packed=packed, autotune=autotune, icm_rounds=icm_rounds)
+    b = PamcBatch(inst, packed=packed, autotune=autotune, icm_rounds=icm_rounds, icm_beta_min=icm_beta_min)
     try:
         st = b.anneal()
         if st != _capi.OK:
@@ -193,7 +195,8 @@ class Pamc:
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
-                 graphs=True, group_replicas=0, autotune=False, packed=False, pop_schedule=None, icm_rounds=0):
+                 graphs=True, group_replicas=0, autotune=False, packed=False, pop_schedule=None, icm_rounds=0,
+                 icm_beta_min=0.0):
         lib = _capi.load()
         self.L = int(L)
         self.N = self.L ** 3
@@ -206,7 +209,8 @@ class Pamc:
                             spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
                             tile_rows=tile_rows, graphs=graphs, group_replicas=group_replicas,
-                            autotune=autotune, pop_schedule=pop_schedule, icm_rounds=icm_rounds)
+                            autotune=autotune, pop_schedule=pop_schedule, icm_rounds=icm_rounds,
+                            icm_beta_min=icm_beta_min)
         self._opt = opt
         h = ctypes.c_void_p()
         create = lib.pamc_create_real if self.real else lib.pamc_create
@@ -320,7 +324,7 @@ class PamcBatch:
     """Many independent instances annealed together (``pamc_batch_*``)."""
 
     def __init__(self, instances, fuse_gather=True, torch_stream=True, graphs=True, autotune=False, packed=False,
-                 icm_rounds=0):
+                 icm_rounds=0, icm_beta_min=0.0):
         lib = _capi.load()
         self._keep = []
         n = len(instances)
@@ -346,7 +350,7 @@ class PamcBatch:
             self.real.append(real)
         opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs,
                             autotune=autotune, spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8,
-                            icm_rounds=icm_rounds)
+                            icm_rounds=icm_rounds, icm_beta_min=icm_beta_min)
         h = ctypes.c_void_p()
         _check(lib.pamc_batch_create(n, arr, ctypes.byref(opt), ctypes.byref(h)), "pamc_batch_create")
         self._h = h

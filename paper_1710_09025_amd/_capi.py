@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("pop_schedule", ctypes.POINTER(ctypes.c_int64)),
         ("real_couplings", ctypes.c_int),
         ("icm_rounds", ctypes.c_int),
+        ("icm_beta_min", ctypes.c_double),
     ]
 
 

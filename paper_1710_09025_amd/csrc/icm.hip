@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     const Work w = work[item];
     const Inst &I = insts[w.inst];
     const int k = *I.k;
-    if (!inst_live(I, k) || k == 0 || round >= I.icm) return;
+    if (!inst_live(I, k) || k == 0 || round >= I.icm || !(I.beta[k] >= I.icm_bmin)) return;
     const uint32_t n = I.Rk[k];
     const uint32_t j = w.row0;
     if (j >= n / 2) return;

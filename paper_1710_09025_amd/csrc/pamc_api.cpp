@@ -87,6 +87,7 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
     if (opt.spin_format != PAMC_SPINS_INT8 && opt.spin_format != PAMC_SPINS_PACKED)
         return invalid("unknown spin format");
     if (opt.icm_rounds < 0 || opt.icm_rounds > 8) return invalid("icm_rounds must be in [0, 8]");
+    if (!std::isfinite(opt.icm_beta_min)) return invalid("icm_beta_min must be finite");
     if (opt.icm_rounds > 0 && opt.spin_format == PAMC_SPINS_PACKED)
         return invalid("cluster moves need int8 spin storage");
     if (real && (__int128)absJ * cap >= ((__int128)1 << 62))
@@ -115,6 +116,7 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
         for (int k = 0; k < nT; ++k) h.pop[(size_t)k] = (double)opt.pop_schedule[k];
     h.real = real ? 1 : 0;
     h.icm = opt.icm_rounds;
+    h.icm_bmin = opt.icm_beta_min;
     if (real)
         h.Jq.assign(Jq, Jq + 3 * N);
     else

@@ -80,6 +80,7 @@ struct Inst {
     int32_t ovl_n;      // number of overlap steps
     int32_t real;       // 1: real couplings in fixed point, J = j 2^-20 (int32 j, |J| < 8)
     int32_t icm;        // cluster-move rounds per step (0: none)
+    double icm_bmin;    // cluster moves only at steps with beta_k >= icm_bmin
     // double-buffered population
     uint8_t *spins[2];
     int32_t *E[2];

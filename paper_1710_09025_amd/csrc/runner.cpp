@@ -380,6 +380,7 @@ int Runner::upload_inst(int i)
     d.sync = (uint32_t *)(b + lay.sync);
     d.real = h.real;
     d.icm = h.icm;
+    d.icm_bmin = h.icm_bmin;
     d.Eq[0] = (int64_t *)(b + lay.Eq0);
     d.Eq[1] = (int64_t *)(b + lay.Eq1);
     d.wrep = (double *)(b + lay.wrep);

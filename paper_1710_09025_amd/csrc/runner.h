@@ -25,6 +25,7 @@ struct HostInst {
     int packed = 0;                    // spins stored one bit per position
     int real = 0;                      // real couplings in fixed point (Jq)
     int icm = 0;                       // cluster-move rounds per step
+    double icm_bmin = 0.0;             // ... at steps with beta_k >= icm_bmin
     int srow_bytes = 0;                // bytes per stored spin row
     int tpr = 0;                       // colour-major sweep: threads per replica
     int rp = 0;                        // colour-major sweep: replica quads per workgroup

@@ -52,6 +52,21 @@ def test_full_run_with_cluster_moves_bit_exact(L, R, nT, NS, bmax, real):
     compare_run(p.observables(), p.step_sums(), o, what=f"icm L={L}")
 
 
+@pytest.mark.parametrize("bmin", [1.7, 10.0])
+def test_temperature_window_bit_exact(bmin):
+    from paper_1710_09025_amd import Pamc
+
+    inst = make(6, 400, 13, 4, 4.0, 33, 34)
+    p = Pamc(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"], icm_rounds=2,
+             icm_beta_min=bmin)
+    assert p.anneal() == 0
+    o = oracle.Oracle(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"],
+                      threads=THREADS, icm_rounds=2, icm_beta_min=bmin)
+    assert o.run() == 0
+    compare_state(p.get_state(), o.get_state(), f"icm window {bmin}")
+    compare_run(p.observables(), p.step_sums(), o, what=f"icm window {bmin}")
+
+
 def test_one_round_and_eight_rounds():
     for rounds in (1, 8):
         inst = make(4, 300, 9, 4, 4.0, 31, 32)

@@ -149,7 +149,7 @@ def test_invalid_real_couplings_are_rejected_on_the_host(lib, case):
     assert not h.value
 
 
-@pytest.mark.parametrize("case", ["packed", "rounds"])
+@pytest.mark.parametrize("case", ["packed", "rounds", "window"])
 def test_invalid_cluster_move_options_are_rejected_on_the_host(lib, case):
     from paper_1710_09025_amd import _capi
 
@@ -161,8 +161,11 @@ def test_invalid_cluster_move_options_are_rejected_on_the_host(lib, case):
     if case == "packed":
         opt.icm_rounds = 2
         opt.spin_format = _capi.SPINS_PACKED
-    else:
+    elif case == "rounds":
         opt.icm_rounds = 9
+    else:
+        opt.icm_rounds = 2
+        opt.icm_beta_min = float("nan")
     h = ctypes.c_void_p()
     st = lib.pamc_create(L, J.ctypes.data_as(ctypes.c_void_p), 100, beta.ctypes.data_as(ctypes.c_void_p),
                          len(beta), 2, 1, ctypes.byref(opt), ctypes.byref(h))

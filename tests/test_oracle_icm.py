@@ -167,3 +167,23 @@ def test_planted_wrong_island_choice_breaks_boltzmann():
     counts = np.bincount(bad, minlength=2 ** N).astype(np.float64)
     G, dof = _gtest_pooled(counts, p)
     assert G > dof + 10 * math.sqrt(2 * dof) + 20
+
+
+def test_temperature_window():
+    """icm_beta_min above every beta gives the run without cluster moves;
+    a window starting mid-anneal agrees with it up to the window's start."""
+    L = 4
+    J = pi.pm_j_couplings(L, 23)
+    beta = pi.linear_beta(3.0, 13)
+    plain = oracle.Oracle(L, J, 200, beta, 4, 9)
+    none = oracle.Oracle(L, J, 200, beta, 4, 9, icm_rounds=2, icm_beta_min=10.0)
+    late = oracle.Oracle(L, J, 200, beta, 4, 9, icm_rounds=2, icm_beta_min=1.5)
+    k_start = int(np.argmax(beta >= 1.5))
+    for k in range(len(beta)):
+        for o in (plain, none, late):
+            assert o.run(1) == 0
+        sp = plain.get_state()["spins"]
+        np.testing.assert_array_equal(none.get_state()["spins"], sp)
+        if k < k_start:
+            np.testing.assert_array_equal(late.get_state()["spins"], sp)
+    assert not np.array_equal(late.get_state()["spins"], plain.get_state()["spins"])
