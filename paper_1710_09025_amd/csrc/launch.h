@@ -25,6 +25,13 @@ constexpr int kMaxSweepLds = 160 * 1024 - 12 * 1024;
 // LDS (above the 64 KB default); returns the HIP status.
 hipError_t sweep_kernels_init();
 
+// LDS stride of the byte planes of a colour-major replica quad: rows of at
+// most 64 bytes keep their length (their four planes fall in disjoint LDS
+// banks); longer ones are padded to a multiple of 256 bytes, so that every
+// plane starts at bank 0 and the lanes of a wave reading consecutive words
+// of any planes never collide.
+inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : (row_bytes + 255) & ~255; }
+
 // default number of replica quads a colour-major workgroup sweeps at once
 // (tpr threads per quad)
 int cm_replicas_per_block(int tpr);

@@ -83,7 +83,8 @@ LayoutInfo layout_for(int L, bool real)
         tpr = (li.gmax + 63) / 64 * 64;
     }
     if (real) {
-        if (tpr <= 1024 && 2 * rb <= 65535 && 4 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 8 * 64 <= kMaxSweepLds) {
+        if (tpr <= 1024 && 2 * rb <= 65535 &&
+            4 * (size_t)cm_plane_bytes(rb) * cm_replicas_per_block(tpr) + 32 + 8 * 64 <= kMaxSweepLds) {
             li.layout = kLayoutCM;
             li.variant = li.ncol == 2 ? kSweepCQ2 : kSweepCQ3;
             li.row_bytes = rb;
@@ -94,7 +95,8 @@ LayoutInfo layout_for(int L, bool real)
         }
         return li;
     }
-    if (tpr <= 1024 && 2 * rb <= 65535 && 8 * (size_t)rb * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= kMaxSweepLds) {
+    if (tpr <= 1024 && 2 * rb <= 65535 &&
+        8 * (size_t)cm_plane_bytes(rb) * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= kMaxSweepLds) {
         li.layout = kLayoutCM;
         li.variant = li.ncol == 2 ? kSweepCM2 : kSweepCM3;
         li.row_bytes = rb;
@@ -440,6 +442,7 @@ int Runner::upload_inst(int i)
     const LayoutInfo li = layout_for(L, h.real != 0);
     for (int c = 0; c < 3; ++c) d.cbase[c] = li.cbase[c];
     d.tpr = li.tpr;
+    d.plane_bytes = cm_plane_bytes(h.row_bytes);
     // storage position of each site
     h.lex_pos.resize(N);
     std::vector<uint16_t> pos16((size_t)N);

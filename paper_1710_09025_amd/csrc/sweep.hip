@@ -607,7 +607,7 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
 //
 // A thread group sweeps four replicas A, B, C, D at once from one LDS slot
 // in which the byte lanes of a word are the replicas: storage position p of
-// the four is the word [A B C D] at plane(p) row_bytes + 4 (p >> 2), with
+// the four is the word [A B C D] at plane(p) plane_bytes + 4 (p >> 2), with
 // plane(p) = p & 3 (threads of neighbouring Philox blocks read neighbouring
 // words), followed by the same four planes of the complement (0/1 swapped).
 // A bond with coupling -1 reads the neighbour from the complement, so one
@@ -633,17 +633,17 @@ __device__ __forceinline__ void replica_barrier(int tpr)
 
 struct CMBlock {
     uint32_t nb[24];  // LDS offsets of the neighbour words, [direction][site]
-    uint32_t own;     // LDS offset of site 0's word (site i at + i row_bytes)
+    uint32_t own;     // LDS offset of site 0's word (site i at + i plane_bytes)
     uint32_t vbits;   // bit i set when site i of the block is a real site
     uint32_t ctr;     // Philox counter word 0
     bool has;
 };
 
 // Byte offset, in a replica-quad slot, of storage position p (p < row_bytes;
-// the complement's positions follow at 4 row_bytes).
-__device__ __forceinline__ uint32_t quad_pos(uint32_t p, uint32_t row_bytes)
+// the complement's positions follow at 4 plane_bytes).
+__device__ __forceinline__ uint32_t quad_pos(uint32_t p, uint32_t plane_bytes)
 {
-    return (p & 3u) * row_bytes + 4u * (p >> 2);
+    return (p & 3u) * plane_bytes + 4u * (p >> 2);
 }
 
 // 4 x 4 byte transpose: word k of the result holds byte k of w0, w1, w2, w3
@@ -686,10 +686,10 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 {
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
-    const int row_bytes = I.row_bytes;
+    const int ps = I.plane_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * 8 * row_bytes;
-    const int nvec = row_bytes >> 4;
+    uint8_t *slot = lds + qsub * 8 * ps;
+    const int nvec = I.row_bytes >> 4, pvec = ps >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
     for (int qb = 0; qb < nrows; qb += 4 * RPG) {
         const int q0 = qb + 4 * qsub;
@@ -717,8 +717,8 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl) {
                     const uint4 w = make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]);
-                    sp[pl * nvec + i] = w;
-                    sp[(4 + pl) * nvec + i] =
+                    sp[pl * pvec + i] = w;
+                    sp[(4 + pl) * pvec + i] =
                         make_uint4(w.x ^ 0x01010101u, w.y ^ 0x01010101u, w.z ^ 0x01010101u, w.w ^ 0x01010101u);
                 }
             }
@@ -733,7 +733,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                     uint32_t own[4], flip[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        own[i] = lds_word(lds, b.own + i * row_bytes);
+                        own[i] = lds_word(lds, b.own + i * ps);
                         flip[i] = ((b.vbits >> i) & 1u) * 0x01010101u;
                     }
                     if constexpr (!ALL) {
@@ -756,8 +756,8 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const uint32_t nw = own[i] ^ flip[i];
-                        *reinterpret_cast<uint32_t *>(lds + b.own + i * row_bytes) = nw;
-                        *reinterpret_cast<uint32_t *>(lds + b.own + (4 + i) * row_bytes) = nw ^ 0x01010101u;
+                        *reinterpret_cast<uint32_t *>(lds + b.own + i * ps) = nw;
+                        *reinterpret_cast<uint32_t *>(lds + b.own + (4 + i) * ps) = nw ^ 0x01010101u;
                     }
                 }
                 replica_barrier(tpr);
@@ -777,7 +777,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                                         lds_word(lds, blk[c].nb[8 + i])) +
                                        (lds_word(lds, blk[c].nb[12 + i]) + lds_word(lds, blk[c].nb[16 + i]) +
                                         lds_word(lds, blk[c].nb[20 + i]));
-                    acc += unsat_from_sum(m, lds_word(lds, blk[c].own + i * row_bytes));
+                    acc += unsat_from_sum(m, lds_word(lds, blk[c].own + i * ps));
                 }
             }
 #pragma unroll
@@ -789,7 +789,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
             for (int i = lane_r; i < nvec; i += tpr) {
                 uint4 w[4];
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) w[pl] = sp[pl * nvec + i];
+                for (int pl = 0; pl < 4; ++pl) w[pl] = sp[pl * pvec + i];
                 uint32_t ox[4], oy[4], oz[4], ow[4];
                 transpose4(w[0].x, w[1].x, w[2].x, w[3].x, ox);
                 transpose4(w[0].y, w[1].y, w[2].y, w[3].y, oy);
@@ -814,12 +814,12 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
-    const int slot_bytes = 8 * row_bytes;
+    const int slot_bytes = 8 * I.plane_bytes;
     int *unsat = reinterpret_cast<int *>(lds + RPG * slot_bytes + 32);
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
     const uint32_t slot = (uint32_t)(qsub * slot_bytes);
-    const uint32_t rb = (uint32_t)row_bytes;
+    const uint32_t rb = (uint32_t)row_bytes, ps = (uint32_t)I.plane_bytes;
     CMBlock blk[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) {
@@ -833,7 +833,7 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
 #pragma unroll
         for (int i = 0; i < 24; ++i) {
             const uint32_t o = d[i];
-            blk[c].nb[i] = slot + (o < rb ? quad_pos(o, rb) : 4u * rb + quad_pos(o - rb, rb));
+            blk[c].nb[i] = slot + (o < rb ? quad_pos(o, ps) : 4u * ps + quad_pos(o - rb, ps));
         }
         const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
         blk[c].vbits = (vm & 1u) | ((vm >> 7) & 2u) | ((vm >> 14) & 4u) | ((vm >> 21) & 8u);
@@ -900,7 +900,7 @@ struct CQBlock {
     uint32_t nb[24];  // LDS offsets of the neighbour words, [direction][site]
     int32_t j[24];    // coupling of each of those bonds (units of 2^-20)
     int32_t j2[4];    // twice the sum of the six couplings of each site
-    uint32_t own;     // LDS offset of site 0's word (site i at + i row_bytes)
+    uint32_t own;     // LDS offset of site 0's word (site i at + i plane_bytes)
     uint32_t vbits;   // bit i set when site i of the block is a real site
     uint32_t ctr;     // Philox counter word 0
     bool has;
@@ -937,10 +937,10 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
 {
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
-    const int row_bytes = I.row_bytes;
+    const int ps = I.plane_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * 4 * row_bytes;
-    const int nvec = row_bytes >> 4;
+    uint8_t *slot = lds + qsub * 4 * ps;
+    const int nvec = I.row_bytes >> 4, pvec = ps >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
     for (int qb = 0; qb < nrows; qb += 4 * RPG) {
         const int q0 = qb + 4 * qsub;
@@ -964,7 +964,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
                 transpose4(v[0].z, v[1].z, v[2].z, v[3].z, oz);
                 transpose4(v[0].w, v[1].w, v[2].w, v[3].w, ow);
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) sp[pl * nvec + i] = spin_ff4(make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]));
+                for (int pl = 0; pl < 4; ++pl) sp[pl * pvec + i] = spin_ff4(make_uint4(ox[pl], oy[pl], oz[pl], ow[pl]));
             }
         }
         replica_barrier(tpr);
@@ -977,7 +977,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
                     uint32_t own[4], flip[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        own[i] = lds_word(lds, b.own + i * row_bytes);
+                        own[i] = lds_word(lds, b.own + i * ps);
                         flip[i] = (b.vbits >> i) & 1u ? 0xFFFFFFFFu : 0u;
                     }
                     if constexpr (!ALL) {
@@ -1001,7 +1001,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
                     }
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        *reinterpret_cast<uint32_t *>(lds + b.own + i * row_bytes) = own[i] ^ flip[i];
+                        *reinterpret_cast<uint32_t *>(lds + b.own + i * ps) = own[i] ^ flip[i];
                 }
                 replica_barrier(tpr);
             }
@@ -1016,7 +1016,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     int32_t a[4];
-                    cq_field(lds, blk[c], i, lds_word(lds, blk[c].own + i * row_bytes), a);
+                    cq_field(lds, blk[c], i, lds_word(lds, blk[c].own + i * ps), a);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) e[r] += a[r];
                 }
@@ -1030,7 +1030,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
             for (int i = lane_r; i < nvec; i += tpr) {
                 uint4 w[4];
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) w[pl] = spin_01(sp[pl * nvec + i]);
+                for (int pl = 0; pl < 4; ++pl) w[pl] = spin_01(sp[pl * pvec + i]);
                 uint32_t ox[4], oy[4], oz[4], ow[4];
                 transpose4(w[0].x, w[1].x, w[2].x, w[3].x, ox);
                 transpose4(w[0].y, w[1].y, w[2].y, w[3].y, oy);
@@ -1112,12 +1112,11 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
 {
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
-    const int row_bytes = I.row_bytes;
-    unsigned long long *eacc = reinterpret_cast<unsigned long long *>(lds + RPG * 4 * row_bytes + 32);
+    const int ps = I.plane_bytes;
+    unsigned long long *eacc = reinterpret_cast<unsigned long long *>(lds + RPG * 4 * ps + 32);
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    const uint32_t slot = (uint32_t)(qsub * 4 * row_bytes);
-    const uint32_t rb = (uint32_t)row_bytes;
+    const uint32_t slot = (uint32_t)(qsub * 4 * ps);
     CQBlock blk[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) {
@@ -1129,7 +1128,7 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
         const int32_t *jd = I.cmj + ((size_t)c * I.gmax + gg) * 24;
 #pragma unroll
         for (int i = 0; i < 24; ++i) {
-            blk[c].nb[i] = slot + quad_pos((uint32_t)d[i], rb);
+            blk[c].nb[i] = slot + quad_pos((uint32_t)d[i], (uint32_t)ps);
             blk[c].j[i] = jd[i];
         }
 #pragma unroll
@@ -1265,7 +1264,7 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
         // rp replica quads, each four planes of the row and of the complement
-        const size_t lds = 8 * (size_t)row_bytes * rp + 32 + 4 * (size_t)tile_rows;
+        const size_t lds = 8 * (size_t)cm_plane_bytes(row_bytes) * rp + 32 + 4 * (size_t)tile_rows;
         const int nt = tpr * rp;
         if (variant == kSweepCM2) {
             if (nt <= 512)
@@ -1282,7 +1281,7 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     }
     if (variant == kSweepCQ2 || variant == kSweepCQ3) {
         // rp replica quads of four planes, and a 64-bit energy per tile row
-        const size_t lds = 4 * (size_t)row_bytes * rp + 32 + 8 * (size_t)tile_rows;
+        const size_t lds = 4 * (size_t)cm_plane_bytes(row_bytes) * rp + 32 + 8 * (size_t)tile_rows;
         const int nt = tpr * rp;
         if (variant == kSweepCQ2) {
             if (nt <= 512)

@@ -44,8 +44,8 @@ bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kS
 
 int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
 {
-    if (is_cq(h)) return 4 * (int64_t)h.row_bytes * rp + 32 + 8 * (int64_t)tile_rows;
-    if (is_cm(h)) return 8 * (int64_t)h.row_bytes * rp + 32 + 4 * (int64_t)tile_rows;
+    if (is_cq(h)) return 4 * (int64_t)cm_plane_bytes(h.row_bytes) * rp + 32 + 8 * (int64_t)tile_rows;
+    if (is_cm(h)) return 8 * (int64_t)cm_plane_bytes(h.row_bytes) * rp + 32 + 4 * (int64_t)tile_rows;
     return (int64_t)tile_rows * h.row_bytes + 32 + 4 * (int64_t)tile_rows;
 }
 
