@@ -22,7 +22,7 @@ enum SweepVariant {
 // measurement's reduction trees).
 constexpr int kMaxSweepLds = 160 * 1024 - 12 * 1024;
 // Lets every sweep kernel launch with up to kMaxSweepLds bytes of dynamic
-// LDS (above the 64 KB default); returns the HIP status.
+// LDS (above the default of 64 KB); returns the HIP status.
 hipError_t sweep_kernels_init();
 
 // LDS stride of the byte planes of a colour-major replica quad: rows of at
