@@ -38,7 +38,7 @@ enum Layout : int32_t {
 };
 
 constexpr int kRowsPerBlock = 1024;  // rows handled per block by row kernels
-constexpr int kOvlPairs = 256;       // replica pairs per overlap workgroup
+constexpr int kOvlPairs = 2048;      // replica pairs per overlap workgroup (few workgroups: most steps measure no overlap)
 constexpr int kOvlLdsBins = 8194;    // overlap histograms up to this many bins (L <= 16) are built in LDS
 
 // Per-step integer record written on the device.  Energies are in units of

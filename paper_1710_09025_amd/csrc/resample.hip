@@ -7,7 +7,7 @@
 //   copies    n_r = floor(tau) + [u_r < frac(tau) 2^32] for 1024 rows, with
 //             their exclusive scan inside the workgroup;
 //   families  n ln n of 2048 family ids, summed by the pairwise tree;
-//   overlap   spin overlaps of 256 replica pairs (at overlap steps).
+//   overlap   spin overlaps of 2048 replica pairs (at overlap steps).
 // The last workgroup of an instance to finish scans the per-workgroup
 // totals into offsets, sets R_{k+1} and the capacity / extinction status,
 // folds the family partial sums, and advances the step.  An expand launch
