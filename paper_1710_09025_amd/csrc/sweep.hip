@@ -1174,57 +1174,6 @@ __global__ __launch_bounds__(MAXT, 2) void k_sweep_cq(const Inst *insts, const W
 }
 
 // ---------------------------------------------------------------------------
-// Stand-alone gather of surviving replicas: destination row d of the other
-// buffer receives source row map[d] (spins, energy, family).  Used when the
-// gather is not fused into the next sweep and to materialise a population
-// for export.  Runs after the step index has moved to the new population.
-// A work item is a block of w.pad destination rows (about 32 KB of spins);
-// each thread keeps four 16-byte loads in flight before its stores.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather(const Inst *insts, const Work *work)
-{
-    const Work w = work[blockIdx.x];
-    const Inst &I = inst_ref(insts, w.inst);
-    const int k = *I.k;
-    if (k >= I.nT || I.status[0] || !*I.mapped) return;
-    const int Rn = (int)I.Rk[k];
-    const int row0 = (int)w.row0;
-    const int rows = min((int)w.pad, Rn - row0);
-    if (rows <= 0) return;
-    const int cur = *I.cur;
-    const int per_row = I.srow_bytes >> 4;
-    const int total = rows * per_row;
-    const uint4 *src = reinterpret_cast<const uint4 *>(I.spins[cur]);
-    uint4 *dst = reinterpret_cast<uint4 *>(I.spins[cur ^ 1]);
-    const int nt = (int)blockDim.x;
-    for (int base = threadIdx.x; base < total; base += 4 * nt) {
-        uint4 v[4];
-        size_t to[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int it = base + u * nt;
-            if (it < total) {
-                const int q = it / per_row, c = it - q * per_row;
-                const uint32_t d = (uint32_t)(row0 + q);
-                v[u] = src[(size_t)I.map[d] * per_row + c];
-                to[u] = (size_t)d * per_row + c;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (base + u * nt < total) dst[to[u]] = v[u];
-    }
-    for (int q = threadIdx.x; q < rows; q += nt) {
-        const uint32_t d = (uint32_t)(row0 + q), s = I.map[d];
-        if (I.real)
-            I.Eq[cur ^ 1][d] = I.Eq[cur][s];
-        else
-            I.E[cur ^ 1][d] = I.E[cur][s];
-        I.fam[cur ^ 1][d] = I.fam[cur][s];
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t sweep_kernels_init()
@@ -1303,11 +1252,6 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     case kSweepEO16: k_sweep_eo<16><<<nwork, 256, lds, st>>>(insts, work, tile_rows, phase); break;
     default: break;
     }
-}
-
-void launch_gather(const Inst *insts, const Work *work, int nwork, hipStream_t st)
-{
-    if (nwork) k_gather<<<nwork, 256, 0, st>>>(insts, work);
 }
 
 }  // namespace pamc
