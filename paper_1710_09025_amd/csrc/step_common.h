@@ -189,18 +189,22 @@ __device__ __forceinline__ void count_wave(uint32_t *arr, uint32_t idx, bool val
 
 // Called by every workgroup of an instance at the end of its work in a
 // launch: returns true in exactly one workgroup, the last to finish, after
-// which the writes of all the others are visible to it.
+// which the writes of all the others are visible to it.  Each workgroup
+// releases its writes (device scope: an L2 write-back, the L2s of the XCDs
+// not being coherent) before it counts itself in; only the last one
+// acquires (an L2 invalidate).  A full fence in every workgroup would also
+// invalidate the L2 under all the workgroups still running.
 __device__ __forceinline__ bool last_workgroup(uint32_t *counter, int expected)
 {
     __shared__ int is_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         is_last = atomicAdd(counter, 1u) == (uint32_t)(expected - 1);
     }
     __syncthreads();
     if (!is_last) return false;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (threadIdx.x == 0) *counter = 0u;
     return true;
 }
