@@ -47,13 +47,6 @@ __device__ uint32_t icm_perm(uint32_t key0, uint32_t key1, uint32_t i, uint32_t 
     return x;
 }
 
-// LDS of one pair: the sector flag of every lexicographic site (bytes), the
-// visited bits, the island queue (site indices, N <= 32768) and its tail.
-__host__ __device__ inline int icm_pair_bytes(int N)
-{
-    return ((N + 15) & ~15) + 4 * ((N + 31) / 32) + ((2 * N + 15) & ~15) + 16;
-}
-
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

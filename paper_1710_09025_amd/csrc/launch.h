@@ -32,6 +32,12 @@ hipError_t sweep_kernels_init();
 // of any planes never collide.
 inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : (row_bytes + 255) & ~255; }
 
+// LDS of one cluster-move pair (the island search of one wave): the sector
+// flag of every lexicographic site (bytes), the visited bits, the island
+// queue (16-bit site indices) and its tail, each part 16-byte aligned.  It
+// must fit in kMaxSweepLds, which holds for L <= 36.
+inline int icm_pair_bytes(int N) { return ((N + 15) & ~15) + 4 * ((N + 31) / 32) + ((2 * N + 15) & ~15) + 16; }
+
 // default number of replica quads a colour-major workgroup sweeps at once
 // (tpr threads per quad)
 int cm_replicas_per_block(int tpr);
