@@ -124,9 +124,7 @@ typedef struct pamc_options {
                                 remaining sweeps.  An update flips, in both
                                 replicas, the island of the smaller overlap
                                 sector that holds a randomly drawn site.
-                                Needs PAMC_SPINS_INT8 and L <= 36 (the
-                                island search of a pair runs in LDS).
-                                Family ids stay with
+                                Needs PAMC_SPINS_INT8.  Family ids stay with
                                 their rows, so S_f and rho_s no longer
                                 measure equilibration (use rho_f)          */
     double icm_beta_min;     /* cluster moves only at steps with beta_k >=

@@ -90,8 +90,6 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
     if (!std::isfinite(opt.icm_beta_min)) return invalid("icm_beta_min must be finite");
     if (opt.icm_rounds > 0 && opt.spin_format == PAMC_SPINS_PACKED)
         return invalid("cluster moves need int8 spin storage");
-    if (opt.icm_rounds > 0 && pamc::icm_pair_bytes(N) > pamc::kMaxSweepLds)
-        return invalid("cluster moves need L <= 36 (the island search of a pair runs in LDS)");
     if (real && (__int128)absJ * cap >= ((__int128)1 << 62))
         return invalid("capacity times the sum of |couplings| must stay below 2^62");
     // the normaliser's tree folds at most 2^19 roots of 1024-row blocks
