@@ -1,14 +1,15 @@
 /*
- * pamc.h -- population annealing Monte Carlo for 3D Edwards-Anderson spin
- * glasses (+-J or real, e.g. Gaussian, couplings) on AMD Instinct MI355X
- * (gfx950).
+ * pamc.h -- population annealing Monte Carlo for Edwards-Anderson spin
+ * glasses in 3D (+-J or real, e.g. Gaussian, couplings) and 2D (real
+ * couplings) on AMD Instinct MI355X (gfx950).
  *
  * The operation is the one of Barzegar, Pattison, Wang and Katzgraber,
  * "Optimization of population annealing Monte Carlo for large-scale
  * spin-glass simulations" (arXiv:1710.09025):
- *   - Sec. II.A, Eq. (1): H = -sum_<ij> J_ij S_i S_j on the periodic L^3
- *     lattice, N = L^3 Ising spins, couplings J_ij = +-1 (pamc_create) or
- *     real (pamc_create_real: the paper's Gaussian case study, held in fixed
+ *   - Sec. II.A, Eq. (1): H = -sum_<ij> J_ij S_i S_j on the periodic L^D
+ *     lattice, N = L^D Ising spins (D = 3, or D = 2 through
+ *     pamc_options.dim), couplings J_ij = +-1 (pamc_create, D = 3) or real
+ *     (pamc_create_real: the paper's Gaussian case study, held in fixed
  *     point, J = j 2^-20 with int32 j, |J| < 8);
  *   - Sec. II.B: R replicas start at random at beta_0 = 0; at each of the
  *     n_temps inverse temperatures beta_k the library runs `sweeps`
@@ -131,6 +132,16 @@ typedef struct pamc_options {
                                 icm_beta_min (the paper restricts them to a
                                 low-temperature window in 3D); 0 = every
                                 step after a resampling                     */
+    int dim;                 /* lattice dimension D (Sec. II.A studies both):
+                                3 (default; 0 also means 3), or 2 = the
+                                periodic L x L square lattice, site
+                                s = x + L y, four neighbours, couplings
+                                [2][L^2] (d = 0, 1 for x, y).  D = 2 takes
+                                real couplings (pamc_create_real or
+                                pamc_instance.real_couplings; +-J instances
+                                as j = +-2^20) and 2 <= L <= 64.  Read by
+                                pamc_footprint and pamc_autotune too.  The
+                                serving API (pamc_server_*) is 3D only.     */
 } pamc_options;
 
 /* Fills *opt with the defaults described above. */
@@ -172,9 +183,11 @@ int pamc_create(int L, const int8_t *couplings, int64_t R, const double *beta, i
 
 /* The same with real couplings (Sec. II.A: the paper's case study draws them
  * from a Gaussian of mean 0 and variance 1), in fixed point:
- *   couplings  int32 [3][N], J = couplings[d*N + s] * 2^-20 with
- *              |couplings| < 2^23 (|J| < 8), same bond order as pamc_create;
- *   L          even L <= 20 or odd L <= 21 (the colour-major sweep);
+ *   couplings  int32 [D][N], J = couplings[d*N + s] * 2^-20 with
+ *              |couplings| < 2^23 (|J| < 8), same bond order as pamc_create
+ *              (D = opt->dim: [3][L^3], or [2][L^2] on the square lattice);
+ *   L          3D: even L <= 20 or odd L <= 21 (the colour-major sweep);
+ *              2D: 2 <= L <= 64;
  *   capacity   at most 2^29, and times the sum of |couplings| below 2^62.
  * Energies are exact integers in units of 2^-20 (the E_min, E_max, sum_E,
  * sum_E2 fields of pamc_step_obs and pamc_state.E_fixed); mean_E, e, C_V,
@@ -306,8 +319,9 @@ typedef struct pamc_instance {
     uint64_t seed;
     const int64_t *pop_schedule; /* NULL or [n_temps], as in pamc_options */
     const int32_t *real_couplings; /* NULL: couplings (+-1) above; else
-                                 [3][L^3] real couplings as in
-                                 pamc_create_real (couplings is ignored) */
+                                 [D][L^D] real couplings as in
+                                 pamc_create_real (couplings is ignored);
+                                 D is the batch options' dim            */
 } pamc_instance;
 
 typedef struct pamc_batch pamc_batch;

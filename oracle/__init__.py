@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.orc_create.argtypes = [i32, P, i64, i64, P, i32, i32, u64, P, P]
         L.orc_create_real.restype = P
         L.orc_create_real.argtypes = [i32, P, i64, i64, P, i32, i32, u64, P, P]
+        L.orc_create_real_dim.restype = P
+        L.orc_create_real_dim.argtypes = [i32, i32, P, i64, i64, P, i32, i32, u64, P, P]
         L.orc_records_wide.argtypes = [P, P]
         L.orc_get_state64.argtypes = [P, P, P, P]
         L.orc_energies64.argtypes = [P, P, i64, P]
@@ -153,14 +155,27 @@ def thresholds(beta: float):
     return T, bool(flag.value)
 
 
+def lattice_dim(L: int, couplings) -> int:
+    """Dimension of the lattice a coupling array describes: [3][L^3] is the
+    cubic lattice, [2][L^2] the square one."""
+    n = np.asarray(couplings).size
+    if n == 3 * L ** 3:
+        return 3
+    if n == 2 * L ** 2:
+        return 2
+    raise ValueError(f"couplings of size {n} fit neither [3][L^3] nor [2][L^2] for L = {L}")
+
+
 class Oracle:
     """One PAMC run on the CPU.  ``couplings`` is int8 [3][L^3] of +-1, or
-    int32 [3][L^3] of fixed-point real couplings (J = j 2^-20, |J| < 8)."""
+    int32 [D][L^D] of fixed-point real couplings (J = j 2^-20, |J| < 8) on
+    the cubic (D = 3) or square (D = 2) lattice."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  threads=1, pop_schedule=None, icm_rounds=0, icm_beta_min=0.0):
         self.L = int(L)
-        self.N = self.L ** 3
+        self.dim = lattice_dim(self.L, couplings)
+        self.N = self.L ** self.dim
         self.R = int(R)
         self.beta = np.ascontiguousarray(beta, dtype=np.float64)
         self.nT = len(self.beta)
@@ -173,9 +188,17 @@ class Oracle:
         self.capacity = int(capacity) if capacity is not None else default_capacity(peak)
         self.real = np.asarray(couplings).dtype == np.int32
         dt = np.int32 if self.real else np.int8
-        J = np.ascontiguousarray(couplings, dtype=dt).reshape(3, self.N)
+        J = np.ascontiguousarray(couplings, dtype=dt).reshape(self.dim, self.N)
         self._J = J
-        create = lib().orc_create_real if self.real else lib().orc_create
+        if self.real:
+            dim = self.dim
+
+            def create(*args):
+                return lib().orc_create_real_dim(dim, *args)
+        elif self.dim == 3:
+            create = lib().orc_create
+        else:
+            raise ValueError("oracle: 2D lattices take real couplings")
         ov = None
         if overlap_steps is not None:
             ov = np.zeros(self.nT, dtype=np.uint8)

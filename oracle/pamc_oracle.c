@@ -1,6 +1,7 @@
 /*
  * pamc_oracle.c -- plain CPU population annealing Monte Carlo (PAMC) for the
- * three-dimensional +-J Edwards-Anderson spin glass.
+ * Edwards-Anderson Ising spin glass on the periodic cubic (D = 3) lattice, and
+ * with real couplings also on the periodic square (D = 2) lattice.
  *
  * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously correct oracle that
  * the GPU library is checked against.  Only the test suite, the smoke check
@@ -41,7 +42,8 @@
  * Readings where the paper is silent (the design notes list every one):
  *   periodic boundaries; +-J couplings; for odd L a three-colouring
  *   c = (g(x)+g(y)+g(z)) mod 3 with g(v) = v mod 2 for v < L-1 and
- *   g(L-1) = 2; a Philox4x32-10 counter contract for every random number;
+ *   g(L-1) = 2 (in 2D the same with z = 0, g(0) = 0); 2D only with real
+ *   couplings (+-J instances enter as real couplings of magnitude 1); a Philox4x32-10 counter contract for every random number;
  *   Metropolis acceptance as a uint32 threshold compare; nearest-integer
  *   (floor/ceil) resampling normalised to the nominal R; weights taken
  *   relative to E_min as a fixed product of powers of exp(-2 dbeta); a
@@ -131,16 +133,16 @@ static uint32_t draw(uint64_t seed, uint32_t x, uint32_t y, uint32_t z, uint32_t
 /* State                                                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int L, N, ncol;
+    int dim, L, N, ncol;  /* N = L^dim; 2 dim neighbours per site         */
     int64_t R, Rcap;
     int nT, NS;
     uint64_t seed;
     double *beta;
     int64_t *Rt;          /* [nT] nominal population at each beta_k, Rt[0] = R */
     int gauss;      /* 1: real couplings in fixed point (units of 2^-20)  */
-    int8_t *J;      /* [3][N]: bond (s, d) joins s and s + e_d (+-1)      */
-    int32_t *Jq;    /* [3][N]: the same for real couplings, J = Jq 2^-20  */
-    int *nbr;       /* [N][6]: +x, -x, +y, -y, +z, -z                     */
+    int8_t *J;      /* [dim][N]: bond (s, d) joins s and s + e_d (+-1)    */
+    int32_t *Jq;    /* [dim][N]: the same for real couplings, J = Jq 2^-20 */
+    int *nbr;       /* [N][6]: +x, -x, +y, -y, +z, -z (the first 2 dim)   */
     int8_t *Jn;     /* [N][6]: coupling of the bond to that neighbour     */
     int32_t *Jnq;   /* [N][6]: the same for real couplings                */
     int *colour;    /* [N]                                                */
@@ -215,12 +217,12 @@ static int64_t coupling(const orc_t *o, int d, int s)
     return o->gauss ? (int64_t)o->Jq[d * o->N + s] : (int64_t)o->J[d * o->N + s];
 }
 
-/* Energy of one replica, Eq. (1): each of the 3N bonds counted once. */
+/* Energy of one replica, Eq. (1): each of the dim N bonds counted once. */
 static int64_t energy(const orc_t *o, const int8_t *S)
 {
     int64_t e = 0;
     for (int s = 0; s < o->N; ++s)
-        for (int d = 0; d < 3; ++d) e -= coupling(o, d, s) * S[s] * S[o->nbr[s * 6 + 2 * d]];
+        for (int d = 0; d < o->dim; ++d) e -= coupling(o, d, s) * S[s] * S[o->nbr[s * 6 + 2 * d]];
     return e;
 }
 
@@ -247,10 +249,13 @@ static void init_population(orc_t *o)
 
 /* pop: NULL for a constant nominal population R, or the nominal population
  * R(beta_k) of every step (pop[0] = R), Sec. III.D. */
-static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64_t Rcap, const double *beta,
-                     int nT, int NS, uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
+static orc_t *create(int dim, int L, const int8_t *J, const int32_t *Jq, int64_t R, int64_t Rcap,
+                     const double *beta, int nT, int NS, uint64_t seed, const uint8_t *overlap_steps,
+                     const int64_t *pop)
 {
-    if (L < 2 || L > 32 || R < 1 || nT < 1 || NS < 1 || (!J && !Jq) || !beta) return NULL;
+    if (dim != 2 && dim != 3) return NULL;
+    if (dim == 2 && !Jq) return NULL;
+    if (L < 2 || L > (dim == 3 ? 32 : 64) || R < 1 || nT < 1 || NS < 1 || (!J && !Jq) || !beta) return NULL;
     if (Rcap < R) return NULL;
     if (pop) {
         if (pop[0] != R) return NULL;
@@ -263,8 +268,9 @@ static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64
     }
     orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
     if (!o) return NULL;
+    o->dim = dim;
     o->L = L;
-    o->N = L * L * L;
+    o->N = dim == 3 ? L * L * L : L * L;
     o->gauss = Jq != NULL;
     o->ncol = (L % 2 == 0) ? 2 : 3;
     o->R = R;
@@ -278,8 +284,8 @@ static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64
     o->Rt = (int64_t *)malloc(sizeof(int64_t) * nT);
     if (o->Rt)
         for (int i = 0; i < nT; ++i) o->Rt[i] = pop ? pop[i] : R;
-    o->J = (int8_t *)calloc(3 * (size_t)N, 1);
-    o->Jq = (int32_t *)calloc(3 * (size_t)N, sizeof(int32_t));
+    o->J = (int8_t *)calloc((size_t)dim * N, 1);
+    o->Jq = (int32_t *)calloc((size_t)dim * N, sizeof(int32_t));
     o->nbr = (int *)malloc(sizeof(int) * 6 * (size_t)N);
     o->Jn = (int8_t *)calloc(6 * (size_t)N, 1);
     o->Jnq = (int32_t *)calloc(6 * (size_t)N, sizeof(int32_t));
@@ -312,7 +318,7 @@ static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64
     }
     memcpy(o->beta, beta, sizeof(double) * nT);
     if (J) {
-        for (int i = 0; i < 3 * N; ++i) {
+        for (int i = 0; i < dim * N; ++i) {
             if (J[i] != 1 && J[i] != -1) {
                 orc_destroy(o);
                 return NULL;
@@ -324,7 +330,7 @@ static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64
          * below 2^62, so sums of energies fit int64 and the variance numerator
          * R sum E^2 - (sum E)^2 fits int128 */
         int64_t A = 0;
-        for (int i = 0; i < 3 * N; ++i) {
+        for (int i = 0; i < dim * N; ++i) {
             if (Jq[i] <= -(1 << 23) || Jq[i] >= (1 << 23)) {
                 orc_destroy(o);
                 return NULL;
@@ -343,17 +349,19 @@ static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64
         o->ovl[nT - 1] = 1;
 
     /* Lattice (Sec. II.A): periodic neighbours and the coupling of each of
-     * the six bonds of a site.  Bond (s, d) is stored at J[d][s] and joins s
-     * to s + e_d, so the bond to s - e_d is J[d][s - e_d].  For L = 2 the
-     * two x-neighbours coincide but the two bonds stay distinct. */
+     * the 2 dim bonds of a site.  Bond (s, d) is stored at J[d][s] and joins
+     * s to s + e_d, so the bond to s - e_d is J[d][s - e_d].  For L = 2 the
+     * two x-neighbours coincide but the two bonds stay distinct.  In 2D the
+     * z entries of the tables are never read. */
     int count[3] = {0, 0, 0};
-    for (int z = 0; z < L; ++z)
+    const int Lz = dim == 3 ? L : 1;
+    for (int z = 0; z < Lz; ++z)
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
                 int s = site(L, x, y, z);
                 int xp = site(L, (x + 1) % L, y, z), xm = site(L, (x + L - 1) % L, y, z);
                 int yp = site(L, x, (y + 1) % L, z), ym = site(L, x, (y + L - 1) % L, z);
-                int zp = site(L, x, y, (z + 1) % L), zm = site(L, x, y, (z + L - 1) % L);
+                int zp = site(L, x, y, (z + 1) % Lz), zm = site(L, x, y, (z + Lz - 1) % Lz);
                 int *nb = o->nbr + 6 * s;
                 nb[0] = xp;
                 nb[1] = xm;
@@ -366,15 +374,15 @@ static orc_t *create(int L, const int8_t *J, const int32_t *Jq, int64_t R, int64
                 jn[1] = o->J[0 * N + xm];
                 jn[2] = o->J[1 * N + s];
                 jn[3] = o->J[1 * N + ym];
-                jn[4] = o->J[2 * N + s];
-                jn[5] = o->J[2 * N + zm];
+                jn[4] = dim == 3 ? o->J[2 * N + s] : 0;
+                jn[5] = dim == 3 ? o->J[2 * N + zm] : 0;
                 int32_t *jq = o->Jnq + 6 * s;
                 jq[0] = o->Jq[0 * N + s];
                 jq[1] = o->Jq[0 * N + xm];
                 jq[2] = o->Jq[1 * N + s];
                 jq[3] = o->Jq[1 * N + ym];
-                jq[4] = o->Jq[2 * N + s];
-                jq[5] = o->Jq[2 * N + zm];
+                jq[4] = dim == 3 ? o->Jq[2 * N + s] : 0;
+                jq[5] = dim == 3 ? o->Jq[2 * N + zm] : 0;
                 int c = colour_of(L, x, y, z);
                 o->colour[s] = c;
                 o->crank[s] = count[c]++;
@@ -387,7 +395,7 @@ orc_t *orc_create(int L, const int8_t *J, int64_t R, int64_t Rcap, const double 
                   uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
 {
     if (!J) return NULL;
-    return create(L, J, NULL, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
+    return create(3, L, J, NULL, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
 }
 
 /* Real couplings: Jq int32 [3][N], J = Jq 2^-20, |J| < 8. */
@@ -395,7 +403,16 @@ orc_t *orc_create_real(int L, const int32_t *Jq, int64_t R, int64_t Rcap, const 
                        uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
 {
     if (!Jq) return NULL;
-    return create(L, NULL, Jq, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
+    return create(3, L, NULL, Jq, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
+}
+
+/* Real couplings on the periodic L^dim lattice, dim = 2 or 3: Jq int32
+ * [dim][N]; 2 <= L <= 64 in 2D. */
+orc_t *orc_create_real_dim(int dim, int L, const int32_t *Jq, int64_t R, int64_t Rcap, const double *beta, int nT,
+                           int NS, uint64_t seed, const uint8_t *overlap_steps, const int64_t *pop)
+{
+    if (!Jq) return NULL;
+    return create(dim, L, NULL, Jq, R, Rcap, beta, nT, NS, seed, overlap_steps, pop);
 }
 
 void orc_set_threads(orc_t *o, int n) { o->nthreads = n < 1 ? 1 : n; }
@@ -472,7 +489,7 @@ static void sweep_one(const orc_t *o, int8_t *S, int64_t *Ep, int64_t r, int k, 
                 if (o->colour[s] != c) continue;
                 const int *nb = o->nbr + 6 * s;
                 int64_t h = 0;
-                for (int d = 0; d < 6; ++d)
+                for (int d = 0; d < 2 * o->dim; ++d)
                     h += (o->gauss ? (int64_t)o->Jnq[6 * s + d] : (int64_t)o->Jn[6 * s + d]) * S[nb[d]];
                 int64_t dE = 2 * S[s] * h;
                 int i = o->crank[s];
@@ -560,7 +577,7 @@ int orc_icm_pair(const orc_t *o, int8_t *Sa, int8_t *Sb, uint32_t j, int k, int 
     in[s0] = 1;
     while (head < tail) {
         const int s = queue[head++];
-        for (int d = 0; d < 6; ++d) {
+        for (int d = 0; d < 2 * o->dim; ++d) {
             const int t = o->nbr[6 * s + d];
             if (!in[t] && (Sa[t] != Sb[t]) == want_diff) {
                 in[t] = 1;

@@ -26,13 +26,14 @@ REAL_SCALE_BITS = 20
 REAL_LIMIT = (1 << 23) - 1
 
 
-def gaussian_couplings(L: int, disorder_seed: int) -> np.ndarray:
+def gaussian_couplings(L: int, disorder_seed: int, dim: int = 3) -> np.ndarray:
     """Gaussian couplings (mean 0, variance 1; the paper's case study,
-    Sec. II.A) rounded to the fixed-point grid, int32 [3][L^3] of j with
-    J = j 2^-20; the rare draws with |J| >= 8 are clipped."""
-    N = L ** 3
+    Sec. II.A) rounded to the fixed-point grid, int32 [D][L^D] of j with
+    J = j 2^-20 on the cubic (D = 3) or square (D = 2) lattice; the rare
+    draws with |J| >= 8 are clipped."""
+    N = L ** dim
     rng = np.random.Generator(np.random.PCG64(np.uint64(disorder_seed)))
-    g = rng.standard_normal(size=(3, N))
+    g = rng.standard_normal(size=(dim, N))
     j = np.rint(g * float(1 << REAL_SCALE_BITS))
     return np.clip(j, -REAL_LIMIT, REAL_LIMIT).astype(np.int32)
 
@@ -56,16 +57,41 @@ def mattis_couplings(L: int, seed: int):
     return J, eps
 
 
+def square_neighbours(L: int):
+    """+x and +y neighbours of every site of the periodic L x L lattice,
+    site s = x + L y."""
+    idx = np.arange(L * L)
+    x, y = idx % L, idx // L
+    return [((x + 1) % L) + L * y, x + L * ((y + 1) % L)]
+
+
+def pm_couplings_as_real(couplings: np.ndarray) -> np.ndarray:
+    """+-1 couplings as fixed-point real couplings (J = j 2^-20, exact)."""
+    return np.asarray(couplings).astype(np.int32) * np.int32(1 << REAL_SCALE_BITS)
+
+
+def pm_j_couplings_2d(L: int, disorder_seed: int) -> np.ndarray:
+    """Random +-1 couplings on the periodic square lattice as fixed-point
+    real couplings, int32 [2][L^2]."""
+    rng = np.random.Generator(np.random.PCG64(np.uint64(disorder_seed)))
+    return pm_couplings_as_real(2 * rng.integers(0, 2, size=(2, L * L)) - 1)
+
+
 def gauge_transform(L: int, couplings: np.ndarray, eps: np.ndarray) -> np.ndarray:
-    """J_ij -> eps_i J_ij eps_j for a +-1 vector eps over the sites."""
-    N = L ** 3
+    """J_ij -> eps_i J_ij eps_j for a +-1 vector eps over the sites (cubic
+    [3][L^3] or square [2][L^2] couplings)."""
+    dim = 3 if np.asarray(couplings).size == 3 * L ** 3 else 2
+    N = L ** dim
     idx = np.arange(N)
-    x, y, z = idx % L, (idx // L) % L, idx // (L * L)
-    nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z),
-          x + L * (y + L * ((z + 1) % L))]
+    if dim == 3:
+        x, y, z = idx % L, (idx // L) % L, idx // (L * L)
+        nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z),
+              x + L * (y + L * ((z + 1) % L))]
+    else:
+        nb = square_neighbours(L)
     dt = np.int32 if np.asarray(couplings).dtype == np.int32 else np.int8
-    J = np.array(couplings, dtype=dt).reshape(3, N).copy()
-    for d in range(3):
+    J = np.array(couplings, dtype=dt).reshape(dim, N).copy()
+    for d in range(dim):
         J[d] = (eps.astype(np.int64) * J[d] * eps[nb[d]]).astype(dt)
     return J
 

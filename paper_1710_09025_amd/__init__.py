@@ -1,9 +1,11 @@
-"""Population annealing Monte Carlo for 3D Edwards-Anderson spin glasses on
+"""Population annealing Monte Carlo for Edwards-Anderson spin glasses on
 AMD Instinct MI355X (gfx950).
 
 Couplings are int8 +-1, or int32 fixed-point real couplings J = j 2^-20
 with |J| < 8 (the paper's Gaussian case study, Sec. II.A); the dtype of the
-array picks the model.  Energies of real-coupling runs (E_min, E_max, sum_E,
+array picks the model.  Their shape picks the lattice: [3][L^3] is the
+periodic cubic lattice, [2][L^2] the periodic square lattice (Sec. II.A
+studies both; 2D takes real couplings).  Energies of real-coupling runs (E_min, E_max, sum_E,
 sum_E2, state energies) are exact integers in units of 2^-20.
 
 Python binding of the C ABI in ``include/pamc.h``: it marshals arguments and
@@ -66,11 +68,24 @@ def _obs_to_dict(arr) -> dict:
     return out
 
 
+def lattice_dim(L, couplings) -> int:
+    """3 for couplings of size 3 L^3 (cubic lattice), 2 for size 2 L^2
+    (square lattice)."""
+    n = np.asarray(couplings).size
+    if n == 3 * int(L) ** 3:
+        return 3
+    if n == 2 * int(L) ** 2:
+        return 2
+    raise ValueError(f"couplings of size {n} fit neither [3][L^3] nor [2][L^2] for L = {L}")
+
+
 def _couplings(L, couplings):
-    """(array, real): int32 fixed-point real couplings, else int8 +-1."""
+    """(array, real, dim): int32 fixed-point real couplings, else int8 +-1,
+    on the lattice of dimension dim."""
     real = np.asarray(couplings).dtype == np.int32
-    J = np.ascontiguousarray(couplings, dtype=np.int32 if real else np.int8).reshape(3, int(L) ** 3)
-    return J, real
+    dim = lattice_dim(L, couplings)
+    J = np.ascontiguousarray(couplings, dtype=np.int32 if real else np.int8).reshape(dim, int(L) ** dim)
+    return J, real, dim
 
 
 class _TorchGlue:
@@ -118,10 +133,11 @@ def _torch_available() -> bool:
 def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_format=_capi.SPINS_INT8,
                   torch_stream=True, torch_allocator=False, keep=None, timing=False, tile_rows=0,
                   graphs=True, group_replicas=0, autotune=False, pop_schedule=None, icm_rounds=0,
-                  icm_beta_min=0.0):
+                  icm_beta_min=0.0, dim=3):
     lib = _capi.load()
     opt = _capi.Options()
     lib.pamc_default_options(ctypes.byref(opt))
+    opt.dim = int(dim)
     opt.spin_format = int(spin_format)
     if capacity is not None:
         opt.capacity = int(capacity)
@@ -149,11 +165,11 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
     return opt
 
 
-def autotune(L, R, sweeps, torch_stream=True, packed=False, real=False):
+def autotune(L, R, sweeps, torch_stream=True, packed=False, real=False, dim=3):
     """Sweep workgroup shape chosen by measurement (``pamc_autotune``):
     (tile_rows, group_replicas, sweep ns per attempt).  Cached per process."""
     keep = []
-    opt = _make_options(torch_stream=torch_stream, keep=keep,
+    opt = _make_options(torch_stream=torch_stream, keep=keep, dim=dim,
                         spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
     opt.real_couplings = 1 if real else 0
     t, g, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
@@ -191,7 +207,8 @@ def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None
 
 class Pamc:
     """One population-annealing run on the GPU (``pamc_create``, or
-    ``pamc_create_real`` for int32 real couplings)."""
+    ``pamc_create_real`` for int32 real couplings; [2][L^2] couplings select
+    the square lattice)."""
 
     def __init__(self, L, couplings, R, beta, sweeps, seed, capacity=None, overlap_steps=None,
                  fuse_gather=True, torch_stream=True, torch_allocator=False, timing=False, tile_rows=0,
@@ -199,13 +216,13 @@ class Pamc:
                  icm_beta_min=0.0):
         lib = _capi.load()
         self.L = int(L)
-        self.N = self.L ** 3
         self.R = int(R)
         self.beta = np.ascontiguousarray(beta, dtype=np.float64)
         self.nT = len(self.beta)
         self._keep = []
-        J, self.real = _couplings(self.L, couplings)
-        opt = _make_options(capacity, overlap_steps, fuse_gather,
+        J, self.real, self.dim = _couplings(self.L, couplings)
+        self.N = self.L ** self.dim
+        opt = _make_options(capacity, overlap_steps, fuse_gather, dim=self.dim,
                             spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8, torch_stream=torch_stream,
                             torch_allocator=torch_allocator, keep=self._keep, timing=timing,
                             tile_rows=tile_rows, graphs=graphs, group_replicas=group_replicas,
@@ -332,9 +349,11 @@ class PamcBatch:
         self.nT = []
         self.N = []
         self.real = []
+        dims = set()
         for i, d in enumerate(instances):
             L = int(d["L"])
-            J, real = _couplings(L, d["couplings"])
+            J, real, dim = _couplings(L, d["couplings"])
+            dims.add(dim)
             b = np.ascontiguousarray(d["beta"], dtype=np.float64)
             self._keep += [J, b]
             pop = None
@@ -346,9 +365,12 @@ class PamcBatch:
                                     _ptr(pop).value if pop is not None else None,
                                     _ptr(J).value if real else None)
             self.nT.append(len(b))
-            self.N.append(L ** 3)
+            self.N.append(L ** dim)
             self.real.append(real)
+        if len(dims) > 1:
+            raise ValueError("the instances of a batch share one lattice dimension")
         opt = _make_options(fuse_gather=fuse_gather, torch_stream=torch_stream, keep=self._keep, graphs=graphs,
+                            dim=dims.pop(),
                             autotune=autotune, spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8,
                             icm_rounds=icm_rounds, icm_beta_min=icm_beta_min)
         h = ctypes.c_void_p()
@@ -407,7 +429,9 @@ class PamcServer:
 
     def submit(self, L, couplings, R, beta, sweeps, seed, pop_schedule=None) -> int:
         L = int(L)
-        J, real = _couplings(L, couplings)
+        J, real, dim = _couplings(L, couplings)
+        if dim != 3:
+            raise ValueError("the serving API runs cubic lattices only")
         b = np.ascontiguousarray(beta, dtype=np.float64)
         pop = None if pop_schedule is None else np.ascontiguousarray(pop_schedule, dtype=np.int64)
         inst = _capi.Instance(L, None if real else _ptr(J).value, int(R), _ptr(b).value, len(b), int(sweeps),

@@ -45,6 +45,7 @@ class Options(ctypes.Structure):
         ("real_couplings", ctypes.c_int),
         ("icm_rounds", ctypes.c_int),
         ("icm_beta_min", ctypes.c_double),
+        ("dim", ctypes.c_int),
     ]
 
 

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     const uint32_t n = I.Rk[k];
     const uint32_t j = w.row0;
     if (j >= n / 2) return;
-    const int N = I.N, L = I.L;
+    const int N = I.N, L = I.L, nnb = 2 * I.dim;
     uint8_t *base = lds + (size_t)wave * pair_bytes;
     uint8_t *member = base;
     uint32_t *vis = reinterpret_cast<uint32_t *>(base + ((N + 15) & ~15));
@@ -146,10 +146,12 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
             const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
             const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
             const int zp = z + 1 == L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+            // on the square lattice (z = 0) only the first four are bonds
             const int nb[6] = {xp + L * yz, xm + L * yz, x + L * (yp + L * z), x + L * (ym + L * z),
                                x + L * (y + L * zp), x + L * (y + L * zm)};
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
+                if (d >= nnb) break;
                 const int q = nb[d];
                 if (!member[q]) continue;
                 const uint32_t bit = 1u << (q & 31);

@@ -51,17 +51,21 @@ int invalid(const std::string &m)
 int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
                     uint64_t seed, const pamc_options &opt, HostInst &h)
 {
-    if (L < 2 || L > 32) return invalid("L must be in [2, 32]");
+    const int dim = opt.dim == 0 ? 3 : opt.dim;
+    if (dim != 2 && dim != 3) return invalid("dim must be 2 or 3");
+    if (dim == 3 && (L < 2 || L > 32)) return invalid("L must be in [2, 32]");
+    if (dim == 2 && (L < 2 || L > 64)) return invalid("square lattice: L must be in [2, 64]");
     if (!J && !Jq) return invalid("couplings is NULL");
+    if (dim == 2 && !Jq) return invalid("the square lattice takes real couplings (+-J as +-2^20)");
     if (!beta) return invalid("beta is NULL");
     if (R < 1) return invalid("R must be >= 1");
     if (nT < 1) return invalid("n_temps must be >= 1");
     if (NS < 1) return invalid("sweeps must be >= 1");
-    const int N = L * L * L;
+    const int N = dim == 3 ? L * L * L : L * L;
     const bool real = Jq != nullptr;
     int64_t absJ = 0;  // sum of |j|: bounds |E| (units of 2^-20)
     if (real) {
-        for (int i = 0; i < 3 * N; ++i) {
+        for (int i = 0; i < dim * N; ++i) {
             if (Jq[i] <= -(1 << 23) || Jq[i] >= (1 << 23)) return invalid("real couplings must satisfy |J| < 8");
             absJ += Jq[i] < 0 ? -(int64_t)Jq[i] : (int64_t)Jq[i];
         }
@@ -94,8 +98,9 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
         return invalid("capacity times the sum of |couplings| must stay below 2^62");
     // the normaliser's tree folds at most 2^19 roots of 1024-row blocks
     if (real && cap > ((int64_t)1 << 29)) return invalid("real couplings: capacity must stay at or below 2^29");
-    const pamc::LayoutInfo li = pamc::layout_for(L, real);
+    const pamc::LayoutInfo li = pamc::layout_for(L, real, dim);
     if (li.layout < 0) return invalid("real couplings need even L <= 20 or odd L <= 21");
+    h.dim = dim;
     h.L = L;
     h.N = N;
     h.ncol = li.ncol;
@@ -118,7 +123,7 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
     h.icm = opt.icm_rounds;
     h.icm_bmin = opt.icm_beta_min;
     if (real)
-        h.Jq.assign(Jq, Jq + 3 * N);
+        h.Jq.assign(Jq, Jq + (size_t)dim * N);
     else
         h.J.assign(J, J + 3 * N);
     h.ovl_slot.assign(nT, -1);
@@ -204,20 +209,21 @@ const char *pamc_last_error(void) { return pamc::last_error_cstr(); }
 
 int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt)
 {
-    if (L < 2 || L > 32 || R < 1 || n_temps < 1) return -1;
     const pamc_options o = resolve(opt);
-    if (o.real_couplings && pamc::layout_for(L, true).layout < 0) return -1;
+    const int dim = o.dim == 0 ? 3 : o.dim;
+    if ((dim != 2 && dim != 3) || L < 2 || L > (dim == 3 ? 32 : 64) || R < 1 || n_temps < 1) return -1;
+    if ((o.real_couplings || dim == 2) && pamc::layout_for(L, true, dim).layout < 0) return -1;
+    const bool real = o.real_couplings != 0 || dim == 2;
     const int64_t cap = o.capacity > 0 ? o.capacity : pamc::default_capacity(R);
     const int nov = (o.overlap_steps && o.n_overlap_steps > 0) ? o.n_overlap_steps : 1;
     if (o.capacity <= 0 && o.pop_schedule) {
         int64_t peak = R;
         for (int k = 0; k < n_temps; ++k) peak = std::max(peak, (int64_t)o.pop_schedule[k]);
         const int64_t c = pamc::default_capacity(peak);
-        return (int64_t)pamc::inst_device_bytes(L, c, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED,
-                                                o.real_couplings != 0);
+        return (int64_t)pamc::inst_device_bytes(L, c, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED, real,
+                                                dim);
     }
-    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED,
-                                            o.real_couplings != 0);
+    return (int64_t)pamc::inst_device_bytes(L, cap, n_temps, nov, o.spin_format == PAMC_SPINS_PACKED, real, dim);
 }
 
 }  // extern "C"
@@ -324,17 +330,19 @@ int pamc_sweep_shape(const pamc_ctx *ctx, int *tile_rows, int *group_replicas)
 int pamc_autotune(int L, int64_t R, int sweeps, const pamc_options *opt, int *tile_rows, int *group_replicas,
                   double *ns_per_attempt)
 {
-    if (L < 2 || L > 32) return invalid("L must be in [2, 32]");
     pamc_options o = resolve(opt);
+    const int dim = o.dim == 0 ? 3 : o.dim;
+    if (dim != 2 && dim != 3) return invalid("dim must be 2 or 3");
+    if (L < 2 || L > (dim == 3 ? 32 : 64)) return invalid("L out of range");
     o.tile_rows = 0;
     o.group_replicas = 0;
     o.autotune = 0;
     o.pop_schedule = nullptr;
     // seeded couplings (splitmix64): +-1, or real ones spread over
     // (-2, 2); the sweep's speed does not depend on their values
-    const int N = L * L * L;
-    std::vector<int8_t> J((size_t)3 * N);
-    std::vector<int32_t> Jq(o.real_couplings ? (size_t)3 * N : 0);
+    const int N = dim == 3 ? L * L * L : L * L;
+    std::vector<int8_t> J((size_t)dim * N);
+    std::vector<int32_t> Jq(o.real_couplings || dim == 2 ? (size_t)dim * N : 0);
     uint64_t x = 0x2545F4914F6CDD1Dull;
     for (size_t i = 0; i < J.size(); ++i) {
         x += 0x9E3779B97F4A7C15ull;

@@ -67,6 +67,7 @@ struct EMoments {
 struct Inst {
     // problem
     int32_t L, N, ncol, layout;
+    int32_t dim;        // lattice dimension: 3 (cubic, N = L^3) or 2 (square, N = L^2; real couplings only)
     int32_t row_bytes;  // bytes per replica row in LDS, one byte per storage position (>= N, multiple of 16)
     int32_t packed;     // 1: the spin buffers hold one bit per storage position
     int32_t srow_bytes; // bytes per replica row in the spin buffers (row_bytes, or row_bytes / 8 rounded up to 16)

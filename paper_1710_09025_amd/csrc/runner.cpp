@@ -53,18 +53,25 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // threads, the slot offsets fit 16 bits and a replica quad's slot fits the
 // workgroup's LDS (even L up to 20, odd L up to 21); else lexicographic.
 // Real couplings: the colour-major layout wherever it fits (a quad slot of
-// four planes), L = 8 and 16 included; no kernel beyond it.
-LayoutInfo layout_for(int L, bool real)
+// four planes), L = 8 and 16 included; no kernel beyond it.  The square
+// lattice (dim = 2) runs only with real couplings, in the same layout.
+LayoutInfo layout_for(int L, bool real, int dim)
 {
     LayoutInfo li{};
-    const int N = L * L * L;
+    const int Lz = dim == 3 ? L : 1;
+    const int N = L * L * Lz;
     li.ncol = (L & 1) ? 3 : 2;
-    for (int z = 0; z < L; ++z)
+    for (int z = 0; z < Lz; ++z)
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) li.ncs[colour_of(L, x, y, z)]++;
     li.gmax = 1;
     for (int c = 0; c < 3; ++c) li.gmax = std::max(li.gmax, (li.ncs[c] + 3) / 4);
     li.row_bytes = (N + 15) & ~15;
+    if (!real && dim != 3) {
+        li.layout = -1;
+        li.variant = -1;
+        return li;
+    }
     if (!real && (L == 8 || L == 16)) {
         li.layout = kLayoutEO;
         li.variant = L == 8 ? kSweepEO8 : kSweepEO16;
@@ -125,10 +132,10 @@ struct InstLayout {
         bq, gpw, total;
 };
 
-InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool packed, bool real)
+InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool packed, bool real, int dim)
 {
-    const int N = L * L * L;
-    const LayoutInfo li = layout_for(L, real);
+    const int N = dim == 3 ? L * L * L : L * L;
+    const LayoutInfo li = layout_for(L, real, dim);
     const int row_bytes = stored_row_bytes(li.row_bytes, packed);
     const int ncol = li.ncol;
     const int nblk = (int)((Rcap + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -162,7 +169,7 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
     l.site = c.take((size_t)N * 16);
     l.grp = c.take((size_t)ncol * gmax * 4 * 2);
     l.jeo = c.take((size_t)2 * (N / 8 + 1) * 6 * 4);
-    l.J = c.take((size_t)3 * N * (real ? 4 : 1));
+    l.J = c.take((size_t)dim * N * (real ? 4 : 1));
     l.pos = c.take((size_t)N * 2);
     l.cmdesc = li.layout == kLayoutCM ? c.take((size_t)ncol * gmax * 32 * 2) : c.take(16);
     l.Rk = c.take((size_t)(nT + 1) * 4);
@@ -186,10 +193,10 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
 
 int stored_row_bytes(int row_bytes, bool packed) { return packed ? (row_bytes + 127) / 128 * 16 : row_bytes; }
 
-size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bool real)
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bool real, int dim)
 {
     // R <= Rcap; use Rcap for the family counters as an upper bound
-    return layout_of(L, Rcap, Rcap, nT, n_ovl, packed, real).total;
+    return layout_of(L, Rcap, Rcap, nT, n_ovl, packed, real, dim).total;
 }
 
 Runner::~Runner()
@@ -317,7 +324,7 @@ int Runner::upload_inst(int i)
 {
     HostInst &h = inst_[i];
     const int L = h.L, N = h.N;
-    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n, h.packed != 0, h.real != 0);
+    const InstLayout lay = layout_of(L, h.R, h.Rcap, h.nT, h.ovl_n, h.packed != 0, h.real != 0, h.dim);
     h.bytes = lay.total;
     h.block = alloc_.get(lay.total);
     if (!h.block) {
@@ -330,6 +337,7 @@ int Runner::upload_inst(int i)
     std::memset(&d, 0, sizeof(d));
     d.L = L;
     d.N = N;
+    d.dim = h.dim;
     d.ncol = h.ncol;
     d.layout = h.layout;
     d.row_bytes = h.row_bytes;
@@ -422,9 +430,10 @@ int Runner::upload_inst(int i)
         rho[k] = std::exp(-2.0 * db);
     }
     // --- colours and colour ranks
+    const int Lz = h.dim == 3 ? L : 1;
     std::vector<int> col(N), rank(N);
     int ncs[3] = {0, 0, 0};
-    for (int z = 0; z < L; ++z)
+    for (int z = 0; z < Lz; ++z)
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
                 const int s = x + L * (y + L * z);
@@ -438,8 +447,10 @@ int Runner::upload_inst(int i)
     d.gmax = std::max(d.gcs[0], std::max(d.gcs[1], d.gcs[2]));
     // coupling of bond (dir, s): +-1, or j (units of 2^-20) for real couplings
     auto J = [&](int dir, int s) { return h.real ? (int)h.Jq[(size_t)dir * N + s] : (int)h.J[(size_t)dir * N + s]; };
-    auto site_of = [L](int x, int y, int z) { return ((x % L + L) % L) + L * (((y % L + L) % L) + L * ((z % L + L) % L)); };
-    const LayoutInfo li = layout_for(L, h.real != 0);
+    auto site_of = [L, Lz](int x, int y, int z) {
+        return ((x % L + L) % L) + L * (((y % L + L) % L) + L * ((z % Lz + Lz) % Lz));
+    };
+    const LayoutInfo li = layout_for(L, h.real != 0, h.dim);
     for (int c = 0; c < 3; ++c) d.cbase[c] = li.cbase[c];
     d.tpr = li.tpr;
     d.plane_bytes = cm_plane_bytes(h.row_bytes);
@@ -484,7 +495,10 @@ int Runner::upload_inst(int i)
     } else if (h.layout == kLayoutCM) {
         // per colour, Philox block and site: the LDS offsets of its six
         // neighbours, in the complemented copy (+row_bytes) for a -1 bond;
-        // for real couplings the plain copy, with the couplings alongside
+        // for real couplings the plain copy, with the couplings alongside.
+        // On the square lattice the two z entries of a site point at the
+        // site itself with coupling 0: they add nothing to its field or to
+        // the energy, so the sweep kernel runs unchanged.
         std::vector<int> site_at((size_t)3 * N, -1);
         for (int s = 0; s < N; ++s) site_at[(size_t)col[s] * N + rank[s]] = s;
         cmdesc.assign((size_t)h.ncol * d.gmax * 32, 0);
@@ -503,9 +517,12 @@ int Runner::upload_inst(int i)
                     vmask |= 1u << (8 * bb);
                     const int s = site_at[(size_t)c * N + i];
                     const int x = s % L, y = (s / L) % L, z = s / (L * L);
+                    const bool sq = h.dim == 2;
                     const int nb[6] = {site_of(x + 1, y, z), site_of(x - 1, y, z), site_of(x, y + 1, z),
-                                       site_of(x, y - 1, z), site_of(x, y, z + 1), site_of(x, y, z - 1)};
-                    const int jv[6] = {J(0, s), J(0, nb[1]), J(1, s), J(1, nb[3]), J(2, s), J(2, nb[5])};
+                                       site_of(x, y - 1, z), sq ? s : site_of(x, y, z + 1),
+                                       sq ? s : site_of(x, y, z - 1)};
+                    const int jv[6] = {J(0, s), J(0, nb[1]), J(1, s), J(1, nb[3]), sq ? 0 : J(2, s),
+                                       sq ? 0 : J(2, nb[5])};
                     for (int dd = 0; dd < 6; ++dd) {
                         if (h.real) {
                             e[4 * dd + bb] = (uint16_t)h.lex_pos[nb[dd]];

@@ -20,6 +20,7 @@
 namespace pamc {
 
 struct HostInst {
+    int dim = 3;                       // lattice dimension (2 or 3), N = L^dim
     int L = 0, N = 0, ncol = 0, layout = 0, variant = 0;
     int row_bytes = 0, tile_rows = 0;
     int packed = 0;                    // spins stored one bit per position
@@ -35,7 +36,7 @@ struct HostInst {
     std::vector<double> beta;
     std::vector<double> pop;           // [nT] nominal population R(beta_k)
     std::vector<int8_t> J;             // [3][N] +-1 couplings
-    std::vector<int32_t> Jq;           // [3][N] real couplings, J = Jq 2^-20
+    std::vector<int32_t> Jq;           // [dim][N] real couplings, J = Jq 2^-20
     std::vector<int32_t> ovl_slot;     // [nT]
     int ovl_n = 0;
     int k_enq = 0;                     // steps enqueued so far
@@ -60,7 +61,7 @@ struct Allocator {
 };
 
 // Footprint and table construction helpers.
-size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bool real = false);
+size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bool real = false, int dim = 3);
 // Bytes per stored spin row: row_bytes, or one bit per position rounded up
 // to 16 bytes.
 int stored_row_bytes(int row_bytes, bool packed);
@@ -76,7 +77,7 @@ struct LayoutInfo {
 };
 // Real couplings use the colour-major layout for every L it covers (L = 8
 // and 16 included).
-LayoutInfo layout_for(int L, bool real = false);
+LayoutInfo layout_for(int L, bool real = false, int dim = 3);
 
 class Runner {
 public:

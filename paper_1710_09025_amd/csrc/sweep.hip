@@ -110,8 +110,9 @@ __global__ __launch_bounds__(256) void k_init(const Inst *insts, const Work *wor
 }
 
 // ---------------------------------------------------------------------------
-// Energies of the rows of the current buffer, Eq. (1): E = -sum over the 3N
-// bonds (s, s + e_d) of J S_s S_{s+e_d}.  One wave per row.
+// Energies of the rows of the current buffer, Eq. (1): E = -sum over the
+// D N bonds (s, s + e_d) of J S_s S_{s+e_d} (D = 3, or 2 on the square
+// lattice, real couplings only).  One wave per row.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *work, const int8_t *const *Jraw)
 {
@@ -125,8 +126,10 @@ __global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *w
     const int L = I.L, N = I.N;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (I.real) {
-        // real couplings: int32 [3][N] in units of 2^-20, 64-bit sums
+        // real couplings: int32 [D][N] in units of 2^-20, 64-bit sums; on
+        // the square lattice z = 0 and the z bond is absent
         const int32_t *Jq = reinterpret_cast<const int32_t *>(J);
+        const int Lz = I.dim == 3 ? L : 1;
         for (int q = wave; q < kRowsPerBlock; q += 4) {
             const int r = (int)w.row0 + q;
             if (r >= Rk) break;
@@ -136,8 +139,8 @@ __global__ __launch_bounds__(256) void k_energy(const Inst *insts, const Work *w
                 const int x = s % L, y = (s / L) % L, z = s / (L * L);
                 const int ss = 2 * stored_spin(I, S, storage_pos(I, s)) - 1;
                 const int nb[3] = {(x + 1) % L + L * (y + L * z), x + L * ((y + 1) % L + L * z),
-                                   x + L * (y + L * ((z + 1) % L))};
-                for (int d = 0; d < 3; ++d)
+                                   x + L * (y + L * ((z + 1) % Lz))};
+                for (int d = 0; d < I.dim; ++d)
                     e -= (long long)Jq[d * N + s] * (ss * (2 * stored_spin(I, S, storage_pos(I, nb[d])) - 1));
             }
             for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);

@@ -247,3 +247,34 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "_lib", None)
     with pytest.raises(_capi.LibraryMissing):
         _capi.load()
+
+
+def test_square_lattice_options_on_the_host(lib):
+    """dim = 2 sizes a real-coupling run of L^2 spins; +-1 couplings, a
+    dimension other than 2 or 3 and L > 64 are rejected before any device
+    work."""
+    from paper_1710_09025_amd import _capi
+
+    opt = _capi.Options()
+    lib.pamc_default_options(ctypes.byref(opt))
+    assert opt.dim == 0
+    three = lib.pamc_footprint(8, 10000, 101, ctypes.byref(opt))
+    opt.dim = 2
+    two = lib.pamc_footprint(32, 10000, 101, ctypes.byref(opt))
+    cap = 10000 + int(np.ceil(8 * np.sqrt(10000))) + 64
+    assert two >= 2 * cap * 1024 and three > 0
+    assert lib.pamc_footprint(64, 100, 11, ctypes.byref(opt)) > 0
+    assert lib.pamc_footprint(65, 100, 11, ctypes.byref(opt)) == -1
+    opt.dim = 4
+    assert lib.pamc_footprint(8, 100, 11, ctypes.byref(opt)) == -1
+    beta = np.linspace(0, 1, 3)
+    for dim, real, Lc in [(2, False, 4), (4, True, 4), (2, True, 65)]:
+        opt.dim = dim
+        N = Lc ** (3 if dim == 4 else dim)
+        J = np.ones((3 if dim == 4 else dim) * N, dtype=np.int32 if real else np.int8)
+        h = ctypes.c_void_p()
+        create = lib.pamc_create_real if real else lib.pamc_create
+        st = create(Lc, J.ctypes.data_as(ctypes.c_void_p), 100, beta.ctypes.data_as(ctypes.c_void_p), len(beta),
+                    2, 1, ctypes.byref(opt), ctypes.byref(h))
+        assert st == _capi.ERR_INVALID, (dim, real, Lc, lib.pamc_last_error())
+        assert not h.value
