@@ -74,9 +74,15 @@ def source_hash() -> str:
 
 
 def workload_inputs(name, real=False):
+    """Configuration, couplings and schedule of a named workload; square
+    lattice workloads (dim = 2) always take Gaussian couplings."""
     cfg = pi.WORKLOADS[name]
-    gen = pi.gaussian_couplings if real else pi.pm_j_couplings
-    J = gen(cfg["L"], cfg["disorder_seed"])
+    dim = cfg.get("dim", 3)
+    if dim == 2:
+        J = pi.gaussian_couplings(cfg["L"], cfg["disorder_seed"], dim=2)
+    else:
+        gen = pi.gaussian_couplings if real else pi.pm_j_couplings
+        J = gen(cfg["L"], cfg["disorder_seed"])
     beta = pi.linear_beta(cfg["beta_max"], cfg["n_temps"])
     return cfg, J, beta
 
@@ -96,7 +102,7 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, i
     from paper_1710_09025_amd import Pamc
 
     cfg, J, beta = workload_inputs(name, real)
-    N = cfg["L"] ** 3
+    N = cfg["L"] ** cfg.get("dim", 3)
     runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune, packed=packed,
                  icm_rounds=icm_rounds) for _ in range(warmup + steps)]
     shape = runs[0].sweep_shape()
@@ -341,6 +347,33 @@ def rho_f_bench(L=8, R=20000, n_temps=201, runs=128, icm_rounds=0, icm_beta_min=
             "seconds": round(t1 - t0, 3)}
 
 
+def rho_f_square_bench(L=8, R=50000, n_temps=101, runs=64, instances=(1, 2, 3, 4), icm_rounds=2):
+    """The paper's 2D cluster-move comparison: rho_f = R var(beta F) of each
+    Gaussian square-lattice instance from `runs` independent runs, without
+    and with icm_rounds x floor(R_k/2) pair updates at every step."""
+    import torch
+
+    from paper_1710_09025_amd import free_energy_variance
+
+    beta = pi.linear_beta(5.0, n_temps)
+    out = {"L": L, "R": R, "n_temps": n_temps, "runs": runs, "icm_rounds": icm_rounds, "instances": {}}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in instances:
+        J = pi.gaussian_couplings(L, 9000 + d, dim=2)
+        row = {}
+        for rounds in (0, icm_rounds):
+            res = free_energy_variance(L, J, R, beta, 10, [11000 + 100 * d + i for i in range(runs)],
+                                       autotune=True, icm_rounds=rounds)
+            row["rho_f_icm" if rounds else "rho_f"] = round(float(res["rho_f"][-1]), 3)
+        out["instances"][str(d)] = row
+    torch.cuda.synchronize()
+    out["seconds"] = round(time.perf_counter() - t0, 3)
+    ratios = [v["rho_f"] / v["rho_f_icm"] for v in out["instances"].values()]
+    out["geomean_ratio_without_over_with"] = round(float(np.exp(np.mean(np.log(ratios)))), 3)
+    return out
+
+
 def icm_bench(name, rounds=2):
     """One anneal of a workload with isoenergetic cluster moves (Sec. IV):
     rounds x floor(R_k/2) pair updates per step between the two halves of
@@ -418,7 +451,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed anneals")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="L8_R100000", choices=sorted(pi.WORKLOADS))
+    ap.add_argument("--workload", default="L8_R100000",
+                    choices=sorted(k for k, v in pi.WORKLOADS.items() if v.get("dim", 3) == 3))
     ap.add_argument("--couplings", default="pm1", choices=("pm1", "gaussian"),
                     help="couplings of the benchmark instance: +-1, or Gaussian in fixed point")
     ap.add_argument("--icm-rounds", type=int, default=0,
@@ -537,6 +571,22 @@ def main():
         # only below T = 1, around and below the spin-glass transition
         extra["rho_f_icm_low_T"] = rho_f_bench(icm_rounds=2, icm_beta_min=1.0)
         log("rho_f and cluster moves done")
+        # the square lattice (Sec. II.A): throughput at the paper's largest
+        # 2D size, and its cluster-move comparison of rho_f
+        s = time_anneals("L32_2D_R1000000", 1, 0)
+        extra["L32_2D_R1000000"] = {
+            "attempts_per_ns": round(s["attempts_per_anneal"] / (s["wall_s"] * 1e9), 3),
+            "sweep_attempts_per_ns": round(s["attempts_per_anneal"] / (s["sweep_ms"] * 1e6), 3),
+            "ms_per_anneal": round(s["wall_s"] * 1e3, 3),
+            "sweep_share": round(s["sweep_ms"] / (s["sweep_ms"] + s["other_ms"]), 4),
+            "sweep_shape": {"tile_rows": s["shape"][0], "group_replicas": s["shape"][1]},
+        }
+        # rho_f is intensive (independent of R once R >> rho_f), so the larger
+        # lattices use R = 5 10^4 to afford more runs and instances
+        extra["rho_f_2D_L8"] = rho_f_square_bench()
+        extra["rho_f_2D_L16"] = rho_f_square_bench(L=16, R=50000, runs=64)
+        extra["rho_f_2D_L32"] = rho_f_square_bench(L=32, R=50000, n_temps=301, runs=32, instances=(1, 2))
+        log("square lattice done")
         if args.batch:
             extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
             log("batch done")

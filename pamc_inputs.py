@@ -166,6 +166,11 @@ WORKLOADS = {
                        seed=2),
     "L16_R500000": dict(L=16, R=500_000, n_temps=301, beta_max=5.0, sweeps=10, disorder_seed=3,
                         seed=3),
+    # the square lattice at the largest size of the paper's cluster-update
+    # runs (L = 32, R = 10^6, 301 temperatures, T_min = 0.2), Gaussian
+    # couplings
+    "L32_2D_R1000000": dict(L=32, R=1_000_000, n_temps=301, beta_max=5.0, sweeps=10, disorder_seed=6,
+                            seed=6, dim=2),
 }
 
 
