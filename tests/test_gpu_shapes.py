@@ -24,13 +24,15 @@ def same_run(a, b, what):
 
 
 # (L, shapes as (tile_rows, group_replicas)): colour-major with two and three
-# colours (8 threads per replica quad at L = 4, 128 at L = 10; tiles that are
-# not multiples of four leave a quad partly empty), even/odd-x (L = 8, 16),
-# per-site (L = 24); ragged tiles and single-pass workgroups
+# colours (8 threads per replica quad at L = 4, 128 at L = 10, 256 at L = 12;
+# tiles that are not multiples of four leave a quad partly empty),
+# even/odd-x (L = 8, 16), per-site (L = 24); ragged tiles and single-pass
+# workgroups
 SHAPES = [
     (4, [(32, 32), (40, 32), (128, 64), (1000, 256)]),
     (5, [(16, 16), (40, 16), (128, 128)]),
-    (10, [(4, 4), (7, 4), (16, 8), (6, 16)]),
+    (10, [(4, 4), (7, 4), (16, 8), (6, 16), (24, 12)]),
+    (12, [(4, 4), (12, 12), (24, 8), (40, 16)]),
     (8, [(8, 0), (16, 0), (64, 0)]),
     (16, [(2, 0), (4, 0), (14, 0)]),
     (24, [(1, 0), (3, 0)]),
@@ -39,7 +41,7 @@ SHAPES = [
 
 @pytest.mark.parametrize("L,shapes", SHAPES)
 def test_every_sweep_shape_gives_identical_results(L, shapes):
-    R = {4: 700, 5: 300, 10: 90, 8: 333, 16: 40, 24: 7}[L]
+    R = {4: 700, 5: 300, 10: 90, 12: 61, 8: 333, 16: 40, 24: 7}[L]
     inst = instance(L, R, 7, 3, 4.0, disorder_seed=30 + L, seed=40 + L)
     base = run(inst)
     for tr, g in shapes:
