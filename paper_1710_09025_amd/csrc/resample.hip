@@ -5,7 +5,8 @@
 // (floor(tau), frac(tau) 2^32) table), one post launch runs three kinds of
 // workgroups per instance:
 //   copies    n_r = floor(tau) + [u_r < frac(tau) 2^32] for 1024 rows, with
-//             their exclusive scan inside the workgroup;
+//             their exclusive scan inside the workgroup; each also clears
+//             a slice of the step's energy histogram;
 //   families  n ln n of 2048 family ids, summed by the pairwise tree;
 //   overlap   spin overlaps of 2048 replica pairs (at overlap steps).
 // The last workgroup of an instance to finish scans the per-workgroup
@@ -256,6 +257,14 @@ __global__ __launch_bounds__(1024) void k_post(const Inst *insts, const Work *wo
     const int k = *I.k;
     if (!inst_live(I, k)) return;
     if (w.role == kRoleCopies) {
+        // the step's energy histogram (+-1 couplings) has been measured:
+        // the nblk copies workgroups clear it for the next sweep, a slice
+        // each, off the measurement's serial path
+        if (!I.real) {
+            const int per = (I.nlev + I.nblk - 1) / I.nblk;
+            const int m0 = (int)(w.row0 / kRowsPerBlock) * per, m1 = min(I.nlev, m0 + per);
+            for (int m = m0 + (int)threadIdx.x; m < m1; m += blockDim.x) I.hist[m] = 0u;
+        }
         if (k < I.nT - 1) copies_role(I, k, w.row0, sh);
     } else if (w.role == kRoleFamilies) {
         families_role(I, k, w.row0, a);

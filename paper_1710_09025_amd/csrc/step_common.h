@@ -214,37 +214,79 @@ __device__ __forceinline__ bool last_workgroup(uint32_t *counter, int expected)
 // (exact integers), and for k < nT-1 the level weights w[m] = exp(-2 dbeta m)
 // as a fixed product of rho^(2^b), their normaliser S by the pairwise tree
 // over 2^ceil(log2(M+1)) levels, and the table (floor(tau), floor(frac(tau)
-// 2^32)) with tau = R w / S.  Clears the histogram and moves the buffer roles
-// on when the sweep wrote the other buffer.  NT bounds the workgroup size
-// (scratch capacity); any workgroup of a multiple of 64 threads works.
+// 2^32)) with tau = R w / S.  Moves the buffer roles on when the sweep wrote
+// the other buffer; the post launch that follows clears the histogram.  NT
+// bounds the workgroup size (scratch capacity); any workgroup of a multiple
+// of 64 threads works.  This runs in one workgroup while the rest of the GPU
+// waits, so every global load it needs is issued as early as possible.
 template <int NT>
 __device__ void measure_step(const Inst &I, int k)
 {
-    __shared__ int64_t sh64[16];
-    __shared__ int32_t sh32[16];
+    __shared__ int64_t sh64[2][16];
+    __shared__ int32_t sh32[2][16];
     __shared__ double tree[NT];
     __shared__ double roots[NT];
     __shared__ double pw[40];
-    const int N3 = 3 * I.N;
+    const bool resample = k < I.nT - 1;
+    // loaded before the histogram pass so that their latency overlaps it
+    const double rho_k = resample ? I.rho[k] : 1.0;
+    const double Rd = resample ? I.Rt[k + 1] : 0.0;  // nominal population at beta_{k+1}
+    const uint32_t Rk = I.Rk[k];
+    const int N3 = 3 * I.N, nlev = I.nlev, nt = (int)blockDim.x;
     int64_t s1 = 0, s2 = 0;
     int32_t lmin = 0x7FFFFFFF, lmax = -1;
-    for (int m = threadIdx.x; m < I.nlev; m += blockDim.x) {
-        const uint32_t c = I.hist[m];
-        if (c) {
+    // the counts come from memory (the election invalidated the L2): each
+    // thread issues its loads eight at a time before using any of them, so
+    // the pass waits for about one memory latency per eight levels per
+    // thread rather than one per level
+    for (int base = threadIdx.x; base < nlev; base += 8 * nt) {
+        uint32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int m = base + u * nt;
+            c[u] = m < nlev ? I.hist[m] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (!c[u]) continue;
+            const int m = base + u * nt;
             const int64_t e = 2 * m - N3;
-            s1 += (int64_t)c * e;
-            s2 += (int64_t)c * e * e;
+            s1 += (int64_t)c[u] * e;
+            s2 += (int64_t)c[u] * e * e;
             lmin = min(lmin, m);
             lmax = max(lmax, m);
         }
     }
-    s1 = block_reduce<int64_t>(s1, sh64, [](int64_t a, int64_t b) { return a + b; });
-    s2 = block_reduce<int64_t>(s2, sh64, [](int64_t a, int64_t b) { return a + b; });
-    lmin = block_reduce<int32_t>(lmin, sh32, [](int32_t a, int32_t b) { return min(a, b); });
-    lmax = block_reduce<int32_t>(lmax, sh32, [](int32_t a, int32_t b) { return max(a, b); });
+    // the four reductions in one pass: within each wave, then over the waves
+    for (int off = 32; off > 0; off >>= 1) {
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+        lmin = min(lmin, __shfl_xor(lmin, off));
+        lmax = max(lmax, __shfl_xor(lmax, off));
+    }
+    {
+        const int wave = threadIdx.x >> 6, nw = (nt + 63) >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            sh64[0][wave] = s1;
+            sh64[1][wave] = s2;
+            sh32[0][wave] = lmin;
+            sh32[1][wave] = lmax;
+        }
+        __syncthreads();
+        s1 = sh64[0][0];
+        s2 = sh64[1][0];
+        lmin = sh32[0][0];
+        lmax = sh32[1][0];
+        for (int i = 1; i < nw; ++i) {
+            s1 += sh64[0][i];
+            s2 += sh64[1][i];
+            lmin = min(lmin, sh32[0][i]);
+            lmax = max(lmax, sh32[1][i]);
+        }
+    }
     StepRec *rec = I.rec + k;
     if (threadIdx.x == 0) {
-        rec->R = I.Rk[k];
+        rec->R = Rk;
         rec->sumE = s1;
         rec->sumE2 = (uint64_t)s2;
         rec->sumE2_hi = 0;
@@ -252,9 +294,9 @@ __device__ void measure_step(const Inst &I, int k)
         rec->Emax = 2 * lmax - N3;
         rec->S = __builtin_nan("");
     }
-    if (k < I.nT - 1) {
+    if (resample) {
         if (threadIdx.x == 0) {
-            pw[0] = I.rho[k];
+            pw[0] = rho_k;
             for (int b = 1; b < 40; ++b) pw[b] = pw[b - 1] * pw[b - 1];
         }
         __syncthreads();
@@ -265,7 +307,6 @@ __device__ void measure_step(const Inst &I, int k)
             P,
             [&](int m) { return m < nl ? (double)I.hist[lmin + m] * level_weight(pw, (uint32_t)m) : 0.0; },
             tree, roots);
-        const double Rd = I.Rt[k + 1];  // nominal population at beta_{k+1}
         for (int m = threadIdx.x; m < nl; m += blockDim.x) {
             const double tau = (Rd * level_weight(pw, (uint32_t)m)) / S;
             const double fl = __builtin_floor(tau);
@@ -276,8 +317,6 @@ __device__ void measure_step(const Inst &I, int k)
         }
         if (threadIdx.x == 0) rec->S = S;
     }
-    __syncthreads();
-    for (int m = threadIdx.x; m < I.nlev; m += blockDim.x) I.hist[m] = 0u;
     // the sweep of this step moved the population to the other buffer
     if (threadIdx.x == 0 && *I.mapped) {
         *I.cur ^= 1;
