@@ -109,6 +109,7 @@ struct Inst {
     const uint16_t *grp;// lex layout: [ncol][gmax][4] sites of each Philox block (0xFFFF: none)
     const uint32_t *jeo;// EO layout: [2][N/8][6] coupling words per block
     const uint16_t *pos;// [N] storage position of each lexicographic site
+    const uint16_t *lexof; // [row_bytes] lexicographic site at each storage position (0xFFFF: padding)
     // CM layout: per colour and Philox block, the 24 LDS byte offsets (within
     // a replica slot) of the 6 neighbours of its 4 sites, in the spin copy or,
     // for a -1 coupling, in the complemented copy at +row_bytes; word 24 is

@@ -128,7 +128,7 @@ struct Carve {
 
 struct InstLayout {
     size_t ctl, status, sync, spins0, spins1, E0, E1, f0, f1, map, loff, bsum, boff, hist, BF, cnt, fpart, thr,
-        beta, rho, Rt, site, grp, jeo, J, pos, cmdesc, Rk, rec, ovl_slot, qhist, Eq0, Eq1, wrep, wpart, emom, cmj,
+        beta, rho, Rt, site, grp, jeo, J, pos, lexof, cmdesc, Rk, rec, ovl_slot, qhist, Eq0, Eq1, wrep, wpart, emom, cmj,
         bq, gpw, total;
 };
 
@@ -171,6 +171,7 @@ InstLayout layout_of(int L, int64_t R, int64_t Rcap, int nT, int n_ovl, bool pac
     l.jeo = c.take((size_t)2 * (N / 8 + 1) * 6 * 4);
     l.J = c.take((size_t)dim * N * (real ? 4 : 1));
     l.pos = c.take((size_t)N * 2);
+    l.lexof = c.take((size_t)li.row_bytes * 2);
     l.cmdesc = li.layout == kLayoutCM ? c.take((size_t)ncol * gmax * 32 * 2) : c.take(16);
     l.Rk = c.take((size_t)(nT + 1) * 4);
     l.rec = c.take((size_t)nT * sizeof(StepRec));
@@ -378,6 +379,7 @@ int Runner::upload_inst(int i)
     d.grp = (const uint16_t *)(b + lay.grp);
     d.jeo = (const uint32_t *)(b + lay.jeo);
     d.pos = (const uint16_t *)(b + lay.pos);
+    d.lexof = (const uint16_t *)(b + lay.lexof);
     d.cmdesc = (const uint16_t *)(b + lay.cmdesc);
     d.k = (int32_t *)(b + lay.ctl);
     d.cur = d.k + 1;
@@ -467,6 +469,10 @@ int Runner::upload_inst(int i)
             h.lex_pos[s] = li.cbase[col[s]] + rank[s];
         pos16[s] = (uint16_t)h.lex_pos[s];
     }
+    // its inverse over the storage positions of a row (cluster moves read
+    // rows in storage order)
+    std::vector<uint16_t> lexof16((size_t)h.row_bytes, (uint16_t)0xFFFF);
+    for (int s = 0; s < N; ++s) lexof16[(size_t)h.lex_pos[s]] = (uint16_t)s;
     std::vector<uint16_t> cmdesc;
     std::vector<int32_t> cmj;
     std::vector<uint32_t> site((size_t)N * 4, 0u);
@@ -600,6 +606,8 @@ int Runner::upload_inst(int i)
         HIPCHK(hipMemcpyAsync(b + lay.cmj, cmj.data(), cmj.size() * 4, hipMemcpyHostToDevice, stream_),
                "upload couplings per neighbour word");
     HIPCHK(hipMemcpyAsync(b + lay.pos, pos16.data(), pos16.size() * 2, hipMemcpyHostToDevice, stream_), "upload pos");
+    HIPCHK(hipMemcpyAsync(b + lay.lexof, lexof16.data(), lexof16.size() * 2, hipMemcpyHostToDevice, stream_),
+           "upload lexof");
     if (!cmdesc.empty())
         HIPCHK(hipMemcpyAsync(b + lay.cmdesc, cmdesc.data(), cmdesc.size() * 2, hipMemcpyHostToDevice, stream_),
                "upload cm descriptors");
