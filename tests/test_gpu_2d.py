@@ -70,7 +70,9 @@ def test_pm_j_instance_as_real_couplings():
     assert np.all(E % (2 << 20) == 0)
 
 
-@pytest.mark.parametrize("L,R,nT,NS", [(4, 400, 11, 6), (8, 501, 15, 10), (16, 200, 9, 4), (25, 64, 7, 4)])
+# 16 lanes per pair up to 1024 sites (L = 32), 32 lanes beyond (L = 40)
+@pytest.mark.parametrize("L,R,nT,NS", [(4, 400, 11, 6), (8, 501, 15, 10), (16, 200, 9, 4), (25, 64, 7, 4),
+                                       (40, 30, 5, 2)])
 def test_cluster_moves_bit_exact(L, R, nT, NS):
     inst = inst2d(L, R, nT, NS, 4.0, 900 + L, 950 + L)
     p, st = gpu(inst, icm_rounds=2)
