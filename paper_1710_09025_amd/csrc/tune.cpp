@@ -13,8 +13,8 @@
 // temperature.
 // Every shape gives bit-identical results, so the choice only affects
 // speed.  Choices are cached for the life of the process, keyed by kernel,
-// L, sweeps per step, the capacity rounded up to a power of two and the
-// spin storage format.
+// lattice (dimension and L), sweeps per step, the capacity rounded up to a
+// power of two and the spin storage format.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -55,7 +55,7 @@ struct Choice {
 };
 
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int>, Choice> g_cache;
+std::map<std::tuple<int, int, int, int, int, int>, Choice> g_cache;
 
 int ceil_log2(int64_t v)
 {
@@ -135,11 +135,11 @@ std::vector<std::pair<int, int>> shape_candidates(const HostInst &h)
 
 int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
 {
-    const auto key = std::make_tuple(h.variant, h.L, h.NS, ceil_log2(h.Rcap), h.packed);
+    const auto key = std::make_tuple(h.variant, h.dim, h.L, h.NS, ceil_log2(h.Rcap), h.packed);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find(key);
-        if (it != g_cache.end()) {
+        if (it != g_cache.end() && shape_valid(h, it->second.tile_rows, it->second.rp, nullptr)) {
             h.tile_rows = it->second.tile_rows;
             h.rp = it->second.rp;
             if (ns_per_attempt) *ns_per_attempt = it->second.ns_per_attempt;

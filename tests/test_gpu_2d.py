@@ -156,3 +156,19 @@ def test_step_parity_L32_large_population(k):
     go, rec = p.observables(), o.records()
     assert go["sum_E"][k] == rec["sumE"][k] and go["sum_E2"][k] == rec["sumE2"][k]
     assert p.step_sums()[0][k] == rec["S"][k]
+
+
+def test_autotuned_shapes_are_kept_apart_from_the_cubic_lattice():
+    """The tuner's cache tells the two lattices of one L apart: a cubic and a
+    square instance with the same L and population, tuned in one process,
+    each run on a shape of its own and match the oracle."""
+    from paper_1710_09025_amd import Pamc
+
+    beta = pi.linear_beta(4.0, 9)
+    cubic = Pamc(8, pi.gaussian_couplings(8, 3), 3000, beta, 4, 5, autotune=True)
+    inst = dict(L=8, couplings=pi.gaussian_couplings(8, 4, dim=2), R=3000, beta=beta, sweeps=4, seed=6)
+    p, st = gpu(inst, autotune=True)
+    assert st == 0 and cubic.anneal() == 0
+    o, sto = orc(inst)
+    assert sto == 0
+    compare_state(p.get_state(), o.get_state(), "2D after a cubic tuning")
