@@ -5,8 +5,9 @@ Couplings are int8 +-1, or int32 fixed-point real couplings J = j 2^-20
 with |J| < 8 (the paper's Gaussian case study, Sec. II.A); the dtype of the
 array picks the model.  Their shape picks the lattice: [3][L^3] is the
 periodic cubic lattice, [2][L^2] the periodic square lattice (Sec. II.A
-studies both; 2D takes real couplings).  Energies of real-coupling runs (E_min, E_max, sum_E,
-sum_E2, state energies) are exact integers in units of 2^-20.
+studies both; 2D takes real couplings).  Energies of real-coupling runs
+(E_min, E_max, sum_E, sum_E2, state energies) are exact integers in units
+of 2^-20.
 
 Python binding of the C ABI in ``include/pamc.h``: it marshals arguments and
 results; every step of the method runs in the HIP kernels of ``libpamc.so``.
