@@ -172,3 +172,16 @@ def test_autotuned_shapes_are_kept_apart_from_the_cubic_lattice():
     o, sto = orc(inst)
     assert sto == 0
     compare_state(p.get_state(), o.get_state(), "2D after a cubic tuning")
+
+
+@pytest.mark.parametrize("L", [5, 16, 32])
+def test_packed_spins_equal_bytes(L):
+    """Bit-packed rows (one bit per site in HBM) give the byte-row run bit for
+    bit on the square lattice too (rows of 16 to 128 packed bytes)."""
+    inst = inst2d(L, 300, 9, 4, 4.0, 110 + L, 120 + L)
+    a, st = gpu(inst)
+    b, st2 = gpu(inst, packed=True)
+    assert st == st2 == 0
+    compare_state(a.get_state(), b.get_state(), f"2D packed L={L}")
+    for key in ("R", "sum_E", "sum_E2", "lnZ", "S_f"):
+        np.testing.assert_array_equal(a.observables()[key], b.observables()[key], err_msg=f"2D packed L={L}: {key}")
