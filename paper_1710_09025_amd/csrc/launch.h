@@ -6,7 +6,8 @@
 
 namespace pamc {
 
-// CM: colour-major, +-1 couplings; CQ: colour-major, real couplings
+// CM: colour-major, +-1 couplings; CQ: colour-major, real couplings; SQ:
+// CQ on the square lattice (four neighbours)
 enum SweepVariant {
     kSweepLex = 0,
     kSweepEO8 = 1,
@@ -14,7 +15,9 @@ enum SweepVariant {
     kSweepCM2 = 3,
     kSweepCM3 = 4,
     kSweepCQ2 = 5,
-    kSweepCQ3 = 6
+    kSweepCQ3 = 6,
+    kSweepSQ2 = 7,
+    kSweepSQ3 = 8
 };
 
 // Dynamic LDS a sweep workgroup may take: gfx950 gives one workgroup up to

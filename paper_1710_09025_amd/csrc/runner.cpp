@@ -93,7 +93,7 @@ LayoutInfo layout_for(int L, bool real, int dim)
         if (tpr <= 1024 && 2 * rb <= 65535 &&
             4 * (size_t)cm_plane_bytes(rb) * cm_replicas_per_block(tpr) + 32 + 8 * 64 <= kMaxSweepLds) {
             li.layout = kLayoutCM;
-            li.variant = li.ncol == 2 ? kSweepCQ2 : kSweepCQ3;
+            li.variant = dim == 2 ? (li.ncol == 2 ? kSweepSQ2 : kSweepSQ3) : (li.ncol == 2 ? kSweepCQ2 : kSweepCQ3);
             li.row_bytes = rb;
             li.tpr = tpr;
         } else {

@@ -895,14 +895,17 @@ __global__ __launch_bounds__(MAXT, MAXT <= 512 ? 3 : 4) void k_sweep_cm(const In
 // S S_nb = 1 - 2 sigma,
 //   dE = 2 S sum_d J_d S_d = 2 sum_d J_d - 4 sum_d sigma_d J_d,
 // where sigma_d J_d is the sign-extended byte ANDed with j.  Each
-// thread keeps the 24 neighbour addresses and the 24 couplings of its block
-// of every colour in registers.  Energy: every bond is seen from both of its
+// thread keeps the 4 NB neighbour addresses and couplings of its block of
+// every colour in registers (NB = 6 on the cubic lattice; the square-lattice
+// kernel reads the first NB = 4 directions of the same tables, whose z
+// entries are zero bonds).  Energy: every bond is seen from both of its
 // sites, so E = -sum_b J_b + sum over sites of sum_d sigma_d J_d.
 // ---------------------------------------------------------------------------
+template <int NB>
 struct CQBlock {
-    uint32_t nb[24];  // LDS offsets of the neighbour words, [direction][site]
-    int32_t j[24];    // coupling of each of those bonds (units of 2^-20)
-    int32_t j2[4];    // twice the sum of the six couplings of each site
+    uint32_t nb[4 * NB];  // LDS offsets of the neighbour words, [direction][site]
+    int32_t j[4 * NB];    // coupling of each of those bonds (units of 2^-20)
+    int32_t j2[4];        // twice the sum of the couplings of each site
     uint32_t own;     // LDS offset of site 0's word (site i at + i plane_bytes)
     uint32_t vbits;   // bit i set when site i of the block is a real site
     uint32_t ctr;     // Philox counter word 0
@@ -911,11 +914,13 @@ struct CQBlock {
 
 // sum_d sigma_d J_d of site i of block b for the four replicas (bytes of the
 // XOR words, 0x00 or 0xFF), given the site's own word.
-__device__ __forceinline__ void cq_field(const uint8_t *lds, const CQBlock &b, int i, uint32_t own, int32_t (&a)[4])
+template <int NB>
+__device__ __forceinline__ void cq_field(const uint8_t *lds, const CQBlock<NB> &b, int i, uint32_t own,
+                                         int32_t (&a)[4])
 {
     a[0] = a[1] = a[2] = a[3] = 0;
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
+    for (int d = 0; d < NB; ++d) {
         const uint32_t x = own ^ lds_word(lds, b.nb[4 * d + i]);
         const int32_t jj = b.j[4 * d + i];
 #pragma unroll
@@ -934,8 +939,8 @@ __device__ __forceinline__ uint4 spin_01(uint4 v)
     return make_uint4(v.x & 0x01010101u, v.y & 0x01010101u, v.z & 0x01010101u, v.w & 0x01010101u);
 }
 
-template <int NCOL, bool ALL>
-__device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, const CQBlock (&blk)[NCOL], float bq,
+template <int NCOL, bool ALL, int NB>
+__device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, const CQBlock<NB> (&blk)[NCOL], float bq,
                                           unsigned long long *eacc, const TileIO &io, int r0, int nrows, int phase)
 {
     const int tpr = I.tpr;
@@ -975,7 +980,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
         for (int t = phase_t0(I, phase); t < t1; ++t) {
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
-                const CQBlock &b = blk[c];
+                const CQBlock<NB> &b = blk[c];
                 if (act && b.has) {
                     uint32_t own[4], flip[4];
 #pragma unroll
@@ -1109,7 +1114,7 @@ __device__ __forceinline__ void tile_moments_real(const Inst &I, const TileIO &i
     }
 }
 
-template <int NCOL>
+template <int NCOL, int NB>
 __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows,
                                               int phase)
 {
@@ -1120,7 +1125,7 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
     const uint32_t slot = (uint32_t)(qsub * 4 * ps);
-    CQBlock blk[NCOL];
+    CQBlock<NB> blk[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) {
         const int g = lane_r;
@@ -1130,14 +1135,17 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
         const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
         const int32_t *jd = I.cmj + ((size_t)c * I.gmax + gg) * 24;
 #pragma unroll
-        for (int i = 0; i < 24; ++i) {
+        for (int i = 0; i < 4 * NB; ++i) {
             blk[c].nb[i] = slot + quad_pos((uint32_t)d[i], (uint32_t)ps);
             blk[c].j[i] = jd[i];
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            blk[c].j2[i] = 2 * (blk[c].j[i] + blk[c].j[4 + i] + blk[c].j[8 + i] + blk[c].j[12 + i] + blk[c].j[16 + i] +
-                                blk[c].j[20 + i]);
+        for (int i = 0; i < 4; ++i) {
+            int32_t s2 = 0;
+#pragma unroll
+            for (int dd = 0; dd < NB; ++dd) s2 += blk[c].j[4 * dd + i];
+            blk[c].j2[i] = 2 * s2;
+        }
         const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
         blk[c].vbits = (vm & 1u) | ((vm >> 7) & 2u) | ((vm >> 14) & 4u) | ((vm >> 21) & 8u);
         blk[c].own = slot + (uint32_t)(I.cbase[c] + 4 * gg);
@@ -1147,9 +1155,9 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
     for (int q = threadIdx.x; q < tile_rows; q += blockDim.x) eacc[q] = 0ull;
     __syncthreads();
     if (all)
-        cq_passes<NCOL, true>(I, k, lds, blk, bq, eacc, io, r0, nrows, phase);
+        cq_passes<NCOL, true, NB>(I, k, lds, blk, bq, eacc, io, r0, nrows, phase);
     else
-        cq_passes<NCOL, false>(I, k, lds, blk, bq, eacc, io, r0, nrows, phase);
+        cq_passes<NCOL, false, NB>(I, k, lds, blk, bq, eacc, io, r0, nrows, phase);
     __syncthreads();
     if (io.map)
         for (int q = threadIdx.x; q < nrows; q += blockDim.x) io.fdst[r0 + q] = io.fsrc[io.map[r0 + q]];
@@ -1169,7 +1177,26 @@ __global__ __launch_bounds__(MAXT, 2) void k_sweep_cq(const Inst *insts, const W
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_cq<NCOL>(I, k, lds, r0, nrows, tile_rows, phase);
+    if (nrows > 0) sweep_tile_cq<NCOL, 6>(I, k, lds, r0, nrows, tile_rows, phase);
+    if (phase == 1)
+        phase1_done(I);
+    else if (last_workgroup(&I.sync[0], I.sweep_tiles))
+        measure_step_real(I, k);
+}
+
+// The same on the square lattice: four neighbours per site.
+template <int NCOL, int MAXT>
+__global__ __launch_bounds__(MAXT, 2) void k_sweep_sq(const Inst *insts, const Work *work, int tile_rows, int phase)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const Work w = work[blockIdx.x];
+    const Inst &I = inst_ref(insts, w.inst);
+    const int k = *I.k;
+    if (k >= I.nT || I.status[0]) return;
+    const int Rk = (int)I.Rk[k];
+    const int r0 = (int)w.row0;
+    const int nrows = min(tile_rows, Rk - r0);
+    if (nrows > 0) sweep_tile_cq<NCOL, 4>(I, k, lds, r0, nrows, tile_rows, phase);
     if (phase == 1)
         phase1_done(I);
     else if (last_workgroup(&I.sync[0], I.sweep_tiles))
@@ -1187,7 +1214,9 @@ hipError_t sweep_kernels_init()
         reinterpret_cast<const void *>(&k_sweep_cm<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<3, 512>),
         reinterpret_cast<const void *>(&k_sweep_cm<3, 1024>), reinterpret_cast<const void *>(&k_sweep_cq<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_cq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cq<3, 512>),
-        reinterpret_cast<const void *>(&k_sweep_cq<3, 1024>),
+        reinterpret_cast<const void *>(&k_sweep_cq<3, 1024>), reinterpret_cast<const void *>(&k_sweep_sq<2, 512>),
+        reinterpret_cast<const void *>(&k_sweep_sq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_sq<3, 512>),
+        reinterpret_cast<const void *>(&k_sweep_sq<3, 1024>),
     };
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
@@ -1228,6 +1257,23 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
                 k_sweep_cm<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
             else
                 k_sweep_cm<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        }
+        return;
+    }
+    if (variant == kSweepSQ2 || variant == kSweepSQ3) {
+        // as below, on the square lattice
+        const size_t lds = 4 * (size_t)cm_plane_bytes(row_bytes) * rp + 32 + 8 * (size_t)tile_rows;
+        const int nt = tpr * rp;
+        if (variant == kSweepSQ2) {
+            if (nt <= 512)
+                k_sweep_sq<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+            else
+                k_sweep_sq<2, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        } else {
+            if (nt <= 512)
+                k_sweep_sq<3, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+            else
+                k_sweep_sq<3, 1024><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
         }
         return;
     }

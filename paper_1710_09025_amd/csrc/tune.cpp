@@ -37,9 +37,13 @@ constexpr double kTuneBeta = 2.0;   // inside the low-temperature part where an 
 
 bool is_cm(const HostInst &h)
 {
-    return h.variant == kSweepCM2 || h.variant == kSweepCM3 || h.variant == kSweepCQ2 || h.variant == kSweepCQ3;
+    return h.variant == kSweepCM2 || h.variant == kSweepCM3 || h.variant == kSweepCQ2 || h.variant == kSweepCQ3 ||
+           h.variant == kSweepSQ2 || h.variant == kSweepSQ3;
 }
-bool is_cq(const HostInst &h) { return h.variant == kSweepCQ2 || h.variant == kSweepCQ3; }
+bool is_cq(const HostInst &h)
+{
+    return h.variant == kSweepCQ2 || h.variant == kSweepCQ3 || h.variant == kSweepSQ2 || h.variant == kSweepSQ3;
+}
 bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kSweepEO16; }
 
 int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
