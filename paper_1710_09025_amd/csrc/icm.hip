@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     }
     wave_sync();
     // breadth-first growth of the island, one frontier per iteration; the
-    // queue only grows and holds each site once, so this ends within N
-    // iterations
+    // queue only grows and holds each site of the island once (at most
+    // cnt <= N / 2 of them), so this ends within N iterations
     int head = 0;
     while (true) {
         const int tail = *reinterpret_cast<volatile int *>(tailp);

@@ -37,11 +37,12 @@ inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : 
 
 // LDS of one cluster-move pair (the island search of one lane group): the
 // sector flag of every lexicographic site (bytes), the visited bits, the
-// island queue (16-bit site indices) and its tail, each part a multiple of
-// 16 bytes, so that every pair's slice starts 16-byte aligned.
+// island queue (16-bit site indices; an island lies in the smaller sector,
+// so it holds at most (N + 1) / 2 sites) and its tail, each part a multiple
+// of 16 bytes, so that every pair's slice starts 16-byte aligned.
 constexpr int icm_pair_bytes(int N)
 {
-    return ((N + 15) & ~15) + ((4 * ((N + 31) / 32) + 15) & ~15) + ((2 * N + 15) & ~15) + 16;
+    return ((N + 15) & ~15) + ((4 * ((N + 31) / 32) + 15) & ~15) + ((2 * ((N + 1) / 2) + 15) & ~15) + 16;
 }
 // the largest lattice the library accepts (L = 32) fits one pair per workgroup
 static_assert(icm_pair_bytes(32 * 32 * 32) <= kMaxSweepLds, "cluster-move pair exceeds the LDS of a workgroup");
