@@ -185,3 +185,25 @@ def test_packed_spins_equal_bytes(L):
     compare_state(a.get_state(), b.get_state(), f"2D packed L={L}")
     for key in ("R", "sum_E", "sum_E2", "lnZ", "S_f"):
         np.testing.assert_array_equal(a.observables()[key], b.observables()[key], err_msg=f"2D packed L={L}: {key}")
+
+
+@pytest.mark.parametrize("L", [6, 16])
+def test_schedules_population_and_overlaps(L):
+    """The square lattice with the LBLT schedule, the clipped exponential
+    population schedule R(beta) and spin overlaps at several steps: every
+    record bit-exact, the overlap moments within 1e-12."""
+    beta = pi.lblt_beta(5.0, 31)
+    pop = pi.clipped_exponential_population(beta, 500)
+    J = pi.gaussian_couplings(L, 130 + L, dim=2)
+    steps = [5, 15, 30]
+    from paper_1710_09025_amd import Pamc
+
+    p = Pamc(L, J, int(pop[0]), beta, 4, 140 + L, pop_schedule=pop, overlap_steps=steps)
+    assert p.anneal() == 0
+    o = oracle.Oracle(L, J, int(pop[0]), beta, 4, 140 + L, threads=THREADS, pop_schedule=pop, overlap_steps=steps)
+    assert o.run() == 0
+    compare_state(p.get_state(), o.get_state(), f"2D schedules L={L}")
+    compare_run(p.observables(), p.step_sums(), o, what=f"2D schedules L={L}")
+    rec = o.records()
+    for k in steps:
+        np.testing.assert_array_equal(p.overlap_hist(k), rec["qhist"][k], err_msg=f"2D overlap histogram step {k}")
