@@ -393,7 +393,7 @@ def icm_bench(name, rounds=2):
     obs = p.observables()
     p.close()
     torch.cuda.empty_cache()
-    att = attempts_of(obs, cfg["L"] ** 3, cfg["sweeps"])
+    att = attempts_of(obs, cfg["L"] ** cfg.get("dim", 3), cfg["sweeps"])
     pairs = rounds * int(np.sum(obs["R"][1:] // 2))
     return {"icm_rounds": rounds, "attempts_per_ns": round(att / ((t1 - t0) * 1e9), 3),
             "ms_per_anneal": round((t1 - t0) * 1e3, 3), "pair_updates": pairs,
@@ -581,6 +581,8 @@ def main():
             "sweep_share": round(s["sweep_ms"] / (s["sweep_ms"] + s["other_ms"]), 4),
             "sweep_shape": {"tile_rows": s["shape"][0], "group_replicas": s["shape"][1]},
         }
+        # the same with two cluster-move rounds per step, the paper's 2D setting
+        extra["L32_2D_R1000000_icm"] = icm_bench("L32_2D_R1000000")
         # rho_f is intensive (independent of R once R >> rho_f), so the larger
         # lattices use R = 5 10^4 to afford more runs and instances
         extra["rho_f_2D_L8"] = rho_f_square_bench()

@@ -62,6 +62,108 @@ __device__ __forceinline__ int group_sum(int v)
     return v;
 }
 
+// Island growth on the square lattice as a bit-parallel flood fill: row y
+// of the sector is the L-bit word Mr[y] (bit x = site x + L y) and the
+// island so far is Vr[y].  A pass replaces each row's island bits by the runs
+// of Mr[y] (cyclic in x) that contain an island bit or a site below an
+// island bit of row y - 1 or y + 1; the set only grows and stays connected
+// to the seed, and a pass that changes no row leaves it closed under the
+// four bonds, i.e. it is then the seed's connected component, the same set
+// the breadth-first search finds.  The runs come from a doubling scan in
+// each direction: after the scan with shift r, bit x is set when a seed bit
+// lies within 2r - 1 sites before it with the whole stretch in the sector.
+template <typename W>
+__device__ __forceinline__ W rot_up(W v, int r, int L, W mask)
+{
+    return ((v << r) | (v >> (L - r))) & mask;
+}
+
+template <typename W>
+__device__ __forceinline__ W rot_down(W v, int r, int L, W mask)
+{
+    return ((v >> r) | (v << (L - r))) & mask;
+}
+
+template <typename W>
+__device__ __forceinline__ W row_runs(W m, W seed, int L, W mask)
+{
+    W fu = seed & m, fd = fu, pu = m, pd = m;
+    for (int r = 1; r < L; r <<= 1) {
+        fu |= pu & rot_up(fu, r, L, mask);
+        fd |= pd & rot_down(fd, r, L, mask);
+        pu &= rot_up(pu, r, L, mask);
+        pd &= rot_down(pd, r, L, mask);
+    }
+    return fu | fd;
+}
+
+// The rows live in the pair's queue area: 2 L words of W fit there for
+// 8 <= L (4-byte words up to L = 32, 8-byte words above, where N > 1024).
+// Lane gl owns rows gl and gl + GS (L <= 2 GS on the square lattice).  On
+// return the island's bits are ORed into vis (which holds the seed).
+template <typename W, int GS>
+__device__ __forceinline__ void flood_square(const uint8_t *member, uint32_t *vis, uint16_t *queue, int L, int gl)
+{
+    const int s0 = queue[0];
+    wave_sync();  // the seed is read before the rows overwrite the queue
+    W *Mr = reinterpret_cast<W *>(queue);
+    W *Vr = Mr + L;
+    const W mask = L == (int)(8 * sizeof(W)) ? ~(W)0 : (((W)1 << L) - 1);
+    const int y0 = s0 / L, x0 = s0 - y0 * L;
+    W m[2], v[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int y = gl + i * GS;
+        m[i] = 0;
+        v[i] = 0;
+        if (y >= L) continue;
+        const uint8_t *row = member + y * L;
+        if ((L & 3) == 0) {
+            for (int x = 0; x < L; x += 4) {
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x);
+                m[i] |= (W)((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) << x;
+            }
+        } else {
+            for (int x = 0; x < L; ++x) m[i] |= (W)row[x] << x;
+        }
+        v[i] = y == y0 ? (W)1 << x0 : (W)0;
+        Vr[y] = v[i];
+    }
+    wave_sync();
+    // every pass but the last adds a site, so at most N + 1 passes
+    for (int pass = 0; pass <= L * L; ++pass) {
+        int changed = 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int y = gl + i * GS;
+            if (y >= L) continue;
+            const W nbv = Vr[y == 0 ? L - 1 : y - 1] | Vr[y == L - 1 ? 0 : y + 1];
+            const W f = row_runs<W>(m[i], v[i] | (m[i] & nbv), L, mask);
+            if (f != v[i]) {
+                v[i] = f;
+                Vr[y] = f;
+                changed = 1;
+            }
+        }
+        changed = group_sum<GS>(changed);
+        wave_sync();
+        if (!changed) break;
+    }
+    // bits y L .. y L + L - 1 of the site bitmap: at most three words
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int y = gl + i * GS;
+        if (y >= L || v[i] == 0) continue;
+        const uint64_t f = (uint64_t)v[i];
+        const int p = y * L, w = p >> 5, sh = p & 31;
+        const uint32_t p0 = (uint32_t)(f << sh), p1 = (uint32_t)(f >> (32 - sh));
+        const uint32_t p2 = sh ? (uint32_t)(f >> (64 - sh)) : 0u;
+        if (p0) atomicOr(&vis[w], p0);
+        if (p1) atomicOr(&vis[w + 1], p1);
+        if (p2) atomicOr(&vis[w + 2], p2);
+    }
+}
+
 // One ICM round.  A lane group of GS lanes updates one pair (work item =
 // instance, pair index j) on its own slice of LDS, so the island search
 // synchronises only inside its wave; small lattices take 16 lanes per pair
@@ -69,7 +171,11 @@ __device__ __forceinline__ int group_sum(int v)
 // or LDS latency and more pairs in flight hide it.  Every exit before the
 // end is uniform over a group, and lanes only exchange values within their
 // group.
-template <int GS>
+//
+// UF: row vectors a lane loads at once in the passes over the two rows
+// (2 when a lane has at most two vectors of a row, else 4: more in flight
+// costs registers and occupancy).
+template <int GS, int UF>
 __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work, int nwork, int round, int pair_bytes)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -104,18 +210,33 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     // sites where the replicas differ: both rows read in 16-byte vectors in
     // storage order (one round of loads per 16 positions), each byte
     // compared and its flag stored at the position's lexicographic site
+    // (UF vectors per lane are loaded before the first is used, so that a
+    // lattice of up to UF GS 16 positions costs one round trip to memory;
+    // indexes past the row reload its last vector and are not used)
     int nd = 0;
-    for (int v = gl; v < nvec; v += GS) {
-        const uint4 a = A4[v], b = B4[v], x0 = X4[2 * v], x1 = X4[2 * v + 1];
-        const uint32_t dw[4] = {a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w};
-        const uint32_t xw[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    for (int v0 = gl; v0 < nvec; v0 += UF * GS) {
+        uint4 a[UF], b[UF], x0[UF], x1[UF];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const uint32_t s = (xw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
-            if (s == 0xFFFFu) continue;  // padding position
-            const uint8_t d = (dw[q >> 2] >> (8 * (q & 3))) & 0xFFu ? 1 : 0;
-            member[s] = d;
-            nd += d;
+        for (int u = 0; u < UF; ++u) {
+            const int v = min(v0 + u * GS, nvec - 1);
+            a[u] = A4[v];
+            b[u] = B4[v];
+            x0[u] = X4[2 * v];
+            x1[u] = X4[2 * v + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            if (v0 + u * GS >= nvec) continue;
+            const uint32_t dw[4] = {a[u].x ^ b[u].x, a[u].y ^ b[u].y, a[u].z ^ b[u].z, a[u].w ^ b[u].w};
+            const uint32_t xw[8] = {x0[u].x, x0[u].y, x0[u].z, x0[u].w, x1[u].x, x1[u].y, x1[u].z, x1[u].w};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const uint32_t s = (xw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+                if (s == 0xFFFFu) continue;  // padding position
+                const uint8_t d = (dw[q >> 2] >> (8 * (q & 3))) & 0xFFu ? 1 : 0;
+                member[s] = d;
+                nd += d;
+            }
         }
     }
     // sector flags beyond N stay 0 (the site search reads 16-byte vectors)
@@ -149,24 +270,46 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     }
     const int excl = incl - c;
     if (excl <= m && m < incl) {
-        int seen = excl;
-        for (int s = 16 * c_begin; s < 16 * c_end; ++s)
-            if (member[s]) {
-                if (seen == m) {
-                    queue[0] = (uint16_t)s;
-                    vis[s >> 5] = 1u << (s & 31);
-                    *tailp = 1;
-                    break;
-                }
-                ++seen;
+        // skip whole 4-byte words by their counts, then walk the word that
+        // holds the site
+        int left = m - excl;
+        const uint32_t *M1 = reinterpret_cast<const uint32_t *>(member);
+        for (int wi = 4 * c_begin; wi < 4 * c_end; ++wi) {
+            const uint32_t f = M1[wi];
+            const int pc = __builtin_popcount(f);
+            if (left >= pc) {
+                left -= pc;
+                continue;
             }
+            int b = 0;
+            for (;; ++b)
+                if ((f >> (8 * b)) & 0xFFu) {
+                    if (left == 0) break;
+                    --left;
+                }
+            const int s = 4 * wi + b;
+            queue[0] = (uint16_t)s;
+            vis[s >> 5] = 1u << (s & 31);
+            *tailp = 1;
+            break;
+        }
     }
     wave_sync();
-    // breadth-first growth of the island, one frontier per iteration; the
-    // queue only grows and holds each site of the island once (at most
-    // cnt <= N / 2 of them), so this ends within N iterations
+    bool grown = false;
+    if constexpr (GS <= 32) {
+        if (I.dim == 2 && L >= 8) {
+            if constexpr (GS == 16)
+                flood_square<uint32_t, GS>(member, vis, queue, L, gl);
+            else
+                flood_square<uint64_t, GS>(member, vis, queue, L, gl);
+            grown = true;
+        }
+    }
+    // otherwise breadth-first growth of the island, one frontier per
+    // iteration; the queue only grows and holds each site of the island
+    // once (at most cnt <= N / 2 of them), so this ends within N iterations
     int head = 0;
-    while (true) {
+    while (!grown) {
         const int tail = *reinterpret_cast<volatile int *>(tailp);
         if (head >= tail) break;
         wave_sync();
@@ -192,32 +335,46 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
         head = tail;
         wave_sync();
     }
+    wave_sync();
     // flip the island in both replicas: the visited bits are exactly the
     // island, so each 16-byte vector of the two rows (storage order) gets a
     // byte mask from the bits of its positions' sites and is rewritten when
     // any of its bytes flips; the rows and the site table are loaded
     // together, one round per vector whatever the island's size (the pairs
     // of a round are disjoint, so no other group writes these rows)
-    for (int v = gl; v < nvec; v += GS) {
-        const uint4 x0 = X4[2 * v], x1 = X4[2 * v + 1], a = A4[v], b = B4[v];
-        const uint32_t xw[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        uint32_t fw[4] = {0u, 0u, 0u, 0u};
+    for (int v0 = gl; v0 < nvec; v0 += UF * GS) {
+        uint4 a[UF], b[UF], x0[UF], x1[UF];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const uint32_t t = (xw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
-            if (t != 0xFFFFu && ((vis[t >> 5] >> (t & 31)) & 1u)) fw[q >> 2] |= 1u << (8 * (q & 3));
+        for (int u = 0; u < UF; ++u) {
+            const int v = min(v0 + u * GS, nvec - 1);
+            x0[u] = X4[2 * v];
+            x1[u] = X4[2 * v + 1];
+            a[u] = A4[v];
+            b[u] = B4[v];
         }
-        if (fw[0] | fw[1] | fw[2] | fw[3]) {
-            A4[v] = make_uint4(a.x ^ fw[0], a.y ^ fw[1], a.z ^ fw[2], a.w ^ fw[3]);
-            B4[v] = make_uint4(b.x ^ fw[0], b.y ^ fw[1], b.z ^ fw[2], b.w ^ fw[3]);
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            const int v = v0 + u * GS;
+            if (v >= nvec) continue;
+            const uint32_t xw[8] = {x0[u].x, x0[u].y, x0[u].z, x0[u].w, x1[u].x, x1[u].y, x1[u].z, x1[u].w};
+            uint32_t fw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const uint32_t t = (xw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+                if (t != 0xFFFFu && ((vis[t >> 5] >> (t & 31)) & 1u)) fw[q >> 2] |= 1u << (8 * (q & 3));
+            }
+            if (fw[0] | fw[1] | fw[2] | fw[3]) {
+                A4[v] = make_uint4(a[u].x ^ fw[0], a[u].y ^ fw[1], a[u].z ^ fw[2], a[u].w ^ fw[3]);
+                B4[v] = make_uint4(b[u].x ^ fw[0], b[u].y ^ fw[1], b[u].z ^ fw[2], b[u].w ^ fw[3]);
+            }
         }
     }
 }
 
 hipError_t icm_kernels_init()
 {
-    const void *fns[] = {reinterpret_cast<const void *>(&k_icm<16>), reinterpret_cast<const void *>(&k_icm<32>),
-                         reinterpret_cast<const void *>(&k_icm<64>)};
+    const void *fns[] = {reinterpret_cast<const void *>(&k_icm<16, 2>), reinterpret_cast<const void *>(&k_icm<16, 4>),
+                         reinterpret_cast<const void *>(&k_icm<32, 4>), reinterpret_cast<const void *>(&k_icm<64, 4>)};
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSweepLds);
         if (e != hipSuccess) return e;
@@ -239,12 +396,17 @@ void launch_icm(const Inst *insts, const Work *work, int nwork, int N, int round
     const int ppb = waves * gpw;  // pairs per workgroup
     const int grid = (nwork + ppb - 1) / ppb;
     const size_t lds = (size_t)ppb * pb;
-    if (gs == 16)
-        k_icm<16><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
+    // about N / 16 row vectors of 16 positions per row (a layout's padding
+    // may add some; the choice only affects speed)
+    const int per_lane = ((N + 15) / 16 + gs - 1) / gs;
+    if (gs == 16 && per_lane <= 2)
+        k_icm<16, 2><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
+    else if (gs == 16)
+        k_icm<16, 4><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
     else if (gs == 32)
-        k_icm<32><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
+        k_icm<32, 4><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
     else
-        k_icm<64><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
+        k_icm<64, 4><<<grid, 64 * waves, lds, st>>>(insts, work, nwork, round, pb);
 }
 
 }  // namespace pamc

@@ -70,9 +70,13 @@ def test_pm_j_instance_as_real_couplings():
     assert np.all(E % (2 << 20) == 0)
 
 
-# 16 lanes per pair up to 1024 sites (L = 32), 32 lanes beyond (L = 40)
-@pytest.mark.parametrize("L,R,nT,NS", [(4, 400, 11, 6), (8, 501, 15, 10), (16, 200, 9, 4), (25, 64, 7, 4),
-                                       (40, 30, 5, 2)])
+# island search: breadth-first below L = 8, row flood fill from L = 8 on, in
+# 4-byte rows up to L = 32 (16 lanes per pair) and 8-byte rows beyond (32
+# lanes); rows filling their whole word (L = 32, 64) and lengths that are
+# not a multiple of four (25, 33)
+@pytest.mark.parametrize("L,R,nT,NS", [(4, 400, 11, 6), (7, 300, 9, 4), (8, 501, 15, 10), (16, 200, 9, 4),
+                                       (25, 64, 7, 4), (32, 60, 6, 2), (33, 24, 5, 2), (40, 30, 5, 2),
+                                       (64, 8, 4, 2)])
 def test_cluster_moves_bit_exact(L, R, nT, NS):
     inst = inst2d(L, R, nT, NS, 4.0, 900 + L, 950 + L)
     p, st = gpu(inst, icm_rounds=2)
