@@ -69,32 +69,55 @@ __device__ __forceinline__ int group_sum(int v)
 // island bit of row y - 1 or y + 1; the set only grows and stays connected
 // to the seed, and a pass that changes no row leaves it closed under the
 // four bonds, i.e. it is then the seed's connected component, the same set
-// the breadth-first search finds.  The runs come from a doubling scan in
-// each direction: after the scan with shift r, bit x is set when a seed bit
-// lies within 2r - 1 sites before it with the whole stretch in the sector.
+// the breadth-first search finds.
 template <typename W>
-__device__ __forceinline__ W rot_up(W v, int r, int L, W mask)
+__device__ __forceinline__ W bit_reverse(W v)
 {
-    return ((v << r) | (v >> (L - r))) & mask;
+    if constexpr (sizeof(W) == 4)
+        return __builtin_bitreverse32(v);
+    else
+        return __builtin_bitreverse64(v);
+}
+
+// Runs of m holding a bit of s (s within m) when no run wraps past the top
+// bit.  Adding s to m carries from the lowest seed of each run to its top
+// and out of it, so m & ~(m + s) is each seeded run from its lowest seed up,
+// except for the higher seeds, which the sum leaves set: OR-ing s restores
+// them.  The same on the bit-reversed words gives each run from its highest
+// seed down.
+template <typename W>
+__device__ __forceinline__ W runs_linear(W m, W s)
+{
+    const W up = (m & ~(m + s)) | s;
+    const W mr = bit_reverse(m), sr = bit_reverse(s);
+    return up | bit_reverse((mr & ~(mr + sr)) | sr);
+}
+
+// Rotations within the low L bits (0 <= n < L).
+template <typename W>
+__device__ __forceinline__ W rot_right(W v, int n, int L, W mask)
+{
+    return n == 0 ? v : ((v >> n) | (v << (L - n))) & mask;
 }
 
 template <typename W>
-__device__ __forceinline__ W rot_down(W v, int r, int L, W mask)
+__device__ __forceinline__ W rot_left(W v, int n, int L, W mask)
 {
-    return ((v >> r) | (v << (L - r))) & mask;
+    return n == 0 ? v : ((v << n) | (v >> (L - n))) & mask;
 }
 
+// Cyclic runs of the L-bit row m holding a bit of seed: the row is rotated
+// so that one of its empty sites sits at bit L - 1, where no run can cross
+// the ends, and the linear form applies; a full row is one run.
 template <typename W>
 __device__ __forceinline__ W row_runs(W m, W seed, int L, W mask)
 {
-    W fu = seed & m, fd = fu, pu = m, pd = m;
-    for (int r = 1; r < L; r <<= 1) {
-        fu |= pu & rot_up(fu, r, L, mask);
-        fd |= pd & rot_down(fd, r, L, mask);
-        pu &= rot_up(pu, r, L, mask);
-        pd &= rot_down(pd, r, L, mask);
-    }
-    return fu | fd;
+    const W s = seed & m;
+    const W gaps = ~m & mask;
+    if (s == 0 || gaps == 0) return s == 0 ? (W)0 : m;
+    const int z = sizeof(W) == 4 ? __builtin_ctz((uint32_t)gaps) : __builtin_ctzll((uint64_t)gaps);
+    const int n = z + 1 == L ? 0 : z + 1;
+    return rot_left<W>(runs_linear<W>(rot_right<W>(m, n, L, mask), rot_right<W>(s, n, L, mask)), n, L, mask);
 }
 
 // The rows live in the pair's queue area: 2 L words of W fit there for
