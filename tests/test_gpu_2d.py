@@ -143,20 +143,22 @@ def test_batch_rejects_mixed_dimensions():
         PamcBatch([a, b])
 
 
-@pytest.mark.parametrize("k", [1, 80])
-def test_step_parity_L32_large_population(k):
+@pytest.mark.parametrize("k,icm", [(1, 0), (80, 0), (1, 2), (80, 2)])
+def test_step_parity_L32_large_population(k, icm):
     """L = 32, R = 10^5 (the paper's largest 2D lattice): one GPU step from
-    an exported state against the oracle's step on the same population."""
+    an exported state against the oracle's step on the same population,
+    without and with two cluster-move rounds (5 10^4 pair updates each, in
+    the launch form the benchmark times)."""
     inst = inst2d(32, 100000, 101, 10, 5.0, 5, 6)
-    p, st = gpu(inst, steps=k)
+    p, st = gpu(inst, steps=k, icm_rounds=icm)
     assert st == 0
     s = p.get_state()
     assert p.anneal(1) == 0
     o = oracle.Oracle(inst["L"], inst["couplings"], inst["R"], inst["beta"], inst["sweeps"], inst["seed"],
-                      threads=THREADS)
+                      threads=THREADS, icm_rounds=icm)
     o.set_state(k, s["spins"], s["family"], s["lnZ"])
     assert o.run(1) == 0
-    compare_state(p.get_state(), o.get_state(), f"2D L=32 step {k}")
+    compare_state(p.get_state(), o.get_state(), f"2D L=32 step {k} icm={icm}")
     go, rec = p.observables(), o.records()
     assert go["sum_E"][k] == rec["sumE"][k] and go["sum_E2"][k] == rec["sumE2"][k]
     assert p.step_sums()[0][k] == rec["S"][k]
