@@ -187,6 +187,70 @@ __device__ __forceinline__ void flood_square(const uint8_t *member, uint32_t *vi
     }
 }
 
+// The same flood fill on the cubic lattice, from L = 8 on: row r = y + L z
+// holds the L sites of x (bit x = site x + L r), its neighbouring rows are
+// y +- 1 and z +- 1 (cyclic), and the sector and island rows, 4-byte words,
+// live in the queue area (8 L^2 <= L^3 bytes).  Lane gl takes rows gl,
+// gl + GS, ...; they stay in LDS (up to 16 per lane).
+template <int GS>
+__device__ __forceinline__ void flood_cubic(const uint8_t *member, uint32_t *vis, uint16_t *queue, int L, int gl)
+{
+    const int s0 = queue[0];
+    wave_sync();  // the seed is read before the rows overwrite the queue
+    const int nr = L * L;
+    uint32_t *Mr = reinterpret_cast<uint32_t *>(queue);
+    uint32_t *Vr = Mr + nr;
+    const uint32_t mask = L == 32 ? ~0u : ((1u << L) - 1u);
+    // r / L as (r mg) >> 16, exact for r < 1024 and L <= 32
+    const uint32_t mg = (65536u + (uint32_t)L - 1u) / (uint32_t)L;
+    const int r0 = s0 / L, x0 = s0 - r0 * L;
+    for (int r = gl; r < nr; r += GS) {
+        const uint8_t *row = member + r * L;
+        uint32_t m = 0;
+        if ((L & 3) == 0) {
+            for (int x = 0; x < L; x += 4) {
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x);
+                m |= ((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) << x;
+            }
+        } else {
+            for (int x = 0; x < L; ++x) m |= (uint32_t)row[x] << x;
+        }
+        Mr[r] = m;
+        Vr[r] = r == r0 ? 1u << x0 : 0u;
+    }
+    wave_sync();
+    // every pass but the last adds a site, so at most N + 1 passes
+    for (int pass = 0; pass <= L * nr; ++pass) {
+        int changed = 0;
+        for (int r = gl; r < nr; r += GS) {
+            const uint32_t m = Mr[r];
+            if (m == 0) continue;
+            const uint32_t v = Vr[r];
+            const int z = (int)(((uint32_t)r * mg) >> 16), y = r - z * L;
+            const int ym = y == 0 ? r + L - 1 : r - 1, yp = y == L - 1 ? r - L + 1 : r + 1;
+            const int zm = z == 0 ? r + nr - L : r - L, zp = z == L - 1 ? r - nr + L : r + L;
+            const uint32_t nbv = Vr[ym] | Vr[yp] | Vr[zm] | Vr[zp];
+            const uint32_t f = row_runs<uint32_t>(m, v | (m & nbv), L, mask);
+            if (f != v) {
+                Vr[r] = f;
+                changed = 1;
+            }
+        }
+        changed = group_sum<GS>(changed);
+        wave_sync();
+        if (!changed) break;
+    }
+    // bits r L .. r L + L - 1 of the site bitmap: at most two words
+    for (int r = gl; r < nr; r += GS) {
+        const uint64_t f = Vr[r];
+        if (f == 0) continue;
+        const int p = r * L, w = p >> 5, sh = p & 31;
+        const uint32_t p0 = (uint32_t)(f << sh), p1 = (uint32_t)(f >> (32 - sh));
+        if (p0) atomicOr(&vis[w], p0);
+        if (p1) atomicOr(&vis[w + 1], p1);
+    }
+}
+
 // One ICM round.  A lane group of GS lanes updates one pair (work item =
 // instance, pair index j) on its own slice of LDS, so the island search
 // synchronises only inside its wave; small lattices take 16 lanes per pair
@@ -327,6 +391,10 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
                 flood_square<uint64_t, GS>(member, vis, queue, L, gl);
             grown = true;
         }
+    }
+    if (I.dim == 3 && L >= 8) {
+        flood_cubic<GS>(member, vis, queue, L, gl);
+        grown = true;
     }
     // otherwise breadth-first growth of the island, one frontier per
     // iteration; the queue only grows and holds each site of the island

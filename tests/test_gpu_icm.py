@@ -29,7 +29,8 @@ def both(inst, rounds=2, **kw):
 
 
 # every sweep kernel: colour-major with two and three colours, even/odd-x
-# (L = 8, 16), per-site (L = 24), real couplings; odd and even N_S, odd R
+# (L = 8, 16), per-site (L = 24, 32), real couplings; odd and even N_S, odd R;
+# the island search as a queue (L < 8) and as a row flood fill (L >= 8)
 CASES = [
     (3, 401, 11, 10, 4.0, False),
     (4, 1000, 21, 10, 4.0, False),
@@ -40,6 +41,13 @@ CASES = [
     (24, 9, 3, 2, 3.0, False),
     (6, 500, 11, 6, 4.0, True),
     (7, 151, 9, 5, 4.0, True),
+    # the row flood fill from L = 8 on: rows of a length that is not a
+    # multiple of four (9), 32-lane groups (12), whole-word rows with 64-lane
+    # groups (32), real couplings
+    (9, 201, 7, 4, 4.0, False),
+    (12, 64, 5, 3, 4.0, False),
+    (32, 4, 3, 2, 3.0, False),
+    (8, 300, 7, 4, 4.0, True),
 ]
 
 
