@@ -125,7 +125,8 @@ __device__ __forceinline__ W row_runs(W m, W seed, int L, W mask)
 // Lane gl owns rows gl and gl + GS (L <= 2 GS on the square lattice).  On
 // return the island's bits are ORed into vis (which holds the seed).
 template <typename W, int GS>
-__device__ __forceinline__ void flood_square(const uint8_t *member, uint32_t *vis, uint16_t *queue, int L, int gl)
+__device__ __forceinline__ void flood_square(const uint8_t *member, int sel, uint32_t *vis, uint16_t *queue, int L,
+                                             int gl)
 {
     const int s0 = queue[0];
     wave_sync();  // the seed is read before the rows overwrite the queue
@@ -143,11 +144,11 @@ __device__ __forceinline__ void flood_square(const uint8_t *member, uint32_t *vi
         const uint8_t *row = member + y * L;
         if ((L & 3) == 0) {
             for (int x = 0; x < L; x += 4) {
-                const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x);
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x) >> sel;
                 m[i] |= (W)((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) << x;
             }
         } else {
-            for (int x = 0; x < L; ++x) m[i] |= (W)row[x] << x;
+            for (int x = 0; x < L; ++x) m[i] |= (W)((row[x] >> sel) & 1u) << x;
         }
         v[i] = y == y0 ? (W)1 << x0 : (W)0;
         Vr[y] = v[i];
@@ -193,7 +194,8 @@ __device__ __forceinline__ void flood_square(const uint8_t *member, uint32_t *vi
 // live in the queue area (8 L^2 <= L^3 bytes).  Lane gl takes rows gl,
 // gl + GS, ...; they stay in LDS (up to 16 per lane).
 template <int GS>
-__device__ __forceinline__ void flood_cubic(const uint8_t *member, uint32_t *vis, uint16_t *queue, int L, int gl)
+__device__ __forceinline__ void flood_cubic(const uint8_t *member, int sel, uint32_t *vis, uint16_t *queue, int L,
+                                            int gl)
 {
     const int s0 = queue[0];
     wave_sync();  // the seed is read before the rows overwrite the queue
@@ -209,11 +211,11 @@ __device__ __forceinline__ void flood_cubic(const uint8_t *member, uint32_t *vis
         uint32_t m = 0;
         if ((L & 3) == 0) {
             for (int x = 0; x < L; x += 4) {
-                const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x);
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(row + x) >> sel;
                 m |= ((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) << x;
             }
         } else {
-            for (int x = 0; x < L; ++x) m |= (uint32_t)row[x] << x;
+            for (int x = 0; x < L; ++x) m |= (uint32_t)((row[x] >> sel) & 1u) << x;
         }
         Mr[r] = m;
         Vr[r] = r == r0 ? 1u << x0 : 0u;
@@ -320,26 +322,27 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
             for (int q = 0; q < 16; ++q) {
                 const uint32_t s = (xw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
                 if (s == 0xFFFFu) continue;  // padding position
-                const uint8_t d = (dw[q >> 2] >> (8 * (q & 3))) & 0xFFu ? 1 : 0;
-                member[s] = d;
-                nd += d;
+                const uint32_t d = (dw[q >> 2] >> (8 * (q & 3))) & 0xFFu ? 1u : 0u;
+                member[s] = (uint8_t)(2u - d);  // bit 0: differ, bit 1: agree
+                nd += (int)d;
             }
         }
     }
-    // sector flags beyond N stay 0 (the site search reads 16-byte vectors)
+    // flags beyond N stay 0 in both bits (the site search reads 16-byte
+    // vectors)
     if (gl < N16 - N) member[N + gl] = 0;
     for (int i = gl; i < (N + 31) / 32; i += GS) vis[i] = 0u;
     nd = group_sum<GS>(nd);
     const bool want = nd <= N - nd;
     const int cnt = want ? nd : N - nd;
     if (cnt == 0) return;  // empty sector: no move (uniform over the group)
-    wave_sync();
-    if (!want)
-        for (int s = gl; s < N; s += GS) member[s] ^= 1u;
+    // the chosen sector's flag is bit sel of each byte
+    const int sel = want ? 0 : 1;
+    const uint32_t bm = 0x01010101u << sel;
     wave_sync();
     // the m-th site of the sector: per-lane counts over 16-byte chunks of
-    // the flags (0 or 1 per byte), a scan over the group, and the owning
-    // lane's walk through its chunk
+    // the flags, a scan over the group, and the owning lane's walk through
+    // its chunk
     const uint32_t u = philox10(make_uint4(j, 4u, (uint32_t)k, kTagIcm | (uint32_t)round), I.key0, I.key1).x;
     const int m = (int)(((uint64_t)u * (uint64_t)cnt) >> 32);
     const int nch = N16 >> 4, per = (nch + GS - 1) / GS;
@@ -348,7 +351,8 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     int c = 0;
     for (int ch = c_begin; ch < c_end; ++ch) {
         const uint4 f = M4[ch];
-        c += __builtin_popcount(f.x) + __builtin_popcount(f.y) + __builtin_popcount(f.z) + __builtin_popcount(f.w);
+        c += __builtin_popcount(f.x & bm) + __builtin_popcount(f.y & bm) + __builtin_popcount(f.z & bm) +
+             __builtin_popcount(f.w & bm);
     }
     int incl = c;
     for (int off = 1; off < GS; off <<= 1) {
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
         int left = m - excl;
         const uint32_t *M1 = reinterpret_cast<const uint32_t *>(member);
         for (int wi = 4 * c_begin; wi < 4 * c_end; ++wi) {
-            const uint32_t f = M1[wi];
+            const uint32_t f = M1[wi] & bm;
             const int pc = __builtin_popcount(f);
             if (left >= pc) {
                 left -= pc;
@@ -386,14 +390,14 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
     if constexpr (GS <= 32) {
         if (I.dim == 2 && L >= 8) {
             if constexpr (GS == 16)
-                flood_square<uint32_t, GS>(member, vis, queue, L, gl);
+                flood_square<uint32_t, GS>(member, sel, vis, queue, L, gl);
             else
-                flood_square<uint64_t, GS>(member, vis, queue, L, gl);
+                flood_square<uint64_t, GS>(member, sel, vis, queue, L, gl);
             grown = true;
         }
     }
     if (I.dim == 3 && L >= 8) {
-        flood_cubic<GS>(member, vis, queue, L, gl);
+        flood_cubic<GS>(member, sel, vis, queue, L, gl);
         grown = true;
     }
     // otherwise breadth-first growth of the island, one frontier per
@@ -417,7 +421,7 @@ __global__ __launch_bounds__(256) void k_icm(const Inst *insts, const Work *work
             for (int d = 0; d < 6; ++d) {
                 if (d >= nnb) break;
                 const int q = nb[d];
-                if (!member[q]) continue;
+                if (!((member[q] >> sel) & 1u)) continue;
                 const uint32_t bit = 1u << (q & 31);
                 if (atomicOr(&vis[q >> 5], bit) & bit) continue;
                 queue[atomicAdd(tailp, 1)] = (uint16_t)q;

@@ -36,7 +36,8 @@ hipError_t sweep_kernels_init();
 inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : (row_bytes + 255) & ~255; }
 
 // LDS of one cluster-move pair (the island search of one lane group): the
-// sector flag of every lexicographic site (bytes), the visited bits, the
+// sector flags of every lexicographic site (a byte: bit 0 where the replicas
+// differ, bit 1 where they agree), the visited bits, the
 // island queue (16-bit site indices; an island lies in the smaller sector,
 // so it holds at most (N + 1) / 2 sites) and its tail, each part a multiple
 // of 16 bytes, so that every pair's slice starts 16-byte aligned.
