@@ -65,11 +65,11 @@ __device__ __forceinline__ int group_sum(int v)
 // Island growth on the square lattice as a bit-parallel flood fill: row y
 // of the sector is the L-bit word Mr[y] (bit x = site x + L y) and the
 // island so far is Vr[y].  A pass replaces each row's island bits by the runs
-// of Mr[y] (cyclic in x) that contain an island bit or a site below an
-// island bit of row y - 1 or y + 1; the set only grows and stays connected
-// to the seed, and a pass that changes no row leaves it closed under the
-// four bonds, i.e. it is then the seed's connected component, the same set
-// the breadth-first search finds.
+// of Mr[y] (cyclic in x) that contain an island bit or a site bonded to an
+// island site of row y - 1 or y + 1 (same x); the set only grows and stays
+// connected to the seed, and a pass that changes no row leaves it closed
+// under the four bonds, i.e. it is then the seed's connected component, the
+// same set the breadth-first search finds.
 template <typename W>
 __device__ __forceinline__ W bit_reverse(W v)
 {
