@@ -172,8 +172,11 @@ typedef struct pamc_ctx pamc_ctx;
  *              periodic neighbour s + e_d (d = 0, 1, 2 for x, y, z; site
  *              s = x + L (y + L z));
  *   R          nominal population, 1 <= R; capacity must stay below 2^31;
- *   beta       double [n_temps], finite, >= 0, non-decreasing (beta_0 = 0
- *              anchors ln Z at N ln 2);
+ *   beta       double [n_temps], finite, non-decreasing, beta[0] = 0
+ *              exactly: the replicas start as independent random spins,
+ *              which is the beta = 0 equilibrium (Sec. II.B), and the free
+ *              energy is anchored there at ln Z_0 = N ln 2 (any other
+ *              beta[0] is PAMC_ERR_INVALID);
  *   sweeps     Metropolis sweeps per temperature, >= 1;
  *   seed       Philox key;
  *   opt        NULL for defaults.
@@ -295,6 +298,29 @@ int pamc_thresholds(const pamc_ctx *ctx, uint32_t *out, uint8_t *accept_all);
  * Any output may be NULL.  PAMC_ERR_STATE if timing is off. */
 int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *resample_ms, double *gather_ms,
                      int64_t *n_steps);
+
+/* +-J instance generator (Sec. II.A: couplings +-1 with probability 1/2
+ * each; the paper's instances are not published).  Fills out, int8
+ * [3][L^3] in the bond order of pamc_create, with out[b] for bond
+ * b = d L^3 + s equal to +1 when bit 31 of word (b & 3) of Philox4x32-10
+ * at counter (b >> 2, 0, 0, 5 * 2^28), key (low, high 32 bits of
+ * disorder_seed), is set, else -1.  Host only (no device, no allocation);
+ * 2 <= L <= 32; out has 3 L^3 bytes, caller-owned.
+ * Errors: PAMC_ERR_INVALID. */
+int pamc_make_pm_j(int L, uint64_t disorder_seed, int8_t *out);
+
+/* Free-energy variance of Eq. (4) (Sec. II.B), rho_f = R var(beta F), over
+ * independent runs of one instance at finite R:
+ *   betaF       double [runs][n_temps], beta F_k of each run (host);
+ *   nominal_R   double [n_temps], the nominal population R(beta_k);
+ *   outputs     double [n_temps] each, NULL to skip: the mean of beta F,
+ *               its sample variance (ddof 1: the sum of squared deviations
+ *               from the mean over runs - 1), and rho_f = R(beta_k) times
+ *               that variance.
+ * Sums run over the runs in order, in FP64.  runs >= 2.  Host only.
+ * Errors: PAMC_ERR_INVALID. */
+int pamc_rho_f(const double *betaF, int runs, int n_temps, const double *nominal_R, double *mean_betaF,
+               double *var_betaF, double *rho_f);
 
 /* Device footprint in bytes of a run with these parameters; -1 for
  * arguments no run accepts. */

@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.orc_observables.argtypes = [P, P, P]
         L.orc_thresholds.argtypes = [dbl, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_make_pm_j.argtypes = [i32, u64, P]
         L.orc_sweep_rows.argtypes = [P, i32, i64, P, P, P]
         L.orc_measure_resample.argtypes = [P]
         L.enum_dos.argtypes = [i32, P, P]
@@ -126,6 +127,14 @@ def philox4x32_10(counter, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def make_pm_j(L: int, disorder_seed: int) -> np.ndarray:
+    """The oracle's +-J instance for a disorder seed, int8 [3][L^3]."""
+    out = np.zeros(3 * L ** 3, dtype=np.int8)
+    if lib().orc_make_pm_j(int(L), ctypes.c_uint64(int(disorder_seed) & (2**64 - 1)), _ptr(out)) != OK:
+        raise ValueError("orc_make_pm_j: invalid arguments")
+    return out.reshape(3, L ** 3)
 
 
 def exp_f32(x: float) -> float:

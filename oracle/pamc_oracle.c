@@ -89,6 +89,7 @@ enum {
 #define TAG_SWEEP 0x20000000u
 #define TAG_RESAMPLE 0x30000000u
 #define TAG_ICM 0x40000000u
+#define TAG_COUPLING 0x50000000u
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
@@ -127,6 +128,21 @@ static uint32_t draw(uint64_t seed, uint32_t x, uint32_t y, uint32_t z, uint32_t
     uint32_t out[4];
     orc_philox4x32_10(ctr, key, out);
     return out[word];
+}
+
+/* +-J disorder (Sec. II.A: each coupling +1 or -1 with probability 1/2;
+ * the instances of the paper are not published).  Bond b = d N + s of the
+ * [3][N] array is +1 when bit 31 of word (b & 3) of the Philox block at
+ * counter (b >> 2, 0, 0, TAG_COUPLING), keyed by the disorder seed, is set. */
+int orc_make_pm_j(int L, uint64_t disorder_seed, int8_t *out)
+{
+    if (L < 2 || L > 32 || !out) return ORC_ERR_INVALID;
+    const int64_t nb = 3 * (int64_t)L * L * L;
+    for (int64_t b = 0; b < nb; ++b) {
+        uint32_t u = draw(disorder_seed, (uint32_t)(b >> 2), 0u, 0u, TAG_COUPLING, (int)(b & 3));
+        out[b] = (u >> 31) ? 1 : -1;
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -262,6 +278,9 @@ static orc_t *create(int dim, int L, const int8_t *J, const int32_t *Jq, int64_t
         for (int i = 0; i < nT; ++i)
             if (pop[i] < 1) return NULL;
     }
+    /* Sec. II.B: the replicas start at random, the beta = 0 sample, which is
+     * also where ln Z = N ln 2 anchors the free energy */
+    if (beta[0] != 0.0) return NULL;
     for (int i = 0; i < nT; ++i) {
         if (!(beta[i] >= 0.0) || !isfinite(beta[i])) return NULL;
         if (i > 0 && beta[i] < beta[i - 1]) return NULL;

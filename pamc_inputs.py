@@ -4,20 +4,59 @@ This module holds no part of the method's arithmetic: it only draws problem
 instances (couplings), builds temperature schedules and the workload
 descriptions, so that the GPU library, the oracle, the tests and the
 benchmark all see the same inputs.  The paper's own disorder instances are not
-published; +-J couplings with probability 1/2 each, or Gaussian couplings
-in fixed point, from a seeded generator stand in for them.
+published; +-J couplings with probability 1/2 each (from the Philox stream
+that the library's pamc_make_pm_j also draws), or Gaussian couplings in
+fixed point from a seeded generator, stand in for them.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
+_M32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(counters: np.ndarray, seed: int) -> np.ndarray:
+    """Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) of every row of
+    counters (uint32 [n][4]) under the key (low, high 32 bits of seed):
+    ten rounds, each multiplying words 0 and 2 by the round multipliers
+    (full 64-bit products), the high halves mixed with words 1 and 3 and the
+    round key by XOR; the key advances by the Weyl constants.  uint32 [n][4].
+    Used here only to draw +-J instances."""
+    c = np.asarray(counters, dtype=np.uint64).reshape(-1, 4).copy()
+    k0 = np.uint64(int(seed) & 0xFFFFFFFF)
+    k1 = np.uint64((int(seed) >> 32) & 0xFFFFFFFF)
+    for _ in range(10):
+        a = np.uint64(0xD2511F53) * c[:, 0]
+        b = np.uint64(0xCD9E8D57) * c[:, 2]
+        n = np.empty_like(c)
+        n[:, 0] = (b >> np.uint64(32)) ^ c[:, 1] ^ k0
+        n[:, 1] = b & _M32
+        n[:, 2] = (a >> np.uint64(32)) ^ c[:, 3] ^ k1
+        n[:, 3] = a & _M32
+        c = n
+        k0 = (k0 + np.uint64(0x9E3779B9)) & _M32
+        k1 = (k1 + np.uint64(0xBB67AE85)) & _M32
+    return c.astype(np.uint32)
+
+
+# counter word 3 of the coupling draws (the library's pamc_make_pm_j draws
+# the same stream)
+COUPLING_TAG = 0x50000000
+
+
 def pm_j_couplings(L: int, disorder_seed: int) -> np.ndarray:
-    """+-J couplings, int8 [3][L^3]: J[d][s] couples site s to s + e_d."""
+    """+-J couplings, int8 [3][L^3]: J[d][s] couples site s to s + e_d.
+    Bond b = d L^3 + s is +1 when bit 31 of word (b & 3) of Philox4x32-10 at
+    counter (b >> 2, 0, 0, COUPLING_TAG), keyed by the disorder seed, is set,
+    else -1, so a C caller gets the same instance from pamc_make_pm_j."""
     N = L ** 3
-    rng = np.random.Generator(np.random.PCG64(np.uint64(disorder_seed)))
-    bits = rng.integers(0, 2, size=(3, N), dtype=np.int8)
-    return (2 * bits - 1).astype(np.int8)
+    nblk = (3 * N + 3) // 4
+    ctr = np.zeros((nblk, 4), dtype=np.uint64)
+    ctr[:, 0] = np.arange(nblk, dtype=np.uint64)
+    ctr[:, 3] = COUPLING_TAG
+    words = philox4x32_10(ctr, disorder_seed).reshape(-1)[: 3 * N]
+    return np.where(words >> np.uint32(31), 1, -1).astype(np.int8).reshape(3, N)
 
 
 # Real couplings are carried in fixed point, J = j 2^-20 with int32 j and

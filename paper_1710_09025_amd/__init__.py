@@ -30,7 +30,8 @@ import numpy as np
 
 from . import _capi
 
-__all__ = ["Pamc", "PamcBatch", "PamcServer", "PamcError", "OBS_FIELDS", "default_capacity"]
+__all__ = ["Pamc", "PamcBatch", "PamcServer", "PamcError", "OBS_FIELDS", "default_capacity", "make_pm_j", "rho_f",
+           "free_energy_variance", "autotune"]
 
 OBS_FIELDS = ("beta", "R", "sum_E", "sum_E2", "E_min", "E_max", "mean_E", "e", "C_V", "lnQ", "lnZ",
               "betaF", "f", "S_f", "rho_s", "q_abs", "q2", "q4", "g_SG", "measured")
@@ -179,13 +180,34 @@ def autotune(L, R, sweeps, torch_stream=True, packed=False, real=False, dim=3):
     return t.value, g.value, ns.value
 
 
+def make_pm_j(L: int, disorder_seed: int) -> np.ndarray:
+    """+-J instance of the library's coupling stream (``pamc_make_pm_j``),
+    int8 [3][L^3]."""
+    out = np.zeros(3 * int(L) ** 3, dtype=np.int8)
+    _check(_capi.load().pamc_make_pm_j(int(L), ctypes.c_uint64(int(disorder_seed) & (2**64 - 1)), _ptr(out)),
+           "pamc_make_pm_j")
+    return out.reshape(3, int(L) ** 3)
+
+
+def rho_f(betaF, nominal_R):
+    """Eq. (4) through ``pamc_rho_f``: betaF [runs][n_temps] of independent
+    runs, nominal_R [n_temps]; returns (mean beta F, var beta F with ddof 1,
+    rho_f), each [n_temps]."""
+    bf = np.ascontiguousarray(betaF, dtype=np.float64)
+    runs, nT = bf.shape
+    Rn = np.ascontiguousarray(np.broadcast_to(np.asarray(nominal_R, dtype=np.float64), (nT,)))
+    mean, var, rf = np.zeros(nT), np.zeros(nT), np.zeros(nT)
+    _check(_capi.load().pamc_rho_f(_ptr(bf), runs, nT, _ptr(Rn), _ptr(mean), _ptr(var), _ptr(rf)), "pamc_rho_f")
+    return mean, var, rf
+
+
 def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None, packed=False, autotune=False,
                          icm_rounds=0, icm_beta_min=0.0):
     """rho_f = R var(beta F) (Sec. II.B, Eq. (4)) from independent runs of one
     instance: the runs (one per seed, at least two; the paper asks for ten or
     more) are annealed together as one batch, and per temperature step the
-    sample variance (ddof 1) of beta F = -ln Z across runs is multiplied by
-    the nominal population R(beta_k).  Returns a dict of arrays over steps:
+    library's ``pamc_rho_f`` takes the sample variance (ddof 1) of
+    beta F = -ln Z across runs times the nominal population R(beta_k).  Returns a dict of arrays over steps:
     beta, mean_betaF, var_betaF, rho_f, and the per-run beta F [runs, steps]."""
     seeds = [int(x) for x in seeds]
     if len(seeds) < 2:
@@ -202,8 +224,8 @@ def free_energy_variance(L, couplings, R, beta, sweeps, seeds, pop_schedule=None
     finally:
         b.close()
     nominal = np.full(len(beta), float(R)) if pop_schedule is None else np.asarray(pop_schedule, dtype=np.float64)
-    var = bf.var(axis=0, ddof=1)
-    return {"beta": beta, "mean_betaF": bf.mean(axis=0), "var_betaF": var, "rho_f": nominal * var, "betaF": bf}
+    mean, var, rf = rho_f(bf, nominal)
+    return {"beta": beta, "mean_betaF": mean, "var_betaF": var, "rho_f": rf, "betaF": bf}
 
 
 class Pamc:

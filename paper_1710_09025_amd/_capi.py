@@ -143,6 +143,8 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]),
     "pamc_footprint": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Options)]),
+    "pamc_make_pm_j": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, P]),
+    "pamc_rho_f": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P, P, P]),
     "pamc_destroy": (None, [P]),
     "pamc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pamc_last_error": (ctypes.c_char_p, []),

@@ -73,6 +73,9 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
         for (int i = 0; i < 3 * N; ++i)
             if (J[i] != 1 && J[i] != -1) return invalid("couplings must be +1 or -1");
     }
+    // the initial replicas are independent random spins, the beta = 0
+    // equilibrium, and ln Z is anchored there at N ln 2 (Sec. II.B)
+    if (beta[0] != 0.0) return invalid("beta[0] must be 0 (random initial spins are the beta = 0 sample)");
     for (int k = 0; k < nT; ++k) {
         if (!std::isfinite(beta[k]) || beta[k] < 0.0) return invalid("beta must be finite and >= 0");
         if (k > 0 && beta[k] < beta[k - 1]) return invalid("beta must be non-decreasing");

@@ -23,6 +23,7 @@
 namespace pamc {
 int make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
               uint64_t seed, const pamc_options &opt, HostInst &h);
+void tune_cache_load();
 }
 
 using pamc::HostInst;
@@ -229,6 +230,7 @@ int pamc_server_create(size_t hbm_budget_bytes, const pamc_server_options *opt, 
     s->device = opt ? opt->device : -1;
     s->autotune = opt && opt->autotune;
     s->spin_format = opt ? opt->spin_format : PAMC_SPINS_INT8;
+    if (s->autotune) pamc::tune_cache_load();
     pamc_options o;
     pamc_default_options(&o);
     o.device = s->device;

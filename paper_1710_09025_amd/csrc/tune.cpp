@@ -6,18 +6,27 @@
 // tiles to spread over the 256 compute units, a large one amortises the tile
 // load, the energy epilogue and the measurement tail over more rows.  The
 // tuner runs each candidate shape on a throw-away run of the instance (its
-// couplings, L, R, capacity and sweeps per step) at a constant beta = 2,
-// where every replica gets exactly one copy and the population stays at R,
-// and keeps the shape whose fastest timed step (HIP events, after a
-// warm-up step) is shortest; a burn-in first brings the energies to that
-// temperature.
+// couplings, L, R, capacity and sweeps per step) at a constant beta = 2
+// after the beta = 0 start, where every replica gets one copy on average
+// and the population stays near R, and keeps the shape whose fastest timed
+// step (HIP events, after a warm-up step) is shortest; a burn-in first
+// brings the energies to that temperature.
 // Every shape gives bit-identical results, so the choice only affects
-// speed.  Choices are cached for the life of the process, keyed by kernel,
-// lattice (dimension and L), sweeps per step, the capacity rounded up to a
-// power of two and the spin storage format.
+// speed.  Choices are cached for the life of the process, keyed by device
+// (architecture and compute units), kernel, lattice (dimension and L),
+// sweeps per step, the capacity rounded up to a power of two and the spin
+// storage format; the cache starts from the file tune_cache.jsonl beside
+// the library and from the file PAMC_TUNE_CACHE names, and new choices are
+// appended to the latter, so a later process finds them.
+#include <dlfcn.h>
+
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -58,8 +67,77 @@ struct Choice {
     double ns_per_attempt;
 };
 
+using Key = std::tuple<int, int, int, int, int, int>;  // variant, dim, L, sweeps, log2 capacity, packed
+
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int, int>, Choice> g_cache;
+std::map<std::pair<std::string, Key>, Choice> g_cache;  // by device and key
+bool g_loaded = false;
+std::string g_save_path;  // where new choices are appended ("" = nowhere)
+
+// The device a choice was measured on: architecture and compute units.
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string arch = p.gcnArchName;
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch.resize(c);
+    return arch + "-" + std::to_string(p.multiProcessorCount) + "cu";
+}
+
+// One choice per line, as a JSON object with these fields in this order.
+const char *kLineFmt =
+    "{\"device\": \"%63[^\"]\", \"variant\": %d, \"dim\": %d, \"L\": %d, \"sweeps\": %d, "
+    "\"cap_log2\": %d, \"packed\": %d, \"tile_rows\": %d, \"group_quads\": %d, "
+    "\"ns_per_attempt\": %lf}";
+
+void load_file(const std::string &path)
+{
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char dev[64];
+        int v, d, L, ns, cl, pk, tr, rp;
+        double npa;
+        if (std::sscanf(line, kLineFmt, dev, &v, &d, &L, &ns, &cl, &pk, &tr, &rp, &npa) != 10) continue;
+        g_cache[{dev, Key(v, d, L, ns, cl, pk)}] = Choice{tr, rp, npa};
+    }
+    std::fclose(f);
+}
+
+// The tuning cache file shipped beside the library (choices measured on
+// MI355X for common sizes), then PAMC_TUNE_CACHE when it names a file;
+// new choices are appended to PAMC_TUNE_CACHE.  Call with g_mu held.
+void load_persistent()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    Dl_info info;
+    if (dladdr((void *)&load_persistent, &info) && info.dli_fname) {
+        std::string dir = info.dli_fname;
+        const size_t sl = dir.rfind('/');
+        dir = sl == std::string::npos ? std::string(".") : dir.substr(0, sl);
+        load_file(dir + "/tune_cache.jsonl");
+    }
+    const char *env = std::getenv("PAMC_TUNE_CACHE");
+    if (env && *env) {
+        g_save_path = env;
+        load_file(g_save_path);
+    }
+}
+
+void save_choice(const std::string &dev, const Key &k, const Choice &c)
+{
+    if (g_save_path.empty()) return;
+    FILE *f = std::fopen(g_save_path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, kLineFmt, dev.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                 std::get<4>(k), std::get<5>(k), c.tile_rows, c.rp, c.ns_per_attempt);
+    std::fputc('\n', f);
+    std::fclose(f);
+}
 
 int ceil_log2(int64_t v)
 {
@@ -139,9 +217,11 @@ std::vector<std::pair<int, int>> shape_candidates(const HostInst &h)
 
 int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
 {
-    const auto key = std::make_tuple(h.variant, h.dim, h.L, h.NS, ceil_log2(h.Rcap), h.packed);
+    const Key k0(h.variant, h.dim, h.L, h.NS, ceil_log2(h.Rcap), h.packed);
+    const auto key = std::make_pair(device_tag(), k0);
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        load_persistent();
         auto it = g_cache.find(key);
         if (it != g_cache.end() && shape_valid(h, it->second.tile_rows, it->second.rp, nullptr)) {
             h.tile_rows = it->second.tile_rows;
@@ -170,8 +250,10 @@ int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
     o.pop_schedule = nullptr;
     o.fuse_gather = 1;
     o.icm_rounds = 0;  // the shape concerns the sweep alone
+    // (beta_0 = 0, where every run starts; then the constant tuning beta)
     const int nT = 1 + kBurnIn + (1 + kTimedSteps) * (int)cand.size();
-    const std::vector<double> beta((size_t)nT, kTuneBeta);
+    std::vector<double> beta((size_t)nT, kTuneBeta);
+    beta[0] = 0.0;
     HostInst t;
     int st = make_inst(h.L, h.real ? nullptr : h.J.data(), h.real ? h.Jq.data() : nullptr, h.R, beta.data(), nT,
                        h.NS, h.seed, o, t);
@@ -209,11 +291,20 @@ int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt)
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_cache[key] = best;
+        save_choice(key.first, k0, best);
     }
     h.tile_rows = best.tile_rows;
     h.rp = best.rp;
     if (ns_per_attempt) *ns_per_attempt = best.ns_per_attempt;
     return PAMC_OK;
+}
+
+// Loads the persistent choices now (the serving loop does this before its
+// first request arrives).
+void tune_cache_load()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_persistent();
 }
 
 }  // namespace pamc

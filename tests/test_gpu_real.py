@@ -235,7 +235,7 @@ def test_server_real_request_matches_oracle():
 
 
 def test_single_temperature_and_single_replica():
-    for L, R, beta in [(4, 50, np.array([0.0])), (5, 1, pi.linear_beta(3.0, 8)), (6, 40, np.array([1.3]))]:
+    for L, R, beta in [(4, 50, np.array([0.0])), (5, 1, pi.linear_beta(3.0, 8)), (6, 40, np.array([0.0, 1.3]))]:
         inst = dict(L=L, couplings=pi.gaussian_couplings(L, 300 + L), R=R, beta=beta, sweeps=2, seed=301 + L)
         p, st = gpu_run(inst)
         o, sto = oracle_run(inst)

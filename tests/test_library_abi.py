@@ -202,7 +202,7 @@ def test_packed_footprint_saves_the_spin_bytes(lib):
 
 
 @pytest.mark.parametrize("case", ["L", "coupling", "beta_order", "beta_nan", "R", "sweeps", "capacity",
-                                  "pop_first", "pop_zero"])
+                                  "pop_first", "pop_zero", "beta0_positive", "beta0_negative_zero_only"])
 def test_invalid_arguments_are_rejected_on_the_host(lib, case):
     from paper_1710_09025_amd import _capi
 
@@ -219,6 +219,12 @@ def test_invalid_arguments_are_rejected_on_the_host(lib, case):
         beta = beta[::-1].copy()
     elif case == "beta_nan":
         beta[2] = np.nan
+    elif case == "beta0_positive":
+        # the random initial population is the beta = 0 sample and ln Z is
+        # anchored there (Sec. II.B): any other first temperature is refused
+        beta = beta + 0.25
+    elif case == "beta0_negative_zero_only":
+        beta = np.full(5, 0.4)
     elif case == "R":
         R = 0
     elif case == "sweeps":
@@ -278,3 +284,110 @@ def test_square_lattice_options_on_the_host(lib):
                     2, 1, ctypes.byref(opt), ctypes.byref(h))
         assert st == _capi.ERR_INVALID, (dim, real, Lc, lib.pamc_last_error())
         assert not h.value
+
+
+def _batch_instance(L, J, R, beta, NS, seed):
+    from paper_1710_09025_amd import _capi
+
+    return _capi.Instance(L, J.ctypes.data_as(ctypes.c_void_p).value, R, beta.ctypes.data_as(ctypes.c_void_p).value,
+                          len(beta), NS, seed, None, None)
+
+
+def test_batch_rejects_a_positive_first_temperature_on_the_host(lib):
+    """pamc_batch_create validates every instance before any device work;
+    the error names the instance."""
+    from paper_1710_09025_amd import _capi
+
+    J = np.ones((3, 64), dtype=np.int8)
+    good = np.linspace(0, 1, 5)
+    bad = np.linspace(0.1, 1, 5)
+    arr = (_capi.Instance * 2)(_batch_instance(4, J, 50, good, 2, 1), _batch_instance(4, J, 50, bad, 2, 2))
+    h = ctypes.c_void_p()
+    st = lib.pamc_batch_create(2, arr, None, ctypes.byref(h))
+    assert st == _capi.ERR_INVALID and not h.value
+    assert b"instance 1" in lib.pamc_last_error() and b"beta[0]" in lib.pamc_last_error()
+
+
+def test_real_couplings_reject_a_positive_first_temperature_on_the_host(lib):
+    from paper_1710_09025_amd import _capi
+
+    Jq = np.full((3, 64), 1 << 20, dtype=np.int32)
+    beta = np.array([0.5, 1.0])
+    h = ctypes.c_void_p()
+    st = lib.pamc_create_real(4, Jq.ctypes.data_as(ctypes.c_void_p), 10, beta.ctypes.data_as(ctypes.c_void_p), 2,
+                              1, 1, None, ctypes.byref(h))
+    assert st == _capi.ERR_INVALID and not h.value
+
+
+def test_oracle_rejects_a_positive_first_temperature():
+    import oracle
+    import pamc_inputs as pi
+
+    J = pi.pm_j_couplings(3, 1)
+    with pytest.raises(ValueError):
+        oracle.Oracle(3, J, 10, [0.3, 0.6], 1, 1)
+    oracle.Oracle(3, J, 10, [0.0, 0.6], 1, 1)
+
+
+@pytest.mark.parametrize("L,seed", [(2, 0), (3, 1), (4, 1), (5, 2 ** 63 + 7), (8, 2), (12, 99), (16, 3),
+                                    (32, 123456789)])
+def test_make_pm_j_matches_the_oracle_and_the_input_module(lib, L, seed):
+    """The library's coupling stream (its own host Philox) draws the same
+    instance as the oracle's generator and the input module's; the values
+    are +-1 and about half of each."""
+    import oracle
+    import pamc_inputs as pi
+    from paper_1710_09025_amd import make_pm_j
+
+    a = make_pm_j(L, seed)
+    np.testing.assert_array_equal(a, oracle.make_pm_j(L, seed))
+    np.testing.assert_array_equal(a, pi.pm_j_couplings(L, seed))
+    assert set(np.unique(a)) <= {-1, 1}
+    n = a.size
+    assert abs(int((a > 0).sum()) - n / 2) < 6 * np.sqrt(n / 4) + 2
+
+
+def test_make_pm_j_words_are_bit_31_of_the_coupling_stream(lib):
+    """Bond b is +1 exactly when bit 31 of word (b & 3) of the oracle's
+    Philox at counter (b >> 2, 0, 0, 5 * 2^28) is set."""
+    import oracle
+    from paper_1710_09025_amd import make_pm_j
+
+    L, seed = 3, 0x1234_5678_9ABC
+    a = make_pm_j(L, seed).reshape(-1)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for b in range(a.size):
+        w = oracle.philox4x32_10([b >> 2, 0, 0, 0x50000000], key)[b & 3]
+        assert a[b] == (1 if int(w) >> 31 else -1), b
+
+
+def test_make_pm_j_rejects_bad_arguments(lib):
+    from paper_1710_09025_amd import _capi
+
+    out = np.zeros(3 * 64, dtype=np.int8)
+    assert lib.pamc_make_pm_j(1, 5, out.ctypes.data_as(ctypes.c_void_p)) == _capi.ERR_INVALID
+    assert lib.pamc_make_pm_j(33, 5, out.ctypes.data_as(ctypes.c_void_p)) == _capi.ERR_INVALID
+    assert lib.pamc_make_pm_j(4, 5, None) == _capi.ERR_INVALID
+
+
+def test_rho_f_is_the_sample_variance_times_the_nominal_population(lib):
+    """Eq. (4) through the library: against numpy's ddof-1 variance, a case
+    with a known answer, constant runs (variance 0) and invalid inputs."""
+    from paper_1710_09025_amd import _capi, rho_f
+
+    rng = np.random.default_rng(7)
+    bf = rng.normal(-40.0, 0.3, size=(13, 9))
+    Rn = rng.integers(100, 10000, size=9).astype(np.float64)
+    mean, var, rf = rho_f(bf, Rn)
+    np.testing.assert_allclose(mean, bf.mean(axis=0), rtol=1e-14)
+    np.testing.assert_allclose(var, bf.var(axis=0, ddof=1), rtol=1e-12)
+    np.testing.assert_allclose(rf, Rn * bf.var(axis=0, ddof=1), rtol=1e-12)
+    # two runs at -1 and +1: mean 0, variance (1 + 1) / 1 = 2
+    mean, var, rf = rho_f(np.array([[-1.0], [1.0]]), [50.0])
+    assert mean[0] == 0.0 and var[0] == 2.0 and rf[0] == 100.0
+    mean, var, rf = rho_f(np.full((4, 3), -7.25), 10.0)
+    assert np.all(var == 0.0) and np.all(rf == 0.0) and np.all(mean == -7.25)
+    one = np.zeros((1, 3))
+    out = np.zeros(3)
+    assert lib.pamc_rho_f(one.ctypes.data_as(ctypes.c_void_p), 1, 3, out.ctypes.data_as(ctypes.c_void_p), None,
+                          None, None) == _capi.ERR_INVALID

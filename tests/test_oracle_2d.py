@@ -75,12 +75,13 @@ def test_energies_equal_enumeration(L):
 
 @pytest.mark.parametrize("beta,icm", [(0.5, 0), (1.3, 0), (1.0, 2)])
 def test_fixed_beta_population_is_boltzmann(beta, icm):
-    """Constant beta: resampling is neutral, and the sweeps (and the pair
+    """From beta = 0, one resampling to beta, then constant beta: later
+    resamplings weight every replica equally, and the sweeps (and the pair
     updates, which keep the product of the pair's Boltzmann weights) leave
     the exact law over all 2^9 configurations invariant."""
     L, N, R = 3, 9, 8000
     J = pi.gaussian_couplings(L, 40, dim=2)
-    o = oracle.Oracle(L, J, R, [beta] * 25, 6, 3 + icm, threads=8, icm_rounds=icm)
+    o = oracle.Oracle(L, J, R, [0.0] + [beta] * 24, 6, 3 + icm, threads=8, icm_rounds=icm)
     assert o.run() == oracle.OK
     E_all = _all_energies(L, J).astype(np.float64) * SCALE
     w = np.exp(-beta * (E_all - E_all.min()))

@@ -118,12 +118,13 @@ def _gtest_pooled(counts, p, min_expected=5.0):
 
 @pytest.mark.parametrize("beta,real", [(0.5, False), (1.0, True)])
 def test_fixed_beta_population_with_icm_is_boltzmann(beta, real):
-    """Constant beta with ICM at every step: the pair updates keep the
-    product of Boltzmann laws invariant, so the population still follows the
-    exact Boltzmann law over all 2^N configurations."""
+    """Constant beta (after the start at beta = 0) with ICM at every step:
+    the pair updates keep the product of Boltzmann laws invariant, so the
+    population still follows the exact Boltzmann law over all 2^N
+    configurations."""
     L, N, R = 2, 8, 6000
     J = pi.gaussian_couplings(L, 9) if real else pi.pm_j_couplings(L, 9)
-    o = oracle.Oracle(L, J, R, [beta] * 25, 4, 3, threads=8, icm_rounds=2)
+    o = oracle.Oracle(L, J, R, [0.0] + [beta] * 24, 4, 3, threads=8, icm_rounds=2)
     assert o.run() == oracle.OK
     st = o.get_state()
     E_all = (oracle.all_energies_real(L, J).astype(np.float64) * 2.0 ** -20 if real

@@ -162,15 +162,16 @@ def _gtest_pooled(counts, p, min_expected=5.0):
 
 @pytest.mark.parametrize("beta,seed", [(0.4, 1), (1.2, 2)])
 def test_fixed_beta_population_is_boltzmann(beta, seed):
-    """Constant beta: every resampling is neutral, so the replicas are
-    independent Metropolis chains whose configurations must follow the
-    exact Boltzmann law over all 2^N configurations."""
+    """From beta = 0, one resampling to beta, then constant beta: later
+    resamplings weight every replica equally, so the replicas evolve as
+    Metropolis chains whose configurations must follow the exact Boltzmann
+    law over all 2^N configurations."""
     L, N, R = 2, 8, 6000
     J = pi.gaussian_couplings(L, 100 + seed)
-    o = oracle.Oracle(L, J, R, [beta] * 25, 10, seed, threads=8)
+    o = oracle.Oracle(L, J, R, [0.0] + [beta] * 24, 10, seed, threads=8)
     assert o.run() == oracle.OK
     st = o.get_state()
-    np.testing.assert_array_equal(st["family"], np.arange(R))
+    assert np.all(np.diff(st["family"].astype(np.int64)) >= 0)
     E_all = oracle.all_energies_real(L, J).astype(np.float64) * SCALE
     w = np.exp(-beta * (E_all - E_all.min()))
     p = w / w.sum()
