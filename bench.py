@@ -6,16 +6,23 @@ One benchmark step is one complete anneal of the workload (every row of the
 hot path: N_S checkerboard Metropolis sweeps of every replica at each of the
 n_temps temperatures, energy histogram, FP64 weight normalisation, copy
 counts, prefix sum and gather of the surviving replicas, family and overlap
-statistics).  Inputs (couplings, initial population) are resident on the GPU
-before the timed region; each timed anneal runs on its own, freshly created
-run handle.
+statistics).  The default workload is the largest one a single GPU runs: L =
+16, R = 5 10^5, 301 temperatures, one byte per spin.  Inputs (couplings,
+initial population) are resident on the GPU before the timed region; each
+timed anneal runs on its own, freshly created run handle.
 
 Prints ONE JSON line.  Besides the contract fields it carries
   roofline      the dominant kernel (the sweep) against the chip's integer
                 VALU peak, timed live with HIP events on the run's stream;
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
-  extra         the other single-GPU workloads (L = 4 latency-bound case,
-                L = 16 throughput case).
+  cpu_baseline  the CPU oracle on a row sample of the same anneal, timed
+                at one thread and at the host's threads and extrapolated;
+  gather        the HBM-bound kernel of the path (stand-alone gather of the
+                surviving replicas) against the HBM peak;
+  extra         the other workloads (bit-packed spins, L = 8 and L = 4
+                instances, Gaussian couplings, schedules, rho_f, cluster
+                moves, the square lattice, the 2000-instance batch against
+                2000 separate runs with a result check, the serving loop,
+                and the calibration kernels of the roofline).
 """
 from __future__ import annotations
 
@@ -132,7 +139,8 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, i
     att = attempts_of(obs, N, cfg["sweeps"])
     Rbar = float(np.mean(obs["R"]))
     return dict(cfg=cfg, wall_s=t1 - t0, sweep_ms=sweep_ms, other_ms=other_ms, nsteps=nsteps,
-                attempts_per_anneal=att, mean_R=Rbar, N=N, shape=shape, real=real)
+                attempts_per_anneal=att, mean_R=Rbar, N=N, shape=shape, real=real, packed=packed,
+                R_steps=np.array(obs["R"], dtype=np.float64))
 
 
 def footprint_gb(name, packed):
@@ -195,7 +203,7 @@ def roofline(res):
     ops = opa * res["attempts_per_anneal"]
     achieved = ops / sweep_s / 1e12
     traffic = None
-    key = res["cfg"].get("name", "") + ("_gaussian" if real else "")
+    key = res["cfg"].get("name", "") + ("_gaussian" if real else "") + ("_packed" if res.get("packed") else "")
     if os.path.exists(COUNTERS_FILE):
         try:
             c = json.load(open(COUNTERS_FILE))
@@ -205,6 +213,8 @@ def roofline(res):
         except Exception:
             traffic = None
     rb = ((res["N"] + 15) // 16) * 16
+    if res.get("packed"):
+        rb = (rb + 127) // 128 * 16
     # tile in + out, map / energy / family
     alg_bytes = 2.0 * res["mean_R"] * rb + (20.0 if real else 16.0) * res["mean_R"]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
@@ -218,7 +228,19 @@ def roofline(res):
                                           / HBM_PEAK_GBS, 4)}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(name, n_steps, real=False):
+    """The oracle on the first n_steps temperature steps of a workload at its
+    full population (small workloads)."""
     import oracle
 
     cfg, J, beta = workload_inputs(name, real)
@@ -231,14 +253,90 @@ def cpu_baseline(name, n_steps, real=False):
     rec = o.records()
     att = float(np.sum(rec["R"][:n_steps])) * cfg["L"] ** 3 * cfg["sweeps"]
     return {"value": round(att / ((t1 - t0) * 1e9), 4), "unit": "attempts/ns", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {n_steps} of {cfg['n_temps']} temperature steps of the same workload "
                       f"(full population R={cfg['R']}, L={cfg['L']}), {t1 - t0:.1f} s"}
 
 
-def batch_bench(n_inst, plain_per_L):
+def cpu_baseline_sampled(name, R_steps, rows_1t=192, rows_nt=2048, rows_resample=20000):
+    """The oracle on a row sample of the workload's anneal, extrapolated to
+    the whole anneal (the full run takes hours on the host).
+
+    Sweeps: the first 10 temperature steps of the first rows of the initial
+    population (the oracle's own, which equals the run's), and the last 10
+    steps of rows sampled evenly from the population the GPU exported at
+    step n_temps - 10; each sample is swept step after step by the oracle's
+    sweep_rows (the same per-replica sweep its run uses), timed.  The time
+    per row and step is interpolated linearly in k between the two samples.
+    Resampling and measurement: the oracle's measure_resample of the first
+    rows_resample rows of the exported population, timed, per row.  The
+    whole anneal is then sum_k R_k (sweep + resampling time per row) with
+    the GPU run's R_k.  Timed at one thread and at the host's threads."""
+    import oracle
+
+    from paper_1710_09025_amd import Pamc
+
+    cfg, J, beta = workload_inputs(name)
+    L, NS, nT = cfg["L"], cfg["sweeps"], cfg["n_temps"]
+    N = L ** 3
+    k_late = nT - 10
+    p = Pamc(L, J, cfg["R"], beta, NS, cfg["seed"], autotune=True)
+    assert p.anneal(k_late) == 0
+    late = p.get_state()
+    p.close()
+    del p
+    threads = min(16, os.cpu_count() or 1)
+    o = oracle.Oracle(L, J, rows_nt, beta, NS, cfg["seed"], threads=threads)
+    first = o.get_state()["spins"]
+    Rs = min(rows_resample, late["R"])
+    o2 = oracle.Oracle(L, J, Rs, beta, NS, cfg["seed"], threads=threads)
+    out = {}
+    t_all0 = time.perf_counter()
+    for thr, rows in ((1, rows_1t), (threads, rows_nt)):
+        o.set_threads(thr)
+        o2.set_threads(thr)
+        sp = first[:rows]
+        idx = np.arange(rows, dtype=np.int64)
+        t0 = time.perf_counter()
+        for k in range(10):
+            sp, _ = o.sweep_rows(k, idx, sp)
+        early = (time.perf_counter() - t0) / (10 * rows)
+        idx = np.linspace(0, late["R"] - 1, rows).astype(np.int64)
+        sp = late["spins"][idx]
+        t0 = time.perf_counter()
+        for k in range(k_late, nT):
+            sp, _ = o.sweep_rows(k, idx, sp)
+        late_t = (time.perf_counter() - t0) / (10 * rows)
+        o2.set_state(k_late, late["spins"][:Rs], np.arange(Rs, dtype=np.uint32), late["lnZ"])
+        t0 = time.perf_counter()
+        assert o2.measure_resample() == 0
+        res_t = (time.perf_counter() - t0) / Rs
+        ks = np.arange(nT, dtype=np.float64)
+        per_row = np.interp(ks, [4.5, k_late + 4.5], [early, late_t]) + res_t
+        total_s = float(np.sum(R_steps * per_row))
+        att = float(np.sum(R_steps)) * N * NS
+        out[thr] = (att / (total_s * 1e9), total_s, early, late_t, res_t)
+    cpu_s = time.perf_counter() - t_all0
+    v, total_s, early, late_t, res_t = out[threads]
+    return {"value": round(v, 4), "unit": "attempts/ns", "cores": threads, "kind": "oracle",
+            "extrapolated": True, "value_1_thread": round(out[1][0], 5),
+            "full_anneal_s_extrapolated": round(total_s, 1),
+            "full_anneal_s_extrapolated_1_thread": round(out[1][1], 1),
+            "cpu_model": cpu_model(),
+            "sample": f"{name}: sweeps of {rows_nt} rows ({rows_1t} at one thread) over the first 10 and the "
+                      f"last 10 of {nT} temperature steps (late rows from the GPU's exported population at step "
+                      f"{k_late}), and one measurement and resampling of {Rs} exported rows, timed and "
+                      f"extrapolated to the whole anneal by the GPU run's population sizes; {cpu_s:.1f} s of "
+                      f"timing",
+            "ms_per_row_step": {"first_steps": round(early * 1e3, 4), "last_steps": round(late_t * 1e3, 4),
+                                "resampling": round(res_t * 1e3, 6)}}
+
+
+def batch_bench(n_inst, plain_n):
     """Mixed-size batch: all instances annealed together (graph-replayed
-    steps) against separate per-instance runs on a stratified sample."""
+    steps) against plain_n separate runs, one after another on one stream
+    (plain_n = n_inst runs every instance).  Every separate run's per-step
+    records must equal its batched twin's; a mismatch fails the leg."""
     import torch
 
     from paper_1710_09025_amd import Pamc, PamcBatch, autotune
@@ -254,49 +352,74 @@ def batch_bench(n_inst, plain_per_L):
     assert st == 0, st
     # attempts actually run: sum_k R_k N N_S over every instance
     att_run = 0.0
-    for i in range(0, n_inst):
+    keys = ("R", "sum_E", "sum_E2", "E_min", "E_max", "lnZ", "S_f")
+    batched = []
+    for i in range(n_inst):
         o = b.observables(i)
         att_run += float(np.sum(o["R"])) * insts[i]["L"] ** 3 * insts[i]["sweeps"]
+        batched.append({k: np.array(o[k]) for k in keys})
     b.close()
     del b
     torch.cuda.empty_cache()
-    # per-instance runs: plain_per_L instances of each size, one after another
-    per_L = {}
-    for L in sorted({d["L"] for d in insts}):
-        sample = [d for d in insts if d["L"] == L][:plain_per_L]
-        ts, tc = [], []
-        for d in sample:
-            c0 = time.perf_counter()
-            p = Pamc(d["L"], d["couplings"], d["R"], d["beta"], d["sweeps"], d["seed"], autotune=True)
-            torch.cuda.synchronize()
-            c1 = time.perf_counter()
-            assert p.anneal() == 0
-            torch.cuda.synchronize()
-            c2 = time.perf_counter()
-            p.close()
-            ts.append(c2 - c1)
-            tc.append(c2 - c0)
-        per_L[L] = (float(np.mean(ts)), float(np.mean(tc)), len(sample))
-    count = {L: sum(1 for d in insts if d["L"] == L) for L in per_L}
+    log(f"batch of {n_inst} annealed in {t2 - t1:.2f} s")
+    # separate runs: the first plain_n instances (all of them by default)
+    t_anneal, t_total, mismatches = 0.0, 0.0, []
+    att_plain = 0.0
+    for i, d in enumerate(insts[:plain_n]):
+        c0 = time.perf_counter()
+        p = Pamc(d["L"], d["couplings"], d["R"], d["beta"], d["sweeps"], d["seed"], autotune=True)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        assert p.anneal() == 0
+        torch.cuda.synchronize()
+        c2 = time.perf_counter()
+        o = p.observables()
+        p.close()
+        t_anneal += c2 - c1
+        t_total += c2 - c0
+        att_plain += float(np.sum(o["R"])) * d["L"] ** 3 * d["sweeps"]
+        if any(list(np.asarray(o[k])) != list(batched[i][k]) for k in keys):
+            mismatches.append(i)
+    count = {}
+    for d in insts:
+        count[d["L"]] = count.get(d["L"], 0) + 1
     shapes = {}
-    for L in per_L:
+    for L in sorted(count):
         d = next(d for d in insts if d["L"] == L)
         t, g, ns = autotune(L, d["R"], d["sweeps"])  # cached: the shapes both sides used
         shapes[str(L)] = {"tile_rows": t, "group_replicas": g, "sweep_ns_per_attempt": round(ns, 6)}
-    plain_anneal = sum(count[L] * per_L[L][0] for L in per_L)
-    plain_total = sum(count[L] * per_L[L][1] for L in per_L)
+    if mismatches:
+        raise AssertionError(f"batched and separate runs differ for instances {mismatches[:10]}")
+    full = plain_n >= n_inst
+    plain_rate = plain_n / t_anneal
     return {
         "instances": n_inst,
         "batched_instances_per_s": round(n_inst / (t2 - t1), 3),
         "batched_instances_per_s_incl_create": round(n_inst / (t2 - t0), 3),
         "batched_attempts_per_ns": round(att_run / ((t2 - t1) * 1e9), 3),
         "batched_anneal_s": round(t2 - t1, 3),
-        "plain_instances_per_s": round(n_inst / plain_anneal, 3),
-        "plain_instances_per_s_incl_create": round(n_inst / plain_total, 3),
-        "plain_sample": f"{plain_per_L} per L, extrapolated by instance count",
-        "speedup": round(plain_anneal / (t2 - t1), 3),
+        "plain_instances_per_s": round(plain_rate, 3),
+        "plain_instances_per_s_incl_create": round(plain_n / t_total, 3),
+        "plain_attempts_per_ns": round(att_plain / (t_anneal * 1e9), 3),
+        "plain_anneal_s": round(t_anneal, 3),
+        "plain_runs": plain_n,
+        "plain_sample": "every instance, one run after another" if full else
+                        f"the first {plain_n} of {n_inst} instances (a sample)",
+        "batched_equals_plain": f"per-step R, sum E, sum E^2, E_min, E_max, ln Z, S_f identical for all "
+                                f"{plain_n} separate runs",
+        "speedup": round((n_inst / (t2 - t1)) / plain_rate, 3),
         "sweep_shapes_autotuned": shapes,
     }
+
+
+def calibration():
+    """Philox-only and plain-VALU rates of the device (pamc_calibrate)."""
+    from paper_1710_09025_amd import calibrate
+
+    words, valu = calibrate()
+    return {"philox_words_per_ns": round(words, 1), "valu_int32_ops_per_ns": round(valu, 1),
+            "valu_peak_ops_per_ns": round(ALU_PEAK_TOPS * 1e3, 1),
+            "valu_frac_of_peak": round(valu / (ALU_PEAK_TOPS * 1e3), 4)}
 
 
 def schedule_bench(name, kind):
@@ -414,12 +537,15 @@ def warm_serving_shapes(sweeps=10):
 
 
 def serve_bench(n_req, rate, budget_gb):
-    """Poisson request stream replayed in real time against the serving loop."""
+    """Poisson request stream replayed in real time against the serving loop;
+    latency = completion - submission; GPU busy = device time of the step
+    batches over the span from the first submission to the last completion."""
     from paper_1710_09025_amd import PamcServer
 
     reqs = pi.serving_requests(n_req, rate=rate)
     srv = PamcServer(int(budget_gb * (1 << 30)), max_active=256, autotune=True)
     ids = []
+    busy0 = srv.usage()["busy_s"]
     t0 = time.perf_counter()
     for d in reqs:
         now = time.perf_counter() - t0
@@ -429,39 +555,52 @@ def serve_bench(n_req, rate, budget_gb):
     lat = []
     last = 0.0
     first = None
-    for rid in ids:
-        st, _, tm = srv.wait(rid, timeout=1200)
+    att = 0.0
+    for rid, d in zip(ids, reqs):
+        st, obs, tm = srv.wait(rid, timeout=1200)
         assert st == 0, st
         lat.append(tm["finish"] - tm["submit"])
         last = max(last, tm["finish"])
         first = tm["submit"] if first is None else min(first, tm["submit"])
+        att += float(np.sum(obs["R"])) * d["L"] ** 3 * d["sweeps"]
+    busy = srv.usage()["busy_s"] - busy0
     srv.close()
     lat = np.array(lat)
-    att = sum(float(d["R"]) * d["L"] ** 3 * d["sweeps"] * len(d["beta"]) for d in reqs)
     span = last - first
     return {"requests": n_req, "offered_rate_per_s": round(rate, 3), "hbm_budget_gb": budget_gb,
             "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
             "instances_per_s": round(n_req / span, 3),
-            "attempts_per_ns": round(att / (span * 1e9), 3)}
+            "attempts_per_ns": round(att / (span * 1e9), 3),
+            "gpu_busy_frac": round(busy / span, 4)}
+
+
+def line_for(res, steps):
+    """Rate figures of one timed workload."""
+    return {"attempts_per_ns": round(res["attempts_per_anneal"] * steps / (res["wall_s"] * 1e9), 3),
+            "sweep_attempts_per_ns": round(res["attempts_per_anneal"] / (res["sweep_ms"] * 1e6), 3),
+            "ms_per_anneal": round(res["wall_s"] / steps * 1e3, 3),
+            "sweep_share": round(res["sweep_ms"] / (res["sweep_ms"] + res["other_ms"]), 4),
+            "spins": "packed" if res.get("packed") else "int8",
+            "sweep_shape": {"tile_rows": res["shape"][0], "group_replicas": res["shape"][1]}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed anneals")
+    ap.add_argument("--steps", type=int, default=3, help="timed anneals")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="L8_R100000",
+    ap.add_argument("--workload", default="L16_R500000",
                     choices=sorted(k for k, v in pi.WORKLOADS.items() if v.get("dim", 3) == 3))
     ap.add_argument("--couplings", default="pm1", choices=("pm1", "gaussian"),
                     help="couplings of the benchmark instance: +-1, or Gaussian in fixed point")
     ap.add_argument("--icm-rounds", type=int, default=0,
                     help="isoenergetic cluster-move rounds per step in the main line (0: none)")
-    ap.add_argument("--cpu-steps", type=int, default=16, help="temperature steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--batch", type=int, default=2000, help="instances of the mixed-size batch (0: skip)")
-    ap.add_argument("--batch-plain", type=int, default=5, help="per-instance runs per L for the comparison")
+    ap.add_argument("--batch-plain", type=int, default=2000,
+                    help="separate runs compared with the batch (the first this many instances)")
     ap.add_argument("--serve", type=int, default=300, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
@@ -471,6 +610,8 @@ def main():
                     help="temperature steps of the stand-alone gather measurement (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated subset of the extra legs to run (default: all)")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -494,6 +635,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    legs = set(x for x in args.legs.split(",") if x)
+
+    def want(leg):
+        return not legs or leg in legs
 
     real = args.couplings == "gaussian"
     res = time_anneals(args.workload, args.steps, args.warmup, real=real, icm_rounds=args.icm_rounds)
@@ -516,8 +661,9 @@ def main():
         "dtype": "u32",
         "data": f"synthetic: {'Gaussian' if real else '+-J'} couplings and Philox-initialised replicas from "
                 "fixed seeds",
-        "config": {"workload": f"3D EA {'Gaussian' if real else '+-J'} L={cfg['L']} periodic, R={cfg['R']}, n_temps={cfg['n_temps']} "
-                               f"beta linear 0->{cfg['beta_max']}, N_S={cfg['sweeps']}, one instance",
+        "config": {"workload": f"3D EA {'Gaussian' if real else '+-J'} L={cfg['L']} periodic, R={cfg['R']}, "
+                               f"n_temps={cfg['n_temps']} beta linear 0->{cfg['beta_max']}, N_S={cfg['sweeps']}, "
+                               "one instance, one byte per spin",
                    "L": cfg["L"], "R": cfg["R"], "n_temps": cfg["n_temps"], "sweeps": cfg["sweeps"],
                    "step": "one complete anneal", "spins": "int8", "icm_rounds": args.icm_rounds},
         "sweep_attempts_per_ns": round(res["attempts_per_anneal"] / (res["sweep_ms"] * 1e6), 3),
@@ -525,83 +671,96 @@ def main():
         "roofline": roofline(res),
     }
     if args.gather_steps and not real:
-        line["gather"] = {name: gather_bench(name, args.gather_steps) for name in (args.workload, "L16_R500000")}
+        line["gather"] = {name: gather_bench(name, args.gather_steps) for name in ("L16_R500000", "L8_R100000")}
         line["gather"]["L16_R500000_packed"] = gather_bench("L16_R500000", args.gather_steps, packed=True)
         log("gather legs done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps if not real else max(1, args.cpu_steps // 4),
-                                            real)
+        if real or args.workload == "L4_R1000":
+            line["cpu_baseline"] = cpu_baseline(args.workload, 3 if real else 20, real)
+        else:
+            line["cpu_baseline"] = cpu_baseline_sampled(args.workload, res["R_steps"])
         log("cpu baseline done")
     if not args.no_extra:
         extra = {}
-        for name, k, w, packed in (("L4_R1000", 5, 1, False), ("L16_R500000", 1, 0, False),
-                                   ("L16_R500000", 1, 0, True)):
-            if name == args.workload and not packed:
-                continue
-            r = time_anneals(name, k, w, packed=packed)
-            log(f"{name}{' packed' if packed else ''} done")
-            extra[name + ("_packed" if packed else "")] = {
-                "attempts_per_ns": round(r["attempts_per_anneal"] * k / (r["wall_s"] * 1e9), 3),
-                "sweep_attempts_per_ns": round(r["attempts_per_anneal"] / (r["sweep_ms"] * 1e6), 3),
-                "ms_per_anneal": round(r["wall_s"] / k * 1e3, 3),
-                "sweep_share": round(r["sweep_ms"] / (r["sweep_ms"] + r["other_ms"]), 4),
-                "spins": "packed" if packed else "int8",
-                "footprint_gb": footprint_gb(name, packed),
-                "sweep_shape": {"tile_rows": r["shape"][0], "group_replicas": r["shape"][1]},
-            }
+        line["extra"] = extra
+
+        def leg(key, fn):
+            """Runs one extra leg; a failure is recorded in its place."""
+            if not want(key.split(":")[0]):
+                return
+            try:
+                extra[key.split(":")[-1]] = fn()
+            except Exception as e:  # noqa: BLE001
+                extra[key.split(":")[-1]] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"{key} done")
+
+        leg("calibration", calibration)
+        if args.workload == "L16_R500000" and not real:
+            def packed_leg():
+                r = time_anneals("L16_R500000", max(1, args.steps - 1), 1, packed=True)
+                r["cfg"]["name"] = "L16_R500000"
+                out = line_for(r, max(1, args.steps - 1))
+                out["footprint_gb"] = footprint_gb("L16_R500000", True)
+                out["roofline"] = roofline(r)
+                return out
+            leg("packed:L16_R500000_packed", packed_leg)
+
+        def small_leg(name, k, w):
+            def f():
+                r = time_anneals(name, k, w)
+                r["cfg"]["name"] = name
+                out = line_for(r, k)
+                out["footprint_gb"] = footprint_gb(name, False)
+                out["roofline"] = roofline(r)
+                out["cpu_baseline"] = cpu_baseline(name, 16 if name == "L8_R100000" else 101)
+                return out
+            return f
+        for name, k, w in (("L8_R100000", 5, 1), ("L4_R1000", 5, 1)):
+            if name != args.workload:
+                leg(f"small:{name}", small_leg(name, k, w))
         if not real:
-            # the paper's own case study: Gaussian couplings, same workload
-            g = time_anneals(args.workload, 3, 1, real=True)
-            g["cfg"]["name"] = args.workload
-            extra[args.workload + "_gaussian"] = {
-                "attempts_per_ns": round(g["attempts_per_anneal"] * 3 / (g["wall_s"] * 1e9), 3),
-                "sweep_attempts_per_ns": round(g["attempts_per_anneal"] / (g["sweep_ms"] * 1e6), 3),
-                "ms_per_anneal": round(g["wall_s"] / 3 * 1e3, 3),
-                "sweep_share": round(g["sweep_ms"] / (g["sweep_ms"] + g["other_ms"]), 4),
-                "roofline": roofline(g),
-                "cpu_baseline": cpu_baseline(args.workload, 3, real=True),
-            }
-            log("gaussian leg done")
+            def gaussian_leg():
+                g = time_anneals("L8_R100000", 3, 1, real=True)
+                g["cfg"]["name"] = "L8_R100000"
+                out = line_for(g, 3)
+                out["roofline"] = roofline(g)
+                out["cpu_baseline"] = cpu_baseline("L8_R100000", 3, real=True)
+                return out
+            leg("gaussian:L8_R100000_gaussian", gaussian_leg)
         for kind in ("lblt", "tspl", "tspl_dynamic_R"):
-            extra[f"{args.workload}_{kind}"] = schedule_bench(args.workload, kind)
-            log(f"schedule {kind} done")
-        extra["rho_f"] = rho_f_bench()
-        extra[f"{args.workload}_icm"] = icm_bench(args.workload)
-        extra["rho_f_icm"] = rho_f_bench(icm_rounds=2)
+            leg(f"schedules:L8_R100000_{kind}", lambda kind=kind: schedule_bench("L8_R100000", kind))
+        leg("rho_f:rho_f", rho_f_bench)
+        leg("icm:L8_R100000_icm", lambda: icm_bench("L8_R100000"))
+        leg("icm:rho_f_icm", lambda: rho_f_bench(icm_rounds=2))
         # only below T = 1, around and below the spin-glass transition
-        extra["rho_f_icm_low_T"] = rho_f_bench(icm_rounds=2, icm_beta_min=1.0)
-        log("rho_f and cluster moves done")
+        leg("icm:rho_f_icm_low_T", lambda: rho_f_bench(icm_rounds=2, icm_beta_min=1.0))
+
         # the square lattice (Sec. II.A): throughput at the paper's largest
         # 2D size, and its cluster-move comparison of rho_f
-        s = time_anneals("L32_2D_R1000000", 1, 0)
-        extra["L32_2D_R1000000"] = {
-            "attempts_per_ns": round(s["attempts_per_anneal"] / (s["wall_s"] * 1e9), 3),
-            "sweep_attempts_per_ns": round(s["attempts_per_anneal"] / (s["sweep_ms"] * 1e6), 3),
-            "ms_per_anneal": round(s["wall_s"] * 1e3, 3),
-            "sweep_share": round(s["sweep_ms"] / (s["sweep_ms"] + s["other_ms"]), 4),
-            "sweep_shape": {"tile_rows": s["shape"][0], "group_replicas": s["shape"][1]},
-        }
-        # the same with two cluster-move rounds per step, the paper's 2D setting
-        extra["L32_2D_R1000000_icm"] = icm_bench("L32_2D_R1000000")
+        def square_leg():
+            r = time_anneals("L32_2D_R1000000", 1, 0)
+            return line_for(r, 1)
+        leg("square:L32_2D_R1000000", square_leg)
+        leg("square:L32_2D_R1000000_icm", lambda: icm_bench("L32_2D_R1000000"))
         # rho_f is intensive (independent of R once R >> rho_f), so the larger
         # lattices use R = 5 10^4 to afford more runs and instances
-        extra["rho_f_2D_L8"] = rho_f_square_bench()
-        extra["rho_f_2D_L16"] = rho_f_square_bench(L=16, R=50000, runs=64)
-        extra["rho_f_2D_L32"] = rho_f_square_bench(L=32, R=50000, n_temps=301, runs=32, instances=(1, 2))
-        log("square lattice done")
+        leg("square:rho_f_2D_L8", rho_f_square_bench)
+        leg("square:rho_f_2D_L16", lambda: rho_f_square_bench(L=16, R=50000, runs=64))
+        leg("square:rho_f_2D_L32", lambda: rho_f_square_bench(L=32, R=50000, n_temps=301, runs=32,
+                                                               instances=(1, 2)))
         if args.batch:
-            extra["batch_mixed_L"] = batch_bench(args.batch, args.batch_plain)
-            log("batch done")
-        if args.serve:
-            warm = warm_serving_shapes()
-            sat = serve_bench(args.serve, args.serve_rate, args.serve_budget_gb)
-            sat["shape_tuning_before_stream_s"] = round(warm, 2)
-            extra["serving"] = sat
-            log("serving done")
-            if args.serve_light:
-                extra["serving_at_0.8x_saturation"] = serve_bench(
-                    args.serve_light, 0.8 * sat["instances_per_s"], args.serve_budget_gb)
-        line["extra"] = extra
+            leg("batch:batch_mixed_L", lambda: batch_bench(args.batch, min(args.batch, args.batch_plain)))
+        if args.serve and want("serving"):
+            t0 = time.perf_counter()
+            warm_serving_shapes()
+            warm = time.perf_counter() - t0
+            leg("serving:serving", lambda: serve_bench(args.serve, args.serve_rate, args.serve_budget_gb))
+            sat = extra.get("serving", {})
+            if "instances_per_s" in sat:
+                sat["shape_tuning_before_stream_s"] = round(warm, 2)
+                if args.serve_light:
+                    leg("serving:serving_at_0.8x_saturation",
+                        lambda: serve_bench(args.serve_light, 0.8 * sat["instances_per_s"], args.serve_budget_gb))
     print(json.dumps(line), flush=True)
 
 

@@ -322,6 +322,17 @@ int pamc_make_pm_j(int L, uint64_t disorder_seed, int8_t *out);
 int pamc_rho_f(const double *betaF, int runs, int n_temps, const double *nominal_R, double *mean_betaF,
                double *var_betaF, double *rho_f);
 
+/* Calibration of the sweep's roofline on a device (-1 = current): the
+ * rate of a kernel that only draws Philox4x32-10 blocks with the sweep's
+ * counter pattern (counter (block, replica, step, TAG_SWEEP | sweep), ten
+ * sweeps per replica, the four words XOR-folded), in 32-bit words per ns,
+ * and the rate of a kernel of independent three-input XORs and adds, in
+ * int32 VALU operations per ns.  The sweep draws one word per attempted
+ * flip (Sec. III.A), so the first rate bounds its attempts per ns.  Each
+ * output may be NULL.  Allocates and frees a small device buffer.
+ * Errors: PAMC_ERR_NOMEM, PAMC_ERR_DEVICE. */
+int pamc_calibrate(int device, double *philox_words_per_ns, double *valu_ops_per_ns);
+
 /* Device footprint in bytes of a run with these parameters; -1 for
  * arguments no run accepts. */
 int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt);
@@ -383,7 +394,9 @@ typedef struct pamc_result {
     double finish_time_s;
 } pamc_result;
 
-/* hbm_budget_bytes bounds the device memory of admitted requests. */
+/* hbm_budget_bytes bounds the device memory of admitted requests: a
+ * request holds pamc_footprint(L, R, n_temps, options with the server's
+ * spin format) + 4096 bytes of it from admission to completion. */
 int pamc_server_create(size_t hbm_budget_bytes, const pamc_server_options *opt, pamc_server **out);
 /* Thread-safe.  PAMC_ERR_REJECTED if the request alone exceeds the budget. */
 int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_id);
@@ -392,6 +405,12 @@ int pamc_server_poll(pamc_server *s, uint64_t req_id, pamc_result *out);
 int pamc_server_cancel(pamc_server *s, uint64_t req_id);
 /* Counters: completed, queued, active. */
 int pamc_server_stats(pamc_server *s, int64_t *completed, int64_t *queued, int64_t *active);
+/* Memory and device use (each output may be NULL): used_bytes, the budget
+ * held by admitted requests (0 when none runs); budget_bytes, the budget;
+ * busy_s, the device time spent running temperature steps since creation
+ * (HIP events around every batch of steps); wall_s, the host time since
+ * creation.  Returns the loop's status. */
+int pamc_server_usage(pamc_server *s, size_t *used_bytes, size_t *budget_bytes, double *busy_s, double *wall_s);
 void pamc_server_destroy(pamc_server *s);
 
 #ifdef __cplusplus

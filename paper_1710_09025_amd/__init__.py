@@ -31,7 +31,7 @@ import numpy as np
 from . import _capi
 
 __all__ = ["Pamc", "PamcBatch", "PamcServer", "PamcError", "OBS_FIELDS", "default_capacity", "make_pm_j", "rho_f",
-           "free_energy_variance", "autotune"]
+           "free_energy_variance", "autotune", "calibrate"]
 
 OBS_FIELDS = ("beta", "R", "sum_E", "sum_E2", "E_min", "E_max", "mean_E", "e", "C_V", "lnQ", "lnZ",
               "betaF", "f", "S_f", "rho_s", "q_abs", "q2", "q4", "g_SG", "measured")
@@ -187,6 +187,14 @@ def make_pm_j(L: int, disorder_seed: int) -> np.ndarray:
     _check(_capi.load().pamc_make_pm_j(int(L), ctypes.c_uint64(int(disorder_seed) & (2**64 - 1)), _ptr(out)),
            "pamc_make_pm_j")
     return out.reshape(3, int(L) ** 3)
+
+
+def calibrate(device: int = -1):
+    """(Philox words per ns, int32 VALU operations per ns) of the device's
+    calibration kernels (``pamc_calibrate``)."""
+    w, v = ctypes.c_double(), ctypes.c_double()
+    _check(_capi.load().pamc_calibrate(int(device), ctypes.byref(w), ctypes.byref(v)), "pamc_calibrate")
+    return w.value, v.value
 
 
 def rho_f(betaF, nominal_R):
@@ -494,6 +502,16 @@ class PamcServer:
         c, q, a = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         st = _capi.load().pamc_server_stats(self._h, ctypes.byref(c), ctypes.byref(q), ctypes.byref(a))
         return {"status": st, "completed": c.value, "queued": q.value, "active": a.value}
+
+    def usage(self):
+        """Budget held by admitted requests, the budget, device busy time
+        and wall time since creation (``pamc_server_usage``)."""
+        u, b = ctypes.c_size_t(), ctypes.c_size_t()
+        busy, wall = ctypes.c_double(), ctypes.c_double()
+        st = _capi.load().pamc_server_usage(self._h, ctypes.byref(u), ctypes.byref(b), ctypes.byref(busy),
+                                            ctypes.byref(wall))
+        return {"status": st, "used_bytes": u.value, "budget_bytes": b.value, "busy_s": busy.value,
+                "wall_s": wall.value}
 
     def close(self):
         if getattr(self, "_h", None):

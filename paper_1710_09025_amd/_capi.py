@@ -144,6 +144,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int64)]),
     "pamc_footprint": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Options)]),
     "pamc_make_pm_j": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, P]),
+    "pamc_calibrate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pamc_rho_f": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P, P, P]),
     "pamc_destroy": (None, [P]),
     "pamc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -162,6 +163,8 @@ SIGNATURES = {
     "pamc_server_cancel": (ctypes.c_int, [P, ctypes.c_uint64]),
     "pamc_server_stats": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "pamc_server_usage": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pamc_server_destroy": (None, [P]),
 }
 

@@ -72,6 +72,9 @@ struct pamc_server {
     uint64_t next_id = 1;
     int64_t completed = 0;
     int loop_status = PAMC_OK;
+    double t_start = 0.0;   // host clock at creation
+    double busy_ms = 0.0;   // device time of the steps run so far
+    hipEvent_t ev_busy[2] = {nullptr, nullptr};
 
     void run_loop();
 };
@@ -176,8 +179,17 @@ void pamc_server::run_loop()
             waiting = !queue.empty();
         }
         const int nsteps = std::max(1, std::min(until_finish, waiting ? 1 : 16));
+        (void)hipEventRecord(ev_busy[0], run.stream());
         int st = run.enqueue_steps(nsteps);
+        (void)hipEventRecord(ev_busy[1], run.stream());
         if (st == PAMC_OK) st = run.sync();
+        if (st == PAMC_OK) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev_busy[0], ev_busy[1]) == hipSuccess) {
+                std::lock_guard<std::mutex> lk(mu);
+                busy_ms += ms;
+            }
+        }
         if (st != PAMC_OK) {
             std::lock_guard<std::mutex> lk(mu);
             loop_status = st;
@@ -239,6 +251,12 @@ int pamc_server_create(size_t hbm_budget_bytes, const pamc_server_options *opt, 
         delete s;
         return st;
     }
+    if (hipEventCreate(&s->ev_busy[0]) != hipSuccess || hipEventCreate(&s->ev_busy[1]) != hipSuccess) {
+        delete s;
+        pamc::set_error("server: hipEventCreate failed");
+        return PAMC_ERR_DEVICE;
+    }
+    s->t_start = now_s();
     s->loop = std::thread([s] { s->run_loop(); });
     *out = s;
     return PAMC_OK;
@@ -330,6 +348,17 @@ int pamc_server_stats(pamc_server *s, int64_t *completed, int64_t *queued, int64
     return s->loop_status;
 }
 
+int pamc_server_usage(pamc_server *s, size_t *used_bytes, size_t *budget_bytes, double *busy_s, double *wall_s)
+{
+    if (!s) return PAMC_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (used_bytes) *used_bytes = s->used;
+    if (budget_bytes) *budget_bytes = s->budget;
+    if (busy_s) *busy_s = s->busy_ms * 1e-3;
+    if (wall_s) *wall_s = now_s() - s->t_start;
+    return s->loop_status;
+}
+
 void pamc_server_destroy(pamc_server *s)
 {
     if (!s) return;
@@ -339,6 +368,8 @@ void pamc_server_destroy(pamc_server *s)
         s->cv.notify_all();
     }
     if (s->loop.joinable()) s->loop.join();
+    for (hipEvent_t e : s->ev_busy)
+        if (e) (void)hipEventDestroy(e);
     delete s;
 }
 

@@ -62,3 +62,31 @@ def run_oracle(inst, overlap_steps=None, capacity=None, steps=-1):
                       capacity=capacity, overlap_steps=overlap_steps, threads=THREADS)
     st = o.run(steps)
     return o, st
+
+
+INT_KEYS = (("R", "R"), ("sum_E", "sumE"), ("sum_E2", "sumE2"), ("E_min", "Emin"), ("E_max", "Emax"))
+FLOAT_KEYS = ("mean_E", "e", "C_V", "lnQ", "lnZ", "betaF", "f", "S_f", "rho_s", "q_abs", "q2", "q4", "g_SG")
+
+
+def compare_obs(gpu_obs, orc, steps=None, what=""):
+    """Per-step records of a run whose normalisers are not exported (batch
+    members, served requests): integers bit-exact, derived observables
+    within REL_TOL, over the first `steps` steps (all by default)."""
+    rec = orc.records()
+    oobs = orc.observables()
+    sl = slice(0, orc.nT if steps is None else steps)
+    for g, o in INT_KEYS:
+        np.testing.assert_array_equal(gpu_obs[g][sl], rec[o][sl], err_msg=f"{what} {g}")
+    for key in FLOAT_KEYS:
+        ok, bad = rel_close(gpu_obs[key][sl], oobs[key][sl])
+        assert ok, (what, key, bad[:5], gpu_obs[key][sl][bad[:5]], oobs[key][sl][bad[:5]])
+
+
+def same_obs(a, b, what=""):
+    """Two GPU runs of the same request: every observable identical."""
+    for key in ("R", "sum_E", "sum_E2", "E_min", "E_max") + FLOAT_KEYS + ("measured",):
+        x, y = np.asarray(a[key]), np.asarray(b[key])
+        if x.dtype == object or np.issubdtype(x.dtype, np.integer):
+            assert list(x) == list(y), (what, key)
+        else:
+            np.testing.assert_array_equal(x, y, err_msg=f"{what} {key}")
