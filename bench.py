@@ -42,16 +42,28 @@ import pamc_inputs as pi  # noqa: E402
 
 METRIC = "spin-flip attempts/ns + HBM GB/s fraction; instances/sec batched vs plain"
 
-# int32 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# int32 VALU peak of MI355X: 256 CUs x 4 SIMDs, each issuing a plain 32-bit
+# wave64 instruction every two cycles (128 lanes per CU per cycle; the fp32
+# vector rate of 157.3 TFLOP/s counts an FMA as two), at 2.4 GHz: 78.6 T
+# operations per second.  The calibration kernels confirm the lane rate
+# (plain chains issue 1.6 wave instructions per CU per cycle, more than a
+# 16-lane SIMD could).
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# Algorithmic int32 operations per spin-flip attempt of the sweep: per
-# Philox block of four attempts, Philox4x32-10 = 10 rounds x (2 widening
-# multiplies + 2 three-input XORs) = 40, the local fields of the four sites
-# packed one byte per site = 6 XORs + 5 adds + 1 byte-align = 12, and the
-# acceptance = 4 x (extract + compare + select) + 2 (downhill mask) + 1
-# (apply) = 15; 67 / 4 = 16.75.
-ALU_OPS_PER_ATTEMPT = 16.75
+# Algorithmic int32 operations per spin-flip attempt of the sweep, per Philox
+# block of four attempts (one Philox4x32-10 call):
+#   Philox: 10 rounds x (2 widening multiplies + 2 three-input XORs) = 40,
+#     of which the first round's products, its XOR with the replica word and
+#     the second round's product and XOR of words fixed for the step are the
+#     same in every sweep of a step (5), leaving 35;
+#   local fields of the four sites packed one byte per site: 6 three-input
+#     XORs + 3 adds (two three-input) + 1 byte-align = 10;
+#   acceptance: 4 x (threshold index + compare + select into the flip mask)
+#     + downhill mask (add, shift, and) + 2 merges of the partial masks = 17;
+#   the flip applied to the word: 1;
+# 63 / 4 = 15.75.  The compiled kernels issue 16.5 lane instructions per
+# attempt (profiles/sweep_L16_R500000_valu_counters.md).
+ALU_OPS_PER_ATTEMPT = 15.75
 # The same with real (Gaussian, fixed-point) couplings, per attempt: Philox
 # 40 / 4 = 10; the local field over six neighbours, each an XOR shared by the
 # four replicas of a word (1/4) + extract + 24-bit multiply-add, and dE from
@@ -98,7 +110,8 @@ def attempts_of(obs, N, sweeps):
     return float(np.sum(obs["R"][obs["measured"] == 1])) * N * sweeps
 
 
-def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, icm_rounds=0):
+def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, icm_rounds=0, tile_rows=0,
+                 group_replicas=0):
     """Creates warmup + steps run handles up front (each temperature step a
     replayed hipGraph; sweep shapes chosen by the autotuner at creation,
     outside the timed region) and anneals them one after another for the
@@ -110,8 +123,9 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, i
 
     cfg, J, beta = workload_inputs(name, real)
     N = cfg["L"] ** cfg.get("dim", 3)
+    shape_kw = dict(tile_rows=tile_rows, group_replicas=group_replicas)
     runs = [Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], autotune=autotune, packed=packed,
-                 icm_rounds=icm_rounds) for _ in range(warmup + steps)]
+                 icm_rounds=icm_rounds, **shape_kw) for _ in range(warmup + steps)]
     shape = runs[0].sweep_shape()
     for r in runs[:warmup]:
         assert r.anneal() == 0
@@ -127,7 +141,7 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, i
         r.close()
     del runs
     timed = Pamc(cfg["L"], J, cfg["R"], beta, cfg["sweeps"], cfg["seed"], timing=True, autotune=autotune,
-                 packed=packed, icm_rounds=icm_rounds)
+                 packed=packed, icm_rounds=icm_rounds, **shape_kw)
     assert timed.sweep_shape() == shape
     assert timed.anneal() == 0
     sweep_ms, other_ms, _, nsteps = timed.phase_times()
@@ -196,7 +210,7 @@ def sweep_kernel_name(L, real):
     return f"k_sweep_eo<{L}>" if L in (8, 16) else "k_sweep_cm / k_sweep_lex"
 
 
-def roofline(res):
+def roofline(res, calib=None):
     sweep_s = res["sweep_ms"] / 1e3
     real = res.get("real", False)
     opa = ALU_OPS_PER_ATTEMPT_REAL if real else ALU_OPS_PER_ATTEMPT
@@ -217,7 +231,7 @@ def roofline(res):
         rb = (rb + 127) // 128 * 16
     # tile in + out, map / energy / family
     alg_bytes = 2.0 * res["mean_R"] * rb + (20.0 if real else 16.0) * res["mean_R"]
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
             "unit": "Tops/s (int32 VALU)", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
             "kernel": sweep_kernel_name(res["cfg"]["L"], real) + " (N_S sweeps of every replica at one temperature)",
             "ops_per_attempt": opa,
@@ -226,6 +240,13 @@ def roofline(res):
             "hbm_gbs_algorithmic": round(alg_bytes / (res["sweep_ms"] / max(1, res["nsteps"]) / 1e3) / 1e9, 1),
             "hbm_frac_algorithmic": round(alg_bytes / (res["sweep_ms"] / max(1, res["nsteps"]) / 1e3) / 1e9
                                           / HBM_PEAK_GBS, 4)}
+    if calib and not real and "philox_words_per_ns" in calib:
+        # one 32-bit Philox word per attempt: the draws alone, measured,
+        # bound the attempts per ns of any sweep that makes them
+        sweep_rate = res["attempts_per_anneal"] / (res["sweep_ms"] * 1e6)
+        out["philox_only_words_per_ns"] = calib["philox_words_per_ns"]
+        out["frac_of_philox_only_ceiling"] = round(sweep_rate / calib["philox_words_per_ns"], 4)
+    return out
 
 
 def cpu_model() -> str:
@@ -610,8 +631,15 @@ def main():
                     help="temperature steps of the stand-alone gather measurement (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run the calibration kernels (Philox-only and plain VALU) and print their rates")
     ap.add_argument("--legs", default="",
                     help="comma-separated subset of the extra legs to run (default: all)")
+    ap.add_argument("--packed", action="store_true", help="main line with bit-packed spin rows")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="main line with this sweep tile instead of the autotuned one (profiling)")
+    ap.add_argument("--group-replicas", type=int, default=0,
+                    help="main line with this colour-major replica group (with --tile-rows)")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -624,6 +652,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n}), flush=True)
+        return
+
+    if args.calibrate:
+        print(json.dumps(calibration()), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -641,7 +673,10 @@ def main():
         return not legs or leg in legs
 
     real = args.couplings == "gaussian"
-    res = time_anneals(args.workload, args.steps, args.warmup, real=real, icm_rounds=args.icm_rounds)
+    fixed = args.tile_rows > 0
+    res = time_anneals(args.workload, args.steps, args.warmup, real=real, icm_rounds=args.icm_rounds,
+                       packed=args.packed, autotune=not fixed, tile_rows=args.tile_rows,
+                       group_replicas=args.group_replicas)
     res["cfg"]["name"] = args.workload
     log(f"{args.workload} ({args.couplings}) timed")
     total_attempts = res["attempts_per_anneal"] * args.steps
@@ -663,13 +698,15 @@ def main():
                 "fixed seeds",
         "config": {"workload": f"3D EA {'Gaussian' if real else '+-J'} L={cfg['L']} periodic, R={cfg['R']}, "
                                f"n_temps={cfg['n_temps']} beta linear 0->{cfg['beta_max']}, N_S={cfg['sweeps']}, "
-                               "one instance, one byte per spin",
+                               "one instance, " + ("one bit per spin" if args.packed else "one byte per spin"),
                    "L": cfg["L"], "R": cfg["R"], "n_temps": cfg["n_temps"], "sweeps": cfg["sweeps"],
-                   "step": "one complete anneal", "spins": "int8", "icm_rounds": args.icm_rounds},
+                   "step": "one complete anneal", "spins": "packed" if args.packed else "int8",
+                   "icm_rounds": args.icm_rounds},
         "sweep_attempts_per_ns": round(res["attempts_per_anneal"] / (res["sweep_ms"] * 1e6), 3),
         "sweep_share": round(res["sweep_ms"] / (res["sweep_ms"] + res["other_ms"]), 4),
-        "roofline": roofline(res),
     }
+    calib = calibration()
+    line["roofline"] = roofline(res, calib)
     if args.gather_steps and not real:
         line["gather"] = {name: gather_bench(name, args.gather_steps) for name in ("L16_R500000", "L8_R100000")}
         line["gather"]["L16_R500000_packed"] = gather_bench("L16_R500000", args.gather_steps, packed=True)
@@ -694,14 +731,14 @@ def main():
                 extra[key.split(":")[-1]] = {"error": f"{type(e).__name__}: {e}"}
             log(f"{key} done")
 
-        leg("calibration", calibration)
+        extra["calibration"] = calib
         if args.workload == "L16_R500000" and not real:
             def packed_leg():
                 r = time_anneals("L16_R500000", max(1, args.steps - 1), 1, packed=True)
                 r["cfg"]["name"] = "L16_R500000"
                 out = line_for(r, max(1, args.steps - 1))
                 out["footprint_gb"] = footprint_gb("L16_R500000", True)
-                out["roofline"] = roofline(r)
+                out["roofline"] = roofline(r, calib)
                 return out
             leg("packed:L16_R500000_packed", packed_leg)
 
@@ -711,7 +748,7 @@ def main():
                 r["cfg"]["name"] = name
                 out = line_for(r, k)
                 out["footprint_gb"] = footprint_gb(name, False)
-                out["roofline"] = roofline(r)
+                out["roofline"] = roofline(r, calib)
                 out["cpu_baseline"] = cpu_baseline(name, 16 if name == "L8_R100000" else 101)
                 return out
             return f
