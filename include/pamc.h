@@ -339,6 +339,32 @@ int64_t pamc_footprint(int L, int64_t R, int n_temps, const pamc_options *opt);
 
 void pamc_destroy(pamc_ctx *ctx);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run
+ * of pamc_create + pamc_anneal + pamc_observables (+ pamc_get_state) with
+ * default options and +-1 couplings, in one call that allocates no device
+ * memory.  Every device buffer comes from one array of 64 MiB that the
+ * library holds on each GPU it runs on until the process ends; runs that
+ * need more (about 2 capacity rows of L^3 bytes plus tables) are refused
+ * with PAMC_ERR_INVALID before any device work.  Arguments as in
+ * pamc_create; stream: the hipStream_t to run on (NULL: the null stream);
+ * the call returns after the run has finished.
+ *   obs          pamc_step_obs [n_temps], caller-owned, filled as by
+ *                pamc_observables;
+ *   final_state  NULL, or caller buffers as in pamc_get_state sized for the
+ *                capacity R + ceil(8 sqrt R) + 64 rows; st->R gives the rows
+ *                written.
+ * Results equal those of pamc_create + pamc_anneal for the same arguments.
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls from one
+ * process are serialised by a lock; calls whose device work overlapped
+ * would race.  Returns PAMC_OK, PAMC_ERR_CAPACITY or PAMC_ERR_EXTINCT (the
+ * observables up to the failing step are still filled), PAMC_ERR_INVALID,
+ * PAMC_ERR_NOMEM (the estimate of the array's use fell short) or
+ * PAMC_ERR_DEVICE. */
+int pamc_anneal_static(int L, const int8_t *couplings, int64_t R, const double *beta, int n_temps, int sweeps,
+                       uint64_t seed, void *stream, pamc_step_obs *obs, pamc_state *final_state);
+
 const char *pamc_status_string(int status);
 const char *pamc_last_error(void);
 

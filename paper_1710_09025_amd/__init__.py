@@ -31,7 +31,7 @@ import numpy as np
 from . import _capi
 
 __all__ = ["Pamc", "PamcBatch", "PamcServer", "PamcError", "OBS_FIELDS", "default_capacity", "make_pm_j", "rho_f",
-           "free_energy_variance", "autotune", "calibrate"]
+           "free_energy_variance", "autotune", "calibrate", "anneal_static"]
 
 OBS_FIELDS = ("beta", "R", "sum_E", "sum_E2", "E_min", "E_max", "mean_E", "e", "C_V", "lnQ", "lnZ",
               "betaF", "f", "S_f", "rho_s", "q_abs", "q2", "q4", "g_SG", "measured")
@@ -187,6 +187,34 @@ def make_pm_j(L: int, disorder_seed: int) -> np.ndarray:
     _check(_capi.load().pamc_make_pm_j(int(L), ctypes.c_uint64(int(disorder_seed) & (2**64 - 1)), _ptr(out)),
            "pamc_make_pm_j")
     return out.reshape(3, int(L) ** 3)
+
+
+def anneal_static(L, couplings, R, beta, sweeps, seed, stream=None, state=True):
+    """One whole anneal without device allocation (``pamc_anneal_static``):
+    returns (status, observables dict, final state dict or None)."""
+    J = np.ascontiguousarray(couplings, dtype=np.int8).reshape(3, int(L) ** 3)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    nT = len(b)
+    arr = (_capi.StepObs * nT)()
+    st_ptr = None
+    bufs = None
+    if state:
+        cap = default_capacity(int(R))
+        N = int(L) ** 3
+        bufs = (np.zeros((cap, N), dtype=np.int8), np.zeros(cap, dtype=np.int32), np.zeros(cap, dtype=np.uint32))
+        st_ptr = _capi.State(0, 0, 0.0, _ptr(bufs[0]).value, _ptr(bufs[1]).value, _ptr(bufs[2]).value, None)
+    status = _capi.load().pamc_anneal_static(int(L), _ptr(J), int(R), _ptr(b), nT, int(sweeps),
+                                             ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                             ctypes.c_void_p(stream or 0), arr,
+                                             ctypes.byref(st_ptr) if st_ptr is not None else None)
+    if status not in (_capi.OK, _capi.ERR_CAPACITY, _capi.ERR_EXTINCT):
+        raise PamcError(status, "pamc_anneal_static")
+    out_state = None
+    if st_ptr is not None:
+        n = st_ptr.R
+        out_state = {"step": st_ptr.step, "R": n, "lnZ": st_ptr.lnZ, "spins": bufs[0][:n], "E": bufs[1][:n],
+                     "family": bufs[2][:n]}
+    return status, _obs_to_dict(arr), out_state
 
 
 def calibrate(device: int = -1):

@@ -147,6 +147,8 @@ SIGNATURES = {
     "pamc_calibrate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pamc_rho_f": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P, P, P]),
     "pamc_destroy": (None, [P]),
+    "pamc_anneal_static": (ctypes.c_int, [ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_uint64, P, ctypes.POINTER(StepObs), ctypes.POINTER(State)]),
     "pamc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pamc_last_error": (ctypes.c_char_p, []),
     "pamc_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Instance), ctypes.POINTER(Options),

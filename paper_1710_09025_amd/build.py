@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpamc.so")
-SOURCES = ["sweep.hip", "gather.hip", "resample.hip", "icm.hip", "calib.hip", "runner.cpp", "pamc_api.cpp",
-           "server.cpp", "tune.cpp", "instances.cpp"]
+SOURCES = ["sweep.hip", "gather.hip", "resample.hip", "icm.hip", "calib.hip", "static_run.hip", "runner.cpp",
+           "pamc_api.cpp", "server.cpp", "tune.cpp", "instances.cpp"]
 ARCH = os.environ.get("PAMC_OFFLOAD_ARCH", "gfx950")
 ROCM_INC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "include")
 

@@ -227,7 +227,7 @@ int Runner::dev_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return dev_fail(e_, what);     \
     } while (0)
 
-int Runner::setup(const pamc_options &opt, int max_slots)
+int Runner::setup(const pamc_options &opt, int max_slots, bool external_stream)
 {
     alloc_.alloc = opt.alloc;
     alloc_.free = opt.free;
@@ -240,7 +240,7 @@ int Runner::setup(const pamc_options &opt, int max_slots)
     HIPCHK(hipGetDevice(&device_), "hipGetDevice");
     HIPCHK(sweep_kernels_init(), "hipFuncSetAttribute (sweep LDS)");
     HIPCHK(icm_kernels_init(), "hipFuncSetAttribute (cluster-move LDS)");
-    if (opt.stream) {
+    if (opt.stream || external_stream) {
         stream_ = (hipStream_t)opt.stream;
     } else {
         HIPCHK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");

@@ -84,7 +84,9 @@ public:
     Runner() = default;
     ~Runner();
     // Stream, allocator and slot capacity of the device instance table.
-    int setup(const pamc_options &opt, int max_slots);
+    // external_stream: run on opt.stream even when it is NULL (the null
+    // stream) instead of creating a stream of the library's own.
+    int setup(const pamc_options &opt, int max_slots, bool external_stream = false);
     // Allocates an instance's device memory and tables; returns its slot
     // (>= 0) or a negative status.  The population is not initialised.
     int add_instance(HostInst &&h);

@@ -391,3 +391,22 @@ def test_rho_f_is_the_sample_variance_times_the_nominal_population(lib):
     out = np.zeros(3)
     assert lib.pamc_rho_f(one.ctypes.data_as(ctypes.c_void_p), 1, 3, out.ctypes.data_as(ctypes.c_void_p), None,
                           None, None) == _capi.ERR_INVALID
+
+
+def test_static_entry_refuses_oversize_runs_on_the_host(lib):
+    """pamc_anneal_static takes every device buffer from a fixed array; a run
+    that needs more is refused with PAMC_ERR_INVALID before any device work
+    (no GPU needed for the refusal)."""
+    from paper_1710_09025_amd import _capi
+
+    L, R = 16, 100000
+    J = np.ones((3, L ** 3), dtype=np.int8)
+    beta = np.linspace(0.0, 1.0, 11)
+    obs = (_capi.StepObs * 11)()
+    st = lib.pamc_anneal_static(L, J.ctypes.data_as(ctypes.c_void_p), R, beta.ctypes.data_as(ctypes.c_void_p), 11,
+                                2, 1, None, obs, None)
+    assert st == _capi.ERR_INVALID
+    assert b"allocation-free" in lib.pamc_last_error()
+    # invalid arguments are refused the same way
+    assert lib.pamc_anneal_static(L, None, R, beta.ctypes.data_as(ctypes.c_void_p), 11, 2, 1, None, obs,
+                                  None) == _capi.ERR_INVALID
