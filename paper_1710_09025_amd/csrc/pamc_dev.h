@@ -25,10 +25,14 @@ constexpr uint32_t kTagIcm = 0x40000000u;
 enum Layout : int32_t {
     // byte per site (0: S = -1, 1: S = +1), lexicographic s = x + L(y + Lz)
     kLayoutLex = 0,
-    // byte per site; each row (y, z) holds its even-x sites then its odd-x
-    // sites: pos = (zL + y)L + (x & 1)(L/2) + (x >> 1).  Used for L % 8 == 0
-    // so that four sites of one colour sharing a Philox block are one
-    // aligned 32-bit word, and so are their y, z and one x neighbour.
+    // byte per site, the sites of colour 0 then those of colour 1, each in
+    // lexicographic order: pos = c N/2 + (zL + y)(L/2) + (x >> 1) for the
+    // site of colour c = (x + y + z) & 1.  Used for L = 8 and 16 (L/2 a
+    // multiple of four): the four sites of one Philox block are one aligned
+    // 32-bit word inside one row (y, z), their y and z neighbours and one x
+    // neighbour are the word at the same place of the other colour's rows,
+    // and the other x neighbour is that word shifted by one byte.  Lanes
+    // sweeping consecutive blocks read consecutive words.
     kLayoutEO = 1,
     // byte per site, colour-major: the sites of colour 0 in lexicographic
     // order, then colour 1 (and 2 for odd L), each colour padded to a

@@ -464,7 +464,7 @@ int Runner::upload_inst(int i)
         if (h.layout == kLayoutLex)
             h.lex_pos[s] = s;
         else if (h.layout == kLayoutEO)
-            h.lex_pos[s] = yz * L + (x & 1) * (L / 2) + (x >> 1);
+            h.lex_pos[s] = col[s] * (N / 2) + yz * (L / 2) + (x >> 1);
         else
             h.lex_pos[s] = li.cbase[col[s]] + rank[s];
         pos16[s] = (uint16_t)h.lex_pos[s];

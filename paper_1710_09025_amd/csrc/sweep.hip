@@ -383,15 +383,18 @@ __device__ void sweep_tile_lex(const Inst &I, int k, uint8_t *lds, int r0, int n
 }
 
 // ---------------------------------------------------------------------------
-// SWAR sweep for L in {8, 16}.  Storage layout kLayoutEO: row (y, z) holds
-// its L/2 even-x sites then its L/2 odd-x sites.  The sites of colour c in
-// row (y, z) are the half p = (c + y + z) & 1, so Philox block g = (row,
-// jb) of colour c is the aligned 32-bit word at row*L + p*L/2 + 4 jb, one
-// byte per site.  Its neighbours: the same word position in rows y +- 1 and
-// z +- 1, the word at the same position of the other half (one x
-// neighbour), and that word shifted by one byte (the other x neighbour),
-// built with a byte-align of two words.  Per byte the six terms
-// s ^ nb ^ [J = -1] are summed without carries (<= 6 per byte).
+// SWAR sweep for L in {8, 16}.  Storage layout kLayoutEO: the sites of
+// colour c fill positions c N/2 ... with row (y, z) holding its L/2 sites of
+// colour c, x >> 1 ascending, at c N/2 + (zL + y) L/2.  Philox block
+// g = (row, jb) of colour c is the aligned 32-bit word at c N/2 + row L/2 +
+// 4 jb, one byte per site; the sites of colour c in row (y, z) have x of
+// parity p = (c + y + z) & 1.  Their neighbours are sites of the other
+// colour: the word at the same place of rows y +- 1 and z +- 1, the word at
+// the same place of the same row (one x neighbour), and that word shifted
+// by one byte (the other x neighbour), built with a byte-align of two
+// words.  Per byte the six terms s ^ nb ^ [J = -1] are summed without
+// carries (<= 6 per byte).  Consecutive blocks are consecutive words, so
+// the lanes of a wave read consecutive LDS words (no bank conflicts).
 //
 // A thread owns GPT Philox blocks of each colour in RPT replicas at once;
 // the replicas of one thread lie a fixed distance apart in LDS, so their
@@ -443,19 +446,19 @@ __device__ __forceinline__ void eo_group_setup(EOGroup &gr, const uint32_t *jeo,
     const int row = g / S::GPR, jb = g - row * S::GPR;
     const int y = row % L, z = row / L;
     const int p = (c + y + z) & 1;
-    const int rb = row * L;
-    gr.own = rb + p * S::H + 4 * jb;
-    const uint32_t oth = rb + (1 - p) * S::H + 4 * jb;
+    const uint32_t base = (uint32_t)c * (S::N / 2), obase = (uint32_t)(1 - c) * (S::N / 2);
+    gr.own = base + row * S::H + 4 * jb;
+    const uint32_t oth = obase + row * S::H + 4 * jb;
     // p = 1: the other x neighbour is one site to the right (next word),
     // p = 0: one site to the left (previous word), with periodic wrap.
-    const uint32_t adj = rb + (1 - p) * S::H + 4 * ((jb + (p ? 1 : S::GPR - 1)) % S::GPR);
+    const uint32_t adj = obase + row * S::H + 4 * ((jb + (p ? 1 : S::GPR - 1)) % S::GPR);
     gr.hi = p ? adj : oth;
     gr.lo = p ? oth : adj;
     gr.sh = p ? 1u : 3u;
-    gr.yp = ((z * L + (y + 1) % L) * L) + p * S::H + 4 * jb;
-    gr.ym = ((z * L + (y + L - 1) % L) * L) + p * S::H + 4 * jb;
-    gr.zp = ((((z + 1) % L) * L + y) * L) + p * S::H + 4 * jb;
-    gr.zm = ((((z + L - 1) % L) * L + y) * L) + p * S::H + 4 * jb;
+    gr.yp = obase + (z * L + (y + 1) % L) * S::H + 4 * jb;
+    gr.ym = obase + (z * L + (y + L - 1) % L) * S::H + 4 * jb;
+    gr.zp = obase + (((z + 1) % L) * L + y) * S::H + 4 * jb;
+    gr.zm = obase + (((z + L - 1) % L) * L + y) * S::H + 4 * jb;
     gr.ctr = ((uint32_t)c << 24) | (uint32_t)g;
     const uint32_t *jw = jeo + ((size_t)c * S::G + g) * 6;
 #pragma unroll
@@ -553,8 +556,15 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
 template <int L>
 __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows, int phase);
 
+// At most 128 VGPRs, so that four waves share each SIMD (the L = 16 kernel
+// would take 145 and run three): the draws' long multiply chains and the LDS
+// round trips of a colour phase hide behind the other waves.  L = 16 went
+// from 1929 to 2110 attempts/ns at R = 5e5 (tile of 8 rows, four
+// workgroups per compute unit); L = 8 needs 121 VGPRs either way.
 template <int L>
-__global__ __launch_bounds__(256) void k_sweep_eo(const Inst *insts, const Work *work, int tile_rows, int phase)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_eo(const Inst *insts,
+                                                                                            const Work *work,
+                                                                                            int tile_rows, int phase)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const Work w = work[blockIdx.x];
