@@ -28,7 +28,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# PAMC_ORACLE_LIB points the binding at another build of the same sources
+# (the sanitizer and mutation tests use it); default: the in-tree build
+LIB_PATH = os.environ.get("PAMC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 SOURCES = ["pamc_oracle.c", "enumerate.c"]
 
 OK = 0

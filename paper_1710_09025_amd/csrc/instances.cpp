@@ -8,10 +8,15 @@
 // over independent runs of one instance.
 #include <cmath>
 #include <cstdint>
-#include <limits>
 #include <string>
 
-#include "runner.h"
+#include "../../include/pamc.h"
+
+// Host code only (no HIP), so that it also builds with a plain C++ compiler
+// (the sanitizer test does that).
+namespace pamc {
+void set_error(const std::string &msg);
+}
 
 namespace {
 
