@@ -203,10 +203,15 @@ size_t inst_device_bytes(int L, int64_t Rcap, int nT, int n_ovl, bool packed, bo
 Runner::~Runner()
 {
     if (stream_) (void)hipStreamSynchronize(stream_);
+    if (side_) (void)hipStreamSynchronize(side_);
+    (void)release_fenced(true);
     for (size_t i = 0; i < inst_.size(); ++i)
         if (used_[i]) alloc_.put(inst_[i].block);
     for (void *p : work_allocs_) alloc_.put(p);
     for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
+    for (hipEvent_t e : fence_pool_) (void)hipEventDestroy(e);
+    if (stage_) (void)hipHostFree(stage_);
+    if (side_) (void)hipStreamDestroy(side_);
     drop_graph();
     alloc_.put(d_insts_);
     alloc_.put(d_nlnn_);
@@ -248,6 +253,7 @@ int Runner::setup(const pamc_options &opt, int max_slots, bool external_stream)
     }
     inst_.resize((size_t)max_slots);
     used_.assign((size_t)max_slots, 0);
+    held_.assign((size_t)max_slots, 0);
     d_insts_ = (Inst *)alloc_.get(sizeof(Inst) * (size_t)max_slots);
     d_Jptr_ = (const int8_t **)alloc_.get(sizeof(void *) * (size_t)max_slots);
     if (!d_insts_ || !d_Jptr_) {
@@ -257,12 +263,107 @@ int Runner::setup(const pamc_options &opt, int max_slots, bool external_stream)
     return PAMC_OK;
 }
 
+int Runner::enable_async(size_t staging_bytes)
+{
+    if (async_) return PAMC_OK;
+    HIPCHK(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking), "hipStreamCreate (uploads)");
+    HIPCHK(hipHostMalloc((void **)&stage_, staging_bytes, hipHostMallocDefault), "hipHostMalloc (staging)");
+    stage_cap_ = staging_bytes;
+    stage_used_ = 0;
+    async_ = true;
+    return PAMC_OK;
+}
+
+int Runner::h2d(void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return PAMC_OK;
+    if (!async_) {
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream_), "upload");
+        return PAMC_OK;
+    }
+    const uint8_t *s = static_cast<const uint8_t *>(src);
+    uint8_t *d = static_cast<uint8_t *>(dst);
+    while (bytes > 0) {
+        // the staging is reused once the copies issued from it have landed
+        if (stage_used_ == stage_cap_) {
+            HIPCHK(hipStreamSynchronize(side_), "staging sync");
+            stage_used_ = 0;
+        }
+        const size_t n = std::min(bytes, stage_cap_ - stage_used_);
+        std::memcpy(stage_ + stage_used_, s, n);
+        HIPCHK(hipMemcpyAsync(d, stage_ + stage_used_, n, hipMemcpyHostToDevice, side_), "staged upload");
+        stage_used_ = std::min(stage_cap_, stage_used_ + ((n + 63) & ~size_t(63)));
+        s += n;
+        d += n;
+        bytes -= n;
+    }
+    return PAMC_OK;
+}
+
+int Runner::upload_sync()
+{
+    HIPCHK(hipStreamSynchronize(up_stream()), "upload sync");
+    stage_used_ = 0;
+    return PAMC_OK;
+}
+
+int Runner::d2h(void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return PAMC_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, up_stream()), "read back");
+    HIPCHK(hipStreamSynchronize(up_stream()), "read back sync");
+    return PAMC_OK;
+}
+
+int Runner::fence(std::vector<void *> ptrs, std::vector<int> slots)
+{
+    hipEvent_t e = nullptr;
+    if (!fence_pool_.empty()) {
+        e = fence_pool_.back();
+        fence_pool_.pop_back();
+    } else {
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate (fence)");
+    }
+    HIPCHK(hipEventRecord(e, stream_), "hipEventRecord (fence)");
+    for (int i : slots) held_[(size_t)i] = 1;
+    fenced_.push_back(Fenced{e, std::move(ptrs), std::move(slots)});
+    return PAMC_OK;
+}
+
+int Runner::release_fenced(bool wait)
+{
+    for (size_t j = 0; j < fenced_.size();) {
+        Fenced &f = fenced_[j];
+        hipError_t q = wait ? hipEventSynchronize(f.ev) : hipEventQuery(f.ev);
+        if (q == hipErrorNotReady) {
+            ++j;
+            continue;
+        }
+        if (q != hipSuccess) return dev_fail(q, "fence");
+        for (void *p : f.ptrs) alloc_.put(p);
+        for (int i : f.slots) held_[(size_t)i] = 0;
+        fence_pool_.push_back(f.ev);
+        fenced_.erase(fenced_.begin() + (long)j);
+    }
+    return PAMC_OK;
+}
+
+int Runner::free_slots() const
+{
+    int n = 0;
+    for (int i = 0; i < max_slots_; ++i)
+        if (!used_[i] && !held_[i]) ++n;
+    return n;
+}
+
 // n ln n for n = 0 .. len-1 (host libm), shared by all instances; grows when
 // an instance with a larger capacity arrives.
 int Runner::ensure_nlnn(int64_t len)
 {
     if (len <= nlnn_len_) return PAMC_OK;
+    // every queued step reads the table that is replaced
     HIPCHK(hipStreamSynchronize(stream_), "nlnn sync");
+    if (side_) HIPCHK(hipStreamSynchronize(side_), "nlnn sync");
     const int64_t n = std::max(len, 2 * nlnn_len_);
     std::vector<double> nl((size_t)n);
     nl[0] = 0.0;
@@ -288,7 +389,7 @@ int Runner::add_instance(HostInst &&h)
 {
     int slot = -1;
     for (int i = 0; i < max_slots_; ++i)
-        if (!used_[i]) {
+        if (!used_[i] && !held_[i]) {
             slot = i;
             break;
         }
@@ -307,16 +408,23 @@ int Runner::add_instance(HostInst &&h)
     }
     used_[slot] = 1;
     const int8_t *jp = inst_[slot].Jdev;
-    HIPCHK(hipMemcpy(d_insts_ + slot, &inst_[slot].dev, sizeof(Inst), hipMemcpyHostToDevice), "upload instance");
-    HIPCHK(hipMemcpy(d_Jptr_ + slot, &jp, sizeof(void *), hipMemcpyHostToDevice), "upload J pointer");
+    st = h2d(d_insts_ + slot, &inst_[slot].dev, sizeof(Inst));
+    if (st == PAMC_OK) st = h2d(d_Jptr_ + slot, &jp, sizeof(void *));
+    if (st == PAMC_OK) st = upload_sync();
+    if (st != PAMC_OK) return st;
     return slot;
 }
 
 void Runner::remove_instance(int slot)
 {
     if (slot < 0 || slot >= max_slots_ || !used_[slot]) return;
-    (void)hipStreamSynchronize(stream_);
-    alloc_.put(inst_[slot].block);
+    if (async_) {
+        // queued steps may still read the instance: release it behind them
+        (void)fence({inst_[slot].block}, {slot});
+    } else {
+        (void)hipStreamSynchronize(stream_);
+        alloc_.put(inst_[slot].block);
+    }
     inst_[slot] = HostInst();
     used_[slot] = 0;
 }
@@ -333,7 +441,7 @@ int Runner::upload_inst(int i)
         return PAMC_ERR_NOMEM;
     }
     uint8_t *b = (uint8_t *)h.block;
-    HIPCHK(hipMemsetAsync(b, 0, lay.total, stream_), "clear instance memory");
+    HIPCHK(hipMemsetAsync(b, 0, lay.total, up_stream()), "clear instance memory");
     Inst &d = h.dev;
     std::memset(&d, 0, sizeof(d));
     d.L = L;
@@ -582,41 +690,34 @@ int Runner::upload_inst(int i)
     std::vector<uint32_t> Rk0((size_t)h.nT + 1, 0u);
     Rk0[0] = (uint32_t)h.R;
     int32_t ctl[4] = {0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(b + lay.ctl, ctl, 16, hipMemcpyHostToDevice, stream_), "upload ctl");
-    HIPCHK(hipMemcpyAsync(b + lay.thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, stream_), "upload thr");
-    HIPCHK(hipMemcpyAsync(b + lay.beta, h.beta.data(), h.beta.size() * 8, hipMemcpyHostToDevice, stream_),
-           "upload beta");
-    HIPCHK(hipMemcpyAsync(b + lay.rho, rho.data(), rho.size() * 8, hipMemcpyHostToDevice, stream_), "upload rho");
-    HIPCHK(hipMemcpyAsync(b + lay.Rt, h.pop.data(), h.pop.size() * 8, hipMemcpyHostToDevice, stream_),
-           "upload nominal populations");
-    HIPCHK(hipMemcpyAsync(b + lay.site, site.data(), site.size() * 4, hipMemcpyHostToDevice, stream_),
-           "upload site");
-    HIPCHK(hipMemcpyAsync(b + lay.grp, grp.data(), grp.size() * 2, hipMemcpyHostToDevice, stream_), "upload grp");
-    HIPCHK(hipMemcpyAsync(b + lay.jeo, jeo.data(), jeo.size() * 4, hipMemcpyHostToDevice, stream_), "upload jeo");
+    int st = PAMC_OK;
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (st == PAMC_OK) st = h2d(b + off, src, bytes);
+    };
+    put(lay.ctl, ctl, 16);
+    put(lay.thr, thr.data(), thr.size() * 4);
+    put(lay.beta, h.beta.data(), h.beta.size() * 8);
+    put(lay.rho, rho.data(), rho.size() * 8);
+    put(lay.Rt, h.pop.data(), h.pop.size() * 8);
+    put(lay.site, site.data(), site.size() * 4);
+    put(lay.grp, grp.data(), grp.size() * 2);
+    put(lay.jeo, jeo.data(), jeo.size() * 4);
     if (h.real)
-        HIPCHK(hipMemcpyAsync(b + lay.J, h.Jq.data(), h.Jq.size() * 4, hipMemcpyHostToDevice, stream_), "upload J");
+        put(lay.J, h.Jq.data(), h.Jq.size() * 4);
     else
-        HIPCHK(hipMemcpyAsync(b + lay.J, h.J.data(), h.J.size(), hipMemcpyHostToDevice, stream_), "upload J");
-    HIPCHK(hipMemcpyAsync(b + lay.bq, bq.data(), bq.size() * 4, hipMemcpyHostToDevice, stream_), "upload bq");
-    HIPCHK(hipMemcpyAsync(b + lay.emom, &em, sizeof(em), hipMemcpyHostToDevice, stream_), "upload moments");
-    if (!gpw.empty())
-        HIPCHK(hipMemcpyAsync(b + lay.gpw, gpw.data(), gpw.size() * 8, hipMemcpyHostToDevice, stream_),
-               "upload weight factors");
-    if (!cmj.empty())
-        HIPCHK(hipMemcpyAsync(b + lay.cmj, cmj.data(), cmj.size() * 4, hipMemcpyHostToDevice, stream_),
-               "upload couplings per neighbour word");
-    HIPCHK(hipMemcpyAsync(b + lay.pos, pos16.data(), pos16.size() * 2, hipMemcpyHostToDevice, stream_), "upload pos");
-    HIPCHK(hipMemcpyAsync(b + lay.lexof, lexof16.data(), lexof16.size() * 2, hipMemcpyHostToDevice, stream_),
-           "upload lexof");
-    if (!cmdesc.empty())
-        HIPCHK(hipMemcpyAsync(b + lay.cmdesc, cmdesc.data(), cmdesc.size() * 2, hipMemcpyHostToDevice, stream_),
-               "upload cm descriptors");
-    HIPCHK(hipMemcpyAsync(b + lay.Rk, Rk0.data(), Rk0.size() * 4, hipMemcpyHostToDevice, stream_), "upload Rk");
-    HIPCHK(hipMemcpyAsync(b + lay.ovl_slot, h.ovl_slot.data(), h.ovl_slot.size() * 4, hipMemcpyHostToDevice,
-                          stream_),
-           "upload ovl");
+        put(lay.J, h.J.data(), h.J.size());
+    put(lay.bq, bq.data(), bq.size() * 4);
+    put(lay.emom, &em, sizeof(em));
+    if (!gpw.empty()) put(lay.gpw, gpw.data(), gpw.size() * 8);
+    if (!cmj.empty()) put(lay.cmj, cmj.data(), cmj.size() * 4);
+    put(lay.pos, pos16.data(), pos16.size() * 2);
+    put(lay.lexof, lexof16.data(), lexof16.size() * 2);
+    if (!cmdesc.empty()) put(lay.cmdesc, cmdesc.data(), cmdesc.size() * 2);
+    put(lay.Rk, Rk0.data(), Rk0.size() * 4);
+    put(lay.ovl_slot, h.ovl_slot.data(), h.ovl_slot.size() * 4);
     // host vectors must outlive the async copies
-    HIPCHK(hipStreamSynchronize(stream_), "upload sync");
+    if (st == PAMC_OK) st = upload_sync();
+    if (st != PAMC_OK) return st;
     h.k_enq = 0;
     h.k_base = 0;
     h.lnZ_base = (double)N * std::log(2.0);
@@ -646,9 +747,17 @@ int Runner::set_shape(int i, int tile_rows, int rp)
 
 int Runner::build_work(const std::vector<int> &active)
 {
-    HIPCHK(hipStreamSynchronize(stream_), "build_work sync");
-    drop_graph();
-    for (void *p : work_allocs_) alloc_.put(p);
+    if (async_) {
+        // the lists being replaced serve the steps already queued
+        if (!work_allocs_.empty()) {
+            const int st = fence(std::move(work_allocs_), {});
+            if (st != PAMC_OK) return st;
+        }
+    } else {
+        HIPCHK(hipStreamSynchronize(stream_), "build_work sync");
+        drop_graph();
+        for (void *p : work_allocs_) alloc_.put(p);
+    }
     work_allocs_.clear();
     sweep_groups_.clear();
     active_ = active;
@@ -656,7 +765,7 @@ int Runner::build_work(const std::vector<int> &active)
         void *p = alloc_.get(bytes);
         if (!p) return nullptr;
         work_allocs_.push_back(p);
-        if (bytes && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        if (h2d(p, src, bytes) != PAMC_OK) return nullptr;
         return p;
     };
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<Work>> groups;
@@ -717,6 +826,8 @@ int Runner::build_work(const std::vector<int> &active)
         if (!d_wblk_) return dev_fail(hipErrorOutOfMemory, "upload weight work");
     }
     if (!d_rows_ || !d_post_ || !d_list_ || !d_gather_) return dev_fail(hipErrorOutOfMemory, "upload work lists");
+    const int ust = upload_sync();
+    if (ust != PAMC_OK) return ust;
     nrows_work_ = (int)rows.size();
     npost_ = (int)post.size();
     nlist_ = (int)list.size();
@@ -731,14 +842,16 @@ int Runner::init_instances(const std::vector<int> &slots)
     if (w.empty()) return PAMC_OK;
     Work *d = (Work *)alloc_.get(w.size() * sizeof(Work));
     if (!d) return PAMC_ERR_NOMEM;
-    HIPCHK(hipMemcpy(d, w.data(), w.size() * sizeof(Work), hipMemcpyHostToDevice), "upload init work");
+    int st = h2d(d, w.data(), w.size() * sizeof(Work));
+    if (st != PAMC_OK) return st;
     size_t lds = 0;
     for (int i : slots)
         if (inst_[i].packed) lds = std::max(lds, (size_t)std::max(16384, inst_[i].row_bytes));
-    launch_init(d_insts_, d, (int)w.size(), lds, stream_);
-    launch_energy(d_insts_, d, (int)w.size(), d_Jptr_, stream_);
+    launch_init(d_insts_, d, (int)w.size(), lds, up_stream());
+    launch_energy(d_insts_, d, (int)w.size(), d_Jptr_, up_stream());
     HIPCHK(hipGetLastError(), "init launch");
-    HIPCHK(hipStreamSynchronize(stream_), "init sync");
+    st = upload_sync();
+    if (st != PAMC_OK) return st;
     alloc_.put(d);
     return PAMC_OK;
 }
@@ -896,9 +1009,12 @@ int Runner::sync()
 int Runner::read_ctl(int i, int32_t ctl[3], uint32_t status[2])
 {
     const HostInst &h = inst_[i];
-    HIPCHK(hipMemcpyAsync(ctl, h.ctl, 12, hipMemcpyDeviceToHost, stream_), "read ctl");
-    HIPCHK(hipMemcpyAsync(status, h.dev.status, 8, hipMemcpyDeviceToHost, stream_), "read status");
-    HIPCHK(hipStreamSynchronize(stream_), "read ctl sync");
+    // in serving mode the instance's steps have completed: read on the
+    // upload path, without waiting for the steps queued behind them
+    const hipStream_t s = async_ ? side_ : stream_;
+    HIPCHK(hipMemcpyAsync(ctl, h.ctl, 12, hipMemcpyDeviceToHost, s), "read ctl");
+    HIPCHK(hipMemcpyAsync(status, h.dev.status, 8, hipMemcpyDeviceToHost, s), "read status");
+    HIPCHK(hipStreamSynchronize(s), "read ctl sync");
     return PAMC_OK;
 }
 
@@ -912,7 +1028,8 @@ int Runner::inst_status(int i, int *step, int64_t *Rk)
     uint32_t r = 0;
     const int k = ctl[0];
     // after the last step the population is that of step nT - 1
-    HIPCHK(hipMemcpy(&r, h.dev.Rk + std::min(k, h.nT - 1), 4, hipMemcpyDeviceToHost), "read Rk");
+    st = d2h(&r, h.dev.Rk + std::min(k, h.nT - 1), 4);
+    if (st != PAMC_OK) return st;
     if (step) *step = k;
     if (Rk) *Rk = r;
     if (status[0] & 1u) {
@@ -939,8 +1056,9 @@ int Runner::observables(int i, pamc_step_obs *out, int n)
     if (st != PAMC_OK) return st;
     std::vector<StepRec> rec((size_t)h.nT);
     std::vector<uint32_t> q((size_t)std::max(1, h.ovl_n) * (2 * h.N + 1));
-    HIPCHK(hipMemcpy(rec.data(), h.dev.rec, rec.size() * sizeof(StepRec), hipMemcpyDeviceToHost), "read rec");
-    HIPCHK(hipMemcpy(q.data(), h.dev.qhist, q.size() * 4, hipMemcpyDeviceToHost), "read qhist");
+    st = d2h(rec.data(), h.dev.rec, rec.size() * sizeof(StepRec));
+    if (st == PAMC_OK) st = d2h(q.data(), h.dev.qhist, q.size() * 4);
+    if (st != PAMC_OK) return st;
     // steps measured: those below the device step, plus the failing step
     int kdone = ctl[0];
     if (status[0]) kdone = (int)status[1] + 1;

@@ -122,7 +122,34 @@ public:
     int phase_times(double *sweep_ms, double *resample_ms, double *gather_ms, int64_t *n_steps);
     bool timing() const { return timing_; }
 
+    // Serving mode.  Instance uploads, initial populations, work-list
+    // uploads and result reads go through a second stream from pinned
+    // staging, so they never wait for the steps queued on the main stream;
+    // an instance removed or a work list replaced while queued steps may
+    // still read it is released only when an event recorded behind those
+    // steps has completed (its slot is not reused before).  Reads of an
+    // instance's results assume its last step has completed.
+    int enable_async(size_t staging_bytes);
+    bool async() const { return async_; }
+    // Releases what retired fences hold once their events have completed
+    // (wait: waits for all of them first).
+    int release_fenced(bool wait);
+    // Slots free for add_instance (not in use, not held by a fence).
+    int free_slots() const;
+    // Sizes the shared n ln n table for populations up to len - 1 rows.
+    int reserve_nlnn(int64_t len) { return ensure_nlnn(len); }
+
 private:
+    // Host-to-device copy through the upload path (the main stream, or in
+    // serving mode the second stream from pinned staging); upload_sync
+    // waits for the path's copies and kernels.
+    int h2d(void *dst, const void *src, size_t bytes);
+    int upload_sync();
+    // Device-to-host copy of data no queued work still writes, waited for.
+    int d2h(void *dst, const void *src, size_t bytes);
+    hipStream_t up_stream() const { return async_ ? side_ : stream_; }
+    // Holds ptrs and slots until the steps enqueued so far have run.
+    int fence(std::vector<void *> ptrs, std::vector<int> slots);
     int upload_inst(int i);
     int ensure_nlnn(int64_t len);
     int read_ctl(int i, int32_t ctl[3], uint32_t status[2]);
@@ -184,6 +211,19 @@ private:
     bool timing_ = false;
     std::vector<hipEvent_t> ev_pool_;
     size_t ev_used_ = 0;
+    // serving mode
+    bool async_ = false;
+    hipStream_t side_ = nullptr;
+    uint8_t *stage_ = nullptr;       // pinned host staging
+    size_t stage_cap_ = 0, stage_used_ = 0;
+    struct Fenced {
+        hipEvent_t ev;
+        std::vector<void *> ptrs;
+        std::vector<int> slots;
+    };
+    std::vector<Fenced> fenced_;
+    std::vector<hipEvent_t> fence_pool_;
+    std::vector<char> held_;         // slot retired, its fence pending
 };
 
 void set_error(const std::string &msg);
