@@ -157,6 +157,29 @@ def time_anneals(name, steps, warmup, autotune=True, packed=False, real=False, i
                 R_steps=np.array(obs["R"], dtype=np.float64))
 
 
+def size_run(L, R, n_temps, tile_rows=0, group_replicas=0):
+    """One timed anneal of a +-J instance of side L (R replicas, n_temps
+    temperatures linear in beta up to 5, N_S = 10): the sweep rate of the
+    kernel that size selects, for profiling one lattice size at a time.
+    Without a tile the shape comes from the autotuner (whose trial launches
+    then precede the anneal)."""
+    from paper_1710_09025_amd import Pamc
+
+    J = pi.pm_j_couplings(L, 7)
+    beta = pi.linear_beta(5.0, n_temps)
+    p = Pamc(L, J, R, beta, 10, 11, timing=True, autotune=tile_rows == 0, tile_rows=tile_rows,
+             group_replicas=group_replicas)
+    shape = p.sweep_shape()
+    assert p.anneal() == 0
+    sweep_ms, other_ms, _, nsteps = p.phase_times()
+    obs = p.observables()
+    p.close()
+    att = attempts_of(obs, L ** 3, 10)
+    return {"L": L, "R": R, "n_temps": n_temps, "shape": list(shape), "sweep_ms": round(sweep_ms, 3),
+            "other_ms": round(other_ms, 3), "sweep_attempts_per_ns": round(att / (sweep_ms * 1e6), 1),
+            "sum_E_last": int(obs["sum_E"][-1])}
+
+
 def footprint_gb(name, packed):
     import ctypes
 
@@ -640,6 +663,10 @@ def main():
                     help="main line with this sweep tile instead of the autotuned one (profiling)")
     ap.add_argument("--group-replicas", type=int, default=0,
                     help="main line with this colour-major replica group (with --tile-rows)")
+    ap.add_argument("--size", type=int, default=0, metavar="L",
+                    help="only anneal one +-J instance of side L (--size-replicas replicas, 201 temperatures) "
+                         "and print its sweep rate (with --tile-rows / --group-replicas: that shape)")
+    ap.add_argument("--size-replicas", type=int, default=200_000)
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -656,6 +683,11 @@ def main():
 
     if args.calibrate:
         print(json.dumps(calibration()), flush=True)
+        return
+
+    if args.size:
+        print(json.dumps(size_run(args.size, args.size_replicas, 201, args.tile_rows, args.group_replicas)),
+              flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

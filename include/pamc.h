@@ -98,10 +98,12 @@ typedef struct pamc_options {
     int group_replicas;      /* L other than 8 and 16 (colour-major sweep):
                                 replicas one sweep workgroup holds at once,
                                 a multiple of four (they are swept in
-                                fours); 0 = the library's choice.  Its
-                                threads (threads per replica quad x
-                                group_replicas / 4) must be whole 64-lane
-                                waves, at most 1024                         */
+                                fours); 0 = the library's choice.  A quad
+                                takes one thread per Philox block of the
+                                largest colour (a power of two up to 64);
+                                the workgroup, rounded up to whole 64-lane
+                                waves, has at most 1024 threads, and quads
+                                of at most 64 threads must fill its waves  */
     int autotune;            /* 1: when tile_rows and group_replicas are 0,
                                 pick them by timing the candidate shapes on
                                 a throw-away run first (see pamc_autotune);

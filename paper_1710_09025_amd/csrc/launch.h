@@ -35,6 +35,28 @@ hipError_t sweep_kernels_init();
 // of any planes never collide.
 inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : (row_bytes + 255) & ~255; }
 
+// Threads of a colour-major sweep workgroup of rp quads of tpr threads:
+// whole waves; quads above 64 threads leave the last wave's spare lanes
+// idle (tpr * rp is a multiple of 64 below).
+inline int cm_launch_threads(int tpr, int rp) { return (tpr * rp + 63) / 64 * 64; }
+
+// LDS stride of one replica-quad slot of `planes` byte planes.  Below 64
+// threads per quad one wave sweeps 64 / tpr quads side by side; unpadded,
+// their slots (a multiple of 64 words for rows longer than 64 bytes, 128
+// words at L = 4) would start in the same LDS bank and every plane read would
+// conflict 64 / tpr ways.  The slot is padded so that its length in words is
+// congruent to max(tpr, 4) modulo the 64 banks: quad q then starts q tpr
+// banks on, and lane q tpr + g reading word g of a plane hits bank (lane +
+// const) mod 64.  Quads of 64 or more threads fill whole waves and take no
+// padding.  The result is a multiple of 16 bytes (slots hold 16-byte rows).
+inline int cm_slot_bytes(int row_bytes, int tpr, int planes)
+{
+    const int base = planes * cm_plane_bytes(row_bytes);
+    if (tpr >= 64) return base;
+    const int want = 4 * (tpr < 4 ? 4 : tpr);  // bytes, modulo 256
+    return base + (((want - base) % 256) + 256) % 256;
+}
+
 // LDS of one cluster-move pair (the island search of one lane group): the
 // sector flags of every lexicographic site (a byte: bit 0 where the replicas
 // differ, bit 1 where they agree), the visited bits, the

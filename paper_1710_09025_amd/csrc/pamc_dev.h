@@ -122,6 +122,7 @@ struct Inst {
     int32_t cbase[3];   // CM layout: first byte of each colour
     int32_t tpr;        // CM layout: threads per replica
     int32_t plane_bytes;// CM layout: LDS stride of a replica quad's byte planes (>= row_bytes)
+    int32_t slot_bytes; // CM layout: LDS stride of the replica quads' slots (bank-skewed)
     int32_t ncs[3];     // sites per colour
     int32_t gcs[3];     // Philox blocks per colour, ceil(ncs / 4)
     int32_t gmax;

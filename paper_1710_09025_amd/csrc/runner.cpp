@@ -83,15 +83,18 @@ LayoutInfo layout_for(int L, bool real, int dim)
         cb += (li.ncs[c] + 3) & ~3;
     }
     const int rb = (cb + 15) & ~15;
+    // threads per replica quad: one per Philox block of the largest colour;
+    // up to 64 blocks rounded up to a power of two, so that whole quads fit
+    // in a wave and sync with wave barriers
     int tpr = 1;
     if (li.gmax <= 64) {
         while (tpr < li.gmax) tpr <<= 1;
     } else {
-        tpr = (li.gmax + 63) / 64 * 64;
+        tpr = li.gmax;
     }
     if (real) {
         if (tpr <= 1024 && 2 * rb <= 65535 &&
-            4 * (size_t)cm_plane_bytes(rb) * cm_replicas_per_block(tpr) + 32 + 8 * 64 <= kMaxSweepLds) {
+            (size_t)cm_slot_bytes(rb, tpr, 4) * cm_replicas_per_block(tpr) + 32 + 8 * 64 <= kMaxSweepLds) {
             li.layout = kLayoutCM;
             li.variant = dim == 2 ? (li.ncol == 2 ? kSweepSQ2 : kSweepSQ3) : (li.ncol == 2 ? kSweepCQ2 : kSweepCQ3);
             li.row_bytes = rb;
@@ -103,7 +106,7 @@ LayoutInfo layout_for(int L, bool real, int dim)
         return li;
     }
     if (tpr <= 1024 && 2 * rb <= 65535 &&
-        8 * (size_t)cm_plane_bytes(rb) * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= kMaxSweepLds) {
+        (size_t)cm_slot_bytes(rb, tpr, 8) * cm_replicas_per_block(tpr) + 32 + 4 * 64 <= kMaxSweepLds) {
         li.layout = kLayoutCM;
         li.variant = li.ncol == 2 ? kSweepCM2 : kSweepCM3;
         li.row_bytes = rb;
@@ -564,6 +567,7 @@ int Runner::upload_inst(int i)
     for (int c = 0; c < 3; ++c) d.cbase[c] = li.cbase[c];
     d.tpr = li.tpr;
     d.plane_bytes = cm_plane_bytes(h.row_bytes);
+    d.slot_bytes = cm_slot_bytes(h.row_bytes, li.tpr, h.real ? 4 : 8);
     // storage position of each site
     h.lex_pos.resize(N);
     std::vector<uint16_t> pos16((size_t)N);

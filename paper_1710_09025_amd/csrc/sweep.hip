@@ -496,6 +496,29 @@ __device__ __forceinline__ uint32_t eo_flip(uint32_t n, uint4 u, const uint8_t *
     return flip;
 }
 
+// eo_flip in two halves: the thresholds of the four bytes of n (and the
+// mask of the bytes that always flip, returned) before the draw, the
+// comparisons with it after.
+__device__ __forceinline__ uint32_t eo_thresholds(uint32_t n, const uint8_t *tab, uint32_t (&th)[4])
+{
+    const uint32_t n4 = n << 2;
+    th[0] = *reinterpret_cast<const uint32_t *>(tab + (n4 & 0x1Cu));
+    th[1] = *reinterpret_cast<const uint32_t *>(tab + __builtin_amdgcn_ubfe(n4, 8, 5));
+    th[2] = *reinterpret_cast<const uint32_t *>(tab + __builtin_amdgcn_ubfe(n4, 16, 5));
+    th[3] = *reinterpret_cast<const uint32_t *>(tab + __builtin_amdgcn_ubfe(n4, 24, 5));
+    return ((n + 0x05050505u) >> 3) & 0x01010101u;
+}
+
+__device__ __forceinline__ uint32_t eo_accept(uint32_t always, const uint32_t (&th)[4], uint4 u)
+{
+    uint32_t flip = always;
+    flip |= u.x < th[0] ? 0x00000001u : 0u;
+    flip |= u.y < th[1] ? 0x00000100u : 0u;
+    flip |= u.z < th[2] ? 0x00010000u : 0u;
+    flip |= u.w < th[3] ? 0x01000000u : 0u;
+    return flip;
+}
+
 // All N_S sweeps of the replicas of the tile.  ALL: beta = 0, every move is
 // accepted.  The replica groups of the last pass may run past the tile's
 // rows into unused LDS rows (the tile holds a multiple of RP rows); their
@@ -701,12 +724,12 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
     const int RPG = (int)blockDim.x / tpr;
     const int ps = I.plane_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * 8 * ps;
+    uint8_t *slot = lds + qsub * I.slot_bytes;
     const int nvec = I.row_bytes >> 4, pvec = ps >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
     for (int qb = 0; qb < nrows; qb += 4 * RPG) {
         const int q0 = qb + 4 * qsub;
-        const bool act = q0 < nrows;
+        const bool act = qsub < RPG && q0 < nrows;  // the last wave's spare lanes idle
         const uint32_t r0q = (uint32_t)(r0 + q0);
         if (act) {
             const uint8_t *src[4];
@@ -749,7 +772,33 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                         own[i] = lds_word(lds, b.own + i * ps);
                         flip[i] = ((b.vbits >> i) & 1u) * 0x01010101u;
                     }
-                    if constexpr (!ALL) {
+                    if constexpr (!ALL && NCOL == 2) {
+                        // the neighbour sums and the threshold reads go out
+                        // before the draws, whose arithmetic then covers
+                        // their LDS latency; the scheduling barrier keeps the
+                        // compiler from moving the draws back in front
+                        uint32_t fa[4], th[4][4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const uint32_t m = (lds_word(lds, b.nb[i]) + lds_word(lds, b.nb[4 + i]) +
+                                                lds_word(lds, b.nb[8 + i])) +
+                                               (lds_word(lds, b.nb[12 + i]) + lds_word(lds, b.nb[16 + i]) +
+                                                lds_word(lds, b.nb[20 + i]));
+                            fa[i] = eo_thresholds(unsat_from_sum(m, own[i]), tab, th[i]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        uint4 u[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            u[j] = philox10(make_uint4(b.ctr, r0q + j, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            flip[i] &= eo_accept(fa[i], th[i], make_uint4(word_of(u[0], i), word_of(u[1], i),
+                                                                          word_of(u[2], i), word_of(u[3], i)));
+                    } else if constexpr (!ALL) {
+                        // three colours hold more neighbour addresses: the
+                        // draws first keeps the sums' registers short-lived
                         uint4 u[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
@@ -827,7 +876,7 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
     const int row_bytes = I.row_bytes;
-    const int slot_bytes = 8 * I.plane_bytes;
+    const int slot_bytes = I.slot_bytes;
     int *unsat = reinterpret_cast<int *>(lds + RPG * slot_bytes + 32);
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
@@ -957,12 +1006,12 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
     const int RPG = (int)blockDim.x / tpr;
     const int ps = I.plane_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    uint8_t *slot = lds + qsub * 4 * ps;
+    uint8_t *slot = lds + qsub * I.slot_bytes;
     const int nvec = I.row_bytes >> 4, pvec = ps >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
     for (int qb = 0; qb < nrows; qb += 4 * RPG) {
         const int q0 = qb + 4 * qsub;
-        const bool act = q0 < nrows;
+        const bool act = qsub < RPG && q0 < nrows;  // the last wave's spare lanes idle
         const uint32_t r0q = (uint32_t)(r0 + q0);
         if (act) {
             const uint8_t *src[4];
@@ -1131,10 +1180,10 @@ __device__ __forceinline__ void sweep_tile_cq(const Inst &I, int k, uint8_t *lds
     const int tpr = I.tpr;
     const int RPG = (int)blockDim.x / tpr;
     const int ps = I.plane_bytes;
-    unsigned long long *eacc = reinterpret_cast<unsigned long long *>(lds + RPG * 4 * ps + 32);
+    unsigned long long *eacc = reinterpret_cast<unsigned long long *>(lds + RPG * I.slot_bytes + 32);
     const TileIO io = tile_io(I);
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
-    const uint32_t slot = (uint32_t)(qsub * 4 * ps);
+    const uint32_t slot = (uint32_t)(qsub * I.slot_bytes);
     CQBlock<NB> blk[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) {
@@ -1245,9 +1294,26 @@ void launch_energy(const Inst *insts, const Work *work, int nwork, const int8_t 
     if (nwork) k_energy<<<nwork, 256, 0, st>>>(insts, work, Jraw);
 }
 
-// Default workgroup shape of the colour-major sweep: tpr threads per
-// replica quad and max(1, 256 / tpr) quads swept at once.
-int cm_replicas_per_block(int tpr) { return tpr >= 256 ? 1 : 256 / tpr; }
+// Default workgroup shape of the colour-major sweep: 256 / tpr quads for
+// quads of at most 64 threads; above, the number of quads (of at most 512
+// threads together) that leaves the fewest idle lanes in the last wave, the
+// one nearest 256 threads among equals.
+int cm_replicas_per_block(int tpr)
+{
+    if (tpr <= 64) return 256 / tpr;
+    int best = 1;
+    double best_use = 0.0;
+    for (int rp = 1; rp * tpr <= 512 || rp == 1; ++rp) {
+        const int nt = rp * tpr;
+        const double use = (double)nt / (double)cm_launch_threads(tpr, rp);
+        const bool nearer = std::abs(nt - 256) < std::abs(best * tpr - 256);
+        if (use > best_use + 1e-9 || (use > best_use - 1e-9 && nearer)) {
+            best = rp;
+            best_use = use;
+        }
+    }
+    return best;
+}
 
 void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, int tile_rows, int row_bytes, int tpr,
                   int rp, int phase, hipStream_t st)
@@ -1255,8 +1321,8 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     if (!nwork) return;
     if (variant == kSweepCM2 || variant == kSweepCM3) {
         // rp replica quads, each four planes of the row and of the complement
-        const size_t lds = 8 * (size_t)cm_plane_bytes(row_bytes) * rp + 32 + 4 * (size_t)tile_rows;
-        const int nt = tpr * rp;
+        const size_t lds = (size_t)cm_slot_bytes(row_bytes, tpr, 8) * rp + 32 + 4 * (size_t)tile_rows;
+        const int nt = cm_launch_threads(tpr, rp);
         if (variant == kSweepCM2) {
             if (nt <= 512)
                 k_sweep_cm<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
@@ -1272,8 +1338,8 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     }
     if (variant == kSweepSQ2 || variant == kSweepSQ3) {
         // as below, on the square lattice
-        const size_t lds = 4 * (size_t)cm_plane_bytes(row_bytes) * rp + 32 + 8 * (size_t)tile_rows;
-        const int nt = tpr * rp;
+        const size_t lds = (size_t)cm_slot_bytes(row_bytes, tpr, 4) * rp + 32 + 8 * (size_t)tile_rows;
+        const int nt = cm_launch_threads(tpr, rp);
         if (variant == kSweepSQ2) {
             if (nt <= 512)
                 k_sweep_sq<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
@@ -1289,8 +1355,8 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
     }
     if (variant == kSweepCQ2 || variant == kSweepCQ3) {
         // rp replica quads of four planes, and a 64-bit energy per tile row
-        const size_t lds = 4 * (size_t)cm_plane_bytes(row_bytes) * rp + 32 + 8 * (size_t)tile_rows;
-        const int nt = tpr * rp;
+        const size_t lds = (size_t)cm_slot_bytes(row_bytes, tpr, 4) * rp + 32 + 8 * (size_t)tile_rows;
+        const int nt = cm_launch_threads(tpr, rp);
         if (variant == kSweepCQ2) {
             if (nt <= 512)
                 k_sweep_cq<2, 512><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);

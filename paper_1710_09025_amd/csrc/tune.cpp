@@ -57,8 +57,8 @@ bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kS
 
 int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
 {
-    if (is_cq(h)) return 4 * (int64_t)cm_plane_bytes(h.row_bytes) * rp + 32 + 8 * (int64_t)tile_rows;
-    if (is_cm(h)) return 8 * (int64_t)cm_plane_bytes(h.row_bytes) * rp + 32 + 4 * (int64_t)tile_rows;
+    if (is_cq(h)) return (int64_t)cm_slot_bytes(h.row_bytes, h.tpr, 4) * rp + 32 + 8 * (int64_t)tile_rows;
+    if (is_cm(h)) return (int64_t)cm_slot_bytes(h.row_bytes, h.tpr, 8) * rp + 32 + 4 * (int64_t)tile_rows;
     return (int64_t)tile_rows * h.row_bytes + 32 + 4 * (int64_t)tile_rows;
 }
 
@@ -157,8 +157,10 @@ bool shape_valid(const HostInst &h, int tile_rows, int rp, const char **why)
         w = "tile_rows must be in [1, 4096]";
     } else if (is_eo(h) && tile_rows % eo_replicas_per_pass(h.L) != 0) {
         w = "tile_rows must be a multiple of the replicas one pass sweeps";
-    } else if (is_cm(h) && (rp < 1 || (h.tpr * rp) % 64 != 0 || h.tpr * rp > 1024)) {
-        w = "group_replicas must be a multiple of four and make whole waves of at most 1024 threads";
+    } else if (is_cm(h) && (rp < 1 || (h.tpr <= 64 && (h.tpr * rp) % 64 != 0) ||
+                            cm_launch_threads(h.tpr, rp) > 1024)) {
+        w = "group_replicas must be a multiple of four giving at most 1024 threads (whole waves when a quad "
+            "takes at most 64)";
     } else if (sweep_lds(h, tile_rows, is_cm(h) ? rp : 0) > kMaxLds) {
         w = "the workgroup's tile does not fit in LDS";
     }
@@ -202,8 +204,11 @@ std::vector<std::pair<int, int>> shape_candidates(const HostInst &h)
             if (shape_valid(h, m * rp, 0, nullptr) && m * rp <= 2 * h.Rcap) c.emplace_back(m * rp, 0);
     } else if (is_cm(h)) {
         static const int kPasses[] = {1, 2, 3, 4, 6, 8};
-        for (int rp = 1; h.tpr * rp <= 1024; rp *= 2) {
-            if ((h.tpr * rp) % 64 != 0) continue;
+        // quads of up to 64 threads: groups of whole waves; wider quads: any
+        // count whose last wave is at least 80% used
+        for (int rp = 1; cm_launch_threads(h.tpr, rp) <= 1024; rp = h.tpr <= 64 ? 2 * rp : rp + 1) {
+            if (h.tpr <= 64 && (h.tpr * rp) % 64 != 0) continue;
+            if (h.tpr > 64 && rp > 1 && 5 * h.tpr * rp < 4 * cm_launch_threads(h.tpr, rp)) continue;
             for (int m : kPasses)
                 if (shape_valid(h, 4 * m * rp, rp, nullptr) && 4 * m * rp <= 2 * h.Rcap)
                     c.emplace_back(4 * m * rp, rp);
