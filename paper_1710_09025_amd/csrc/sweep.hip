@@ -630,10 +630,16 @@ __device__ void sweep_tile_eo(const Inst &I, int k, uint8_t *lds, int r0, int nr
         eo_sweeps<L, true>(I, k, lds, gr, tb, unsat, r0, nrows, phase);
     else
         eo_sweeps<L, false>(I, k, lds, gr, tb, unsat, r0, nrows, phase);
-    tile_store(io, lds, r0, nrows, SH::N);
+    // the output pointers are read again rather than held through the
+    // sweeps: held, their registers spilled to scratch on every pass (the
+    // empty asm's memory clobber keeps the compiler from reusing the first
+    // reads)
+    asm volatile("" ::: "memory");
+    const TileIO out = tile_io(I);
+    tile_store(out, lds, r0, nrows, SH::N);
     if (phase == 1) return;
-    tile_energy_out(I, io, unsat, r0, nrows);
-    tile_family_count(I, io, r0, nrows);
+    tile_energy_out(I, out, unsat, r0, nrows);
+    tile_family_count(I, out, r0, nrows);
 }
 
 // ---------------------------------------------------------------------------

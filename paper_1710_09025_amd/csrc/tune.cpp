@@ -86,11 +86,15 @@ std::string device_tag()
     return arch + "-" + std::to_string(p.multiProcessorCount) + "cu";
 }
 
-// One choice per line, as a JSON object with these fields in this order.
-const char *kLineFmt =
-    "{\"device\": \"%63[^\"]\", \"variant\": %d, \"dim\": %d, \"L\": %d, \"sweeps\": %d, "
-    "\"cap_log2\": %d, \"packed\": %d, \"tile_rows\": %d, \"group_quads\": %d, "
-    "\"ns_per_attempt\": %lf}";
+// One choice per line, as a JSON object with these fields in this order
+// (read with kLineFmt, written with kLineOut).
+#define PAMC_TUNE_LINE(DEV, NS)                                                                     \
+    "{\"device\": \"" DEV "\", \"variant\": %d, \"dim\": %d, \"L\": %d, \"sweeps\": %d, "  \
+    "\"cap_log2\": %d, \"packed\": %d, \"tile_rows\": %d, \"group_quads\": %d, "               \
+    "\"ns_per_attempt\": " NS "}"
+const char *kLineFmt = PAMC_TUNE_LINE("%63[^\"]", "%lf");
+const char *kLineOut = PAMC_TUNE_LINE("%s", "%.6e");
+#undef PAMC_TUNE_LINE
 
 void load_file(const std::string &path)
 {
@@ -133,7 +137,7 @@ void save_choice(const std::string &dev, const Key &k, const Choice &c)
     if (g_save_path.empty()) return;
     FILE *f = std::fopen(g_save_path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, kLineFmt, dev.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+    std::fprintf(f, kLineOut, dev.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
                  std::get<4>(k), std::get<5>(k), c.tile_rows, c.rp, c.ns_per_attempt);
     std::fputc('\n', f);
     std::fclose(f);
