@@ -569,14 +569,14 @@ def icm_bench(name, rounds=2):
 
 def warm_serving_shapes(sweeps=10):
     """Tunes the sweep shapes of the serving size classes before the stream
-    (as a deployment would ship a tuning cache): every L of the request mix
-    and a grid of populations covering its capacity classes."""
+    (found in the shipped tuning cache, so normally instant): every L of the
+    request mix at the population the server tunes requests for."""
     from paper_1710_09025_amd import autotune
 
     t0 = time.perf_counter()
     for L in range(4, 15):
-        for R in (5000, 8000, 12000, 16000, 24000, 32000, 40000, 50000):
-            autotune(L, R, sweeps)
+        # the server tunes every request for a population of 10^5 rows
+        autotune(L, 100_000, sweeps)
     return time.perf_counter() - t0
 
 

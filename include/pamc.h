@@ -408,7 +408,11 @@ typedef struct pamc_server_options {
     int device;          /* -1 = current                                    */
     int autotune;        /* 1: each request's sweep shape is chosen by
                             measurement at submission (pamc_autotune, cached
-                            per process); 0: the fixed rule                 */
+                            per process and in the shipped tuning file),
+                            for a population of 10^5 rows of the request's
+                            lattice: requests of one size sweep together in
+                            one launch, whatever their own R; 0: the fixed
+                            rule                                            */
     int spin_format;     /* PAMC_SPINS_INT8 or PAMC_SPINS_PACKED for every
                             request (footprints follow it)                  */
 } pamc_server_options;

@@ -207,6 +207,7 @@ Runner::~Runner()
 {
     if (stream_) (void)hipStreamSynchronize(stream_);
     if (side_) (void)hipStreamSynchronize(side_);
+    for (hipStream_t s : aux_) (void)hipStreamSynchronize(s);
     (void)release_fenced(true);
     for (size_t i = 0; i < inst_.size(); ++i)
         if (used_[i]) alloc_.put(inst_[i].block);
@@ -219,6 +220,9 @@ Runner::~Runner()
     alloc_.put(d_insts_);
     alloc_.put(d_nlnn_);
     alloc_.put(d_Jptr_);
+    for (hipEvent_t e : ev_join_) (void)hipEventDestroy(e);
+    if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+    for (hipStream_t s : aux_) (void)hipStreamDestroy(s);
     if (own_stream_ && stream_) (void)hipStreamDestroy(stream_);
 }
 
@@ -253,6 +257,17 @@ int Runner::setup(const pamc_options &opt, int max_slots, bool external_stream)
     } else {
         HIPCHK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");
         own_stream_ = true;
+    }
+    if (max_slots > 1) {
+        for (int a = 0; a < kAuxStreams; ++a) {
+            hipStream_t s = nullptr;
+            hipEvent_t e = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate (sweep groups)");
+            aux_.push_back(s);
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate (sweep groups)");
+            ev_join_.push_back(e);
+        }
+        HIPCHK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming), "hipEventCreate (sweep groups)");
     }
     inst_.resize((size_t)max_slots);
     used_.assign((size_t)max_slots, 0);
@@ -877,9 +892,35 @@ void Runner::drop_graph()
 // population size live on the device), so the sequence can be captured once.
 int Runner::launch_step_kernels()
 {
-    // runs with cluster moves split their sweeps around the ICM rounds
+    // the shape groups touch disjoint instances: with several of them, fork
+    // them onto the auxiliary streams, the largest first, and join before
+    // the resampling (a launch's last workgroups then share the chip with
+    // the next group's first ones)
+    std::vector<const SweepGroup *> plain;
     for (auto &g : sweep_groups_)
-        if (!g.icm) launch_sweep(g.variant, d_insts_, g.work, g.nwork, g.tile_rows, g.row_bytes, g.tpr, g.rp, 0, stream_);
+        if (!g.icm) plain.push_back(&g);
+    const int ns = std::min((int)aux_.size(), (int)plain.size() - 1);
+    if (ns <= 0) {
+        for (const SweepGroup *g : plain)
+            launch_sweep(g->variant, d_insts_, g->work, g->nwork, g->tile_rows, g->row_bytes, g->tpr, g->rp, 0, stream_);
+    } else {
+        std::stable_sort(plain.begin(), plain.end(), [](const SweepGroup *a, const SweepGroup *b) {
+            return (double)a->nwork * a->tile_rows * a->row_bytes > (double)b->nwork * b->tile_rows * b->row_bytes;
+        });
+        HIPCHK(hipEventRecord(ev_fork_, stream_), "hipEventRecord (fork)");
+        for (int a = 0; a < ns; ++a) HIPCHK(hipStreamWaitEvent(aux_[a], ev_fork_, 0), "hipStreamWaitEvent (fork)");
+        for (size_t j = 0; j < plain.size(); ++j) {
+            const int lane = (int)(j % (size_t)(ns + 1));
+            const SweepGroup *g = plain[j];
+            launch_sweep(g->variant, d_insts_, g->work, g->nwork, g->tile_rows, g->row_bytes, g->tpr, g->rp, 0,
+                         lane == 0 ? stream_ : aux_[lane - 1]);
+        }
+        for (int a = 0; a < ns; ++a) {
+            HIPCHK(hipEventRecord(ev_join_[a], aux_[a]), "hipEventRecord (join)");
+            HIPCHK(hipStreamWaitEvent(stream_, ev_join_[a], 0), "hipStreamWaitEvent (join)");
+        }
+    }
+    // runs with cluster moves split their sweeps around the ICM rounds
     if (nicm_) {
         for (auto &g : sweep_groups_)
             if (g.icm)

@@ -179,6 +179,13 @@ private:
         int nwork;
     };
     std::vector<SweepGroup> sweep_groups_;
+    // Runs of several instances sweep their shape groups side by side: the
+    // groups go round-robin to the main stream and these, which start after
+    // the fork event on the main stream and rejoin it before the resampling.
+    static constexpr int kAuxStreams = 2;
+    std::vector<hipStream_t> aux_;
+    hipEvent_t ev_fork_ = nullptr;
+    std::vector<hipEvent_t> ev_join_;
     Work *d_rows_ = nullptr;   // 1024-row blocks (expand)
     int nrows_work_ = 0;
     Work *d_wblk_ = nullptr;   // 1024-row blocks of instances with real couplings (weights)

@@ -33,10 +33,16 @@ namespace pamc {
 int make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const double *beta, int nT, int NS,
               uint64_t seed, const pamc_options &opt, HostInst &h);
 void tune_cache_load();
+bool shape_valid(const HostInst &h, int tile_rows, int rp, const char **why);
+int tune_shape(HostInst &h, const pamc_options &opt, double *ns_per_attempt);
 }
 
 using pamc::HostInst;
 using pamc::Runner;
+
+namespace {
+constexpr int64_t kServeShapeRows = 100000;  // population the serving shapes are tuned for
+}
 
 namespace {
 
@@ -501,13 +507,29 @@ int pamc_server_submit(pamc_server *s, const pamc_instance *inst, uint64_t *req_
     pamc_options o;
     pamc_default_options(&o);
     o.device = s->device;
-    o.autotune = s->autotune ? 1 : 0;
     o.spin_format = s->spin_format;
     o.pop_schedule = inst->pop_schedule;
     Request r;
     int st = pamc::make_inst(inst->L, inst->real_couplings ? nullptr : inst->couplings, inst->real_couplings,
                              inst->R, inst->beta, inst->n_temps, inst->sweeps, inst->seed, o, r.h);
     if (st != PAMC_OK) return st;
+    if (s->autotune) {
+        // The requests of one lattice size in flight together sweep as one
+        // launch of about kServeShapeRows rows: the shape is the one tuned
+        // for that population, not for the request alone (whose own tuning
+        // favours small tiles to fill the chip by itself), and requests of
+        // one size share it, hence one launch per size and step.
+        HostInst t = r.h;
+        t.R = kServeShapeRows;
+        t.Rcap = pamc::default_capacity(kServeShapeRows);
+        o.autotune = 1;
+        st = pamc::tune_shape(t, o, nullptr);
+        if (st != PAMC_OK) return st;
+        if (pamc::shape_valid(r.h, t.tile_rows, t.rp, nullptr)) {
+            r.h.tile_rows = t.tile_rows;
+            r.h.rp = t.rp;
+        }
+    }
     r.bytes = pamc::inst_device_bytes(inst->L, r.h.Rcap, inst->n_temps, r.h.ovl_n, r.h.packed != 0,
                                       r.h.real != 0) +
               4096;

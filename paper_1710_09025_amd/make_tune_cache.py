@@ -18,8 +18,8 @@ import os
 import sys
 import time
 
-# the serving size classes: every L of 4 .. 14 over a grid of populations
-# that covers the capacity classes between 5 10^3 and 5 10^4 replicas
+# single runs of the request sizes of the serving mix: every L of 4 .. 14
+# over a grid of populations covering the capacity classes of 5e3 .. 5e4 rows
 SERVING_L = range(4, 15)
 SERVING_R = (5000, 8000, 12000, 16000, 24000, 32000, 40000, 50000)
 
