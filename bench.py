@@ -430,8 +430,13 @@ def batch_bench(n_inst, plain_n):
     shapes = {}
     for L in sorted(count):
         d = next(d for d in insts if d["L"] == L)
-        t, g, ns = autotune(L, d["R"], d["sweeps"])  # cached: the shapes both sides used
-        shapes[str(L)] = {"tile_rows": t, "group_replicas": g, "sweep_ns_per_attempt": round(ns, 6)}
+        # cached: the separate runs tune for their own population, the batch
+        # for the population of its launch of that size (at most 2e5 rows)
+        t, g, ns = autotune(L, d["R"], d["sweeps"])
+        tb, gb, nsb = autotune(L, min(count[L] * d["R"], 200_000), d["sweeps"])
+        shapes[str(L)] = {"separate": {"tile_rows": t, "group_replicas": g, "sweep_ns_per_attempt": round(ns, 6)},
+                          "batched": {"tile_rows": tb, "group_replicas": gb,
+                                      "sweep_ns_per_attempt": round(nsb, 6)}}
     if mismatches:
         raise AssertionError(f"batched and separate runs differ for instances {mismatches[:10]}")
     full = plain_n >= n_inst

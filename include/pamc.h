@@ -391,6 +391,9 @@ typedef struct pamc_instance {
 
 typedef struct pamc_batch pamc_batch;
 
+/* With opt->autotune and no explicit shape, the instances of one lattice
+ * size (and kernel) share the shape tuned for their summed population, up to
+ * 2e5 rows: they sweep as one launch per step. */
 int pamc_batch_create(int n, const pamc_instance *inst, const pamc_options *opt, pamc_batch **out);
 int pamc_batch_anneal(pamc_batch *b);
 int pamc_batch_observables(const pamc_batch *b, int i, pamc_step_obs *out, int n);

@@ -4,9 +4,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "runner.h"
@@ -406,22 +408,60 @@ int pamc_phase_times(pamc_ctx *ctx, double *sweep_ms, double *resample_ms, doubl
 void pamc_destroy(pamc_ctx *ctx) { delete ctx; }
 
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kGroupShapeRows = 200000;  // population batch shapes are tuned for (at most)
+}
+
 int pamc_batch_create(int n, const pamc_instance *inst, const pamc_options *opt, pamc_batch **out)
 {
     if (!out) return invalid("out is NULL");
     *out = nullptr;
     if (n < 1 || !inst) return invalid("need at least one instance");
     const pamc_options o = resolve(opt);
+    // Instances of one lattice (and kernel) sweep as one launch per step:
+    // with autotuning and no explicit shape, that launch's shape is the one
+    // tuned for the group's population (up to kGroupShapeRows rows), not
+    // for each instance alone, whose own tuning favours small tiles to fill
+    // the chip by itself.
+    const bool group_tune = o.autotune && o.tile_rows == 0 && o.group_replicas == 0;
     std::vector<HostInst> v((size_t)n);
     for (int i = 0; i < n; ++i) {
         const pamc_instance &p = inst[i];
         pamc_options oi = o;
         oi.pop_schedule = p.pop_schedule;
+        if (group_tune) oi.autotune = 0;
         int st = pamc::make_inst(p.L, p.real_couplings ? nullptr : p.couplings, p.real_couplings, p.R, p.beta,
                                  p.n_temps, p.sweeps, p.seed, oi, v[(size_t)i]);
         if (st != PAMC_OK) {
             pamc::set_error("instance " + std::to_string(i) + ": " + pamc_last_error());
             return st;
+        }
+    }
+    if (group_tune) {
+        using GKey = std::tuple<int, int, int, int, int>;  // variant, dim, L, sweeps, packed
+        auto gkey = [](const HostInst &h) { return GKey(h.variant, h.dim, h.L, h.NS, h.packed); };
+        std::map<GKey, int64_t> rows;
+        for (const HostInst &h : v) rows[gkey(h)] += h.R;
+        std::map<GKey, std::pair<int, int>> shape;
+        for (auto &kv : rows) {
+            HostInst t;
+            for (const HostInst &h : v)
+                if (gkey(h) == kv.first) {
+                    t = h;
+                    break;
+                }
+            t.R = std::min<int64_t>(kv.second, kGroupShapeRows);
+            t.Rcap = pamc::default_capacity(t.R);
+            const int st = pamc::tune_shape(t, o, nullptr);
+            if (st != PAMC_OK) return st;
+            shape[kv.first] = {t.tile_rows, t.rp};
+        }
+        for (HostInst &h : v) {
+            const auto s = shape[gkey(h)];
+            if (pamc::shape_valid(h, s.first, s.second, nullptr)) {
+                h.tile_rows = s.first;
+                h.rp = s.second;
+            }
         }
     }
     std::unique_ptr<pamc_batch> b(new (std::nothrow) pamc_batch());
