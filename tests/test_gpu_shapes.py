@@ -24,8 +24,10 @@ def same_run(a, b, what):
 
 
 # (L, shapes as (tile_rows, group_replicas)): colour-major with two and three
-# colours (8 threads per replica quad at L = 4, 128 at L = 10, 256 at L = 12;
-# tiles that are not multiples of four leave a quad partly empty),
+# colours (8 threads per replica quad at L = 4, 125 at L = 10, 216 at L = 12,
+# 194 at L = 13, 343 at L = 14: quads above 64 threads leave the last wave
+# partly idle, and groups of them take the 512-, 768- and 1024-thread
+# kernels; tiles that are not multiples of four leave a quad partly empty),
 # even/odd-x (L = 8, 16), per-site (L = 24); ragged tiles and single-pass
 # workgroups
 SHAPES = [
@@ -33,6 +35,8 @@ SHAPES = [
     (5, [(16, 16), (40, 16), (128, 128)]),
     (10, [(4, 4), (7, 4), (16, 8), (6, 16), (24, 12)]),
     (12, [(4, 4), (12, 12), (24, 8), (40, 16)]),
+    (13, [(8, 4), (16, 8), (24, 12), (32, 16)]),
+    (14, [(8, 4), (16, 8), (10, 8)]),
     (8, [(8, 0), (16, 0), (64, 0)]),
     (16, [(2, 0), (4, 0), (14, 0)]),
     (24, [(1, 0), (3, 0)]),
@@ -41,7 +45,7 @@ SHAPES = [
 
 @pytest.mark.parametrize("L,shapes", SHAPES)
 def test_every_sweep_shape_gives_identical_results(L, shapes):
-    R = {4: 700, 5: 300, 10: 90, 12: 61, 8: 333, 16: 40, 24: 7}[L]
+    R = {4: 700, 5: 300, 10: 90, 12: 61, 13: 61, 14: 37, 8: 333, 16: 40, 24: 7}[L]
     inst = instance(L, R, 7, 3, 4.0, disorder_seed=30 + L, seed=40 + L)
     base = run(inst)
     for tr, g in shapes:
