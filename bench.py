@@ -696,8 +696,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs an instance on one device and has no "
+              "multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
