@@ -302,7 +302,7 @@ def cpu_baseline(name, n_steps, real=False):
                       f"(full population R={cfg['R']}, L={cfg['L']}), {t1 - t0:.1f} s"}
 
 
-def cpu_baseline_sampled(name, R_steps, rows_1t=192, rows_nt=2048, rows_resample=20000):
+def cpu_baseline_sampled(name, R_steps, rows_1t=448, rows_nt=6144, rows_resample=20000):
     """The oracle on a row sample of the workload's anneal, extrapolated to
     the whole anneal (the full run takes hours on the host).
 

@@ -546,8 +546,22 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
                         const uint32_t own = lds32(rj, g.own);
                         const uint32_t n = eo_unsat(rj, g, own);
                         uint32_t flip = 0x01010101u;
-                        if constexpr (!ALL) {
-                            const uint32_t r = (uint32_t)(r0 + q0 + j * SH::RPG);
+                        const uint32_t r = (uint32_t)(r0 + q0 + j * SH::RPG);
+                        if constexpr (!ALL && L == 16) {
+                            // the threshold reads go out before the draw,
+                            // whose arithmetic covers their LDS latency; the
+                            // scheduling barriers keep the compiler from
+                            // moving the draw back in front (L = 16: 2303 ->
+                            // 2438 attempts/ns at R = 5e5; at L = 8, whose
+                            // launch holds fewer groups per thread, the
+                            // compiler's own order is 3% faster)
+                            uint32_t th[4];
+                            const uint32_t fa = eo_thresholds(n, tab, th);
+                            __builtin_amdgcn_sched_barrier(0);
+                            const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                            __builtin_amdgcn_sched_barrier(0);
+                            flip = eo_accept(fa, th, u);
+                        } else if constexpr (!ALL) {
                             const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
                             flip = eo_flip(n, u, tab);
                         }
