@@ -6,8 +6,9 @@
 
 namespace pamc {
 
-// CM: colour-major, +-1 couplings; CQ: colour-major, real couplings; SQ:
-// CQ on the square lattice (four neighbours)
+// CM: colour-major, +-1 couplings (CM2T: two colours with the neighbour
+// offsets in an LDS table); CQ: colour-major, real couplings; SQ: CQ on the
+// square lattice (four neighbours)
 enum SweepVariant {
     kSweepLex = 0,
     kSweepEO8 = 1,
@@ -17,7 +18,8 @@ enum SweepVariant {
     kSweepCQ2 = 5,
     kSweepCQ3 = 6,
     kSweepSQ2 = 7,
-    kSweepSQ3 = 8
+    kSweepSQ3 = 8,
+    kSweepCM2T = 9
 };
 
 // Dynamic LDS a sweep workgroup may take: gfx950 gives one workgroup up to
@@ -39,6 +41,11 @@ inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : 
 // whole waves; quads above 64 threads leave the last wave's spare lanes
 // idle (tpr * rp is a multiple of 64 below).
 inline int cm_launch_threads(int tpr, int rp) { return (tpr * rp + 63) / 64 * 64; }
+
+// LDS of the neighbour table of the two-colour table form: per colour and
+// Philox block (tpr records a colour) 24 slot offsets of 16 bits, 48 bytes;
+// 16 more for its alignment.
+inline int cm_table_bytes(int variant, int tpr) { return variant == kSweepCM2T ? 16 + 96 * tpr : 0; }
 
 // LDS stride of one replica-quad slot of `planes` byte planes.  Below 64
 // threads per quad one wave sweeps 64 / tpr quads side by side; unpadded,

@@ -689,6 +689,7 @@ __device__ __forceinline__ void replica_barrier(int tpr)
 
 struct CMBlock {
     uint32_t nb[24];  // LDS offsets of the neighbour words, [direction][site]
+    uint32_t tabp;    // table form: LDS offset of the block's record in the table
     uint32_t own;     // LDS offset of site 0's word (site i at + i plane_bytes)
     uint32_t vbits;   // bit i set when site i of the block is a real site
     uint32_t ctr;     // Philox counter word 0
@@ -731,11 +732,40 @@ __device__ __forceinline__ uint32_t lds_word(const uint8_t *lds, uint32_t a)
     return *reinterpret_cast<const uint32_t *>(lds + a);
 }
 
+// The 24 neighbour addresses of block b in the quad slot at sbase: kept in
+// registers, or (TAB) read from the block's record in the workgroup's LDS
+// table, two 16-bit slot offsets a word (each extracted and added in one
+// SDWA instruction).  The table form holds 24 fewer registers per colour:
+// with two colours 125 VGPRs, four waves per SIMD instead of three.
+template <bool TAB>
+__device__ __forceinline__ void cm_neighbours(const uint8_t *lds, const CMBlock &b, uint32_t sbase,
+                                              uint32_t (&nb)[24])
+{
+    if constexpr (TAB) {
+        const uint4 *rq = reinterpret_cast<const uint4 *>(lds + b.tabp);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const uint4 w = rq[v];
+            nb[8 * v + 0] = sbase + (w.x & 0xFFFFu);
+            nb[8 * v + 1] = sbase + (w.x >> 16);
+            nb[8 * v + 2] = sbase + (w.y & 0xFFFFu);
+            nb[8 * v + 3] = sbase + (w.y >> 16);
+            nb[8 * v + 4] = sbase + (w.z & 0xFFFFu);
+            nb[8 * v + 5] = sbase + (w.z >> 16);
+            nb[8 * v + 6] = sbase + (w.w & 0xFFFFu);
+            nb[8 * v + 7] = sbase + (w.w >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 24; ++j) nb[j] = b.nb[j];
+    }
+}
+
 // Sweeps of the replicas of the tile, four per thread group at a time, each
 // quad loaded into the group's LDS slot (through the copy map) and stored
 // back after its N_S sweeps.  ALL: beta = 0, every move is accepted.
 // Missing replicas of the last quad are swept as zeros and never stored.
-template <int NCOL, bool ALL>
+template <int NCOL, bool ALL, bool TAB>
 __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, const CMBlock (&blk)[NCOL],
                                           const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows,
                                           int phase)
@@ -745,6 +775,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
     const int ps = I.plane_bytes;
     const int lane_r = (int)threadIdx.x % tpr, qsub = (int)threadIdx.x / tpr;
     uint8_t *slot = lds + qsub * I.slot_bytes;
+    const uint32_t sbase = (uint32_t)(qsub * I.slot_bytes);
     const int nvec = I.row_bytes >> 4, pvec = ps >> 4;
     const uint32_t key0 = I.key0, key1 = I.key1;
     for (int qb = 0; qb < nrows; qb += 4 * RPG) {
@@ -797,13 +828,14 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                         // before the draws, whose arithmetic then covers
                         // their LDS latency; the scheduling barrier keeps the
                         // compiler from moving the draws back in front
-                        uint32_t fa[4], th[4][4];
+                        uint32_t fa[4], th[4][4], nb[24];
+                        cm_neighbours<TAB>(lds, b, sbase, nb);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const uint32_t m = (lds_word(lds, b.nb[i]) + lds_word(lds, b.nb[4 + i]) +
-                                                lds_word(lds, b.nb[8 + i])) +
-                                               (lds_word(lds, b.nb[12 + i]) + lds_word(lds, b.nb[16 + i]) +
-                                                lds_word(lds, b.nb[20 + i]));
+                            const uint32_t m = (lds_word(lds, nb[i]) + lds_word(lds, nb[4 + i]) +
+                                                lds_word(lds, nb[8 + i])) +
+                                               (lds_word(lds, nb[12 + i]) + lds_word(lds, nb[16 + i]) +
+                                                lds_word(lds, nb[20 + i]));
                             fa[i] = eo_thresholds(unsat_from_sum(m, own[i]), tab, th[i]);
                         }
                         __builtin_amdgcn_sched_barrier(0);
@@ -852,13 +884,15 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
                 if (!blk[c].has) continue;
+                uint32_t nb[24];
+                cm_neighbours<TAB>(lds, blk[c], sbase, nb);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if (!((blk[c].vbits >> i) & 1u)) continue;
-                    const uint32_t m = (lds_word(lds, blk[c].nb[i]) + lds_word(lds, blk[c].nb[4 + i]) +
-                                        lds_word(lds, blk[c].nb[8 + i])) +
-                                       (lds_word(lds, blk[c].nb[12 + i]) + lds_word(lds, blk[c].nb[16 + i]) +
-                                        lds_word(lds, blk[c].nb[20 + i]));
+                    const uint32_t m = (lds_word(lds, nb[i]) + lds_word(lds, nb[4 + i]) +
+                                        lds_word(lds, nb[8 + i])) +
+                                       (lds_word(lds, nb[12 + i]) + lds_word(lds, nb[16 + i]) +
+                                        lds_word(lds, nb[20 + i]));
                     acc += unsat_from_sum(m, lds_word(lds, blk[c].own + i * ps));
                 }
             }
@@ -887,7 +921,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
     }
 }
 
-template <int NCOL>
+template <int NCOL, bool TAB>
 __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows,
                                               int phase)
 {
@@ -912,10 +946,34 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
         const uint16_t *d = I.cmdesc + ((size_t)c * I.gmax + gg) * 32;
         // byte offset o of the single-replica slot [row | complement]: row
         // position o, or complement position o - row_bytes
+        if constexpr (TAB) {
+            // the table follows the row energies, 16-byte aligned; the
+            // first quad's threads write it (slot offsets are the same for
+            // every quad)
+            const uint32_t tbase = ((uint32_t)(RPG * slot_bytes + 32 + 4 * tile_rows) + 15u) & ~15u;
+            blk[c].tabp = tbase + 48u * (uint32_t)(c * tpr + g);
+            if (qsub == 0) {
+                uint32_t w[12];
 #pragma unroll
-        for (int i = 0; i < 24; ++i) {
-            const uint32_t o = d[i];
-            blk[c].nb[i] = slot + (o < rb ? quad_pos(o, ps) : 4u * ps + quad_pos(o - rb, ps));
+                for (int i = 0; i < 24; ++i) {
+                    const uint32_t o = d[i];
+                    const uint32_t off = o < rb ? quad_pos(o, ps) : 4u * ps + quad_pos(o - rb, ps);
+                    if (i & 1)
+                        w[i >> 1] |= off << 16;
+                    else
+                        w[i >> 1] = off;
+                }
+                uint4 *rec = reinterpret_cast<uint4 *>(lds + blk[c].tabp);
+                rec[0] = make_uint4(w[0], w[1], w[2], w[3]);
+                rec[1] = make_uint4(w[4], w[5], w[6], w[7]);
+                rec[2] = make_uint4(w[8], w[9], w[10], w[11]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 24; ++i) {
+                const uint32_t o = d[i];
+                blk[c].nb[i] = slot + (o < rb ? quad_pos(o, ps) : 4u * ps + quad_pos(o - rb, ps));
+            }
         }
         const uint32_t vm = blk[c].has ? (uint32_t)d[24] | ((uint32_t)d[25] << 16) : 0u;
         blk[c].vbits = (vm & 1u) | ((vm >> 7) & 2u) | ((vm >> 14) & 4u) | ((vm >> 21) & 8u);
@@ -929,9 +987,9 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     __syncthreads();
     const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
     if (all)
-        cm_passes<NCOL, true>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
+        cm_passes<NCOL, true, TAB>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
     else
-        cm_passes<NCOL, false>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
+        cm_passes<NCOL, false, TAB>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
     __syncthreads();
     // every bond was counted from both of its ends
     for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] >>= 1;
@@ -949,7 +1007,7 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
 // needs four waves per SIMD and spills.  The 768-thread form lets quads
 // wider than 64 threads come in threes and fours (L = 12: 3 x 216 threads
 // in 11 waves, 92% of the lanes busy, against 84% for one quad).
-template <int NCOL, int MAXT>
+template <int NCOL, int MAXT, bool TAB = false>
 __global__ __launch_bounds__(MAXT, MAXT <= 768 ? 3 : 4) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows,
                                                                        int phase)
 {
@@ -961,7 +1019,7 @@ __global__ __launch_bounds__(MAXT, MAXT <= 768 ? 3 : 4) void k_sweep_cm(const In
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_cm<NCOL>(I, k, lds, r0, nrows, tile_rows, phase);
+    if (nrows > 0) sweep_tile_cm<NCOL, TAB>(I, k, lds, r0, nrows, tile_rows, phase);
     if (phase == 1)
         phase1_done(I);
     else if (last_workgroup(&I.sync[0], I.sweep_tiles))
@@ -1303,7 +1361,8 @@ hipError_t sweep_kernels_init()
         reinterpret_cast<const void *>(&k_sweep_eo<16>),      reinterpret_cast<const void *>(&k_sweep_cm<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_cm<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<3, 512>),
         reinterpret_cast<const void *>(&k_sweep_cm<3, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<2, 768>),
-        reinterpret_cast<const void *>(&k_sweep_cm<3, 768>), reinterpret_cast<const void *>(&k_sweep_cq<2, 512>),
+        reinterpret_cast<const void *>(&k_sweep_cm<3, 768>),  reinterpret_cast<const void *>(&k_sweep_cm<2, 512, true>),
+        reinterpret_cast<const void *>(&k_sweep_cm<2, 1024, true>), reinterpret_cast<const void *>(&k_sweep_cq<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_cq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cq<3, 512>),
         reinterpret_cast<const void *>(&k_sweep_cq<3, 1024>), reinterpret_cast<const void *>(&k_sweep_sq<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_sq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_sq<3, 512>),
@@ -1351,6 +1410,17 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
                   int rp, int phase, hipStream_t st)
 {
     if (!nwork) return;
+    if (variant == kSweepCM2T) {
+        // as below, with the neighbour table after the row energies
+        const size_t lds = (size_t)cm_slot_bytes(row_bytes, tpr, 8) * rp + 32 + 4 * (size_t)tile_rows +
+                           cm_table_bytes(variant, tpr);
+        const int nt = cm_launch_threads(tpr, rp);
+        if (nt <= 512)
+            k_sweep_cm<2, 512, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        else
+            k_sweep_cm<2, 1024, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        return;
+    }
     if (variant == kSweepCM2 || variant == kSweepCM3) {
         // rp replica quads, each four planes of the row and of the complement
         const size_t lds = (size_t)cm_slot_bytes(row_bytes, tpr, 8) * rp + 32 + 4 * (size_t)tile_rows;

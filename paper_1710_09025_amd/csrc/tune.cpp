@@ -46,8 +46,8 @@ constexpr double kTuneBeta = 2.0;   // inside the low-temperature part where an 
 
 bool is_cm(const HostInst &h)
 {
-    return h.variant == kSweepCM2 || h.variant == kSweepCM3 || h.variant == kSweepCQ2 || h.variant == kSweepCQ3 ||
-           h.variant == kSweepSQ2 || h.variant == kSweepSQ3;
+    return h.variant == kSweepCM2 || h.variant == kSweepCM2T || h.variant == kSweepCM3 || h.variant == kSweepCQ2 ||
+           h.variant == kSweepCQ3 || h.variant == kSweepSQ2 || h.variant == kSweepSQ3;
 }
 bool is_cq(const HostInst &h)
 {
@@ -58,7 +58,9 @@ bool is_eo(const HostInst &h) { return h.variant == kSweepEO8 || h.variant == kS
 int64_t sweep_lds(const HostInst &h, int tile_rows, int rp)
 {
     if (is_cq(h)) return (int64_t)cm_slot_bytes(h.row_bytes, h.tpr, 4) * rp + 32 + 8 * (int64_t)tile_rows;
-    if (is_cm(h)) return (int64_t)cm_slot_bytes(h.row_bytes, h.tpr, 8) * rp + 32 + 4 * (int64_t)tile_rows;
+    if (is_cm(h))
+        return (int64_t)cm_slot_bytes(h.row_bytes, h.tpr, 8) * rp + 32 + 4 * (int64_t)tile_rows +
+               cm_table_bytes(h.variant, h.tpr);
     return (int64_t)tile_rows * h.row_bytes + 32 + 4 * (int64_t)tile_rows;
 }
 
