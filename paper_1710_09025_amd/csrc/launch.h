@@ -6,8 +6,8 @@
 
 namespace pamc {
 
-// CM: colour-major, +-1 couplings (CM2T: two colours with the neighbour
-// offsets in an LDS table); CQ: colour-major, real couplings; SQ: CQ on the
+// CM: colour-major, +-1 couplings (CM2T, CM3T: two or three colours with the
+// neighbour offsets in an LDS table); CQ: colour-major, real couplings; SQ: CQ on the
 // square lattice (four neighbours)
 enum SweepVariant {
     kSweepLex = 0,
@@ -19,7 +19,8 @@ enum SweepVariant {
     kSweepCQ3 = 6,
     kSweepSQ2 = 7,
     kSweepSQ3 = 8,
-    kSweepCM2T = 9
+    kSweepCM2T = 9,
+    kSweepCM3T = 10
 };
 
 // Dynamic LDS a sweep workgroup may take: gfx950 gives one workgroup up to
@@ -42,10 +43,13 @@ inline int cm_plane_bytes(int row_bytes) { return row_bytes <= 64 ? row_bytes : 
 // idle (tpr * rp is a multiple of 64 below).
 inline int cm_launch_threads(int tpr, int rp) { return (tpr * rp + 63) / 64 * 64; }
 
-// LDS of the neighbour table of the two-colour table form: per colour and
-// Philox block (tpr records a colour) 24 slot offsets of 16 bits, 48 bytes;
-// 16 more for its alignment.
-inline int cm_table_bytes(int variant, int tpr) { return variant == kSweepCM2T ? 16 + 96 * tpr : 0; }
+// LDS of the neighbour table of the table forms: per colour and Philox
+// block (tpr records a colour) 24 slot offsets of 16 bits, 48 bytes; 16
+// more for its alignment.
+inline int cm_table_bytes(int variant, int tpr)
+{
+    return variant == kSweepCM2T ? 16 + 96 * tpr : variant == kSweepCM3T ? 16 + 144 * tpr : 0;
+}
 
 // LDS stride of one replica-quad slot of `planes` byte planes.  Below 64
 // threads per quad one wave sweeps 64 / tpr quads side by side; unpadded,

@@ -147,6 +147,7 @@ int pamc::make_inst(int L, const int8_t *J, const int32_t *Jq, int64_t R, const 
     if (opt.tile_rows < 0 || opt.tile_rows > 4096) return invalid("tile_rows out of range");
     if (opt.group_replicas < 0 || opt.group_replicas > 1024) return invalid("group_replicas out of range");
     const bool cm = h.variant == pamc::kSweepCM2 || h.variant == pamc::kSweepCM2T || h.variant == pamc::kSweepCM3 ||
+                    h.variant == pamc::kSweepCM3T ||
                     h.variant == pamc::kSweepCQ2 || h.variant == pamc::kSweepCQ3 || h.variant == pamc::kSweepSQ2 ||
                     h.variant == pamc::kSweepSQ3;
     if (opt.tile_rows > 0 || (cm && opt.group_replicas > 0)) {

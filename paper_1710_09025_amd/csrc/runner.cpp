@@ -105,14 +105,23 @@ LayoutInfo layout_for(int L, bool real, int dim)
         }
         return li;
     }
-    // two colours with quads of at most 128 threads (L <= 10) take the
-    // neighbour table in LDS (four waves per SIMD instead of three: 6-12%
-    // faster there; above, the extra table reads and adds cost more than
-    // the occupancy gains)
-    const int cmv = li.ncol == 2 ? (tpr <= 128 ? kSweepCM2T : kSweepCM2) : kSweepCM3;
-    if (tpr <= 1024 && 2 * rb <= 65535 &&
-        (size_t)cm_slot_bytes(rb, tpr, 8) * cm_replicas_per_block(tpr) + 32 + 4 * 64 + cm_table_bytes(cmv, tpr) <=
-            kMaxSweepLds) {
+    // The neighbour table in LDS instead of registers: three colours always
+    // (136 VGPRs without spills against 168 with 38 spilled: 10-20% faster
+    // at L = 5 ... 13), two colours with quads of at most 128 threads
+    // (L <= 10: four waves per SIMD instead of three, 7-12% faster; above,
+    // the extra table reads and adds cost what the occupancy gains).  The
+    // table holds 16-bit slot offsets, so the slot must stay within 64 KB,
+    // and slot and table must fit the workgroup's LDS; otherwise the
+    // register form.
+    auto fits = [&](int v) {
+        const size_t tab = (size_t)cm_table_bytes(v, tpr);
+        return (size_t)cm_slot_bytes(rb, tpr, 8) * cm_replicas_per_block(tpr) + 32 + 4 * 64 + tab <= kMaxSweepLds &&
+               (tab == 0 || 8 * (size_t)cm_plane_bytes(rb) <= 65536);
+    };
+    const int tab_form = li.ncol == 2 ? (tpr <= 128 ? kSweepCM2T : -1) : kSweepCM3T;
+    const int reg_form = li.ncol == 2 ? kSweepCM2 : kSweepCM3;
+    const int cmv = tab_form >= 0 && fits(tab_form) ? tab_form : fits(reg_form) ? reg_form : -1;
+    if (tpr <= 1024 && 2 * rb <= 65535 && cmv >= 0) {
         li.layout = kLayoutCM;
         li.variant = cmv;
         li.row_bytes = rb;

@@ -855,12 +855,14 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             u[j] = philox10(make_uint4(b.ctr, r0q + j, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                        uint32_t nb[24];
+                        cm_neighbours<TAB>(lds, b, sbase, nb);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const uint32_t m = (lds_word(lds, b.nb[i]) + lds_word(lds, b.nb[4 + i]) +
-                                                lds_word(lds, b.nb[8 + i])) +
-                                               (lds_word(lds, b.nb[12 + i]) + lds_word(lds, b.nb[16 + i]) +
-                                                lds_word(lds, b.nb[20 + i]));
+                            const uint32_t m = (lds_word(lds, nb[i]) + lds_word(lds, nb[4 + i]) +
+                                                lds_word(lds, nb[8 + i])) +
+                                               (lds_word(lds, nb[12 + i]) + lds_word(lds, nb[16 + i]) +
+                                                lds_word(lds, nb[20 + i]));
                             const uint32_t n = unsat_from_sum(m, own[i]);
                             flip[i] &= eo_flip(n, make_uint4(word_of(u[0], i), word_of(u[1], i), word_of(u[2], i),
                                                              word_of(u[3], i)),
@@ -1362,7 +1364,9 @@ hipError_t sweep_kernels_init()
         reinterpret_cast<const void *>(&k_sweep_cm<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<3, 512>),
         reinterpret_cast<const void *>(&k_sweep_cm<3, 1024>), reinterpret_cast<const void *>(&k_sweep_cm<2, 768>),
         reinterpret_cast<const void *>(&k_sweep_cm<3, 768>),  reinterpret_cast<const void *>(&k_sweep_cm<2, 512, true>),
-        reinterpret_cast<const void *>(&k_sweep_cm<2, 1024, true>), reinterpret_cast<const void *>(&k_sweep_cq<2, 512>),
+        reinterpret_cast<const void *>(&k_sweep_cm<2, 1024, true>),
+        reinterpret_cast<const void *>(&k_sweep_cm<3, 512, true>),  reinterpret_cast<const void *>(&k_sweep_cm<3, 768, true>),
+        reinterpret_cast<const void *>(&k_sweep_cm<3, 1024, true>), reinterpret_cast<const void *>(&k_sweep_cq<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_cq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_cq<3, 512>),
         reinterpret_cast<const void *>(&k_sweep_cq<3, 1024>), reinterpret_cast<const void *>(&k_sweep_sq<2, 512>),
         reinterpret_cast<const void *>(&k_sweep_sq<2, 1024>), reinterpret_cast<const void *>(&k_sweep_sq<3, 512>),
@@ -1410,15 +1414,24 @@ void launch_sweep(int variant, const Inst *insts, const Work *work, int nwork, i
                   int rp, int phase, hipStream_t st)
 {
     if (!nwork) return;
-    if (variant == kSweepCM2T) {
+    if (variant == kSweepCM2T || variant == kSweepCM3T) {
         // as below, with the neighbour table after the row energies
         const size_t lds = (size_t)cm_slot_bytes(row_bytes, tpr, 8) * rp + 32 + 4 * (size_t)tile_rows +
                            cm_table_bytes(variant, tpr);
         const int nt = cm_launch_threads(tpr, rp);
-        if (nt <= 512)
-            k_sweep_cm<2, 512, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
-        else
-            k_sweep_cm<2, 1024, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        if (variant == kSweepCM2T) {
+            if (nt <= 512)
+                k_sweep_cm<2, 512, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+            else
+                k_sweep_cm<2, 1024, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        } else {
+            if (nt <= 512)
+                k_sweep_cm<3, 512, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+            else if (nt <= 768)
+                k_sweep_cm<3, 768, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+            else
+                k_sweep_cm<3, 1024, true><<<nwork, nt, lds, st>>>(insts, work, tile_rows, phase);
+        }
         return;
     }
     if (variant == kSweepCM2 || variant == kSweepCM3) {

@@ -46,8 +46,8 @@ constexpr double kTuneBeta = 2.0;   // inside the low-temperature part where an 
 
 bool is_cm(const HostInst &h)
 {
-    return h.variant == kSweepCM2 || h.variant == kSweepCM2T || h.variant == kSweepCM3 || h.variant == kSweepCQ2 ||
-           h.variant == kSweepCQ3 || h.variant == kSweepSQ2 || h.variant == kSweepSQ3;
+    return h.variant == kSweepCM2 || h.variant == kSweepCM2T || h.variant == kSweepCM3 || h.variant == kSweepCM3T ||
+           h.variant == kSweepCQ2 || h.variant == kSweepCQ3 || h.variant == kSweepSQ2 || h.variant == kSweepSQ3;
 }
 bool is_cq(const HostInst &h)
 {
