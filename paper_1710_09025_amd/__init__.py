@@ -169,7 +169,9 @@ def _make_options(capacity=None, overlap_steps=None, fuse_gather=True, spin_form
 
 def autotune(L, R, sweeps, torch_stream=True, packed=False, real=False, dim=3):
     """Sweep workgroup shape chosen by measurement (``pamc_autotune``):
-    (tile_rows, group_replicas, sweep ns per attempt).  Cached per process."""
+    (tile_rows, group_replicas, sweep ns per attempt).  Choices are cached
+    per process and read from the tuning file shipped beside the library and
+    from the file ``PAMC_TUNE_CACHE`` names, to which new ones are appended."""
     keep = []
     opt = _make_options(torch_stream=torch_stream, keep=keep, dim=dim,
                         spin_format=_capi.SPINS_PACKED if packed else _capi.SPINS_INT8)
