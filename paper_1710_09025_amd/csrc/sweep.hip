@@ -543,6 +543,10 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                     for (int j = 0; j < SH::RPT; ++j) {
                         uint8_t *rj = row + j * SH::RSTRIDE;
+                        // raised issue priority while the LDS reads and the
+                        // sums that index the thresholds go out, the normal
+                        // one for the draw (see the colour-major kernel)
+                        if constexpr (!ALL && L == 16) __builtin_amdgcn_s_setprio(1);
                         const uint32_t own = lds32(rj, g.own);
                         const uint32_t n = eo_unsat(rj, g, own);
                         uint32_t flip = 0x01010101u;
@@ -558,6 +562,7 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
                             uint32_t th[4];
                             const uint32_t fa = eo_thresholds(n, tab, th);
                             __builtin_amdgcn_sched_barrier(0);
+                            __builtin_amdgcn_s_setprio(0);
                             const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
                             __builtin_amdgcn_sched_barrier(0);
                             flip = eo_accept(fa, th, u);
@@ -817,6 +822,15 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
             for (int c = 0; c < NCOL; ++c) {
                 const CMBlock &b = blk[c];
                 if (act && b.has) {
+                    // The wave issues its LDS reads, and the sums that index
+                    // the thresholds, at raised priority and drops back for
+                    // the draws: a wave whose reads are due then goes ahead
+                    // of the others' long multiply chains instead of waiting
+                    // behind them, so more reads are in flight under the
+                    // arithmetic (2% at L = 12 and 14, 0.5% for the
+                    // even/odd-x kernel at L = 16, as much on the real-
+                    // coupling kernel).
+                    if constexpr (!ALL && NCOL == 2) __builtin_amdgcn_s_setprio(1);
                     uint32_t own[4], flip[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -839,6 +853,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                             fa[i] = eo_thresholds(unsat_from_sum(m, own[i]), tab, th[i]);
                         }
                         __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_s_setprio(0);
                         uint4 u[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
@@ -850,11 +865,15 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                                                                           word_of(u[2], i), word_of(u[3], i)));
                     } else if constexpr (!ALL) {
                         // three colours hold more neighbour addresses: the
-                        // draws first keeps the sums' registers short-lived
+                        // draws first keeps the sums' registers short-lived;
+                        // the reads that follow go out at raised priority
+                        // (L = 9, 11, 13: +3, +5, +1.5%)
                         uint4 u[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             u[j] = philox10(make_uint4(b.ctr, r0q + j, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
+                        __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_s_setprio(1);
                         uint32_t nb[24];
                         cm_neighbours<TAB>(lds, b, sbase, nb);
 #pragma unroll
@@ -868,6 +887,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                                                              word_of(u[3], i)),
                                                tab);
                         }
+                        __builtin_amdgcn_s_setprio(0);
                     }
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -1125,6 +1145,9 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
             for (int c = 0; c < NCOL; ++c) {
                 const CQBlock<NB> &b = blk[c];
                 if (act && b.has) {
+                    // raised issue priority for the field reads, as in the
+                    // +-1 colour-major kernel
+                    if constexpr (!ALL) __builtin_amdgcn_s_setprio(1);
                     uint32_t own[4], flip[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -1139,6 +1162,7 @@ __device__ __forceinline__ void cq_passes(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                         for (int i = 0; i < 4; ++i) cq_field(lds, b, i, own[i], aa[i]);
                         __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_s_setprio(0);
                         uint4 u[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
