@@ -543,9 +543,8 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
 #pragma unroll
                     for (int j = 0; j < SH::RPT; ++j) {
                         uint8_t *rj = row + j * SH::RSTRIDE;
-                        // raised issue priority while the LDS reads and the
-                        // sums that index the thresholds go out, the normal
-                        // one for the draw (see the colour-major kernel)
+                        // raised issue priority for everything but the draw
+                        // (see the colour-major kernel)
                         if constexpr (!ALL && L == 16) __builtin_amdgcn_s_setprio(1);
                         const uint32_t own = lds32(rj, g.own);
                         const uint32_t n = eo_unsat(rj, g, own);
@@ -565,6 +564,7 @@ __device__ __forceinline__ void eo_sweeps(const Inst &I, int k, uint8_t *lds, co
                             __builtin_amdgcn_s_setprio(0);
                             const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
                             __builtin_amdgcn_sched_barrier(0);
+                            __builtin_amdgcn_s_setprio(1);
                             flip = eo_accept(fa, th, u);
                         } else if constexpr (!ALL) {
                             const uint4 u = philox10(make_uint4(g.ctr, r, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
@@ -822,14 +822,16 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
             for (int c = 0; c < NCOL; ++c) {
                 const CMBlock &b = blk[c];
                 if (act && b.has) {
-                    // The wave issues its LDS reads, and the sums that index
-                    // the thresholds, at raised priority and drops back for
-                    // the draws: a wave whose reads are due then goes ahead
-                    // of the others' long multiply chains instead of waiting
-                    // behind them, so more reads are in flight under the
-                    // arithmetic (2% at L = 12 and 14, 0.5% for the
-                    // even/odd-x kernel at L = 16, as much on the real-
-                    // coupling kernel).
+                    // Two colours: the wave runs everything but the draws
+                    // (its LDS reads, the sums that index the thresholds,
+                    // the decisions and the writes) at raised priority and
+                    // drops back for the draws, so that a wave whose reads
+                    // or writes are due goes ahead of the others' long
+                    // multiply chains instead of waiting behind them: more
+                    // reads are in flight under the arithmetic and a colour
+                    // step's last writes reach the barrier sooner (L = 10,
+                    // 12, 14: +3.5, +4.5, +2%; the even/odd-x kernel at
+                    // L = 16: +0.5-1%).
                     if constexpr (!ALL && NCOL == 2) __builtin_amdgcn_s_setprio(1);
                     uint32_t own[4], flip[4];
 #pragma unroll
@@ -859,6 +861,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                         for (int j = 0; j < 4; ++j)
                             u[j] = philox10(make_uint4(b.ctr, r0q + j, (uint32_t)k, kTagSweep | (uint32_t)t), key0, key1);
                         __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
                             flip[i] &= eo_accept(fa[i], th[i], make_uint4(word_of(u[0], i), word_of(u[1], i),
