@@ -770,7 +770,9 @@ __device__ __forceinline__ void cm_neighbours(const uint8_t *lds, const CMBlock 
 // quad loaded into the group's LDS slot (through the copy map) and stored
 // back after its N_S sweeps.  ALL: beta = 0, every move is accepted.
 // Missing replicas of the last quad are swept as zeros and never stored.
-template <int NCOL, bool ALL, bool TAB>
+// SF (sums first): the neighbour sums and threshold reads of a block before
+// its draws, else the draws first.
+template <int NCOL, bool ALL, bool TAB, bool SF>
 __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, const CMBlock (&blk)[NCOL],
                                           const uint8_t *tab, int *unsat, const TileIO &io, int r0, int nrows,
                                           int phase)
@@ -822,7 +824,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
             for (int c = 0; c < NCOL; ++c) {
                 const CMBlock &b = blk[c];
                 if (act && b.has) {
-                    // Two colours: the wave runs everything but the draws
+                    // Sums first: the wave runs everything but the draws
                     // (its LDS reads, the sums that index the thresholds,
                     // the decisions and the writes) at raised priority and
                     // drops back for the draws, so that a wave whose reads
@@ -832,14 +834,14 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                     // step's last writes reach the barrier sooner (L = 10,
                     // 12, 14: +3.5, +4.5, +2%; the even/odd-x kernel at
                     // L = 16: +0.5-1%).
-                    if constexpr (!ALL && NCOL == 2) __builtin_amdgcn_s_setprio(1);
+                    if constexpr (!ALL && SF) __builtin_amdgcn_s_setprio(1);
                     uint32_t own[4], flip[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         own[i] = lds_word(lds, b.own + i * ps);
                         flip[i] = ((b.vbits >> i) & 1u) * 0x01010101u;
                     }
-                    if constexpr (!ALL && NCOL == 2) {
+                    if constexpr (!ALL && SF) {
                         // the neighbour sums and the threshold reads go out
                         // before the draws, whose arithmetic then covers
                         // their LDS latency; the scheduling barrier keeps the
@@ -867,10 +869,11 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
                             flip[i] &= eo_accept(fa[i], th[i], make_uint4(word_of(u[0], i), word_of(u[1], i),
                                                                           word_of(u[2], i), word_of(u[3], i)));
                     } else if constexpr (!ALL) {
-                        // three colours hold more neighbour addresses: the
-                        // draws first keeps the sums' registers short-lived;
-                        // the reads that follow go out at raised priority
-                        // (L = 9, 11, 13: +3, +5, +1.5%)
+                        // draws first (three colours in registers, or in a
+                        // 1024-thread workgroup held to 128 VGPRs): the sums'
+                        // registers stay short-lived; the reads that follow
+                        // go out at raised priority (L = 9, 11, 13: +3, +5,
+                        // +1.5%)
                         uint4 u[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
@@ -946,7 +949,7 @@ __device__ __forceinline__ void cm_passes(const Inst &I, int k, uint8_t *lds, co
     }
 }
 
-template <int NCOL, bool TAB>
+template <int NCOL, bool TAB, bool SF>
 __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds, int r0, int nrows, int tile_rows,
                                               int phase)
 {
@@ -1012,9 +1015,9 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
     __syncthreads();
     const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
     if (all)
-        cm_passes<NCOL, true, TAB>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
+        cm_passes<NCOL, true, TAB, SF>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
     else
-        cm_passes<NCOL, false, TAB>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
+        cm_passes<NCOL, false, TAB, SF>(I, k, lds, blk, tb, unsat, io, r0, nrows, phase);
     __syncthreads();
     // every bond was counted from both of its ends
     for (int q = threadIdx.x; q < nrows; q += blockDim.x) unsat[q] >>= 1;
@@ -1031,7 +1034,11 @@ __device__ __forceinline__ void sweep_tile_cm(const Inst &I, int k, uint8_t *lds
 // every neighbour address stays in a register.  A 1024-thread workgroup
 // needs four waves per SIMD and spills.  The 768-thread form lets quads
 // wider than 64 threads come in threes and fours (L = 12: 3 x 216 threads
-// in 11 waves, 92% of the lanes busy, against 84% for one quad).
+// in 11 waves, 92% of the lanes busy, against 84% for one quad).  Sums
+// before draws wherever the registers allow it: two colours, and three in
+// the table form up to 768 threads (142 VGPRs; L = 7, 9, 11: +2.7, +2.3,
+// +1.1%); the 1024-thread three-colour table form would spill with that
+// order (8% slower at L = 13) and keeps the draws first.
 template <int NCOL, int MAXT, bool TAB = false>
 __global__ __launch_bounds__(MAXT, MAXT <= 768 ? 3 : 4) void k_sweep_cm(const Inst *insts, const Work *work, int tile_rows,
                                                                        int phase)
@@ -1044,7 +1051,8 @@ __global__ __launch_bounds__(MAXT, MAXT <= 768 ? 3 : 4) void k_sweep_cm(const In
     const int Rk = (int)I.Rk[k];
     const int r0 = (int)w.row0;
     const int nrows = min(tile_rows, Rk - r0);
-    if (nrows > 0) sweep_tile_cm<NCOL, TAB>(I, k, lds, r0, nrows, tile_rows, phase);
+    constexpr bool kSumsFirst = NCOL == 2 || (TAB && MAXT < 1024);
+    if (nrows > 0) sweep_tile_cm<NCOL, TAB, kSumsFirst>(I, k, lds, r0, nrows, tile_rows, phase);
     if (phase == 1)
         phase1_done(I);
     else if (last_workgroup(&I.sync[0], I.sweep_tiles))
